@@ -1,0 +1,272 @@
+"""FP64 oracle: truncated PCG inner solve and the LM outer loop (alg:lm_inexact).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Vectors of R^(2n) are flat complex arrays (object entries, then probe entries
+for joint problems); a diagonal of R^(2n) is a real array of shape (n, 2)
+holding the (Re, Im) weights of each complex entry.
+
+Readings of points the paper leaves open (each used identically by the GPU
+library):
+* rejection (rho <= rho_min): mu <- kappa mu, z unchanged, the linearisation
+  (G, J, grad ell, D) of the outer iteration is reused and the inner solve is
+  repeated with the new lambda, at most ``retry_max`` times;
+* rho is reset to 0 at the start of every outer iteration;
+* eta = min(beta, sqrt(||J^T grad ell||)) (the printed J grad ell is ill-typed);
+* predicted reduction = 1/2 Delta^T (lambda D Delta - g) (the printed formula
+  has an unbalanced bracket);
+* a non-positive predicted reduction or a non-finite ratio counts as a reject;
+* warm start: the inner solve starts from the last accepted step (zero at
+  t = 0 and after a reject);
+* the inner stopping test uses the unpreconditioned residual norm;
+* zero diagonal entries (unilluminated pixels) are floored at
+  ``diag_floor`` times the largest entry of their block.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ptycho
+
+
+# ----------------------------------------------------------------------------
+# vector helpers
+# ----------------------------------------------------------------------------
+def rdot(u: np.ndarray, v: np.ndarray) -> float:
+    """Real inner product <u, v> = Re sum conj(u) v of the real coordinates."""
+    return float(np.sum(u.real * v.real + u.imag * v.imag))
+
+
+def rnorm(u: np.ndarray) -> float:
+    return math.sqrt(rdot(u, u))
+
+
+def apply_diag(d: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Multiply a real-coordinate diagonal (n, 2) into a complex vector (n,)."""
+    return d[:, 0] * v.real + 1j * d[:, 1] * v.imag
+
+
+def pack(O_part, P_part=None) -> np.ndarray:
+    if P_part is None:
+        return O_part.ravel().copy()
+    return np.concatenate([O_part.ravel(), P_part.ravel()])
+
+
+def unpack(v: np.ndarray, obj_shape, probe_shape, joint: bool):
+    N = obj_shape[0] * obj_shape[1]
+    O_part = v[:N].reshape(obj_shape)
+    P_part = v[N:].reshape(probe_shape) if joint else None
+    return O_part, P_part
+
+
+def pack_diag(dO, dP=None) -> np.ndarray:
+    if dP is None:
+        return dO.reshape(-1, 2).copy()
+    return np.concatenate([dO.reshape(-1, 2), dP.reshape(-1, 2)], axis=0)
+
+
+def floor_block(d: np.ndarray, frac: float) -> np.ndarray:
+    """Raise entries below frac * max(d) to that value (unilluminated pixels)."""
+    return np.maximum(d, frac * float(d.max()))
+
+
+# ----------------------------------------------------------------------------
+# truncated PCG (eq:lma_termination_magnitude)
+# ----------------------------------------------------------------------------
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    r: np.ndarray
+    iters: int
+    res_norms: list
+
+
+def pcg(apply_A, g: np.ndarray, x0: np.ndarray, precond_inv, eta: float, cg_max: int) -> PCGResult:
+    """Solve A x = -g by preconditioned CG until ||A x + g|| <= eta ||g||.
+
+    ``precond_inv`` maps a residual r to z = M^{-1} r (None: identity).  The
+    iteration is the textbook PCG recurrence; all inner products are real and
+    in FP64.  Stops after ``cg_max`` products with A, or on a non-positive
+    curvature p^T A p (impossible for the SPD systems here, kept as a guard).
+    """
+    pc = precond_inv if precond_inv is not None else (lambda r: r.copy())
+    x = x0.copy()
+    r = -g - apply_A(x) if np.any(x0) else -g.copy()
+    z = pc(r)
+    p = z.copy()
+    rz = rdot(r, z)
+    gn = rnorm(g)
+    norms = [rnorm(r)]
+    it = 0
+    while it < cg_max:
+        if norms[-1] <= eta * gn:
+            break
+        Ap = apply_A(p)
+        pAp = rdot(p, Ap)
+        if not pAp > 0.0:
+            break
+        alpha = rz / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = pc(r)
+        rz_new = rdot(r, z)
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+        it += 1
+        norms.append(rnorm(r))
+    return PCGResult(x=x, r=r, iters=it, res_norms=norms)
+
+
+# ----------------------------------------------------------------------------
+# LM step control (alg:lm_inexact)
+# ----------------------------------------------------------------------------
+@dataclass
+class LMParams:
+    mu0: float = 1e-5        # Sec. 5 hyperparameters
+    mu_min: float = 1e-8
+    kappa: float = 4.0
+    nu: float = 1.0
+    rho_min: float = 1e-4
+    beta: float = 0.1        # 0.1 Gaussian, 0.9 Poisson (Sec. 4.2)
+    cg_max: int = 10
+    retry_max: int = 10
+    scaling: int = 0         # 0: D = I, 1: D = Dg(G) (App. B diagonal)
+    precond: int = 0         # 0: none, 1: Jacobi Dg(G + lambda D), 2: learned + lambda
+    diag_floor: float = 1e-6
+    warm_start: bool = True
+
+
+def gain_ratio(dfa: float, dfp: float) -> float:
+    """rho = actual / predicted reduction; -inf when undefined (reject)."""
+    if not (dfp > 0.0) or not math.isfinite(dfa) or not math.isfinite(dfp):
+        return -math.inf
+    rho = dfa / dfp
+    return rho if math.isfinite(rho) else -math.inf
+
+
+def mu_update(rho: float, mu: float, p: LMParams):
+    """Damping update and acceptance of alg:lm_inexact (thresholds strict).
+
+    Returns (new mu, accepted).
+    """
+    if rho > 0.75:
+        return max(mu / p.kappa, p.mu_min), True
+    if rho > 0.25:
+        return mu, True
+    if rho > p.rho_min:
+        return p.kappa * mu, True
+    return p.kappa * mu, False
+
+
+def damping(mu: float, resid_norm: float, scaled: bool, p: LMParams) -> float:
+    """lambda = mu ||grad_zeta ell||^nu when D = I, else lambda = mu."""
+    return mu if scaled else mu * resid_norm ** p.nu
+
+
+@dataclass
+class Attempt:
+    t: int
+    f: float
+    f_trial: float
+    mu: float
+    lam: float
+    eta: float
+    rho: float
+    cg_iters: int
+    accepted: bool
+
+
+@dataclass
+class LMResult:
+    O: np.ndarray
+    P: np.ndarray
+    f: float
+    history: list = field(default_factory=list)
+    f_per_iter: list = field(default_factory=list)
+
+
+def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
+             learned_diag=None, loss_fn=None) -> LMResult:
+    """Truncated matrix-free LM, alg:lm_inexact, step by step.
+
+    ``learned_diag`` is a real-coordinate diagonal (n, 2) used as the PCG
+    preconditioner (plus lambda) when ``params.precond == 2``.  ``loss_fn``
+    overrides the trial-loss evaluation (used to force branches in tests).
+    """
+    p = params
+    O = np.array(O0, dtype=np.complex128)
+    P = np.array(P0, dtype=np.complex128)
+    obj_shape, probe_shape = O.shape, P.shape
+    mu = p.mu0
+    prev_step = None
+    res = LMResult(O=O, P=P, f=float("nan"))
+    trial_loss = loss_fn or (lambda O_, P_: ptycho.loss(O_, P_, pos, y, b, metric))
+
+    for t in range(T):
+        # line "Calculate G, J, grad ell and D_t" -- once per outer iteration
+        lin = ptycho.linearize(O, P, pos, y, b, metric, joint)
+        f_t = lin.f
+        res.f_per_iter.append(f_t)
+        gO, gP = ptycho.gradient(lin)
+        g = pack(gO, gP)
+        gnorm = rnorm(g)
+        zres = ptycho.zeta_residual_norm(lin)
+        dg = None
+        if p.scaling == 1 or p.precond == 1:
+            dO, dP = ptycho.ggn_diag_paper(lin)
+            blocks = [floor_block(dO.reshape(-1, 2), p.diag_floor)]
+            if joint:
+                blocks.append(floor_block(dP.reshape(-1, 2), p.diag_floor))
+            dg = np.concatenate(blocks, axis=0)
+        scaled = p.scaling == 1
+
+        def apply_G(v):
+            vO, vP = unpack(v, obj_shape, probe_shape, joint)
+            return pack(*ptycho.ggn_vp(lin, vO, vP))
+
+        retries = 0
+        while True:  # the "while rho < rho_min" loop with its reject branch
+            lam = damping(mu, zres, scaled, p)
+            if scaled:
+                A = lambda v, lam=lam: apply_G(v) + lam * apply_diag(dg, v)
+            else:
+                A = lambda v, lam=lam: apply_G(v) + lam * v
+            if p.precond == 1:
+                m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
+                pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
+            elif p.precond == 2:
+                m = learned_diag + lam
+                pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
+            else:
+                pc = None
+            eta = min(p.beta, math.sqrt(gnorm))
+            x0 = prev_step if (p.warm_start and retries == 0 and prev_step is not None) \
+                else np.zeros_like(g)
+            sol = pcg(A, g, x0, pc, eta, p.cg_max)
+            step = sol.x
+            sO, sP = unpack(step, obj_shape, probe_shape, joint)
+            O_t = O + sO
+            P_t = P + sP if joint else P
+            f_trial = trial_loss(O_t, P_t)
+            dfa = f_t - f_trial
+            Dstep = lam * (apply_diag(dg, step) if scaled else step)
+            dfp = 0.5 * rdot(step, Dstep - g)
+            rho = gain_ratio(dfa, dfp)
+            mu_new, accepted = mu_update(rho, mu, p)
+            res.history.append(Attempt(t, f_t, f_trial, mu, lam, eta, rho, sol.iters, accepted))
+            mu = mu_new
+            if accepted:
+                O, P = O_t, P_t
+                prev_step = step
+                break
+            retries += 1
+            if retries >= p.retry_max:
+                break
+
+    res.O, res.P = O, P
+    res.f = ptycho.loss(O, P, pos, y, b, metric)
+    return res

@@ -1,0 +1,428 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself.
+
+Each test checks an oracle function against something it cannot agree with by
+construction: the DFT written from its definition, Parseval, finite
+differences of the forward model alone, the adjoint identity, a dense Jacobian
+built by finite differences, null vectors that follow from the model's
+symmetries, a dense linear solve, and zero-loss convergence on noise-free
+data.  A dropped term, a wrong sign or index, or a transposed operand anywhere
+in ``oracle.ptycho`` / ``oracle.solver`` fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ptycho, solver
+
+RNG = np.random.default_rng(12345)
+
+
+def dft_matrix(n):
+    """Unitary DFT matrix from the definition exp(-2 pi i j k / n) / sqrt(n)."""
+    j = np.arange(n)
+    return np.exp(-2j * math.pi * np.outer(j, j) / n) / math.sqrt(n)
+
+
+def brute_dft2(x):
+    My, Mx = x.shape[-2:]
+    return dft_matrix(My) @ x @ dft_matrix(Mx).T
+
+
+def tiny_problem(seed=7, obj=(9, 10), probe=(4, 3), joint=True, metric="gauss", noisy=True):
+    rng = np.random.default_rng(seed)
+    O = synth.random_complex(rng, obj) * 0.5 + 0.8
+    P = synth.random_complex(rng, probe)
+    pos = np.array([[r, c] for r in range(0, obj[0] - probe[0] + 1, 2)
+                    for c in range(0, obj[1] - probe[1] + 1, 3)], dtype=np.int32)
+    h = ptycho.intensity(O, P, pos, 1e-3)
+    y = synth.poisson_counts(rng, 20 * h) / 20 if noisy else h
+    if metric == "poisson":
+        y = synth.poisson_counts(rng, h * 5.0)
+        O = O * math.sqrt(5.0)
+    return O, P, pos, y
+
+
+# ---------------------------------------------------------------- forward model
+@pytest.mark.parametrize("shape", [(4, 4), (6, 6), (8, 4), (3, 5)])
+def test_dft_matches_definition(shape):
+    x = synth.random_complex(RNG, (2,) + shape)
+    np.testing.assert_allclose(ptycho.F(x), brute_dft2(x), atol=1e-13)
+    np.testing.assert_allclose(ptycho.FH(ptycho.F(x)), x, atol=1e-13)
+
+
+def test_parseval():
+    x = synth.random_complex(RNG, (3, 16, 8))
+    np.testing.assert_allclose(np.sum(np.abs(ptycho.F(x)) ** 2, axis=(1, 2)),
+                               np.sum(np.abs(x) ** 2, axis=(1, 2)), rtol=1e-13)
+
+
+def test_exit_wave_by_indexing():
+    O = synth.random_complex(RNG, (7, 9))
+    P = synth.random_complex(RNG, (3, 4))
+    pos = np.array([[0, 0], [4, 5], [2, 3]], dtype=np.int32)
+    psi = ptycho.exit_waves(O, P, pos)
+    for k, (r, c) in enumerate(pos):
+        for i in range(3):
+            for j in range(4):
+                assert abs(psi[k, i, j] - P[i, j] * O[r + i, c + j]) <= 1e-15 * abs(psi[k, i, j])
+
+
+def test_single_position_full_probe_is_textbook_magnitude():
+    O = synth.random_complex(RNG, (6, 6))
+    P = np.ones((6, 6), complex)
+    pos = np.zeros((1, 2), np.int32)
+    b = 0.25
+    zeta = ptycho.magnitude(O, P, pos, b)[0]
+    np.testing.assert_allclose(zeta, np.sqrt(np.abs(brute_dft2(O)) ** 2 + b), rtol=1e-13)
+
+
+def test_adjoint_extract():
+    O = synth.random_complex(RNG, (8, 7))
+    pos = np.array([[0, 1], [3, 2], [5, 4]], dtype=np.int32)
+    w = synth.random_complex(RNG, (3, 3, 3))
+    lhs = np.vdot(w, ptycho.extract(O, pos, (3, 3)))
+    rhs = np.vdot(ptycho.extract_adjoint(w, pos, O.shape), O)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_metric_values_and_derivatives_by_fd():
+    z = np.linspace(0.3, 3.0, 11)
+    y = np.linspace(0.0, 4.0, 11)
+    np.testing.assert_allclose(ptycho.ell(z, y, "gauss"), 0.5 * (z - np.sqrt(y)) ** 2)
+    np.testing.assert_allclose(ptycho.ell(z, y, "poisson"), z ** 2 - y * np.log(z ** 2))
+    h = 1e-5
+    for m in ("gauss", "poisson"):
+        fd1 = (ptycho.ell(z + h, y, m) - ptycho.ell(z - h, y, m)) / (2 * h)
+        np.testing.assert_allclose(ptycho.ell_d1(z, y, m), fd1, rtol=1e-8, atol=1e-9)
+        fd2 = (ptycho.ell_d1(z + h, y, m) - ptycho.ell_d1(z - h, y, m)) / (2 * h)
+        np.testing.assert_allclose(ptycho.ell_d2(z, y, m), fd2, rtol=1e-8)
+
+
+# ---------------------------------------------------------------- derivatives
+def _fd_jacobian(O, P, pos, b, joint):
+    """Dense J by central differences of the forward model only."""
+    h = 1e-6
+    cols = []
+    targets = [("O", O.shape)] + ([("P", P.shape)] if joint else [])
+    for name, shp in targets:
+        n = shp[0] * shp[1]
+        for part in (1.0, 1j):
+            for i in range(n):
+                d = np.zeros(n, complex)
+                d[i] = part * h
+                d = d.reshape(shp)
+                if name == "O":
+                    zp = ptycho.magnitude(O + d, P, pos, b)
+                    zm = ptycho.magnitude(O - d, P, pos, b)
+                else:
+                    zp = ptycho.magnitude(O, P + d, pos, b)
+                    zm = ptycho.magnitude(O, P - d, pos, b)
+                cols.append(((zp - zm) / (2 * h)).ravel())
+    # column order: [Re O, Im O, Re P, Im P]
+    return np.stack(cols, axis=1)
+
+
+def _to_real(vO, vP=None):
+    parts = [vO.real.ravel(), vO.imag.ravel()]
+    if vP is not None:
+        parts += [vP.real.ravel(), vP.imag.ravel()]
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("joint", [False, True])
+def test_jvp_matches_finite_differences(joint):
+    O, P, pos, y = tiny_problem(joint=joint)
+    b = 1e-3
+    lin = ptycho.linearize(O, P, pos, y, b, "gauss", joint)
+    vO = synth.random_complex(RNG, O.shape)
+    vP = synth.random_complex(RNG, P.shape) if joint else None
+    h = 1e-6
+    zp = ptycho.magnitude(O + h * vO, P + (h * vP if joint else 0), pos, b)
+    zm = ptycho.magnitude(O - h * vO, P - (h * vP if joint else 0), pos, b)
+    fd = (zp - zm) / (2 * h)
+    np.testing.assert_allclose(ptycho.jvp(lin, vO, vP), fd, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+@pytest.mark.parametrize("joint", [False, True])
+def test_gradient_matches_finite_differences(metric, joint):
+    O, P, pos, y = tiny_problem(joint=joint, metric=metric)
+    b = 1e-3
+    lin = ptycho.linearize(O, P, pos, y, b, metric, joint)
+    gO, gP = ptycho.gradient(lin)
+    h = 1e-6
+    f = lambda O_, P_: ptycho.loss(O_, P_, pos, y, b, metric)
+    for idx in [(0, 0), (3, 4), (O.shape[0] - 1, O.shape[1] - 1), (2, 1)]:
+        for part in (1.0, 1j):
+            d = np.zeros(O.shape, complex)
+            d[idx] = part * h
+            fd = (f(O + d, P) - f(O - d, P)) / (2 * h)
+            an = gO[idx].real if part == 1.0 else gO[idx].imag
+            assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (idx, part, an, fd)
+    if joint:
+        for idx in [(0, 0), (1, 2), (3, 1)]:
+            for part in (1.0, 1j):
+                d = np.zeros(P.shape, complex)
+                d[idx] = part * h
+                fd = (f(O, P + d) - f(O, P - d)) / (2 * h)
+                an = gP[idx].real if part == 1.0 else gP[idx].imag
+                assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (idx, part, an, fd)
+
+
+@pytest.mark.parametrize("joint", [False, True])
+def test_adjoint_identity(joint):
+    O, P, pos, y = tiny_problem(joint=joint)
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", joint)
+    vO = synth.random_complex(RNG, O.shape)
+    vP = synth.random_complex(RNG, P.shape) if joint else None
+    w = RNG.standard_normal(lin.zeta.shape)
+    lhs = float(np.sum(ptycho.jvp(lin, vO, vP) * w))
+    gO, gP = ptycho.vjp(lin, w)
+    rhs = solver.rdot(vO, gO) + (solver.rdot(vP, gP) if joint else 0.0)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+@pytest.mark.parametrize("joint", [False, True])
+def test_ggn_matches_dense_fd_jacobian(metric, joint):
+    O, P, pos, y = tiny_problem(obj=(7, 7), probe=(3, 3), joint=joint, metric=metric)
+    b = 1e-3
+    lin = ptycho.linearize(O, P, pos, y, b, metric, joint)
+    J = _fd_jacobian(O, P, pos, b, joint)
+    G = J.T @ (lin.l2.ravel()[:, None] * J)
+    vO = synth.random_complex(RNG, O.shape)
+    vP = synth.random_complex(RNG, P.shape) if joint else None
+    gO, gP = ptycho.ggn_vp(lin, vO, vP)
+    dense = G @ _to_real(vO, vP)
+    mf = _to_real(gO, gP)
+    assert np.linalg.norm(mf - dense) <= 1e-7 * np.linalg.norm(dense)
+    # symmetric and PSD
+    assert np.allclose(G, G.T, atol=1e-7 * np.abs(G).max())
+    ev = np.linalg.eigvalsh(0.5 * (G + G.T))
+    assert ev.min() >= -1e-7 * ev.max()
+    # exact diagonal equals diag(J^T diag(l'') J)
+    dO, dP = ptycho.ggn_diag_exact(lin)
+    n = O.size
+    dg = np.diag(G)
+    np.testing.assert_allclose(dO[..., 0].ravel(), dg[:n], rtol=1e-6, atol=1e-8 * dg.max())
+    np.testing.assert_allclose(dO[..., 1].ravel(), dg[n:2 * n], rtol=1e-6, atol=1e-8 * dg.max())
+    if joint:
+        m = P.size
+        np.testing.assert_allclose(dP[..., 0].ravel(), dg[2 * n:2 * n + m], rtol=1e-6, atol=1e-8 * dg.max())
+        np.testing.assert_allclose(dP[..., 1].ravel(), dg[2 * n + m:], rtol=1e-6, atol=1e-8 * dg.max())
+
+
+def test_ggn_symmetry_matrix_free():
+    O, P, pos, y = tiny_problem(obj=(12, 11), probe=(4, 4))
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", True)
+    u = (synth.random_complex(RNG, O.shape), synth.random_complex(RNG, P.shape))
+    v = (synth.random_complex(RNG, O.shape), synth.random_complex(RNG, P.shape))
+    Gu, Gv = ptycho.ggn_vp(lin, *u), ptycho.ggn_vp(lin, *v)
+    a = solver.rdot(v[0], Gu[0]) + solver.rdot(v[1], Gu[1])
+    c = solver.rdot(u[0], Gv[0]) + solver.rdot(u[1], Gv[1])
+    assert abs(a - c) <= 1e-11 * abs(a)
+
+
+def test_null_vectors():
+    O, P, pos, y = tiny_problem(obj=(12, 13), probe=(4, 5))
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", True)
+    scale = np.linalg.norm(ptycho.jvp(lin, synth.random_complex(RNG, O.shape), None))
+    # global phase (SPR and BPR)
+    assert np.linalg.norm(ptycho.jvp(lin, 1j * O, None)) < 1e-12 * scale
+    assert np.linalg.norm(ptycho.jvp(lin, 1j * O, -1j * P)) < 1e-12 * scale
+    # scale ambiguity O -> sO, P -> P/s
+    assert np.linalg.norm(ptycho.jvp(lin, O, -P)) < 1e-12 * scale
+    # linear phase ramps in x and y
+    yy, xx = np.mgrid[0:O.shape[0], 0:O.shape[1]]
+    my, mx = np.mgrid[0:P.shape[0], 0:P.shape[1]]
+    assert np.linalg.norm(ptycho.jvp(lin, 1j * xx * O, -1j * mx * P)) < 1e-12 * scale
+    assert np.linalg.norm(ptycho.jvp(lin, 1j * yy * O, -1j * my * P)) < 1e-12 * scale
+    # the GGN annihilates them too
+    gO, gP = ptycho.ggn_vp(lin, 1j * O, -1j * P)
+    ref = ptycho.ggn_vp(lin, synth.random_complex(RNG, O.shape), None)[0]
+    assert np.linalg.norm(gO) < 1e-11 * np.linalg.norm(ref)
+
+
+def test_unilluminated_pixels_have_zero_products():
+    O, P, pos, y = tiny_problem(obj=(12, 12), probe=(4, 4))
+    pos = pos[pos[:, 0] < 6]
+    y = y[: len(pos)]
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", False)
+    gO, _ = ptycho.gradient(lin)
+    assert np.all(gO[11, :] == 0)
+
+
+def test_ggn_equals_hessian_at_zero_residual():
+    """Gaussian metric, noise-free data, at the truth: grad^2 f v = G v (eq:ggn_approximation)."""
+    O, P, pos, _ = tiny_problem(obj=(10, 10), probe=(4, 4), noisy=False)
+    b = 1e-3
+    y = ptycho.intensity(O, P, pos, b)
+    lin = ptycho.linearize(O, P, pos, y, b, "gauss", True)
+    vO, vP = synth.random_complex(RNG, O.shape), synth.random_complex(RNG, P.shape)
+    h = 1e-5
+    gp = ptycho.gradient(ptycho.linearize(O + h * vO, P + h * vP, pos, y, b, "gauss", True))
+    gm = ptycho.gradient(ptycho.linearize(O - h * vO, P - h * vP, pos, y, b, "gauss", True))
+    HvO, HvP = (gp[0] - gm[0]) / (2 * h), (gp[1] - gm[1]) / (2 * h)
+    GvO, GvP = ptycho.ggn_vp(lin, vO, vP)
+    assert np.linalg.norm(GvO - HvO) <= 1e-6 * np.linalg.norm(GvO)
+    assert np.linalg.norm(GvP - HvP) <= 1e-6 * np.linalg.norm(GvP)
+    # and away from zero residual the two differ (the dropped term is real)
+    yn = y * 1.5
+    lin2 = ptycho.linearize(O, P, pos, yn, b, "gauss", True)
+    gp = ptycho.gradient(ptycho.linearize(O + h * vO, P + h * vP, pos, yn, b, "gauss", True))
+    gm = ptycho.gradient(ptycho.linearize(O - h * vO, P - h * vP, pos, yn, b, "gauss", True))
+    G2 = ptycho.ggn_vp(lin2, vO, vP)[0]
+    assert np.linalg.norm(G2 - (gp[0] - gm[0]) / (2 * h)) > 1e-3 * np.linalg.norm(G2)
+
+
+# ---------------------------------------------------------------- diagonals
+def test_paper_diagonal_follows_appendix_b_dense_route():
+    """App. B under h ~ |psi_hat|^2: D = 1/4 sum_k S_k^T diag(P) C_k diag(P*) S_k with
+    C_k = F^T diag(l'') F^*, built densely; its diagonal, doubled by the change to
+    (Re, Im) coordinates, is the oracle's ``ggn_diag_paper``."""
+    O, P, pos, y = tiny_problem(obj=(8, 9), probe=(3, 4), joint=True)
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", True)
+    My, Mx = P.shape
+    Fm = np.kron(dft_matrix(My), dft_matrix(Mx))  # acts on row-major vectors
+    N = O.size
+    Dw = np.zeros((N, N), complex)
+    for k, (r, c) in enumerate(pos):
+        S = np.zeros((My * Mx, N))
+        for i in range(My):
+            for j in range(Mx):
+                S[i * Mx + j, (r + i) * O.shape[1] + (c + j)] = 1.0
+        C = Fm.T @ np.diag(lin.l2[k].ravel()) @ Fm.conj()
+        assert np.allclose(np.diag(C), lin.l2[k].sum() / (My * Mx))  # circulant diagonal = trace/M
+        Dw += 0.25 * S.T @ np.diag(P.ravel()) @ C @ np.diag(P.conj().ravel()) @ S
+    dO, _ = ptycho.ggn_diag_paper(lin)
+    np.testing.assert_allclose(dO[..., 0].ravel(), 2 * np.diag(Dw).real, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(dO[..., 1].ravel(), 2 * np.diag(Dw).real, rtol=1e-12, atol=1e-14)
+
+
+def test_paper_diagonal_gaussian_is_half_overlap_map():
+    O, P, pos, y = tiny_problem(obj=(10, 9), probe=(4, 3))
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", False)
+    dO, _ = ptycho.ggn_diag_paper(lin)
+    ov = ptycho.illumination_overlap(P, pos, O.shape)
+    np.testing.assert_allclose(dO[..., 0], 0.5 * ov, rtol=1e-12)
+
+
+def test_paper_diagonal_is_exact_without_dropped_terms():
+    """With |e| = 1 (b -> 0) the paper's diagonal equals the exact one minus the B-term."""
+    O, P, pos, y = tiny_problem(obj=(9, 9), probe=(4, 4), joint=True)
+    lin = ptycho.linearize(O, P, pos, y, 1e-14, "gauss", True)
+    dO_a, dP_a = ptycho.ggn_diag_paper(lin)
+    dO_e, dP_e = ptycho.ggn_diag_exact(lin)
+    # the B-term has opposite signs in the Re and Im coordinates: their mean drops it
+    np.testing.assert_allclose(dO_a[..., 0], 0.5 * (dO_e[..., 0] + dO_e[..., 1]), rtol=1e-9)
+    np.testing.assert_allclose(dP_a[..., 0], 0.5 * (dP_e[..., 0] + dP_e[..., 1]), rtol=1e-9)
+
+
+# ---------------------------------------------------------------- PCG and LM
+def test_pcg_matches_dense_solve():
+    O, P, pos, y = tiny_problem(obj=(6, 6), probe=(3, 3), joint=False)
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", False)
+    n = O.size
+    lam = 0.3
+    A = lambda v: ptycho.ggn_vp(lin, v.reshape(O.shape))[0].ravel() + lam * v
+    cols = []
+    for i in range(2 * n):
+        e = np.zeros(n, complex)
+        e[i % n] = 1.0 if i < n else 1j
+        Ae = A(e)
+        cols.append(np.concatenate([Ae.real, Ae.imag]))
+    Ad = np.stack(cols, axis=1)
+    g = ptycho.gradient(lin)[0].ravel()
+    xd = np.linalg.solve(Ad, -np.concatenate([g.real, g.imag]))
+    dg = solver.pack_diag(ptycho.ggn_diag_paper(lin)[0]) + lam
+    pc = lambda r: r.real / dg[:, 0] + 1j * r.imag / dg[:, 1]
+    for precond in (None, pc):
+        res = solver.pcg(A, g, np.zeros(n, complex), precond, 1e-13, 4 * n)
+        x = np.concatenate([res.x.real, res.x.imag])
+        np.testing.assert_allclose(x, xd, rtol=1e-7, atol=1e-9 * np.abs(xd).max())
+    # warm start from the solution: zero iterations needed
+    res = solver.pcg(A, g, xd[:n] + 1j * xd[n:], None, 1e-6, 10)
+    assert res.iters == 0
+
+
+def test_pcg_energy_norm_error_decreases():
+    O, P, pos, y = tiny_problem(obj=(8, 8), probe=(3, 3), joint=False)
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", False)
+    lam = 0.1
+    A = lambda v: ptycho.ggn_vp(lin, v.reshape(O.shape))[0].ravel() + lam * v
+    g = ptycho.gradient(lin)[0].ravel()
+    xs = solver.pcg(A, g, np.zeros_like(g), None, 1e-14, 400).x
+    errs = []
+    for k in range(1, 12):
+        x = solver.pcg(A, g, np.zeros_like(g), None, 0.0, k).x
+        e = x - xs
+        errs.append(solver.rdot(e, A(e)))
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(errs, errs[1:]))
+
+
+@pytest.mark.parametrize("rho,mu_f,acc", [
+    (0.9, 0.25, True), (0.76, 0.25, True), (0.75, 1.0, True), (0.5, 1.0, True),
+    (0.25, 4.0, True), (0.2, 4.0, True), (1e-3, 4.0, True), (1e-4, 4.0, False),
+    (-5.0, 4.0, False), (-math.inf, 4.0, False)])
+def test_mu_update_branches(rho, mu_f, acc):
+    p = solver.LMParams()
+    mu, a = solver.mu_update(rho, 1.0, p)
+    assert a == acc and mu == pytest.approx(mu_f)
+    # floor
+    mu, _ = solver.mu_update(0.9, 2e-8, p)
+    assert mu == p.mu_min
+
+
+def test_gain_ratio_degenerate():
+    assert solver.gain_ratio(1.0, 0.0) == -math.inf
+    assert solver.gain_ratio(1.0, -1.0) == -math.inf
+    assert solver.gain_ratio(math.nan, 1.0) == -math.inf
+    assert solver.gain_ratio(2.0, 4.0) == 0.5
+
+
+def test_lm_all_rejects_keeps_iterate():
+    pr = synth.make_small(3, obj_side=24, probe=(8, 8), n=3, step=5, photons=None, mode="object")
+    y = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)
+    p = solver.LMParams(retry_max=3)
+    res = solver.lm_solve(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False, p, 1,
+                          loss_fn=lambda O_, P_: math.inf)
+    assert len(res.history) == 3 and not any(h.accepted for h in res.history)
+    assert np.array_equal(res.O, pr.O_init)
+    assert res.history[-1].mu == pytest.approx(p.mu0 * p.kappa ** 2)
+    # lambda follows mu ||grad ell|| on every retry
+    lams = [h.lam for h in res.history]
+    assert lams[1] == pytest.approx(4 * lams[0]) and lams[2] == pytest.approx(16 * lams[0])
+
+
+def _aligned_error(O, O_true, mask):
+    c = np.vdot(O[mask], O_true[mask])
+    ph = c / abs(c)
+    return np.linalg.norm(O[mask] * ph - O_true[mask]) / np.linalg.norm(O_true[mask])
+
+
+def test_lm_noise_free_c0_converges_to_truth():
+    pr = synth.make_c0()
+    y = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)
+    res = solver.lm_solve(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False,
+                          solver.LMParams(), 20)
+    fs = res.f_per_iter + [res.f]
+    assert all(b <= a for a, b in zip(fs, fs[1:]))       # accepted steps never increase f
+    assert res.f < 1e-6 * fs[0]
+    ov = ptycho.illumination_overlap(pr.P_true, pr.pos, pr.O_true.shape)
+    mask = ov > 0.05 * ov.max()
+    assert _aligned_error(res.O, pr.O_true, mask) < 1e-3
+    # gain ratio tends to 1 near the zero-residual solution
+    assert abs(res.history[-1].rho - 1.0) < 0.3
+
+
+def test_lm_joint_with_scaling_and_jacobi_decreases():
+    pr = synth.make_small(5, obj_side=32, probe=(8, 8), n=4, step=4, photons=1e3, mode="joint")
+    rng = np.random.default_rng(5)
+    h = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)
+    y = synth.poisson_counts(rng, h)
+    p = solver.LMParams(scaling=1, precond=1)
+    res = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y, pr.background, "gauss", True, p, 8)
+    assert res.f < 0.2 * res.f_per_iter[0]
+    assert all(h.lam == h.mu for h in res.history)        # lambda = mu when D = Dg(G)
