@@ -1,0 +1,179 @@
+/*
+ * ptlm.h -- C ABI of the MI355X (gfx950) matrix-free Levenberg-Marquardt
+ * ptychography library.
+ *
+ * The calls follow the problem statement of Kandel et al., "Efficient
+ * ptychographic phase retrieval via a matrix-free Levenberg-Marquardt
+ * algorithm" (arXiv 2103.01767): far-field model of Sec. 2
+ * (eq:exit_wave, eq:expected_count), magnitude-based metrics of Sec. 4.1
+ * (eq:magnitude, eq:ell_magnitude), the GGN matrix eq:ggn_magnitude used
+ * matrix-free (App. A), the analytic diagonal of App. B, and the truncated LM
+ * iteration alg:lm_inexact with the PCG stopping rule
+ * eq:lma_termination_magnitude / eq:lma_termination_eta.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* or typed as device arrays are DEVICE pointers (HIP
+ *   global memory) owned by the caller; pointers named h_* are host pointers.
+ * - Arrays are row-major.  Complex arrays are interleaved (re, im) float pairs
+ *   (complex64).  Object: ny x nx.  Probe: my x mx.  Per-measurement arrays:
+ *   K x my x mx, position-major, detector pixels in FFT order (no shift).
+ * - Positions are int32 pairs (row, col): the top-left object pixel of the
+ *   probe window, 0 <= row <= ny-my, 0 <= col <= nx-mx.
+ * - A real vector of R^(2n) is stored as the complex array whose real and
+ *   imaginary parts are its two halves (Sec. 3 real coordinates).  Real
+ *   diagonals of R^(2n) are float arrays of 2n entries interleaved the same
+ *   way (one weight per real coordinate).  Gradients are real-coordinate
+ *   gradients (twice the Wirtinger gradient of App. B).
+ * - The 2D DFT F is unitary.
+ * - Every call that takes a stream is asynchronous on that stream and never
+ *   synchronises unless its comment says so.  No call allocates device memory:
+ *   the caller passes one workspace sized by ptlm_workspace_bytes.
+ * - Status codes are returned; no exception crosses the ABI.  On a non-OK
+ *   status ptlm_last_error() returns a message (thread-local).
+ * - A handle may be used from one host thread at a time.  Calls on one handle
+ *   share its workspace and must be ordered on one stream.
+ */
+#ifndef PTLM_H
+#define PTLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PTLM_OK = 0,
+  PTLM_ENOTACCEPTED = 1, /* LM: every retry of the outer iteration was rejected (not an error) */
+  PTLM_EINVAL = -1,      /* invalid argument: sizes, positions, null pointers, unsupported shape */
+  PTLM_EWORKSPACE = -2,  /* workspace missing or smaller than ptlm_workspace_bytes */
+  PTLM_EHIP = -3,        /* a HIP runtime call failed */
+  PTLM_ENUMERIC = -4     /* non-finite loss or gradient: iterate left at its last accepted value */
+} ptlm_status;
+
+typedef enum { PTLM_GAUSS = 0, PTLM_POISSON = 1 } ptlm_metric; /* eq:ell_magnitude */
+typedef enum { PTLM_OBJECT = 0, PTLM_JOINT = 1 } ptlm_mode;    /* SPR eq:cdp / BPR eq:bp */
+
+/* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128. */
+typedef struct {
+  int32_t ny, nx;     /* object shape */
+  int32_t my, mx;     /* probe shape */
+  int32_t K;          /* number of scan positions (>= 1) */
+  int32_t metric;     /* ptlm_metric */
+  int32_t mode;       /* ptlm_mode: PTLM_JOINT optimises object and probe */
+  float background;   /* b > 0 of eq:expected_count, per detector pixel */
+} ptlm_desc;
+
+/* LM hyper-parameters (alg:lm_inexact; defaults of Sec. 5 via ptlm_lm_default_params). */
+typedef struct {
+  double mu0, mu_min, kappa, nu, rho_min;
+  double beta;        /* eq:lma_termination_eta: 0.1 Gaussian, 0.9 Poisson */
+  double diag_floor;  /* floor of D and of the Jacobi diagonal, relative to the block maximum */
+  int32_t cg_max;     /* cap on PCG products per solve */
+  int32_t retry_max;  /* cap on rejected attempts per outer iteration */
+  int32_t scaling;    /* 0: D = I, 1: D = Dg(G) (App. B diagonal) */
+  int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: caller diagonal + lambda */
+  int32_t warm_start; /* 1: PCG starts from the last accepted step */
+} ptlm_lm_params;
+
+/* LM state, FP64, in DEVICE memory (written by the library, read by the caller). */
+typedef struct {
+  double f;          /* f(z_t) at the current linearisation */
+  double f_trial;    /* f(z_t + Delta) of the last attempt */
+  double mu, lambda, rho, eta;
+  double gnorm;      /* ||g|| = ||J^T grad ell|| */
+  double resid_norm; /* ||grad_zeta ell|| */
+  double pred;       /* predicted reduction of the last attempt */
+  double rz, rr, alpha, beta_cg, pap; /* PCG scalars */
+  int32_t t;         /* outer iterations completed */
+  int32_t cg_iters;  /* products with A in the last solve */
+  int32_t cg_total;  /* products with A since ptlm_lm_init */
+  int32_t accepted;  /* last attempt accepted */
+  int32_t cg_active; /* internal: PCG loop still running */
+  int32_t retries;   /* rejected attempts in the current outer iteration */
+  int32_t need_lin;  /* internal: next attempt must re-linearise */
+  int32_t nonfinite; /* a non-finite value was met */
+} ptlm_lm_state;
+
+typedef struct ptlm_handle ptlm_handle;
+
+/* Fill p with the paper's values: mu0=1e-5, mu_min=1e-8, nu=1, rho_min=1e-4, kappa=4
+ * (Sec. 5), beta=0.1 (Sec. 4.2), cg_max=10, retry_max=10, D=I, no preconditioner. */
+void ptlm_lm_default_params(ptlm_lm_params* p);
+
+/* Host only.  Bytes of device workspace needed for this problem.  h_pos: K (row, col)
+ * pairs, host memory.  Returns PTLM_EINVAL for unsupported shapes or positions. */
+ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes);
+
+/* Create a handle.  Validates desc and every position (0 <= r <= n - m), copies the
+ * positions and constant tables into the workspace on `stream` and returns without
+ * waiting.  d_ws must stay valid until ptlm_destroy; the handle owns only host
+ * metadata. */
+ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
+                        void* stream, ptlm_handle** out);
+ptlm_status ptlm_destroy(ptlm_handle* h);
+
+/* zeta = (|F(P * S_k O)|^2 + b)^(1/2) for every position (eq:exit_wave, eq:expected_count,
+ * eq:magnitude).  d_O: ny*nx complex, d_P: my*mx complex, d_zeta: K*my*mx float. */
+ptlm_status ptlm_forward(ptlm_handle* h, const float* d_O, const float* d_P, float* d_zeta, void* stream);
+
+/* f = sum ell(zeta, y) (eq:error_metric_magnitude), accumulated in FP64 into d_f[0].
+ * d_y: K*my*mx float counts >= 0.  d_resid (nullable): ell'(zeta), K*my*mx float. */
+ptlm_status ptlm_loss(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y,
+                      double* d_f, float* d_resid, void* stream);
+
+/* Linearise at (O, P): f (FP64, d_f[0]), ||grad_zeta ell||^2 (d_f[1]) and the gradient
+ * g = J^T grad_zeta ell (App. A step 1) into d_gO (ny*nx complex) and, in PTLM_JOINT mode,
+ * d_gP (my*mx complex; nullable in PTLM_OBJECT mode).  Stores the linearisation
+ * (O, P and the per-pixel weighted phasor field) in the workspace for ptlm_jvp, ptlm_vjp,
+ * ptlm_ggn_vp and ptlm_diag. */
+ptlm_status ptlm_linearize(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y,
+                           double* d_f, float* d_gO, float* d_gP, void* stream);
+
+/* J v at the last linearisation: d zeta along v (App. A, JVP).  d_vP ignored (may be null)
+ * in PTLM_OBJECT mode.  d_out: K*my*mx float. */
+ptlm_status ptlm_jvp(ptlm_handle* h, const float* d_vO, const float* d_vP, float* d_out, void* stream);
+
+/* J^T w at the last linearisation (eq:arbitrary_jtvp_sequence).  d_w: K*my*mx float.
+ * d_outP nullable in PTLM_OBJECT mode. */
+ptlm_status ptlm_vjp(ptlm_handle* h, const float* d_w, float* d_outO, float* d_outP, void* stream);
+
+/* (G + lambda D) v at the last linearisation, G = J^T grad^2_zeta ell J (eq:ggn_magnitude,
+ * App. A steps 2-4).  d_dO (2*ny*nx floats) / d_dP (2*my*mx) give D; null means D = I.
+ * d_vP / d_outP ignored in PTLM_OBJECT mode. */
+ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
+                        const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
+                        void* stream);
+
+/* Diagonal of G at the last linearisation, per real coordinate (2*ny*nx and 2*my*mx floats).
+ * exact = 0: the paper's analytic approximation (App. B, eq:ggn_diag_mat converted by
+ * eq:ggn_coord_trans; equal Re/Im weights).  exact = 1: the exact diagonal
+ * sum_j ell''_j J_ji^2.  d_dP nullable in PTLM_OBJECT mode. */
+ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream);
+
+/* Truncated LM (alg:lm_inexact).  ptlm_lm_init resets d_state (mu = mu0, t = 0) on the
+ * stream.  ptlm_lm_step runs one outer iteration in place on d_O (and d_P in PTLM_JOINT
+ * mode): linearise, then up to retry_max attempts of {lambda, PCG solve, trial loss, gain
+ * ratio, mu update}.  It synchronises the stream once per attempt to read the acceptance
+ * flag.  Returns PTLM_OK when a step was accepted, PTLM_ENOTACCEPTED when all retries were
+ * rejected (iterate unchanged), PTLM_ENUMERIC on a non-finite loss (iterate unchanged).
+ * d_precond (2n floats, nullable) is the caller diagonal used when params->precond == 2.
+ * ptlm_lm_solve runs T outer iterations, stopping early on PTLM_ENUMERIC. */
+ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_state* d_state,
+                         void* stream);
+ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_y,
+                         const ptlm_lm_params* params, ptlm_lm_state* d_state,
+                         const float* d_precond, void* stream);
+ptlm_status ptlm_lm_solve(ptlm_handle* h, float* d_O, float* d_P, const float* d_y,
+                          const ptlm_lm_params* params, int32_t T, ptlm_lm_state* d_state,
+                          const float* d_precond, void* stream);
+
+/* Thread-local message describing the last non-OK status on this thread. */
+const char* ptlm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTLM_H */

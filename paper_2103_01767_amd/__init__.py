@@ -1,0 +1,254 @@
+"""Python binding of the ptlm C ABI (include/ptlm.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libptlm.so``; this module only
+checks tensor shapes/dtypes/devices, passes raw device pointers and the current
+HIP stream, and converts status codes to exceptions.  Importing it fails
+loudly when the compiled library is missing.
+
+Low-level functions carry the C names (``ptlm_forward`` ...) and take a
+``Handle``; ``Problem`` bundles a handle with its workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptlm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libptlm.so is not built (run paper_2103_01767_amd.build.build() or "
+                      "__graft_entry__.build()); there is no fallback implementation")
+_lib = ctypes.CDLL(LIB_PATH)
+
+PTLM_OK = 0
+PTLM_ENOTACCEPTED = 1
+PTLM_EINVAL = -1
+PTLM_EWORKSPACE = -2
+PTLM_EHIP = -3
+PTLM_ENUMERIC = -4
+GAUSS, POISSON = 0, 1
+OBJECT, JOINT = 0, 1
+
+
+class ptlm_desc(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("my", ctypes.c_int32),
+                ("mx", ctypes.c_int32), ("K", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("background", ctypes.c_float)]
+
+
+class ptlm_lm_params(ctypes.Structure):
+    _fields_ = [("mu0", ctypes.c_double), ("mu_min", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("nu", ctypes.c_double), ("rho_min", ctypes.c_double), ("beta", ctypes.c_double),
+                ("diag_floor", ctypes.c_double), ("cg_max", ctypes.c_int32),
+                ("retry_max", ctypes.c_int32), ("scaling", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+
+
+_STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
+                  "rz", "rr", "alpha", "beta_cg", "pap"]
+_STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "need_lin", "nonfinite"]
+
+
+class ptlm_lm_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in _STATE_DOUBLES] + [(n, ctypes.c_int32) for n in _STATE_INTS]
+
+
+STATE_BYTES = ctypes.sizeof(ptlm_lm_state)
+
+_vp = ctypes.c_void_p
+_sig = {
+    "ptlm_lm_default_params": (None, [ctypes.POINTER(ptlm_lm_params)]),
+    "ptlm_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ptlm_desc), _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ptlm_create": (ctypes.c_int, [ctypes.POINTER(ptlm_desc), _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "ptlm_destroy": (ctypes.c_int, [_vp]),
+    "ptlm_forward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ptlm_loss": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_linearize": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_jvp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ptlm_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ptlm_ggn_vp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_diag": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "ptlm_lm_init": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp]),
+    "ptlm_lm_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp, _vp]),
+    "ptlm_lm_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), ctypes.c_int32,
+                                     _vp, _vp, _vp]),
+    "ptlm_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTS = tuple(_sig)
+
+
+class PtlmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ptlm status %d: %s" % (status, msg))
+        self.status = status
+
+
+def _check(st, allow=(PTLM_OK,)):
+    if st not in allow:
+        raise PtlmError(st, _lib.ptlm_last_error().decode())
+    return st
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return _vp(t.data_ptr())
+
+
+def default_params(**kw) -> ptlm_lm_params:
+    p = ptlm_lm_params()
+    _lib.ptlm_lm_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def state_from_tensor(buf: torch.Tensor) -> ptlm_lm_state:
+    """Decode a device LM state buffer (copies to the host)."""
+    raw = buf.detach().cpu().numpy().tobytes()
+    return ptlm_lm_state.from_buffer_copy(raw[:STATE_BYTES])
+
+
+class Problem:
+    """One ptychography problem on one GPU: handle + workspace + positions."""
+
+    def __init__(self, obj_shape, probe_shape, positions, metric="gauss", mode="object",
+                 background=1e-8, device="cuda"):
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
+        self.obj_shape = tuple(int(v) for v in obj_shape)
+        self.probe_shape = tuple(int(v) for v in probe_shape)
+        self.K = int(pos.shape[0])
+        self.joint = mode in ("joint", JOINT)
+        self.desc = ptlm_desc(self.obj_shape[0], self.obj_shape[1], self.probe_shape[0], self.probe_shape[1],
+                              self.K, POISSON if metric in ("poisson", POISSON) else GAUSS,
+                              JOINT if self.joint else OBJECT, float(background))
+        self._pos = pos
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.ptlm_workspace_bytes(ctypes.byref(self.desc), pos.ctypes.data_as(_vp), ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.ptlm_create(ctypes.byref(self.desc), pos.ctypes.data_as(_vp), _vp(self.ws.data_ptr()),
+                                self.ws_bytes, _stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.ptlm_destroy(h)
+            self.handle = None
+
+    # -- shapes
+    @property
+    def meas_shape(self):
+        return (self.K,) + self.probe_shape
+
+    def _o(self, t, name="O"):
+        return _ptr(t, torch.complex64, self.obj_shape, name)
+
+    def _p(self, t, name="P"):
+        return _ptr(t, torch.complex64, self.probe_shape, name)
+
+    def _m(self, t, name):
+        return _ptr(t, torch.float32, self.meas_shape, name)
+
+    # -- calls (one C call each)
+    def forward(self, O, P):
+        out = torch.empty(self.meas_shape, dtype=torch.float32, device=self.device)
+        _check(_lib.ptlm_forward(self.handle, self._o(O), self._p(P), self._m(out, "zeta"), _stream()))
+        return out
+
+    def loss(self, O, P, y, residual=False):
+        f = torch.zeros(1, dtype=torch.float64, device=self.device)
+        r = torch.empty(self.meas_shape, dtype=torch.float32, device=self.device) if residual else None
+        _check(_lib.ptlm_loss(self.handle, self._o(O), self._p(P), self._m(y, "y"), _ptr(f, torch.float64),
+                              self._m(r, "resid") if residual else None, _stream()))
+        return (f, r) if residual else f
+
+    def linearize(self, O, P, y):
+        f = torch.zeros(2, dtype=torch.float64, device=self.device)
+        gO = torch.empty(self.obj_shape, dtype=torch.complex64, device=self.device)
+        gP = torch.empty(self.probe_shape, dtype=torch.complex64, device=self.device) if self.joint else None
+        _check(_lib.ptlm_linearize(self.handle, self._o(O), self._p(P), self._m(y, "y"), _ptr(f, torch.float64),
+                                   self._o(gO, "gO"), self._p(gP, "gP") if self.joint else None, _stream()))
+        return f, gO, gP
+
+    def jvp(self, vO, vP=None):
+        out = torch.empty(self.meas_shape, dtype=torch.float32, device=self.device)
+        _check(_lib.ptlm_jvp(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
+                             self._m(out, "out"), _stream()))
+        return out
+
+    def vjp(self, w):
+        oO = torch.empty(self.obj_shape, dtype=torch.complex64, device=self.device)
+        oP = torch.empty(self.probe_shape, dtype=torch.complex64, device=self.device) if self.joint else None
+        _check(_lib.ptlm_vjp(self.handle, self._m(w, "w"), self._o(oO, "outO"),
+                             self._p(oP, "outP") if self.joint else None, _stream()))
+        return oO, oP
+
+    def ggn_vp(self, vO, vP=None, lam=0.0, dO=None, dP=None, out=None):
+        if out is None:
+            oO = torch.empty(self.obj_shape, dtype=torch.complex64, device=self.device)
+            oP = torch.empty(self.probe_shape, dtype=torch.complex64, device=self.device) if self.joint else None
+        else:
+            oO, oP = out
+        dOp = _ptr(dO, torch.float32, self.obj_shape + (2,), "dO") if dO is not None else None
+        dPp = _ptr(dP, torch.float32, self.probe_shape + (2,), "dP") if dP is not None else None
+        _check(_lib.ptlm_ggn_vp(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
+                                float(lam), dOp, dPp, self._o(oO, "outO"),
+                                self._p(oP, "outP") if self.joint else None, _stream()))
+        return oO, oP
+
+    def diag(self, exact=False):
+        dO = torch.empty(self.obj_shape + (2,), dtype=torch.float32, device=self.device)
+        dP = torch.empty(self.probe_shape + (2,), dtype=torch.float32, device=self.device) if self.joint else None
+        _check(_lib.ptlm_diag(self.handle, _ptr(dO, torch.float32), _ptr(dP, torch.float32) if self.joint else None,
+                              1 if exact else 0, _stream()))
+        return dO, dP
+
+    def new_state(self):
+        return torch.zeros(STATE_BYTES, dtype=torch.uint8, device=self.device)
+
+    def lm_init(self, params, state):
+        _check(_lib.ptlm_lm_init(self.handle, ctypes.byref(params), _vp(state.data_ptr()), _stream()))
+
+    def lm_step(self, O, P, y, params, state, precond=None):
+        pc = _ptr(precond, torch.float32, None, "precond") if precond is not None else None
+        return _check(_lib.ptlm_lm_step(self.handle, self._o(O), self._p(P), self._m(y, "y"),
+                                        ctypes.byref(params), _vp(state.data_ptr()), pc, _stream()),
+                      allow=(PTLM_OK, PTLM_ENOTACCEPTED))
+
+    def lm_solve(self, O, P, y, params, T, state, precond=None):
+        pc = _ptr(precond, torch.float32, None, "precond") if precond is not None else None
+        return _check(_lib.ptlm_lm_solve(self.handle, self._o(O), self._p(P), self._m(y, "y"),
+                                         ctypes.byref(params), int(T), _vp(state.data_ptr()), pc, _stream()),
+                      allow=(PTLM_OK, PTLM_ENOTACCEPTED))
+
+
+def lib():
+    """The loaded ctypes library (for tests of the raw ABI)."""
+    return _lib

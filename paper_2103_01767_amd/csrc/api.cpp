@@ -1,0 +1,433 @@
+// C ABI of the library: problem planning, workspace layout, validation and the
+// product calls (forward, loss, linearise, JVP, VJP, GGN-vector product,
+// diagonal).  The LM driver lives in lm.cpp.
+#include "api_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+namespace ptlm {
+
+thread_local std::string g_last_error;
+
+ptlm_status fail(ptlm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ptlm_status hip_fail(hipError_t e, const char* where) {
+  return fail(PTLM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define PTLM_CHECK_H(h)                                    \
+  do {                                                     \
+    if (!(h)) return fail(PTLM_EINVAL, "handle is null"); \
+  } while (0)
+#define PTLM_HIP(call, where)                         \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Workgroups per CU the tile kernels can keep resident (LDS- and wave-limited).
+static int wgs_per_cu(int my, int mx) {
+  const size_t lds = tile_lds_bytes(my, mx);
+  const int wg = tile_threads(my, mx);
+  int by_lds = (int)((160 * 1024) / lds);
+  int by_waves = 2048 / wg;
+  return std::max(1, std::min(by_lds, by_waves));
+}
+
+ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
+  if (!d) return fail(PTLM_EINVAL, "desc is null");
+  if (!h_pos && d->K > 0) return fail(PTLM_EINVAL, "positions are null");
+  if (d->K < 1) return fail(PTLM_EINVAL, "K must be >= 1");
+  if (!tile_shape_supported(d->my, d->mx))
+    return fail(PTLM_EINVAL, "probe sides must each be 16, 32, 64 or 128");
+  if (d->ny < d->my || d->nx < d->mx) return fail(PTLM_EINVAL, "object smaller than probe");
+  if (d->metric != PTLM_GAUSS && d->metric != PTLM_POISSON) return fail(PTLM_EINVAL, "unknown metric");
+  if (d->mode != PTLM_OBJECT && d->mode != PTLM_JOINT) return fail(PTLM_EINVAL, "unknown mode");
+  if (!(d->background > 0.0f) || !std::isfinite(d->background))
+    return fail(PTLM_EINVAL, "background must be finite and > 0");
+  if ((long long)d->ny * d->nx > (1LL << 31)) return fail(PTLM_EINVAL, "object too large");
+  for (int k = 0; k < d->K; ++k) {
+    const int r = h_pos[2 * k], c = h_pos[2 * k + 1];
+    if (r < 0 || c < 0 || r > d->ny - d->my || c > d->nx - d->mx) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "position %d = (%d, %d) outside [0, %d] x [0, %d]", k, r, c, d->ny - d->my,
+               d->nx - d->mx);
+      return fail(PTLM_EINVAL, buf);
+    }
+  }
+  p.d = *d;
+  const int K = d->K, M = d->my * d->mx;
+  const long long N = (long long)d->ny * d->nx;
+  p.tpw = tile_per_wg(d->my, d->mx);
+  const int gmax = 256 * wgs_per_cu(d->my, d->mx);
+  p.grid = std::max(1, std::min((K + p.tpw - 1) / p.tpw, gmax));
+  p.nseg = p.grid * p.tpw;
+
+  // contiguous segments of the position list, lengths differing by at most one
+  p.seg_start.resize(p.nseg + 1);
+  for (int s = 0; s <= p.nseg; ++s) p.seg_start[s] = (int)(((long long)s * K) / p.nseg);
+  p.seg_box.assign(p.nseg, make_int4(0, 0, 0, 0));
+  p.seg_off.assign(p.nseg, 0);
+  long long off = 0;
+  for (int s = 0; s < p.nseg; ++s) {
+    const int b = p.seg_start[s], e = p.seg_start[s + 1];
+    if (b == e) {
+      p.seg_off[s] = off;
+      continue;
+    }
+    int r0 = INT32_MAX, c0 = INT32_MAX, r1 = 0, c1 = 0;
+    for (int k = b; k < e; ++k) {
+      r0 = std::min(r0, h_pos[2 * k]);
+      c0 = std::min(c0, h_pos[2 * k + 1]);
+      r1 = std::max(r1, h_pos[2 * k] + d->my);
+      c1 = std::max(c1, h_pos[2 * k + 1] + d->mx);
+    }
+    p.seg_box[s] = make_int4(r0, c0, r1 - r0, c1 - c0);
+    p.seg_off[s] = off;
+    off += (long long)(r1 - r0) * (c1 - c0);
+  }
+  p.strip_elems = off;
+
+  // object 16x16 tiles -> segments / positions meeting them (CSR)
+  p.oty = (d->ny + 15) / 16;
+  p.otx = (d->nx + 15) / 16;
+  const int ntiles = p.oty * p.otx;
+  auto build_csr = [&](auto boxes, int count, std::vector<int>& ptr, std::vector<int>& idx) {
+    std::vector<int> cnt(ntiles + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      int r0, c0, h, w;
+      boxes(i, r0, c0, h, w);
+      if (h <= 0 || w <= 0) continue;
+      for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+        for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) cnt[ty * p.otx + tx + 1]++;
+    }
+    for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+    ptr = cnt;
+    idx.assign(std::max(1, cnt[ntiles]), 0);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < count; ++i) {
+      int r0, c0, h, w;
+      boxes(i, r0, c0, h, w);
+      if (h <= 0 || w <= 0) continue;
+      for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+        for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) idx[fill[ty * p.otx + tx]++] = i;
+    }
+  };
+  build_csr(
+      [&](int s, int& r0, int& c0, int& h, int& w) {
+        r0 = p.seg_box[s].x; c0 = p.seg_box[s].y; h = p.seg_box[s].z; w = p.seg_box[s].w;
+      },
+      p.nseg, p.otile_ptr, p.otile_seg);
+  build_csr(
+      [&](int k, int& r0, int& c0, int& h, int& w) {
+        r0 = h_pos[2 * k]; c0 = h_pos[2 * k + 1]; h = d->my; w = d->mx;
+      },
+      K, p.ptile_ptr, p.ptile_pos);
+
+  // twiddles W_L^(n k) = exp(-2 pi i n k / L), n < L/16, k < 16, L = 32, 64, 128
+  p.tw.assign(224, make_float2(0.f, 0.f));
+  int base = 0;
+  for (int L : {32, 64, 128}) {
+    for (int n = 0; n < L / 16; ++n)
+      for (int k = 0; k < 16; ++k) {
+        const double ang = -2.0 * M_PI * (double)(n * k) / (double)L;
+        p.tw[base + n * 16 + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+    base += (L / 16) * 16;
+  }
+  p.pos.assign(h_pos, h_pos + 2 * K);
+
+  // workspace layout
+  const bool joint = d->mode == PTLM_JOINT;
+  const size_t n2 = (size_t)(N + (joint ? M : 0));  // complex entries of a vector of R^(2n)
+  p.nvec = n2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  p.off.tw = take(p.tw.size() * sizeof(float2));
+  p.off.pos = take((size_t)K * sizeof(int2));
+  p.off.seg_start = take(p.seg_start.size() * sizeof(int));
+  p.off.seg_box = take(p.seg_box.size() * sizeof(int4));
+  p.off.seg_off = take(p.seg_off.size() * sizeof(long long));
+  p.off.otile_ptr = take(p.otile_ptr.size() * sizeof(int));
+  p.off.otile_seg = take(p.otile_seg.size() * sizeof(int));
+  p.off.ptile_ptr = take(p.ptile_ptr.size() * sizeof(int));
+  p.off.ptile_pos = take(p.ptile_pos.size() * sizeof(int));
+  p.off.O_lin = take((size_t)N * sizeof(float2));
+  p.off.P_lin = take((size_t)M * sizeof(float2));
+  p.off.afield = take((size_t)K * M * sizeof(float2));
+  p.off.w2 = d->metric == PTLM_POISSON ? take((size_t)K * M * sizeof(float)) : 0;
+  p.off.trace = take((size_t)K * sizeof(double));
+  p.off.strips = take((size_t)p.strip_elems * sizeof(float2));
+  p.off.probe_part = take((size_t)p.nseg * M * sizeof(float2));
+  p.off.partials = take((size_t)std::max(p.grid, 1024) * 4 * sizeof(double));
+  p.off.scal = take(64 * sizeof(double));
+  // LM / PCG vectors (complex entries of R^(2n)) and real diagonals
+  p.off.g = take(n2 * sizeof(float2));
+  p.off.dx = take(n2 * sizeof(float2));
+  p.off.prev = take(n2 * sizeof(float2));
+  p.off.r = take(n2 * sizeof(float2));
+  p.off.z = take(n2 * sizeof(float2));
+  p.off.p = take(n2 * sizeof(float2));
+  p.off.Ap = take(n2 * sizeof(float2));
+  p.off.diag = take(n2 * sizeof(float2));
+  p.off.ztrial = take(n2 * sizeof(float2));
+  p.off.lmstate = take(sizeof(ptlm_lm_state));
+  p.ws_bytes = o;
+  return PTLM_OK;
+}
+
+ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s) {
+  TileArgs a{};
+  a.O = h->g.O_lin;
+  a.P = h->g.P_lin;
+  hipError_t e = launch_tile(h->g, OP_DIAG_EXACT, a, s);
+  if (e != hipSuccess) return hip_fail(e, "diag exact");
+  e = launch_obj_reduce(h->g, (float2*)dO, 0.0, nullptr, nullptr, nullptr, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "diag exact O");
+  if (dP) {
+    e = launch_probe_reduce(h->g, (float2*)dP, 0.0, nullptr, nullptr, nullptr, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "diag exact P");
+  }
+  return PTLM_OK;
+}
+
+ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
+                           float2* gO, float2* gP, hipStream_t s) {
+  Geometry& g = h->g;
+  const size_t N = (size_t)g.ny * g.nx, M = (size_t)g.my * g.mx;
+  if ((const void*)O != (const void*)g.O_lin)
+    PTLM_HIP(hipMemcpyAsync(g.O_lin, O, N * sizeof(float2), hipMemcpyDeviceToDevice, s), "linearize copy O");
+  if ((const void*)P != (const void*)g.P_lin)
+    PTLM_HIP(hipMemcpyAsync(g.P_lin, P, M * sizeof(float2), hipMemcpyDeviceToDevice, s), "linearize copy P");
+  TileArgs a{};
+  a.O = g.O_lin;
+  a.P = g.P_lin;
+  a.y = y;
+  PTLM_HIP(launch_tile(g, OP_LINEARIZE, a, s), "linearize");
+  PTLM_HIP(launch_sum_partials(g.partials, g.grid, d_f, 2, s), "linearize sum");
+  PTLM_HIP(launch_obj_reduce(g, gO, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gO");
+  if (g.joint && gP) PTLM_HIP(launch_probe_reduce(g, gP, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gP");
+  return PTLM_OK;
+}
+
+ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
+                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s) {
+  TileArgs a{};
+  a.O = h->g.O_lin;
+  a.P = h->g.P_lin;
+  a.vO = vO;
+  a.vP = h->g.joint ? vP : nullptr;
+  a.predicate = pred;
+  PTLM_HIP(launch_tile(h->g, OP_GGNV, a, s), "ggn_vp");
+  PTLM_HIP(launch_obj_reduce(h->g, outO, lam, lam_dev, dO, vO, pred, s), "ggn_vp O");
+  if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, outP, lam, lam_dev, dP, vP, pred, s), "ggn_vp P");
+  return PTLM_OK;
+}
+
+}  // namespace ptlm
+
+using namespace ptlm;
+
+extern "C" {
+
+void ptlm_lm_default_params(ptlm_lm_params* p) {
+  if (!p) return;
+  p->mu0 = 1e-5;
+  p->mu_min = 1e-8;
+  p->kappa = 4.0;
+  p->nu = 1.0;
+  p->rho_min = 1e-4;
+  p->beta = 0.1;
+  p->diag_floor = 1e-6;
+  p->cg_max = 10;
+  p->retry_max = 10;
+  p->scaling = 0;
+  p->precond = 0;
+  p->warm_start = 1;
+}
+
+ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {
+  if (!bytes) return fail(PTLM_EINVAL, "bytes is null");
+  Plan p;
+  ptlm_status st = make_plan(desc, h_pos, p);
+  if (st != PTLM_OK) return st;
+  *bytes = p.ws_bytes;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes, void* stream,
+                        ptlm_handle** out) {
+  if (!out) return fail(PTLM_EINVAL, "out is null");
+  *out = nullptr;
+  ptlm_handle* h = new ptlm_handle();
+  ptlm_status st = make_plan(desc, h_pos, h->plan);
+  if (st != PTLM_OK) {
+    delete h;
+    return st;
+  }
+  Plan& p = h->plan;
+  if (!d_ws || ws_bytes < p.ws_bytes) {
+    delete h;
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes, %zu needed", ws_bytes, p.ws_bytes);
+    return fail(PTLM_EWORKSPACE, buf);
+  }
+  h->ws = (char*)d_ws;
+  hipStream_t s = (hipStream_t)stream;
+  Geometry& g = h->g;
+  const ptlm_desc& d = p.d;
+  g.ny = d.ny; g.nx = d.nx; g.my = d.my; g.mx = d.mx; g.K = d.K;
+  g.metric = d.metric;
+  g.joint = d.mode == PTLM_JOINT;
+  g.background = d.background;
+  g.nseg = p.nseg;
+  g.grid = p.grid;
+  auto at = [&](size_t o) { return (void*)(h->ws + o); };
+  g.tw = (const float2*)at(p.off.tw);
+  g.pos = (const int2*)at(p.off.pos);
+  g.seg_start = (const int*)at(p.off.seg_start);
+  g.seg_box = (const int4*)at(p.off.seg_box);
+  g.seg_off = (const long long*)at(p.off.seg_off);
+  g.otile_ptr = (const int*)at(p.off.otile_ptr);
+  g.otile_seg = (const int*)at(p.off.otile_seg);
+  g.ptile_ptr = (const int*)at(p.off.ptile_ptr);
+  g.ptile_pos = (const int*)at(p.off.ptile_pos);
+  g.otiles_y = p.oty;
+  g.otiles_x = p.otx;
+  g.O_lin = (float2*)at(p.off.O_lin);
+  g.P_lin = (float2*)at(p.off.P_lin);
+  g.afield = (float2*)at(p.off.afield);
+  g.w2 = d.metric == PTLM_POISSON ? (float*)at(p.off.w2) : nullptr;
+  g.trace = (double*)at(p.off.trace);
+  g.strips = (float2*)at(p.off.strips);
+  g.probe_part = (float2*)at(p.off.probe_part);
+  g.partials = (double*)at(p.off.partials);
+
+  hipError_t e;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(at(off), src, bytes, hipMemcpyHostToDevice, s);
+  };
+  if ((e = up(p.off.tw, p.tw.data(), p.tw.size() * sizeof(float2))) != hipSuccess ||
+      (e = up(p.off.pos, p.pos.data(), p.pos.size() * sizeof(int))) != hipSuccess ||
+      (e = up(p.off.seg_start, p.seg_start.data(), p.seg_start.size() * sizeof(int))) != hipSuccess ||
+      (e = up(p.off.seg_box, p.seg_box.data(), p.seg_box.size() * sizeof(int4))) != hipSuccess ||
+      (e = up(p.off.seg_off, p.seg_off.data(), p.seg_off.size() * sizeof(long long))) != hipSuccess ||
+      (e = up(p.off.otile_ptr, p.otile_ptr.data(), p.otile_ptr.size() * sizeof(int))) != hipSuccess ||
+      (e = up(p.off.otile_seg, p.otile_seg.data(), p.otile_seg.size() * sizeof(int))) != hipSuccess ||
+      (e = up(p.off.ptile_ptr, p.ptile_ptr.data(), p.ptile_ptr.size() * sizeof(int))) != hipSuccess ||
+      (e = up(p.off.ptile_pos, p.ptile_pos.data(), p.ptile_pos.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMemsetAsync(at(p.off.strips), 0, (size_t)p.strip_elems * sizeof(float2), s)) != hipSuccess ||
+      (e = hipMemsetAsync(at(p.off.probe_part), 0, (size_t)p.nseg * d.my * d.mx * sizeof(float2), s)) !=
+          hipSuccess) {
+    delete h;
+    return hip_fail(e, "ptlm_create upload");
+  }
+  *out = h;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_destroy(ptlm_handle* h) {
+  delete h;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_forward(ptlm_handle* h, const float* d_O, const float* d_P, float* d_zeta, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_O || !d_P || !d_zeta) return fail(PTLM_EINVAL, "null array");
+  TileArgs a{};
+  a.O = (const float2*)d_O;
+  a.P = (const float2*)d_P;
+  a.rout = d_zeta;
+  PTLM_HIP(launch_tile(h->g, OP_FORWARD, a, (hipStream_t)stream), "forward");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_loss(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y, double* d_f,
+                      float* d_resid, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_O || !d_P || !d_y || !d_f) return fail(PTLM_EINVAL, "null array");
+  hipStream_t s = (hipStream_t)stream;
+  TileArgs a{};
+  a.O = (const float2*)d_O;
+  a.P = (const float2*)d_P;
+  a.y = d_y;
+  a.rout = d_resid;
+  PTLM_HIP(launch_tile(h->g, OP_LOSS, a, s), "loss");
+  PTLM_HIP(launch_sum_partials(h->g.partials, h->g.grid, d_f, 1, s), "loss sum");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_linearize(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y, double* d_f,
+                           float* d_gO, float* d_gP, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_O || !d_P || !d_y || !d_f || !d_gO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && !d_gP) return fail(PTLM_EINVAL, "joint mode needs d_gP");
+  return linearize_impl(h, (const float2*)d_O, (const float2*)d_P, d_y, d_f, (float2*)d_gO, (float2*)d_gP,
+                        (hipStream_t)stream);
+}
+
+ptlm_status ptlm_jvp(ptlm_handle* h, const float* d_vO, const float* d_vP, float* d_out, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_vO || !d_out) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && !d_vP) return fail(PTLM_EINVAL, "joint mode needs d_vP");
+  TileArgs a{};
+  a.O = h->g.O_lin;
+  a.P = h->g.P_lin;
+  a.vO = (const float2*)d_vO;
+  a.vP = h->g.joint ? (const float2*)d_vP : nullptr;
+  a.rout = d_out;
+  PTLM_HIP(launch_tile(h->g, OP_JVP, a, (hipStream_t)stream), "jvp");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_vjp(ptlm_handle* h, const float* d_w, float* d_outO, float* d_outP, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_w || !d_outO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && !d_outP) return fail(PTLM_EINVAL, "joint mode needs d_outP");
+  hipStream_t s = (hipStream_t)stream;
+  TileArgs a{};
+  a.O = h->g.O_lin;
+  a.P = h->g.P_lin;
+  a.win = d_w;
+  PTLM_HIP(launch_tile(h->g, OP_VJP, a, s), "vjp");
+  PTLM_HIP(launch_obj_reduce(h->g, (float2*)d_outO, 0.0, nullptr, nullptr, nullptr, nullptr, s), "vjp O");
+  if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, (float2*)d_outP, 0.0, nullptr, nullptr, nullptr, nullptr, s), "vjp P");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda, const float* d_dO,
+                        const float* d_dP, float* d_outO, float* d_outP, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_vO || !d_outO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && (!d_vP || !d_outP)) return fail(PTLM_EINVAL, "joint mode needs d_vP and d_outP");
+  if (!std::isfinite(lambda) || lambda < 0.0) return fail(PTLM_EINVAL, "lambda must be finite and >= 0");
+  return ggnv_impl(h, (const float2*)d_vO, (const float2*)d_vP, lambda, nullptr, d_dO, d_dP, (float2*)d_outO,
+                   (float2*)d_outP, nullptr, (hipStream_t)stream);
+}
+
+ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_dO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && !d_dP) return fail(PTLM_EINVAL, "joint mode needs d_dP");
+  if (exact) return diag_exact_impl(h, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream);
+  PTLM_HIP(launch_diag_paper(h->g, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream), "diag");
+  return PTLM_OK;
+}
+
+const char* ptlm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

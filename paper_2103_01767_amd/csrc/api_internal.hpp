@@ -1,0 +1,53 @@
+// Host-side internals of the C ABI: the problem plan and the handle.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/ptlm.h"
+#include "internal.hpp"
+
+namespace ptlm {
+
+struct Offsets {
+  size_t tw, pos, seg_start, seg_box, seg_off, otile_ptr, otile_seg, ptile_ptr, ptile_pos;
+  size_t O_lin, P_lin, afield, w2, trace, strips, probe_part, partials, scal;
+  size_t g, dx, prev, r, z, p, Ap, diag, ztrial, lmstate;
+};
+
+// Everything derived on the host from the description and the positions.
+struct Plan {
+  ptlm_desc d{};
+  int tpw = 1, grid = 1, nseg = 1;
+  std::vector<int> seg_start;
+  std::vector<int4> seg_box;           // (row0, col0, rows, cols)
+  std::vector<long long> seg_off;
+  long long strip_elems = 0;
+  int oty = 0, otx = 0;
+  std::vector<int> otile_ptr, otile_seg, ptile_ptr, ptile_pos;
+  std::vector<float2> tw;
+  std::vector<int> pos;
+  size_t nvec = 0;                     // complex entries of one vector of R^(2n)
+  Offsets off{};
+  size_t ws_bytes = 0;
+};
+
+}  // namespace ptlm
+
+struct ptlm_handle {
+  ptlm::Plan plan;
+  ptlm::Geometry g{};
+  char* ws = nullptr;
+  bool prev_valid = false;  // an accepted LM step exists (PCG warm start)
+};
+
+namespace ptlm {
+extern thread_local std::string g_last_error;
+ptlm_status fail(ptlm_status st, const std::string& msg);
+ptlm_status hip_fail(hipError_t e, const char* where);
+ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p);
+ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
+                           float2* gO, float2* gP, hipStream_t s);
+ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
+                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s);
+ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s);
+}  // namespace ptlm

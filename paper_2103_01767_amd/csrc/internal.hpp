@@ -1,0 +1,82 @@
+// Internal declarations shared by the kernel translation units and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ptlm {
+
+// Which per-pixel operation a tile kernel performs between the transforms.
+enum TileOp : int {
+  OP_FORWARD = 0,  // gather psi, F, write zeta
+  OP_LOSS = 1,     // gather psi, F, metric sum (+ optional residual ell')
+  OP_LINEARIZE = 2,// gather psi, F, metric, store weighted phasors, F^H(ell' e), overlap-add
+  OP_JVP = 3,      // gather d psi, F, Re(conj(e) .)
+  OP_VJP = 4,      // w e, F^H, overlap-add
+  OP_GGNV = 5,     // gather d psi, F, Re(conj(a) .) a, F^H, overlap-add
+  OP_DIAG_EXACT = 6// conj(a)^2, F, read at 2m', overlap-add of the exact diagonal terms
+};
+
+// Geometry and buffers of one problem as the kernels see them.
+struct Geometry {
+  int ny, nx, my, mx, K;
+  int metric;  // 0 Gauss, 1 Poisson
+  int joint;   // 1: probe part is computed
+  float background;
+  int nseg;    // number of position segments (= grid * tiles per workgroup)
+  int grid;    // workgroups of the tile kernels
+  // constant tables in the workspace
+  const float2* tw;       // twiddles W_L^(n k), L = 32, 64, 128 (offsets 0, 32, 96)
+  const int2* pos;        // K (row, col)
+  const int* seg_start;   // nseg + 1
+  const int4* seg_box;    // nseg: (row0, col0, rows, cols) of the segment's strip
+  const long long* seg_off;  // nseg: offset of the strip in `strips` (complex elements)
+  const int* otile_ptr;   // object 16x16 tiles -> segments whose strip meets the tile (CSR)
+  const int* otile_seg;
+  const int* ptile_ptr;   // object 16x16 tiles -> positions whose window meets the tile (CSR)
+  const int* ptile_pos;
+  int otiles_y, otiles_x;
+  // linearisation state
+  float2* O_lin;          // N
+  float2* P_lin;          // M
+  float2* afield;         // K*M: sqrt(ell'') e / sqrt(M), detector order
+  float* w2;              // K*M: sqrt(ell'') (Poisson only, else null)
+  double* trace;          // K: sum_m ell''_km
+  // scratch
+  float2* strips;         // per-segment private overlap-add strips (kept zero between calls)
+  float2* probe_part;     // nseg * M per-segment probe partial sums
+  double* partials;       // grid * 4 per-workgroup FP64 partial sums
+};
+
+struct TileArgs {
+  const float2* O;        // object used for the gather / probe products
+  const float2* P;        // probe
+  const float2* vO;       // direction (GGNV / JVP)
+  const float2* vP;       // probe direction (joint), may be null
+  const float* y;         // data (LOSS / LINEARIZE)
+  const float* win;       // K*M real input (VJP)
+  float* rout;            // K*M real output (FORWARD zeta, LOSS residual, JVP)
+  const int* predicate;   // if non-null and *predicate == 0 the launch does nothing
+};
+
+// tile kernels (kernels_tile.hip)
+hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+bool tile_shape_supported(int my, int mx);
+int tile_threads(int my, int mx);       // threads per workgroup
+int tile_per_wg(int my, int mx);        // tiles (concurrent positions) per workgroup
+size_t tile_lds_bytes(int my, int mx);
+
+// reductions and vector kernels (kernels_vec.hip)
+// out_O = sum of strips (strips zeroed after the read) [+ lam * dO .* vO]
+// lam_dev (nullable) overrides lam with a device scalar.
+hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const double* lam_dev, const float* dO,
+                             const float2* vO, const int* predicate, hipStream_t s);
+// out_P = sum of probe partials [+ lam * dP .* vP]
+hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
+                               const float2* vP, const int* predicate, hipStream_t s);
+// out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)
+hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s);
+// paper's App. B diagonal from the stored traces
+hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s);
+
+}  // namespace ptlm

@@ -1,0 +1,287 @@
+// Truncated PCG (eq:lma_termination_magnitude) and the LM step control of
+// alg:lm_inexact, on the GPU.  Vector kernels stream the R^(2n) vectors once
+// and leave per-block FP64 partial sums; one-block finalize kernels reduce
+// them in a fixed order and run the scalar logic in FP64 (CG alpha/beta,
+// stopping test, damping lambda, forcing term eta, gain ratio rho, mu update,
+// acceptance).  Kernels inside the PCG loop read the device flag cg_active and
+// return at once when the solve has stopped, so a fixed launch sequence serves
+// every solve without host synchronisation.
+#include <cmath>
+
+#include "lm_internal.hpp"
+
+namespace ptlm {
+
+__device__ __forceinline__ double rdot(float2 a, float2 b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+
+// z = M^{-1} r for the PCG preconditioner of this attempt (per real coordinate)
+__device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r, double lam) {
+  if (a.prm.precond == 1) {
+    const float2 d = a.diag[i];
+    if (a.prm.scaling) {
+      const float s = (float)(1.0 + lam);
+      return make_float2(r.x / (s * d.x), r.y / (s * d.y));
+    }
+    return make_float2(r.x / (d.x + (float)lam), r.y / (d.y + (float)lam));
+  }
+  if (a.prm.precond == 2) {
+    const float2 d = a.learned[i];
+    return make_float2(r.x / (d.x + (float)lam), r.y / (d.y + (float)lam));
+  }
+  return r;
+}
+
+__device__ __forceinline__ float2 apply_D(const LMArgs& a, size_t i, float2 v) {
+  if (a.prm.scaling) {
+    const float2 d = a.diag[i];
+    return make_float2(d.x * v.x, d.y * v.y);
+  }
+  return v;
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void vec_kernel(LMArgs a) {
+  constexpr bool PRED = OP == V_PAP || OP == V_CG_UPDATE || OP == V_PUPDATE;
+  if (PRED && a.st->cg_active == 0) return;
+  const double lam = a.st->lambda;
+  const float alpha = (float)a.st->alpha;
+  const float beta = (float)a.st->beta_cg;
+  double acc0 = 0.0, acc1 = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    if constexpr (OP == V_GNORM) {
+      const float2 g = a.g[i];
+      acc0 += rdot(g, g);
+    } else if constexpr (OP == V_DIAGMAX) {
+      const float2 d = a.diag[i];
+      const double m = fmax((double)d.x, (double)d.y);
+      if (i < a.nobj) acc0 = fmax(acc0, m);
+      else acc1 = fmax(acc1, m);
+    } else if constexpr (OP == V_DIAGFLOOR) {
+      const float f = (float)(a.prm.diag_floor * (i < a.nobj ? a.scal[SC_DMAX_O] : a.scal[SC_DMAX_P]));
+      const float2 d = a.diag[i];
+      a.diag[i] = make_float2(fmaxf(d.x, f), fmaxf(d.y, f));
+    } else if constexpr (OP == V_CG_INIT) {
+      const float2 g = a.g[i];
+      float2 r;
+      if (a.use_warm) {
+        const float2 ap = a.Ap[i];
+        a.dx[i] = a.prev[i];
+        r = make_float2(-g.x - ap.x, -g.y - ap.y);
+      } else {
+        a.dx[i] = make_float2(0.f, 0.f);
+        r = make_float2(-g.x, -g.y);
+      }
+      const float2 z = apply_minv(a, i, r, lam);
+      a.r[i] = r;
+      a.z[i] = z;
+      a.p[i] = z;
+      acc0 += rdot(r, z);
+      acc1 += rdot(r, r);
+    } else if constexpr (OP == V_PAP) {
+      acc0 += rdot(a.p[i], a.Ap[i]);
+    } else if constexpr (OP == V_CG_UPDATE) {
+      const float2 p = a.p[i], ap = a.Ap[i];
+      float2 x = a.dx[i], r = a.r[i];
+      x.x = fmaf(alpha, p.x, x.x);
+      x.y = fmaf(alpha, p.y, x.y);
+      r.x = fmaf(-alpha, ap.x, r.x);
+      r.y = fmaf(-alpha, ap.y, r.y);
+      const float2 z = apply_minv(a, i, r, lam);
+      a.dx[i] = x;
+      a.r[i] = r;
+      a.z[i] = z;
+      acc0 += rdot(r, z);
+      acc1 += rdot(r, r);
+    } else if constexpr (OP == V_PUPDATE) {
+      const float2 z = a.z[i], p = a.p[i];
+      a.p[i] = make_float2(fmaf(beta, p.x, z.x), fmaf(beta, p.y, z.y));
+    } else if constexpr (OP == V_TRIAL) {
+      const float2 x = a.dx[i];
+      const float2 base = i < a.nobj ? a.O[i] : a.P[i - a.nobj];
+      a.ztrial[i] = make_float2(base.x + x.x, base.y + x.y);
+      const float2 dd = apply_D(a, i, x);
+      const float2 g = a.g[i];
+      acc0 += (double)x.x * (lam * (double)dd.x - (double)g.x) + (double)x.y * (lam * (double)dd.y - (double)g.y);
+    }
+  }
+  constexpr bool SUMS = OP == V_GNORM || OP == V_DIAGMAX || OP == V_CG_INIT || OP == V_PAP ||
+                        OP == V_CG_UPDATE || OP == V_TRIAL;
+  if constexpr (SUMS) {
+    __shared__ double sh[256][2];
+    sh[threadIdx.x][0] = acc0;
+    sh[threadIdx.x][1] = acc1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        if constexpr (OP == V_DIAGMAX) {
+          sh[threadIdx.x][0] = fmax(sh[threadIdx.x][0], sh[threadIdx.x + w][0]);
+          sh[threadIdx.x][1] = fmax(sh[threadIdx.x][1], sh[threadIdx.x + w][1]);
+        } else {
+          sh[threadIdx.x][0] += sh[threadIdx.x + w][0];
+          sh[threadIdx.x][1] += sh[threadIdx.x + w][1];
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.partials[blockIdx.x * 4 + 0] = sh[0][0];
+      a.partials[blockIdx.x * 4 + 1] = sh[0][1];
+    }
+  }
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
+
+// One block: reduce `count` partials (fixed order), then run the scalar step.
+template <int OP>
+__global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
+  constexpr bool PRED = OP == F_PAP || OP == F_CG_UPDATE;
+  if (PRED && a.st->cg_active == 0) return;
+  __shared__ double sh[256][2];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) {
+    if constexpr (OP == F_DIAGMAX) {
+      acc0 = fmax(acc0, a.partials[i * 4]);
+      acc1 = fmax(acc1, a.partials[i * 4 + 1]);
+    } else {
+      acc0 += a.partials[i * 4];
+      acc1 += a.partials[i * 4 + 1];
+    }
+  }
+  sh[threadIdx.x][0] = acc0;
+  sh[threadIdx.x][1] = acc1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      if constexpr (OP == F_DIAGMAX) {
+        sh[threadIdx.x][0] = fmax(sh[threadIdx.x][0], sh[threadIdx.x + w][0]);
+        sh[threadIdx.x][1] = fmax(sh[threadIdx.x][1], sh[threadIdx.x + w][1]);
+      } else {
+        sh[threadIdx.x][0] += sh[threadIdx.x + w][0];
+        sh[threadIdx.x][1] += sh[threadIdx.x + w][1];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double s0 = sh[0][0], s1 = sh[0][1];
+  ptlm_lm_state& st = *a.st;
+  const ptlm_lm_params& p = a.prm;
+  if constexpr (OP == F_LIN) {
+    // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM
+    st.f = a.scal[SC_F];
+    st.resid_norm = sqrt(a.scal[SC_L1SQ]);
+    st.gnorm = sqrt(s0);
+    st.nonfinite = (finite_d(st.f) && finite_d(st.gnorm)) ? 0 : 1;
+    st.retries = 0;
+  } else if constexpr (OP == F_DIAGMAX) {
+    a.scal[SC_DMAX_O] = s0;
+    a.scal[SC_DMAX_P] = s1;
+  } else if constexpr (OP == F_BEGIN) {
+    // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
+    // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).
+    st.lambda = p.scaling ? st.mu : st.mu * pow(st.resid_norm, p.nu);
+    st.eta = fmin(p.beta, sqrt(st.gnorm));
+    st.cg_iters = 0;
+    st.cg_active = 1;
+    st.accepted = 0;
+    st.alpha = 0.0;
+    st.beta_cg = 0.0;
+  } else if constexpr (OP == F_CG_INIT) {
+    st.rz = s0;
+    st.rr = s1;
+    st.cg_active = (p.cg_max > 0 && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
+  } else if constexpr (OP == F_PAP) {
+    st.pap = s0;
+    if (s0 > 0.0 && finite_d(s0)) {
+      st.alpha = st.rz / s0;
+    } else {
+      st.cg_active = 0;  // non-positive curvature: keep the current iterate
+    }
+  } else if constexpr (OP == F_CG_UPDATE) {
+    st.beta_cg = s0 / st.rz;
+    st.rz = s0;
+    st.rr = s1;
+    st.cg_iters += 1;
+    st.cg_total += 1;
+    st.cg_active = (st.cg_iters < p.cg_max && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
+  } else if constexpr (OP == F_PRED) {
+    st.pred = 0.5 * s0;  // 1/2 Delta^T (lambda D Delta - g)
+  } else if constexpr (OP == F_TRIAL_END) {
+    st.f_trial = s0;
+    const double dfa = st.f - s0;
+    const double dfp = st.pred;
+    double rho = -INFINITY;
+    if (dfp > 0.0 && finite_d(dfa) && finite_d(dfp)) {
+      rho = dfa / dfp;
+      if (!finite_d(rho)) rho = -INFINITY;
+    }
+    st.rho = rho;
+    const double mu = st.mu;
+    if (rho > 0.75) {
+      st.mu = fmax(mu / p.kappa, p.mu_min);
+      st.accepted = 1;
+    } else if (rho > 0.25) {
+      st.accepted = 1;
+    } else if (rho > p.rho_min) {
+      st.mu = p.kappa * mu;
+      st.accepted = 1;
+    } else {
+      st.mu = p.kappa * mu;
+      st.accepted = 0;
+      st.retries += 1;
+    }
+    st.cg_active = 0;
+  } else if constexpr (OP == F_STEP_END) {
+    st.t += 1;
+  } else if constexpr (OP == F_INIT) {
+    st = ptlm_lm_state{};
+    st.mu = p.mu0;
+  }
+}
+
+template <int OP>
+static hipError_t vlaunch(const LMArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(vec_kernel<OP>, dim3(LM_BLOCKS), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <int OP>
+static hipError_t flaunch(const LMArgs& a, int count, hipStream_t s) {
+  hipLaunchKernelGGL(fin_kernel<OP>, dim3(1), dim3(256), 0, s, a, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec(int op, const LMArgs& a, hipStream_t s) {
+  switch (op) {
+    case V_GNORM: return vlaunch<V_GNORM>(a, s);
+    case V_DIAGMAX: return vlaunch<V_DIAGMAX>(a, s);
+    case V_DIAGFLOOR: return vlaunch<V_DIAGFLOOR>(a, s);
+    case V_CG_INIT: return vlaunch<V_CG_INIT>(a, s);
+    case V_PAP: return vlaunch<V_PAP>(a, s);
+    case V_CG_UPDATE: return vlaunch<V_CG_UPDATE>(a, s);
+    case V_PUPDATE: return vlaunch<V_PUPDATE>(a, s);
+    case V_TRIAL: return vlaunch<V_TRIAL>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fin(int op, const LMArgs& a, int count, hipStream_t s) {
+  switch (op) {
+    case F_LIN: return flaunch<F_LIN>(a, count, s);
+    case F_DIAGMAX: return flaunch<F_DIAGMAX>(a, count, s);
+    case F_BEGIN: return flaunch<F_BEGIN>(a, count, s);
+    case F_CG_INIT: return flaunch<F_CG_INIT>(a, count, s);
+    case F_PAP: return flaunch<F_PAP>(a, count, s);
+    case F_CG_UPDATE: return flaunch<F_CG_UPDATE>(a, count, s);
+    case F_PRED: return flaunch<F_PRED>(a, count, s);
+    case F_TRIAL_END: return flaunch<F_TRIAL_END>(a, count, s);
+    case F_STEP_END: return flaunch<F_STEP_END>(a, count, s);
+    case F_INIT: return flaunch<F_INIT>(a, count, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ptlm

@@ -1,0 +1,648 @@
+// Per-position tile kernels: gather -> 2D FFT -> per-pixel op -> inverse 2D FFT -> overlap-add.
+//
+// One workgroup owns a contiguous segment of scan positions (TPW concurrent
+// tile slots for small probes, one slot for 64x64 and larger) and walks it
+// position by position.  A position's My x Mx tile is transformed with a
+// four-pass Stockham FFT per 2D transform: radix-16 then radix-(L/16) along x,
+// the same along y.  Each thread holds 16 complex values in registers during
+// a pass; passes exchange data through one padded LDS tile.  The last forward
+// pass and the first inverse pass share the register layout, so the per-pixel
+// work between the transforms (metric, weighting by the stored phasor field)
+// happens in registers with coalesced global reads.
+//
+// Overlap-add (the adjoint S_k^T of the shift operator, Sec. 2) never uses
+// atomics: each segment accumulates into its own private strip (the bounding
+// box of its windows) with plain read-modify-write, and the probe part of the
+// sum is kept in registers per thread across the segment.  Separate gather
+// kernels sum strips and probe partials in a fixed order.
+#include "dft.hpp"
+#include "internal.hpp"
+
+namespace ptlm {
+
+template <int MY_, int MX_>
+struct Cfg {
+  static constexpr int MY = MY_, MX = MX_, M = MY * MX;
+  static constexpr int NV = M / 16;                       // virtual threads per tile (16 values each)
+  static constexpr int V = 1;                             // virtual threads per real thread
+  static constexpr int NT = NV / V;                       // real threads per tile
+  static constexpr int TPW = NT >= 256 ? 1 : 256 / NT;    // tiles per workgroup
+  static constexpr int WG = NT * TPW;
+  static constexpr int RX = MX / 16, RY = MY / 16;        // second-pass radices
+  static constexpr int GX = 16 / RX, GY = 16 / RY;        // second-pass groups per virtual thread
+  static constexpr int PAD = MX >= 64 ? 8 : (MX == 32 ? 2 : 1);
+  static constexpr int LDX = MX + PAD;                    // LDS row stride (complex)
+  static constexpr int TILE = MY * LDX;                   // LDS complex per tile
+  static constexpr int NWAVE = WG / 64 > 0 ? WG / 64 : 1;
+  // probe partial kept in registers across the segment, or read-modify-written in the
+  // segment's global probe slot each position (largest tile: no register room)
+  static constexpr bool PROBE_REGS = NT < 1024;
+};
+
+__device__ __forceinline__ const float2* tw_table(const float2* tw, int L) {
+  return tw + (L == 32 ? 0 : (L == 64 ? 32 : 96));
+}
+
+// Sum of a double over the NT real threads of this thread's tile, returned to every
+// thread of the tile.  Uses red[] (one slot per wave, column `col`) when the tile spans
+// several waves; contains one workgroup barrier in that case.
+template <class C>
+__device__ __forceinline__ double tile_sum(double x, double* red, int col, int slot) {
+  constexpr int L = C::NT < 64 ? C::NT : 64;
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  if constexpr (C::NT > 64) {
+    if ((threadIdx.x & 63) == 0) red[(threadIdx.x / 64) * 2 + col] = x;
+    __syncthreads();
+    x = 0.0;
+    for (int w = 0; w < C::NT / 64; ++w) x += red[(slot * (C::NT / 64) + w) * 2 + col];
+  }
+  return x;
+}
+
+template <int MY, int MX, int OP>
+__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
+  using C = Cfg<MY, MX>;
+  constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, V = C::V, NT = C::NT;
+  constexpr bool FWD_FFT = OP != OP_VJP;
+  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
+  constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
+  constexpr bool SUMS = OP == OP_LOSS || OP == OP_LINEARIZE;
+  if (a.predicate && *a.predicate == 0) return;
+
+  extern __shared__ float2 smem[];
+  double* red = reinterpret_cast<double*>(smem + C::TPW * C::TILE);  // [NWAVE][2]
+
+  const int slot = threadIdx.x / NT;
+  const int t = threadIdx.x % NT;
+  float2* lds = smem + slot * C::TILE;
+  const int seg = blockIdx.x * C::TPW + slot;
+  const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
+  int maxlen = 0;
+#pragma unroll
+  for (int s = 0; s < C::TPW; ++s) {
+    const int q = blockIdx.x * C::TPW + s;
+    maxlen = max(maxlen, g.seg_start[q + 1] - g.seg_start[q]);
+  }
+  const float2* twx = tw_table(g.tw, MX);
+  const float2* twy = tw_table(g.tw, MY);
+  const float isq = rsqrtf((float)C::M);
+  const bool joint = g.joint != 0;
+
+  constexpr int VA = C::PROBE_REGS ? V : 1;
+  constexpr int JA = C::PROBE_REGS ? 16 : 1;
+  float2 accP[VA][JA];
+#pragma unroll
+  for (int u = 0; u < VA; ++u)
+#pragma unroll
+    for (int j = 0; j < JA; ++j) accP[u][j] = make_float2(0.f, 0.f);
+  float2* pslot = g.probe_part + (size_t)seg * C::M;  // this segment's probe partial
+  if constexpr (SCATTER && !C::PROBE_REGS) {
+    // zero the global probe slot before the segment's first read-modify-write
+    if (joint) {
+      for (int i = t; i < C::M; i += NT) pslot[i] = make_float2(0.f, 0.f);
+    }
+  }
+  double s0 = 0.0, s1 = 0.0;
+
+  float2* strip = nullptr;
+  int4 box = make_int4(0, 0, 0, 0);
+  if constexpr (SCATTER) {
+    strip = g.strips + g.seg_off[seg];
+    box = g.seg_box[seg];
+  }
+
+  for (int it = 0; it < maxlen; ++it) {
+    const int k = kbeg + it;
+    const bool act = k < kend;
+    int ry = 0, rx = 0;
+    if (act) {
+      const int2 p = g.pos[k];
+      ry = p.x;
+      rx = p.y;
+    }
+    float2 v[V][16];
+    double asum = 0.0;  // OP_DIAG_EXACT: sum |a|^2 over this thread's pixels
+
+    if constexpr (FWD_FFT) {
+      // ---------------- gather the exit wave (or its perturbation), x-pass-1 layout
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
+          if constexpr (OP == OP_DIAG_EXACT) {
+            // conj(a)^2 of the stored phasor field, read as a My x Mx image
+            const float2* arow = g.afield + (size_t)k * C::M + xy * MX + xn1;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              const float2 as = arow[RX * j];
+              asum += (double)fmaf(as.x, as.x, as.y * as.y);
+              v[u][j] = make_float2(fmaf(as.x, as.x, -as.y * as.y), -2.f * as.x * as.y);
+            }
+          } else {
+            const float2* Orow = a.O + (size_t)(ry + xy) * g.nx + rx + xn1;
+            const float2* Prow = a.P + xy * MX + xn1;
+            if constexpr (OP == OP_JVP || OP == OP_GGNV) {
+              const float2* Vrow = a.vO + (size_t)(ry + xy) * g.nx + rx + xn1;
+              if (a.vP) {
+                const float2* VProw = a.vP + xy * MX + xn1;
+#pragma unroll
+                for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+                  for (int j = jj; j < jj + 4; ++j)
+                    v[u][j] = cadd(cmul(Prow[RX * j], Vrow[RX * j]), cmul(VProw[RX * j], Orow[RX * j]));
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+              } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[u][j] = cmul(Prow[RX * j], Vrow[RX * j]);
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < 16; ++j) v[u][j] = cmul(Prow[RX * j], Orow[RX * j]);
+            }
+          }
+          // x pass 1: DFT16 over j, twiddle W_MX^(n1 k1)
+          dft16<false>(v[u]);
+          if constexpr (RX > 1) {
+#pragma unroll
+            for (int k1 = 1; k1 < 16; ++k1) v[u][k1] = cmul(v[u][k1], twx[xn1 * 16 + k1]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
+#pragma unroll
+          for (int k1 = 0; k1 < 16; ++k1) lds[xy * LDX + k1 * RX + xn1] = v[u][k1];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+      // ---------------- x pass 2
+      if constexpr (RX > 1) {
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT;
+#pragma unroll
+            for (int gg = 0; gg < GX; ++gg) {
+              const int q = tv * GX + gg, yy = q >> 4, k1 = q & 15;
+#pragma unroll
+              for (int n1 = 0; n1 < RX; ++n1) v[u][gg * RX + n1] = lds[yy * LDX + k1 * RX + n1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT;
+#pragma unroll
+            for (int gg = 0; gg < GX; ++gg) {
+              const int q = tv * GX + gg, yy = q >> 4, k1 = q & 15;
+              dftR<RX, false>(v[u] + gg * RX);
+#pragma unroll
+              for (int k2 = 0; k2 < RX; ++k2) lds[yy * LDX + k1 + 16 * k2] = v[u][gg * RX + k2];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+      }
+      // ---------------- y pass 1
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) v[u][j] = lds[(ys + RY * j) * LDX + yc];
+          dft16<false>(v[u]);
+          if constexpr (RY > 1) {
+#pragma unroll
+            for (int k1 = 1; k1 < 16; ++k1) v[u][k1] = cmul(v[u][k1], twy[ys * 16 + k1]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (RY > 1) {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) lds[(k1 * RY + ys) * LDX + yc] = v[u][k1];
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+        // ---------------- y pass 2
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+            for (int gg = 0; gg < GY; ++gg) {
+              const int k1 = ys * GY + gg;
+#pragma unroll
+              for (int n1 = 0; n1 < RY; ++n1) v[u][gg * RY + n1] = lds[(k1 * RY + n1) * LDX + yc];
+              dftR<RY, false>(v[u] + gg * RY);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+    }
+
+    // ---------------- per-pixel work in the frequency layout: v[u][r] <-> (ky, kx)
+    {
+      double tr = 0.0;
+      if (act) {
+        const size_t base = (size_t)k * C::M;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int ky = ys * GY + r / RY + 16 * (r % RY);
+            const size_t gi = base + (size_t)ky * MX + yc;
+            if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
+              const float2 ps = cscale(v[u][r], isq);
+              const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, g.background));
+              const float iz = rsqrtf(h);
+              const float zeta = h * iz;
+              if constexpr (OP == OP_FORWARD) {
+                a.rout[gi] = zeta;
+              } else {
+                const float yv = a.y[gi];
+                float l, l1, l2;
+                if (g.metric == 0) {
+                  const float d = zeta - sqrtf(yv);
+                  l = 0.5f * d * d;
+                  l1 = d;
+                  l2 = 1.0f;
+                } else {
+                  l = h - yv * logf(h);
+                  l1 = 2.0f * zeta - 2.0f * yv * iz;
+                  l2 = 2.0f + 2.0f * yv / h;
+                }
+                s0 += (double)l;
+                s1 += (double)l1 * (double)l1;
+                if constexpr (OP == OP_LOSS) {
+                  if (a.rout) a.rout[gi] = l1;
+                } else {
+                  tr += (double)l2;
+                  const float w = sqrtf(l2);
+                  const float2 e = cscale(ps, iz);
+                  g.afield[gi] = cscale(e, w * isq);
+                  if (g.w2) g.w2[gi] = w;
+                  v[u][r] = cscale(e, l1 * isq);
+                }
+              }
+            } else if constexpr (OP == OP_JVP) {
+              const float2 as = g.afield[gi];
+              float val = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
+              if (g.w2) val /= g.w2[gi];
+              a.rout[gi] = val;
+            } else if constexpr (OP == OP_GGNV) {
+              const float2 as = g.afield[gi];
+              const float tt = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
+              v[u][r] = cscale(as, tt);
+            } else if constexpr (OP == OP_VJP) {
+              const float2 as = g.afield[gi];
+              float w = a.win[gi];
+              if (g.w2) w /= g.w2[gi];
+              v[u][r] = cscale(as, w);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (OP == OP_LINEARIZE) {
+        // per-position trace of the metric Hessian (App. B), reduced over the tile
+        tr = tile_sum<C>(tr, red, 0, slot);
+        if (act && t == 0) g.trace[k] = tr;
+      }
+    }
+
+    if constexpr (OP == OP_DIAG_EXACT) {
+      // B_k = DFT(conj(a)^2) to LDS in detector order, then every pixel m' of the
+      // window reads B_k at 2m' (mod the probe shape) and forms the exact diagonal
+      // terms |Q|^2 A_k / 2 +- Re(Q^2 B_k[2m']) / 2, Q = P (object) or S_k O (probe).
+      asum = tile_sum<C>(asum, red, 1, slot);
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int ky = ys * GY + r / RY + 16 * (r % RY);
+            lds[ky * LDX + yc] = v[u][r];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const float A = (float)asum;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
+          const int Y = ry + xy;
+          float2* srow = strip + (size_t)(Y - box.x) * box.w + (rx + xn1 - box.y);
+          const float2* Prow = a.P + xy * MX + xn1;
+          const float2* Orow = a.O + (size_t)Y * g.nx + rx + xn1;
+          const int by = (2 * xy) & (MY - 1);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int x = xn1 + RX * j;
+            const float2 B = lds[by * LDX + ((2 * x) & (MX - 1))];
+            const float2 q = Prow[RX * j];
+            float base = 0.5f * A * fmaf(q.x, q.x, q.y * q.y);
+            float cross = 0.5f * (fmaf(q.x, q.x, -q.y * q.y) * B.x - 2.f * q.x * q.y * B.y);
+            const float2 cur = srow[RX * j];
+            srow[RX * j] = make_float2(cur.x + base + cross, cur.y + base - cross);
+            if (joint) {
+              const float2 o = Orow[RX * j];
+              base = 0.5f * A * fmaf(o.x, o.x, o.y * o.y);
+              cross = 0.5f * (fmaf(o.x, o.x, -o.y * o.y) * B.x - 2.f * o.x * o.y * B.y);
+              if constexpr (C::PROBE_REGS) {
+                accP[u][j] = make_float2(accP[u][j].x + base + cross, accP[u][j].y + base - cross);
+              } else {
+                float2* pp = pslot + xy * MX + xn1 + RX * j;
+                const float2 c0 = *pp;
+                *pp = make_float2(c0.x + base + cross, c0.y + base - cross);
+              }
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+
+    if constexpr (INV_FFT) {
+      // ---------------- inverse y pass 2 (DFT over k2 -> n1, conjugate twiddle)
+      if constexpr (RY > 1) {
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, ys = tv / MX;
+#pragma unroll
+            for (int gg = 0; gg < GY; ++gg) {
+              const int k1 = ys * GY + gg;
+              dftR<RY, true>(v[u] + gg * RY);
+#pragma unroll
+              for (int n1 = 1; n1 < RY; ++n1) v[u][gg * RY + n1] = cmulc(v[u][gg * RY + n1], twy[n1 * 16 + k1]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+            for (int gg = 0; gg < GY; ++gg) {
+              const int k1 = ys * GY + gg;
+#pragma unroll
+              for (int n1 = 0; n1 < RY; ++n1) lds[(k1 * RY + n1) * LDX + yc] = v[u][gg * RY + n1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) v[u][k1] = lds[(k1 * RY + ys) * LDX + yc];
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+      // ---------------- inverse y pass 1 (DFT16 over k1 -> n2), natural rows
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) dft16<true>(v[u]);
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) lds[(ys + RY * j) * LDX + yc] = v[u][j];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+      // ---------------- inverse x pass 2
+      if constexpr (RX > 1) {
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT;
+#pragma unroll
+            for (int gg = 0; gg < GX; ++gg) {
+              const int q = tv * GX + gg, yy = q >> 4, k1 = q & 15;
+#pragma unroll
+              for (int k2 = 0; k2 < RX; ++k2) v[u][gg * RX + k2] = lds[yy * LDX + k1 + 16 * k2];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT;
+#pragma unroll
+            for (int gg = 0; gg < GX; ++gg) {
+              const int q = tv * GX + gg, yy = q >> 4, k1 = q & 15;
+              dftR<RX, true>(v[u] + gg * RX);
+#pragma unroll
+              for (int n1 = 1; n1 < RX; ++n1)
+                v[u][gg * RX + n1] = cmulc(v[u][gg * RX + n1], twx[n1 * 16 + k1]);
+#pragma unroll
+              for (int n1 = 0; n1 < RX; ++n1) lds[yy * LDX + k1 * RX + n1] = v[u][gg * RX + n1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __syncthreads();
+      }
+      // ---------------- inverse x pass 1 -> pixel (xy, xn1 + RX j), then overlap-add
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
+#pragma unroll
+          for (int k1 = 0; k1 < 16; ++k1) v[u][k1] = lds[xy * LDX + k1 * RX + xn1];
+          dft16<true>(v[u]);
+          // object strip (plain RMW, segment-private) and probe registers
+          const int Y = ry + xy;
+          float2* srow = strip + (size_t)(Y - box.x) * box.w + (rx + xn1 - box.y);
+          const float2* Prow = a.P + xy * MX + xn1;
+#pragma unroll
+          for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+            for (int j = jj; j < jj + 4; ++j) {
+              const float2 cur = srow[RX * j];
+              srow[RX * j] = cadd(cur, cmulc(v[u][j], Prow[RX * j]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          if (joint) {
+            const float2* Orow = a.O + (size_t)Y * g.nx + rx + xn1;
+            if constexpr (C::PROBE_REGS) {
+#pragma unroll
+              for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+                for (int j = jj; j < jj + 4; ++j) accP[u][j] = cadd(accP[u][j], cmulc(v[u][j], Orow[RX * j]));
+                __builtin_amdgcn_sched_barrier(0);
+              }
+            } else {
+              float2* prow = pslot + xy * MX + xn1;
+#pragma unroll
+              for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+                for (int j = jj; j < jj + 4; ++j) prow[RX * j] = cadd(prow[RX * j], cmulc(v[u][j], Orow[RX * j]));
+                __builtin_amdgcn_sched_barrier(0);
+              }
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+  }
+
+  if constexpr (SCATTER && C::PROBE_REGS) {
+    if (joint) {
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
+        float2* pp = g.probe_part + (size_t)seg * C::M + xy * MX + xn1;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pp[RX * j] = accP[u][j];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  if constexpr (SUMS) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+      red[wave * 2] = s0;
+      red[wave * 2 + 1] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int w = 0; w < C::NWAVE; ++w) {
+        a0 += red[w * 2];
+        a1 += red[w * 2 + 1];
+      }
+      g.partials[blockIdx.x * 4 + 0] = a0;
+      g.partials[blockIdx.x * 4 + 1] = a1;
+      g.partials[blockIdx.x * 4 + 2] = 0.0;
+      g.partials[blockIdx.x * 4 + 3] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int MY, int MX>
+static size_t lds_bytes() {
+  using C = Cfg<MY, MX>;
+  return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)C::NWAVE * 2 * sizeof(double);
+}
+
+template <int MY, int MX, int OP>
+static hipError_t launch_one(const Geometry& g, const TileArgs& a, hipStream_t s) {
+  using C = Cfg<MY, MX>;
+  const size_t lds = lds_bytes<MY, MX>();
+  static bool attr_set = false;  // per instantiation, host-side
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<MY, MX, OP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile_kernel<MY, MX, OP>), dim3(g.grid), dim3(C::WG), lds, s, g, a);
+  return hipGetLastError();
+}
+
+template <int MY, int MX>
+static hipError_t launch_op(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
+  switch (op) {
+    case OP_FORWARD: return launch_one<MY, MX, OP_FORWARD>(g, a, s);
+    case OP_LOSS: return launch_one<MY, MX, OP_LOSS>(g, a, s);
+    case OP_LINEARIZE: return launch_one<MY, MX, OP_LINEARIZE>(g, a, s);
+    case OP_JVP: return launch_one<MY, MX, OP_JVP>(g, a, s);
+    case OP_VJP: return launch_one<MY, MX, OP_VJP>(g, a, s);
+    case OP_GGNV: return launch_one<MY, MX, OP_GGNV>(g, a, s);
+    case OP_DIAG_EXACT: return launch_one<MY, MX, OP_DIAG_EXACT>(g, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MY>
+static hipError_t launch_mx(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
+  switch (g.mx) {
+    case 16: return launch_op<MY, 16>(g, op, a, s);
+    case 32: return launch_op<MY, 32>(g, op, a, s);
+    case 64: return launch_op<MY, 64>(g, op, a, s);
+    case 128: return launch_op<MY, 128>(g, op, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
+  switch (g.my) {
+    case 16: return launch_mx<16>(g, op, a, s);
+    case 32: return launch_mx<32>(g, op, a, s);
+    case 64: return launch_mx<64>(g, op, a, s);
+    case 128: return launch_mx<128>(g, op, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static bool side_ok(int m) { return m == 16 || m == 32 || m == 64 || m == 128; }
+bool tile_shape_supported(int my, int mx) { return side_ok(my) && side_ok(mx); }
+
+template <int MY, int MX>
+static void cfg_of(int* wg, int* tpw, size_t* lds) {
+  *wg = Cfg<MY, MX>::WG;
+  *tpw = Cfg<MY, MX>::TPW;
+  *lds = lds_bytes<MY, MX>();
+}
+static void cfg_dispatch(int my, int mx, int* wg, int* tpw, size_t* lds) {
+#define PTLM_CFG(A, B) if (my == A && mx == B) { cfg_of<A, B>(wg, tpw, lds); return; }
+  PTLM_CFG(16, 16) PTLM_CFG(16, 32) PTLM_CFG(16, 64) PTLM_CFG(16, 128)
+  PTLM_CFG(32, 16) PTLM_CFG(32, 32) PTLM_CFG(32, 64) PTLM_CFG(32, 128)
+  PTLM_CFG(64, 16) PTLM_CFG(64, 32) PTLM_CFG(64, 64) PTLM_CFG(64, 128)
+  PTLM_CFG(128, 16) PTLM_CFG(128, 32) PTLM_CFG(128, 64) PTLM_CFG(128, 128)
+#undef PTLM_CFG
+  *wg = 0; *tpw = 0; *lds = 0;
+}
+int tile_threads(int my, int mx) { int w, t; size_t l; cfg_dispatch(my, mx, &w, &t, &l); return w; }
+int tile_per_wg(int my, int mx) { int w, t; size_t l; cfg_dispatch(my, mx, &w, &t, &l); return t; }
+size_t tile_lds_bytes(int my, int mx) { int w, t; size_t l; cfg_dispatch(my, mx, &w, &t, &l); return l; }
+
+}  // namespace ptlm

@@ -1,0 +1,118 @@
+"""GPU LM runs against the FP64 oracle's LM on the same problem.
+
+Bar: final loss f_gpu <= 1.01 f_oracle + f_floor, where f_floor is twice the
+FP32 GPU loss at the ground truth (noise-free data drive f to ~0, where an FP32
+evaluation cannot reproduce an FP64 ratio).  LM trajectories are not compared
+iterate by iterate: FP32 vs FP64 rounding legitimately changes accept/reject
+decisions near convergence.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ptycho, solver
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2103_01767_amd as pt  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=dt))).to(DEV)
+
+
+def test_c0_plain_lm_matches_oracle_final_loss():
+    print("case c0 lm", flush=True)
+    pr = synth.make_c0()
+    O0 = pr.O_init.astype(np.complex64)
+    P = pr.P_true.astype(np.complex64)
+    Ot = pr.O_true.astype(np.complex64)
+    y = ptycho.intensity(Ot.astype(np.complex128), P.astype(np.complex128), pr.pos, pr.background)
+    y32 = y.astype(np.float32)
+    ref = solver.lm_solve(O0.astype(np.complex128), P.astype(np.complex128), pr.pos, y32.astype(np.float64),
+                          pr.background, "gauss", False, solver.LMParams(), 20)
+    prob = pt.Problem(pr.O_true.shape, P.shape, pr.pos, mode="object", background=pr.background, device=DEV)
+    O = to_dev(O0, np.complex64)
+    Pd = to_dev(P, np.complex64)
+    yd = to_dev(y32, np.float32)
+    params = pt.default_params()
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_solve(O, Pd, yd, params, 20, st)
+    torch.cuda.synchronize()
+    s = pt.state_from_tensor(st)
+    f_gpu = float(prob.loss(O, Pd, yd).cpu()[0])
+    f_floor = 2.0 * float(prob.loss(to_dev(Ot, np.complex64), Pd, yd).cpu()[0])
+    print("c0 oracle f=%.3e gpu f=%.3e floor=%.3e t=%d cg=%d" % (ref.f, f_gpu, f_floor, s.t, s.cg_total))
+    assert s.t == 20
+    assert f_gpu <= 1.01 * ref.f + f_floor
+    assert f_gpu < 1e-4 * ref.f_per_iter[0]
+    # the reconstruction matches the truth up to the global phase on illuminated pixels
+    Og = O.cpu().numpy().astype(np.complex128)
+    ov = ptycho.illumination_overlap(P.astype(np.complex128), pr.pos, pr.O_true.shape)
+    m = ov > 0.05 * ov.max()
+    c = np.vdot(Og[m], pr.O_true[m])
+    err = np.linalg.norm(Og[m] * c / abs(c) - pr.O_true[m]) / np.linalg.norm(pr.O_true[m])
+    assert err < 1e-2
+
+
+def test_joint_scaled_jacobi_lm_matches_oracle():
+    print("case joint lm", flush=True)
+    pr = synth.make_small(5, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(5)
+    O0 = pr.O_init.astype(np.complex64)
+    P0 = pr.P_init.astype(np.complex64)
+    h = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)
+    y = synth.poisson_counts(rng, h).astype(np.float32)
+    p_or = solver.LMParams(scaling=1, precond=1)
+    ref = solver.lm_solve(O0.astype(np.complex128), P0.astype(np.complex128), pr.pos, y.astype(np.float64),
+                          pr.background, "gauss", True, p_or, 10)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(O0, np.complex64), to_dev(P0, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(scaling=1, precond=1)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_solve(O, P, yd, params, 10, st)
+    f_gpu = float(prob.loss(O, P, yd).cpu()[0])
+    print("joint oracle f=%.6e gpu f=%.6e (start %.3e)" % (ref.f, f_gpu, ref.f_per_iter[0]))
+    assert f_gpu <= 1.01 * ref.f
+    assert f_gpu < 0.5 * ref.f_per_iter[0]
+
+
+def test_first_attempt_matches_oracle_step():
+    """One LM attempt from the same point: same lambda, eta, PCG iterations and rho."""
+    pr = synth.make_small(7, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(7)
+    O0 = pr.O_init.astype(np.complex64)
+    P0 = pr.P_init.astype(np.complex64)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    for scaling, precond in ((0, 0), (1, 1), (0, 1)):
+        p_or = solver.LMParams(scaling=scaling, precond=precond)
+        ref = solver.lm_solve(O0.astype(np.complex128), P0.astype(np.complex128), pr.pos, y.astype(np.float64),
+                              pr.background, "gauss", True, p_or, 1)
+        attempts = [h for h in ref.history if h.t == 0]
+        h0 = attempts[-1]                      # the state reflects the last attempt of the iteration
+        prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background,
+                          device=DEV)
+        O, P, yd = to_dev(O0, np.complex64), to_dev(P0, np.complex64), to_dev(y, np.float32)
+        params = pt.default_params(scaling=scaling, precond=precond)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        prob.lm_step(O, P, yd, params, st)
+        s = pt.state_from_tensor(st)
+        print(scaling, precond, "oracle", h0.lam, h0.eta, h0.cg_iters, h0.rho, "gpu", s.lambda_, s.eta, s.cg_iters,
+              s.rho)
+        assert s.f == pytest.approx(h0.f, rel=1e-5)
+        assert s.eta == pytest.approx(h0.eta, rel=1e-5)
+        assert s.lambda_ == pytest.approx(h0.lam, rel=1e-5)
+        assert s.retries == len(attempts) - 1 if h0.accepted else s.retries == len(attempts)
+        assert abs(s.cg_iters - h0.cg_iters) <= 1
+        if s.cg_iters == h0.cg_iters:
+            assert s.rho == pytest.approx(h0.rho, rel=1e-3, abs=1e-3)
