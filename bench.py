@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free LM ptychography hot path on one MI355X.
+
+Workload: the joint object+probe problem with a 512x512 object, a 128x128
+probe and a 40x40 raster (1600 positions, step 8, +-1 jitter), Poisson data at
+1e4 photons per pattern, Gaussian magnitude metric, LM with D = Dg(G) and the
+Jacobi preconditioner, at most 10 PCG products per solve.
+
+One step = one outer LM iteration (linearisation with gradient and diagonal,
+then attempts of {PCG solve of up to 10 GGN-vector products, trial loss, gain
+ratio, damping update}) -- every row of the hot path.  ``value`` = scan
+positions pushed through GGN-vector products per second of whole-step wall
+time (inputs resident in HBM).  The dominant kernel (the per-position GGN-vector
+kernel) is also timed alone with HIP events on its stream for the roofline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (published)
+METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learned vs plain"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--calls", type=int, default=50, help="isolated GGN-vector product calls")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-calls", type=int, default=3)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(positions would be sharded across GPUs; see the design notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2103_01767_amd as pt
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pr = synth.make_c1()
+    K = pr.K
+    (ny, nx), (my, mx) = pr.O_true.shape, pr.P_true.shape
+    M, N = my * mx, ny * nx
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    prob = pt.Problem((ny, nx), (my, mx), pr.pos, metric="gauss", mode="joint", background=pr.background,
+                      device=dev)
+
+    # synthetic Poisson data from the model itself (expected counts = zeta^2)
+    zeta = prob.forward(c64(pr.O_true), c64(pr.P_true))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1001)
+    y = torch.poisson((zeta.double() ** 2).float(), generator=gen).contiguous()
+    del zeta
+
+    O = c64(pr.O_init)
+    P = c64(pr.P_init)
+    params = pt.default_params(scaling=1, precond=1, cg_max=10)
+    state = prob.new_state()
+    prob.lm_init(params, state)
+    stream = torch.cuda.current_stream()
+
+    # ---------------- whole hot path: LM outer iterations
+    for _ in range(args.warmup):
+        prob.lm_step(O, P, y, params, state)
+    torch.cuda.synchronize()
+    s0 = pt.state_from_tensor(state)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prob.lm_step(O, P, y, params, state)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = pt.state_from_tensor(state)
+    step_s = (t1 - t0) / max(args.steps, 1)
+    products = s1.products - s0.products
+    attempts = s1.attempts - s0.attempts
+    value = K * products / (t1 - t0) if t1 > t0 else float("nan")
+
+    # ---------------- dominant kernel alone: per-position GGN-vector kernel (HIP events)
+    f, gO, gP = prob.linearize(O, P, y)
+    g2 = torch.Generator(device=dev)
+    g2.manual_seed(7)
+    vO = torch.randn((ny, nx), dtype=torch.complex64, device=dev, generator=g2)
+    vP = torch.randn((my, mx), dtype=torch.complex64, device=dev, generator=g2)
+    outO = torch.empty_like(vO)
+    outP = torch.empty_like(vP)
+    for _ in range(5):
+        prob.ggn_vp(vO, vP, out=(outO, outP))
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.calls)]
+    for a, b, c in ev:
+        a.record(stream)
+        prob.ggn_vp_stage(1, vO, vP)
+        b.record(stream)
+        prob.ggn_vp_stage(2, vO, vP, out=(outO, outP))
+        c.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    call_ms = float(np.median([a.elapsed_time(c) for a, _, c in ev]))
+    red_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+
+    # algorithmic bytes of one launch of the per-position kernel: the stored phasor field
+    # (K*M complex64) plus the object-sized and probe-sized inputs it gathers (O, vO, P, vP)
+    kern_bytes = K * M * 8 + 2 * N * 8 + 2 * M * 8
+    achieved_gbs = kern_bytes / (kern_ms * 1e-3) / 1e9
+    fft_flops = 2 * 5 * M * math.log2(M) * K  # two 2D FFTs per position (5 M log2 M convention)
+    fft_tflops = fft_flops / (kern_ms * 1e-3) / 1e12
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(pr, O, P, y, vO, vP, args.cpu_calls)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "scan-positions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64/f32 (f64 scalars)",
+        "data": "synthetic",
+        "config": {"workload": "joint LM, object 512x512, probe 128x128, 40x40 raster step 8 +-1, "
+                               "Poisson 1e4 photons/pattern, D=Dg(G), Jacobi PCG, cg_max 10",
+                   "positions": K, "probe": [my, mx], "object": [ny, nx]},
+        "ggnv_products_per_step": round(products / max(args.steps, 1), 2),
+        "lm_attempts_per_step": round(attempts / max(args.steps, 1), 2),
+        "ggnv_call_ms": round(call_ms, 4),
+        "ggnv_positions_per_s_isolated": round(K / (call_ms * 1e-3), 1),
+        "ggnv_kernel_ms": round(kern_ms, 4),
+        "ggnv_reduce_ms": round(red_ms, 4),
+        "fft_tflops": round(fft_tflops, 2),
+        "fft_frac_fp32_peak": round(fft_tflops / FP32_PEAK_TFLOPS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(pr, O, P, y, vO, vP, calls):
+    """The FP64 oracle's GGN-vector product on the same linearisation point, timed on the host."""
+    from oracle import ptycho
+    Oh = O.cpu().numpy().astype(np.complex128)
+    Ph = P.cpu().numpy().astype(np.complex128)
+    yh = y.cpu().numpy().astype(np.float64)
+    vOh = vO.cpu().numpy().astype(np.complex128)
+    vPh = vP.cpu().numpy().astype(np.complex128)
+    lin = ptycho.linearize(Oh, Ph, pr.pos, yh, pr.background, "gauss", True)
+    times = []
+    for _ in range(max(calls, 1)):
+        t = time.perf_counter()
+        ptycho.ggn_vp(lin, vOh, vPh)
+        times.append(time.perf_counter() - t)
+    per = float(np.median(times))
+    return {"value": round(pr.K / per, 2), "unit": "scan-positions/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full GGN-vector products (1600 positions, 128x128, complex128 NumPy FFT, "
+                      "single thread) at the linearisation point of the GPU run; median %.2f s each"
+                      % (len(times), per)}
+
+
+if __name__ == "__main__":
+    main()

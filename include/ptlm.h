@@ -93,8 +93,9 @@ typedef struct {
   int32_t accepted;  /* last attempt accepted */
   int32_t cg_active; /* internal: PCG loop still running */
   int32_t retries;   /* rejected attempts in the current outer iteration */
-  int32_t need_lin;  /* internal: next attempt must re-linearise */
   int32_t nonfinite; /* a non-finite value was met */
+  int32_t products;  /* GGN-vector products since ptlm_lm_init (PCG and warm starts) */
+  int32_t attempts;  /* LM attempts (trial points) since ptlm_lm_init */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;
@@ -146,6 +147,15 @@ ptlm_status ptlm_vjp(ptlm_handle* h, const float* d_w, float* d_outO, float* d_o
 ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
                         const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
                         void* stream);
+
+/* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
+ * stage = 1: per-position kernel only (accumulates into workspace strips);
+ * stage = 2: the finishing reductions only (writes d_outO / d_outP and clears the strips);
+ * stage = 3: both (identical to ptlm_ggn_vp).  Every stage-1 call must be followed by a
+ * stage-2 call before any other product on the handle. */
+ptlm_status ptlm_ggn_vp_stage(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
+                              const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
+                              int32_t stage, void* stream);
 
 /* Diagonal of G at the last linearisation, per real coordinate (2*ny*nx and 2*my*mx floats).
  * exact = 0: the paper's analytic approximation (App. B, eq:ggn_diag_mat converted by

@@ -50,7 +50,8 @@ class ptlm_lm_params(ctypes.Structure):
 
 _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
                   "rz", "rr", "alpha", "beta_cg", "pap"]
-_STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "need_lin", "nonfinite"]
+_STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
+               "attempts"]
 
 
 class ptlm_lm_state(ctypes.Structure):
@@ -71,6 +72,8 @@ _sig = {
     "ptlm_jvp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptlm_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptlm_ggn_vp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_ggn_vp_stage": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                         _vp]),
     "ptlm_diag": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
     "ptlm_lm_init": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp]),
     "ptlm_lm_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp, _vp]),
@@ -222,6 +225,14 @@ class Problem:
                                 float(lam), dOp, dPp, self._o(oO, "outO"),
                                 self._p(oP, "outP") if self.joint else None, _stream()))
         return oO, oP
+
+    def ggn_vp_stage(self, stage, vO, vP=None, out=None):
+        """Run one stage of the GGN-vector product (1: per-position kernel, 2: reductions)."""
+        oO, oP = out if out is not None else (None, None)
+        _check(_lib.ptlm_ggn_vp_stage(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
+                                      0.0, None, None, self._o(oO, "outO") if oO is not None else None,
+                                      self._p(oP, "outP") if (self.joint and oP is not None) else None,
+                                      int(stage), _stream()))
 
     def diag(self, exact=False):
         dO = torch.empty(self.obj_shape + (2,), dtype=torch.float32, device=self.device)

@@ -1,6 +1,6 @@
 """Build the HIP library libptlm.so for gfx950, in-tree.
 
-    python -m paper_2103_01767_amd.build        # or build() from Python
+    python paper_2103_01767_amd/build.py        # or __graft_entry__.build()
 
 Every source under csrc/ is compiled by hipcc (device code for gfx950 only,
 packed-FP32 instruction selection disabled) and linked into

@@ -224,16 +224,21 @@ ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, con
 }
 
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
-                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s) {
-  TileArgs a{};
-  a.O = h->g.O_lin;
-  a.P = h->g.P_lin;
-  a.vO = vO;
-  a.vP = h->g.joint ? vP : nullptr;
-  a.predicate = pred;
-  PTLM_HIP(launch_tile(h->g, OP_GGNV, a, s), "ggn_vp");
-  PTLM_HIP(launch_obj_reduce(h->g, outO, lam, lam_dev, dO, vO, pred, s), "ggn_vp O");
-  if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, outP, lam, lam_dev, dP, vP, pred, s), "ggn_vp P");
+                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
+                      int stage) {
+  if (stage & 1) {
+    TileArgs a{};
+    a.O = h->g.O_lin;
+    a.P = h->g.P_lin;
+    a.vO = vO;
+    a.vP = h->g.joint ? vP : nullptr;
+    a.predicate = pred;
+    PTLM_HIP(launch_tile(h->g, OP_GGNV, a, s), "ggn_vp");
+  }
+  if (stage & 2) {
+    PTLM_HIP(launch_obj_reduce(h->g, outO, lam, lam_dev, dO, vO, pred, s), "ggn_vp O");
+    if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, outP, lam, lam_dev, dP, vP, pred, s), "ggn_vp P");
+  }
   return PTLM_OK;
 }
 
@@ -409,14 +414,21 @@ ptlm_status ptlm_vjp(ptlm_handle* h, const float* d_w, float* d_outO, float* d_o
   return PTLM_OK;
 }
 
-ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda, const float* d_dO,
-                        const float* d_dP, float* d_outO, float* d_outP, void* stream) {
+ptlm_status ptlm_ggn_vp_stage(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
+                              const float* d_dO, const float* d_dP, float* d_outO, float* d_outP, int32_t stage,
+                              void* stream) {
   PTLM_CHECK_H(h);
-  if (!d_vO || !d_outO) return fail(PTLM_EINVAL, "null array");
-  if (h->g.joint && (!d_vP || !d_outP)) return fail(PTLM_EINVAL, "joint mode needs d_vP and d_outP");
+  if (stage < 1 || stage > 3) return fail(PTLM_EINVAL, "stage must be 1, 2 or 3");
+  if (!d_vO || ((stage & 2) && !d_outO)) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && (!d_vP || ((stage & 2) && !d_outP))) return fail(PTLM_EINVAL, "joint mode needs d_vP and d_outP");
   if (!std::isfinite(lambda) || lambda < 0.0) return fail(PTLM_EINVAL, "lambda must be finite and >= 0");
   return ggnv_impl(h, (const float2*)d_vO, (const float2*)d_vP, lambda, nullptr, d_dO, d_dP, (float2*)d_outO,
-                   (float2*)d_outP, nullptr, (hipStream_t)stream);
+                   (float2*)d_outP, nullptr, (hipStream_t)stream, stage);
+}
+
+ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda, const float* d_dO,
+                        const float* d_dP, float* d_outO, float* d_outP, void* stream) {
+  return ptlm_ggn_vp_stage(h, d_vO, d_vP, lambda, d_dO, d_dP, d_outO, d_outP, 3, stream);
 }
 
 ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream) {

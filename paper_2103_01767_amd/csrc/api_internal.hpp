@@ -48,6 +48,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p);
 ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
                            float2* gO, float2* gP, hipStream_t s);
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
-                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s);
+                      const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
+                      int stage = 3);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s);
 }  // namespace ptlm

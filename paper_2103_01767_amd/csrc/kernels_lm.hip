@@ -191,10 +191,12 @@ __global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
     st.alpha = 0.0;
     st.beta_cg = 0.0;
   } else if constexpr (OP == F_CG_INIT) {
+    if (a.use_warm) st.products += 1;
     st.rz = s0;
     st.rr = s1;
     st.cg_active = (p.cg_max > 0 && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
   } else if constexpr (OP == F_PAP) {
+    st.products += 1;
     st.pap = s0;
     if (s0 > 0.0 && finite_d(s0)) {
       st.alpha = st.rz / s0;
@@ -211,6 +213,7 @@ __global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
   } else if constexpr (OP == F_PRED) {
     st.pred = 0.5 * s0;  // 1/2 Delta^T (lambda D Delta - g)
   } else if constexpr (OP == F_TRIAL_END) {
+    st.attempts += 1;
     st.f_trial = s0;
     const double dfa = st.f - s0;
     const double dfp = st.pred;

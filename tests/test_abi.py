@@ -1,0 +1,67 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the header
+declares, and the host-only calls validate their inputs.  No device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptlm.h")
+
+pt = pytest.importorskip("paper_2103_01767_amd")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return re.findall(r"^(?:ptlm_status|void|const char\*)\s+(ptlm_\w+)\s*\(", text, re.M)
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = header_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(pt.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pt.EXPORTS)
+
+
+def _ws(desc, pos):
+    n = ctypes.c_size_t(0)
+    st = pt.lib().ptlm_workspace_bytes(ctypes.byref(desc), pos.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_validation():
+    pos = np.array([[0, 0], [8, 8], [16, 0]], np.int32)
+    d = pt.ptlm_desc(48, 40, 32, 16, 3, pt.GAUSS, pt.JOINT, 1e-8)
+    st, n = _ws(d, pos)
+    assert st == pt.PTLM_OK and n > 3 * 32 * 16 * 8
+    for bad in ([17, 0], [0, 25], [-1, 0]):
+        p2 = pos.copy()
+        p2[2] = bad
+        assert _ws(d, p2)[0] == pt.PTLM_EINVAL
+        assert b"position 2" in pt.lib().ptlm_last_error()
+    for field, val in (("my", 48), ("mx", 24), ("K", 0), ("metric", 7), ("mode", 3), ("background", 0.0)):
+        d2 = pt.ptlm_desc(48, 40, 32, 16, 3, pt.GAUSS, pt.JOINT, 1e-8)
+        setattr(d2, field, val)
+        assert _ws(d2, pos)[0] == pt.PTLM_EINVAL, field
+    # more positions need more workspace (stored phasor field grows with K)
+    many = np.array([[i % 17, i % 25] for i in range(40)], np.int32)
+    d3 = pt.ptlm_desc(48, 40, 32, 16, 40, pt.GAUSS, pt.JOINT, 1e-8)
+    assert _ws(d3, many)[1] > n
+
+
+def test_create_rejects_small_workspace():
+    pos = np.array([[0, 0]], np.int32)
+    d = pt.ptlm_desc(16, 16, 16, 16, 1, pt.GAUSS, pt.OBJECT, 1e-8)
+    h = ctypes.c_void_p()
+    st = pt.lib().ptlm_create(ctypes.byref(d), pos.ctypes.data_as(ctypes.c_void_p), None, 0, None, ctypes.byref(h))
+    assert st == pt.PTLM_EWORKSPACE and not h.value
+
+
+def test_default_params_are_the_papers():
+    p = pt.default_params()
+    assert (p.mu0, p.mu_min, p.kappa, p.nu, p.rho_min, p.beta) == (1e-5, 1e-8, 4.0, 1.0, 1e-4, 0.1)
+    assert p.cg_max == 10 and p.scaling == 0 and p.precond == 0
