@@ -151,8 +151,8 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
 /* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
  * stage = 1: per-position kernel only (accumulates into workspace strips);
  * stage = 2: the finishing reductions only (writes d_outO / d_outP and clears the strips);
- * stage = 3: both (identical to ptlm_ggn_vp).  Every stage-1 call must be followed by a
- * stage-2 call before any other product on the handle. */
+ * stage = 3: both (identical to ptlm_ggn_vp).  A stage-2 call finishes the most recent
+ * stage-1 call on the handle; any other product in between replaces its partial sums. */
 ptlm_status ptlm_ggn_vp_stage(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
                               const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
                               int32_t stage, void* stream);

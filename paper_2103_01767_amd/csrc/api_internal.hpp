@@ -3,7 +3,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ptlm.h"
+#include "ptlm.h"
 #include "internal.hpp"
 
 namespace ptlm {

@@ -43,7 +43,7 @@ struct Geometry {
   float* w2;              // K*M: sqrt(ell'') (Poisson only, else null)
   double* trace;          // K: sum_m ell''_km
   // scratch
-  float2* strips;         // per-segment private overlap-add strips (kept zero between calls)
+  float2* strips;         // per-segment private overlap-add strips (rewritten by every scatter)
   float2* probe_part;     // nseg * M per-segment probe partial sums
   double* partials;       // grid * 4 per-workgroup FP64 partial sums
 };
@@ -67,7 +67,7 @@ int tile_per_wg(int my, int mx);        // tiles (concurrent positions) per work
 size_t tile_lds_bytes(int my, int mx);
 
 // reductions and vector kernels (kernels_vec.hip)
-// out_O = sum of strips (strips zeroed after the read) [+ lam * dO .* vO]
+// out_O = sum of the segment strips [+ lam * dO .* vO]
 // lam_dev (nullable) overrides lam with a device scalar.
 hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const double* lam_dev, const float* dO,
                              const float2* vO, const int* predicate, hipStream_t s);

@@ -30,14 +30,37 @@ struct Cfg {
   static constexpr int WG = NT * TPW;
   static constexpr int RX = MX / 16, RY = MY / 16;        // second-pass radices
   static constexpr int GX = 16 / RX, GY = 16 / RY;        // second-pass groups per virtual thread
-  static constexpr int PAD = MX >= 64 ? 8 : (MX == 32 ? 2 : 1);
-  static constexpr int LDX = MX + PAD;                    // LDS row stride (complex)
+  // LDS layout (bank-conflict-free for every exchange of the four passes): after x pass 1
+  // element (n1, k1) of a row sits at column k1 * XA + n1; rows are LDX complex apart.
+  static constexpr int XA = MX == 16 ? 1 : (MX == 32 ? 2 : (MX == 64 ? 5 : 9));
+  static constexpr int LDX = MX == 16 ? 17 : (MX == 32 ? 35 : (MX == 64 ? 83 : 144));
   static constexpr int TILE = MY * LDX;                   // LDS complex per tile
   static constexpr int NWAVE = WG / 64 > 0 ? WG / 64 : 1;
   // probe partial kept in registers across the segment, or read-modify-written in the
   // segment's global probe slot each position (largest tile: no register room)
   static constexpr bool PROBE_REGS = NT < 1024;
 };
+
+// Order this wave's LDS writes before its later LDS reads (exchanges whose readers are the
+// writers' own wavefront need no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each
+// XCD a contiguous run of segments -- consecutive scan positions, overlapping windows -- so
+// the object windows it gathers stay in its L2.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  if (n % 8 != 0) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
+// streamed (read-once) complex load that bypasses cache allocation
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const double d = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));
+  return __builtin_bit_cast(float2, d);
+}
 
 __device__ __forceinline__ const float2* tw_table(const float2* tw, int L) {
   return tw + (L == 32 ? 0 : (L == 64 ? 32 : 96));
@@ -63,7 +86,7 @@ __device__ __forceinline__ double tile_sum(double x, double* red, int col, int s
 template <int MY, int MX, int OP>
 __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
   using C = Cfg<MY, MX>;
-  constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, V = C::V, NT = C::NT;
+  constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
   constexpr bool FWD_FFT = OP != OP_VJP;
   constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
@@ -72,20 +95,24 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
 
   extern __shared__ float2 smem[];
   double* red = reinterpret_cast<double*>(smem + C::TPW * C::TILE);  // [NWAVE][2]
+  float2* s_tw = smem + C::TPW * C::TILE + 2 * C::NWAVE;             // twiddles W_L^(n k), L = 32, 64, 128
+  for (int i = threadIdx.x; i < 224; i += C::WG) s_tw[i] = g.tw[i];
+  __syncthreads();
 
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x % NT;
   float2* lds = smem + slot * C::TILE;
-  const int seg = blockIdx.x * C::TPW + slot;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int seg = blk * C::TPW + slot;
   const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
   int maxlen = 0;
 #pragma unroll
   for (int s = 0; s < C::TPW; ++s) {
-    const int q = blockIdx.x * C::TPW + s;
+    const int q = blk * C::TPW + s;
     maxlen = max(maxlen, g.seg_start[q + 1] - g.seg_start[q]);
   }
-  const float2* twx = tw_table(g.tw, MX);
-  const float2* twy = tw_table(g.tw, MY);
+  const float2* twx = tw_table(s_tw, MX);
+  const float2* twy = tw_table(s_tw, MY);
   const float isq = rsqrtf((float)C::M);
   const bool joint = g.joint != 0;
 
@@ -97,19 +124,27 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
 #pragma unroll
     for (int j = 0; j < JA; ++j) accP[u][j] = make_float2(0.f, 0.f);
   float2* pslot = g.probe_part + (size_t)seg * C::M;  // this segment's probe partial
-  if constexpr (SCATTER && !C::PROBE_REGS) {
-    // zero the global probe slot before the segment's first read-modify-write
-    if (joint) {
-      for (int i = t; i < C::M; i += NT) pslot[i] = make_float2(0.f, 0.f);
-    }
-  }
   double s0 = 0.0, s1 = 0.0;
 
+  // The segment's first position stores its contribution into the strip (and the global
+  // probe slot); later positions read-modify-write.  Strip pixels outside the first window
+  // are cleared here, so no separate clearing pass is needed between calls.
   float2* strip = nullptr;
   int4 box = make_int4(0, 0, 0, 0);
   if constexpr (SCATTER) {
     strip = g.strips + g.seg_off[seg];
     box = g.seg_box[seg];
+    if (kend > kbeg) {
+      const int2 p0 = g.pos[kbeg];
+      const int area = box.z * box.w;
+      for (int i = t; i < area; i += NT) {
+        const int Y = box.x + i / box.w, X = box.y + i % box.w;
+        if ((unsigned)(Y - p0.x) >= (unsigned)MY || (unsigned)(X - p0.y) >= (unsigned)MX)
+          strip[i] = make_float2(0.f, 0.f);
+      }
+    } else if (!C::PROBE_REGS && joint) {
+      for (int i = t; i < C::M; i += NT) pslot[i] = make_float2(0.f, 0.f);
+    }
   }
 
   for (int it = 0; it < maxlen; ++it) {
@@ -171,17 +206,21 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      __syncthreads();
+      // the x-pass exchanges touch only this wavefront's rows; after an inverse transform the
+      // previous position's last reads of these rows (inverse x pass 1) came from this wave
+      if constexpr (INV_FFT) wave_lds_sync();
+      else __syncthreads();
       if (act) {
 #pragma unroll
         for (int u = 0; u < V; ++u) {
           const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
 #pragma unroll
-          for (int k1 = 0; k1 < 16; ++k1) lds[xy * LDX + k1 * RX + xn1] = v[u][k1];
+          for (int k1 = 0; k1 < 16; ++k1) lds[xy * LDX + k1 * XA + xn1] = v[u][k1];
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      __syncthreads();
+      if constexpr (RX > 1) wave_lds_sync();
+      else __syncthreads();
       // ---------------- x pass 2
       if constexpr (RX > 1) {
         if (act) {
@@ -192,12 +231,12 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
             for (int gg = 0; gg < GX; ++gg) {
               const int q = tv * GX + gg, yy = q >> 4, k1 = q & 15;
 #pragma unroll
-              for (int n1 = 0; n1 < RX; ++n1) v[u][gg * RX + n1] = lds[yy * LDX + k1 * RX + n1];
+              for (int n1 = 0; n1 < RX; ++n1) v[u][gg * RX + n1] = lds[yy * LDX + k1 * XA + n1];
             }
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act) {
 #pragma unroll
           for (int u = 0; u < V; ++u) {
@@ -305,16 +344,16 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
                 }
               }
             } else if constexpr (OP == OP_JVP) {
-              const float2 as = g.afield[gi];
+              const float2 as = ld_stream(g.afield + gi);
               float val = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
               if (g.w2) val /= g.w2[gi];
               a.rout[gi] = val;
             } else if constexpr (OP == OP_GGNV) {
-              const float2 as = g.afield[gi];
+              const float2 as = ld_stream(g.afield + gi);
               const float tt = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
               v[u][r] = cscale(as, tt);
             } else if constexpr (OP == OP_VJP) {
-              const float2 as = g.afield[gi];
+              const float2 as = ld_stream(g.afield + gi);
               float w = a.win[gi];
               if (g.w2) w /= g.w2[gi];
               v[u][r] = cscale(as, w);
@@ -366,7 +405,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
             const float2 q = Prow[RX * j];
             float base = 0.5f * A * fmaf(q.x, q.x, q.y * q.y);
             float cross = 0.5f * (fmaf(q.x, q.x, -q.y * q.y) * B.x - 2.f * q.x * q.y * B.y);
-            const float2 cur = srow[RX * j];
+            const float2 cur = it == 0 ? make_float2(0.f, 0.f) : srow[RX * j];
             srow[RX * j] = make_float2(cur.x + base + cross, cur.y + base - cross);
             if (joint) {
               const float2 o = Orow[RX * j];
@@ -376,7 +415,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
                 accP[u][j] = make_float2(accP[u][j].x + base + cross, accP[u][j].y + base - cross);
               } else {
                 float2* pp = pslot + xy * MX + xn1 + RX * j;
-                const float2 c0 = *pp;
+                const float2 c0 = it == 0 ? make_float2(0.f, 0.f) : *pp;
                 *pp = make_float2(c0.x + base + cross, c0.y + base - cross);
               }
             }
@@ -459,7 +498,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act) {
 #pragma unroll
           for (int u = 0; u < V; ++u) {
@@ -472,12 +511,12 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
               for (int n1 = 1; n1 < RX; ++n1)
                 v[u][gg * RX + n1] = cmulc(v[u][gg * RX + n1], twx[n1 * 16 + k1]);
 #pragma unroll
-              for (int n1 = 0; n1 < RX; ++n1) lds[yy * LDX + k1 * RX + n1] = v[u][gg * RX + n1];
+              for (int n1 = 0; n1 < RX; ++n1) lds[yy * LDX + k1 * XA + n1] = v[u][gg * RX + n1];
             }
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        __syncthreads();
+        wave_lds_sync();
       }
       // ---------------- inverse x pass 1 -> pixel (xy, xn1 + RX j), then overlap-add
       if (act) {
@@ -485,20 +524,25 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
         for (int u = 0; u < V; ++u) {
           const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
 #pragma unroll
-          for (int k1 = 0; k1 < 16; ++k1) v[u][k1] = lds[xy * LDX + k1 * RX + xn1];
+          for (int k1 = 0; k1 < 16; ++k1) v[u][k1] = lds[xy * LDX + k1 * XA + xn1];
           dft16<true>(v[u]);
           // object strip (plain RMW, segment-private) and probe registers
           const int Y = ry + xy;
           float2* srow = strip + (size_t)(Y - box.x) * box.w + (rx + xn1 - box.y);
           const float2* Prow = a.P + xy * MX + xn1;
+          if (it == 0) {
 #pragma unroll
-          for (int jj = 0; jj < 16; jj += 4) {
+            for (int j = 0; j < 16; ++j) srow[RX * j] = cmulc(v[u][j], Prow[RX * j]);
+          } else {
 #pragma unroll
-            for (int j = jj; j < jj + 4; ++j) {
-              const float2 cur = srow[RX * j];
-              srow[RX * j] = cadd(cur, cmulc(v[u][j], Prow[RX * j]));
+            for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+              for (int j = jj; j < jj + 4; ++j) {
+                const float2 cur = srow[RX * j];
+                srow[RX * j] = cadd(cur, cmulc(v[u][j], Prow[RX * j]));
+              }
+              __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
           }
           if (joint) {
             const float2* Orow = a.O + (size_t)Y * g.nx + rx + xn1;
@@ -511,11 +555,16 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
               }
             } else {
               float2* prow = pslot + xy * MX + xn1;
+              if (it == 0) {
 #pragma unroll
-              for (int jj = 0; jj < 16; jj += 4) {
+                for (int j = 0; j < 16; ++j) prow[RX * j] = cmulc(v[u][j], Orow[RX * j]);
+              } else {
 #pragma unroll
-                for (int j = jj; j < jj + 4; ++j) prow[RX * j] = cadd(prow[RX * j], cmulc(v[u][j], Orow[RX * j]));
-                __builtin_amdgcn_sched_barrier(0);
+                for (int jj = 0; jj < 16; jj += 4) {
+#pragma unroll
+                  for (int j = jj; j < jj + 4; ++j) prow[RX * j] = cadd(prow[RX * j], cmulc(v[u][j], Orow[RX * j]));
+                  __builtin_amdgcn_sched_barrier(0);
+                }
               }
             }
           }
@@ -570,7 +619,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
 template <int MY, int MX>
 static size_t lds_bytes() {
   using C = Cfg<MY, MX>;
-  return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)C::NWAVE * 2 * sizeof(double);
+  return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)C::NWAVE * 2 * sizeof(double) + 224 * sizeof(float2);
 }
 
 template <int MY, int MX, int OP>

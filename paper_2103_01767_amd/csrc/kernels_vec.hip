@@ -7,25 +7,50 @@
 namespace ptlm {
 
 // out_O[n] = sum over segments s whose strip covers n of strip_s[n]   (S_k^T overlap-add)
-//          [+ lam * D .* v]; each strip entry read is reset to zero for the next call.
+//          [+ lam * D .* v].  Strips are only read: the tile kernels rewrite them each call.
+// One block per 16x16 object tile: the tile's segment list (boxes, offsets) is staged in
+// LDS, then every thread sums its pixel over the list with independent loads.
+constexpr int OBJ_LIST = 256;
 __global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
-                                                         const float* d, const float2* v,
-                                                         const int* pred) {
+                                                         const float* d, const float2* v, const int* pred) {
   if (pred && *pred == 0) return;
+  __shared__ int4 s_box[OBJ_LIST];
+  __shared__ long long s_off[OBJ_LIST];
   const float lam = lam_dev ? (float)*lam_dev : lam_h;
   const int X = blockIdx.x * 16 + (threadIdx.x & 15);
   const int Y = blockIdx.y * 16 + (threadIdx.x >> 4);
   const bool in = X < g.nx && Y < g.ny;
   const int tile = blockIdx.y * g.otiles_x + blockIdx.x;
-  float2 acc = make_float2(0.f, 0.f);
   const int b = g.otile_ptr[tile], e = g.otile_ptr[tile + 1];
-  for (int i = b; i < e; ++i) {
-    const int s = g.otile_seg[i];
-    const int4 bx = g.seg_box[s];
-    if (in && Y >= bx.x && Y < bx.x + bx.z && X >= bx.y && X < bx.y + bx.w) {
-      float2* p = g.strips + g.seg_off[s] + (size_t)(Y - bx.x) * bx.w + (X - bx.y);
-      acc = cadd(acc, *p);
-      *p = make_float2(0.f, 0.f);
+  float2 acc = make_float2(0.f, 0.f);
+  for (int c0 = b; c0 < e; c0 += OBJ_LIST) {
+    const int cnt = min(OBJ_LIST, e - c0);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const int s = g.otile_seg[c0 + threadIdx.x];
+      s_box[threadIdx.x] = g.seg_box[s];
+      s_off[threadIdx.x] = g.seg_off[s];
+    }
+    __syncthreads();
+    // batches of 8 independent loads (misses read a valid dummy address and are dropped)
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      float2 val[8];
+      bool hit[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = min(i0 + j, cnt - 1);
+        const int4 bx = s_box[i];
+        const int ry = Y - bx.x, rx = X - bx.y;
+        hit[j] = in && (i0 + j < cnt) && (unsigned)ry < (unsigned)bx.z && (unsigned)rx < (unsigned)bx.w;
+        val[j] = g.strips[hit[j] ? s_off[i] + (size_t)ry * bx.w + rx : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (hit[j]) {
+          acc.x += val[j].x;
+          acc.y += val[j].y;
+        }
+      }
     }
   }
   if (!in) return;
@@ -43,18 +68,30 @@ __global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out
   out[n] = acc;
 }
 
-// out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v]
+// out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v]; 64 pixels per block, the segment
+// sum split four ways and combined in LDS in a fixed order.
 __global__ __launch_bounds__(256) void probe_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
-                                                           const float* d, const float2* v,
-                                                           const int* pred) {
+                                                           const float* d, const float2* v, const int* pred) {
   if (pred && *pred == 0) return;
+  __shared__ float2 sh[4][64];
   const float lam = lam_dev ? (float)*lam_dev : lam_h;
   const int M = g.my * g.mx;
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  if (m >= M) return;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int m = blockIdx.x * 64 + lane;
   float2 acc = make_float2(0.f, 0.f);
-  const float2* p = g.probe_part + m;
-  for (int s = 0; s < g.nseg; ++s) acc = cadd(acc, p[(size_t)s * M]);
+  if (m < M) {
+    const float2* p = g.probe_part + m;
+#pragma unroll 8
+    for (int s = grp; s < g.nseg; s += 4) {
+      const float2 val = p[(size_t)s * M];
+      acc.x += val.x;
+      acc.y += val.y;
+    }
+  }
+  sh[grp][lane] = acc;
+  __syncthreads();
+  if (grp != 0 || m >= M) return;
+  acc = cadd(cadd(sh[0][lane], sh[1][lane]), cadd(sh[2][lane], sh[3][lane]));
   if (lam != 0.f && v) {
     const float2 vv = v[m];
     if (d) {
@@ -86,40 +123,65 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* partial
 }
 
 // App. B diagonal, object part: d_n = (1/2M) sum_{k covering n} trace_k |P[n - r_k]|^2,
-// the same weight for the Re and Im coordinates.
+// the same weight for the Re and Im coordinates.  The tile's position list is staged in LDS.
 __global__ __launch_bounds__(256) void diag_paper_obj_kernel(Geometry g, float* dO) {
+  __shared__ int2 s_pos[OBJ_LIST];
+  __shared__ double s_tr[OBJ_LIST];
   const int X = blockIdx.x * 16 + (threadIdx.x & 15);
   const int Y = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (X >= g.nx || Y >= g.ny) return;
+  const bool in = X < g.nx && Y < g.ny;
   const int tile = blockIdx.y * g.otiles_x + blockIdx.x;
+  const int b = g.ptile_ptr[tile], e = g.ptile_ptr[tile + 1];
   double acc = 0.0;
-  for (int i = g.ptile_ptr[tile]; i < g.ptile_ptr[tile + 1]; ++i) {
-    const int k = g.ptile_pos[i];
-    const int2 r = g.pos[k];
-    const int my = Y - r.x, mx = X - r.y;
-    if (my >= 0 && my < g.my && mx >= 0 && mx < g.mx) {
-      const float2 p = g.P_lin[my * g.mx + mx];
-      acc += g.trace[k] * (double)(p.x * p.x + p.y * p.y);
+  for (int c0 = b; c0 < e; c0 += OBJ_LIST) {
+    const int cnt = min(OBJ_LIST, e - c0);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const int k = g.ptile_pos[c0 + threadIdx.x];
+      s_pos[threadIdx.x] = g.pos[k];
+      s_tr[threadIdx.x] = g.trace[k];
+    }
+    __syncthreads();
+    if (in) {
+#pragma unroll 4
+      for (int i = 0; i < cnt; ++i) {
+        const int2 r = s_pos[i];
+        const int my = Y - r.x, mx = X - r.y;
+        if ((unsigned)my < (unsigned)g.my && (unsigned)mx < (unsigned)g.mx) {
+          const float2 p = g.P_lin[my * g.mx + mx];
+          acc += s_tr[i] * (double)fmaf(p.x, p.x, p.y * p.y);
+        }
+      }
     }
   }
+  if (!in) return;
   const float val = (float)(acc / (2.0 * g.my * g.mx));
   const size_t n = (size_t)Y * g.nx + X;
   dO[2 * n] = val;
   dO[2 * n + 1] = val;
 }
 
-// App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2
+// App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; 64 pixels per
+// block, the position sum split four ways and combined in a fixed order.
 __global__ __launch_bounds__(256) void diag_paper_probe_kernel(Geometry g, float* dP) {
+  __shared__ double sh[4][64];
   const int M = g.my * g.mx;
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  if (m >= M) return;
-  const int my = m / g.mx, mx = m % g.mx;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int m = blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int k = 0; k < g.K; ++k) {
-    const int2 r = g.pos[k];
-    const float2 o = g.O_lin[(size_t)(r.x + my) * g.nx + r.y + mx];
-    acc += g.trace[k] * (double)(o.x * o.x + o.y * o.y);
+  if (m < M) {
+    const int my = m / g.mx, mx = m % g.mx;
+#pragma unroll 4
+    for (int k = grp; k < g.K; k += 4) {
+      const int2 r = g.pos[k];
+      const float2 o = g.O_lin[(size_t)(r.x + my) * g.nx + r.y + mx];
+      acc += g.trace[k] * (double)fmaf(o.x, o.x, o.y * o.y);
+    }
   }
+  sh[grp][lane] = acc;
+  __syncthreads();
+  if (grp != 0 || m >= M) return;
+  acc = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
   const float val = (float)(acc / (2.0 * M));
   dP[2 * m] = val;
   dP[2 * m + 1] = val;
@@ -135,7 +197,7 @@ hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const 
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* pred, hipStream_t s) {
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(probe_reduce_kernel, dim3((M + 255) / 256), dim3(256), 0, s, g, outP, (float)lam, lam_dev, dP,
+  hipLaunchKernelGGL(probe_reduce_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, outP, (float)lam, lam_dev, dP,
                      vP, pred);
   return hipGetLastError();
 }
@@ -150,7 +212,7 @@ hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !dP) return e;
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 255) / 256), dim3(256), 0, s, g, dP);
+  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, dP);
   return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Internal declarations of the LM / PCG kernels.
 #pragma once
-#include "../../include/ptlm.h"
+#include "ptlm.h"
 #include "internal.hpp"
 
 namespace ptlm {
