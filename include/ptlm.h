@@ -74,7 +74,7 @@ typedef struct {
   int32_t cg_max;     /* cap on PCG products per solve */
   int32_t retry_max;  /* cap on rejected attempts per outer iteration */
   int32_t scaling;    /* 0: D = I, 1: D = Dg(G) (App. B diagonal) */
-  int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: caller diagonal + lambda */
+  int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: learned diagonal + lambda D */
   int32_t warm_start; /* 1: PCG starts from the last accepted step */
 } ptlm_lm_params;
 
@@ -169,7 +169,9 @@ ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, v
  * ratio, mu update}.  It synchronises the stream once per attempt to read the acceptance
  * flag.  Returns PTLM_OK when a step was accepted, PTLM_ENOTACCEPTED when all retries were
  * rejected (iterate unchanged), PTLM_ENUMERIC on a non-finite loss (iterate unchanged).
- * d_precond (2n floats, nullable) is the caller diagonal used when params->precond == 2.
+ * With params->precond == 2 the PCG preconditioner is d + lambda D, where d is the network's
+ * learned diagonal (ptlm_lm_set_cnn, refreshed every outer iteration) or, if no network is
+ * registered, the caller's d_precond (2n floats).
  * ptlm_lm_solve runs T outer iterations, stopping early on PTLM_ENUMERIC. */
 ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_state* d_state,
                          void* stream);
@@ -179,6 +181,48 @@ ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_
 ptlm_status ptlm_lm_solve(ptlm_handle* h, float* d_O, float* d_P, const float* d_y,
                           const ptlm_lm_params* params, int32_t T, ptlm_lm_state* d_state,
                           const float* d_precond, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned diagonal preconditioner (a project addition; the paper preconditions PCG with the
+ * analytic diagonal Dg(G + lambda D) of App. B and mentions stochastic diagonal estimates).
+ * A small CNN of `layers` 3x3 "same" convolutions (zero padding, ReLU between layers) maps
+ * 3 feature maps on the object grid -- illumination overlap sum_k S_k^T |P|^2, overlap-
+ * weighted |P|^2 and overlap-weighted arg P (ptlm_cnn_features) -- to 2 maps r; the learned
+ * object diagonal is d_paper * exp(r) per real coordinate (positive by construction), the
+ * probe part (joint mode) stays the App. B diagonal.  Tensors are NCHW float32 device arrays;
+ * parameters are one float array: per layer W (Cout, Cin, 3, 3) then b (Cout).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n, h, w;            /* batch and spatial size */
+  int32_t cin, cmid, cout;    /* channels: input, hidden, output (each 2, 3, 4, 8, 16 or 32) */
+  int32_t layers;             /* number of conv layers, 1..15 */
+} ptlm_cnn_desc;
+
+ptlm_status ptlm_cnn_param_count(const ptlm_cnn_desc* d, size_t* count);           /* host only */
+ptlm_status ptlm_cnn_workspace_bytes(const ptlm_cnn_desc* d, size_t* bytes);        /* host only */
+/* d_out: n x cout x h x w (the log-correction r). */
+ptlm_status ptlm_cnn_forward(const ptlm_cnn_desc* d, const float* d_params, const float* d_x, float* d_out,
+                             void* d_ws, size_t ws_bytes, void* stream);
+/* Loss L = sum_mask (r - t)^2 / (2 count) (mask > 0 selects pixels) into d_loss[0] (FP64)
+ * and dL/dparams into d_grad (param_count floats). */
+ptlm_status ptlm_cnn_loss_grad(const ptlm_cnn_desc* d, const float* d_params, const float* d_x, const float* d_t,
+                               const float* d_mask, double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes,
+                               void* stream);
+/* One Adam step (Kingma & Ba) on `count` parameters; step counts from 1. */
+ptlm_status ptlm_cnn_adam(size_t count, float* d_params, const float* d_grad, float* d_m, float* d_v,
+                          int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+/* The 3 input maps (3 x ny x nx floats) at the last linearisation of the handle. */
+ptlm_status ptlm_cnn_features(ptlm_handle* h, float* d_feat, void* stream);
+/* Learned PCG diagonal (2n floats, interleaved like ptlm_diag) from r (2 x ny x nx) at the
+ * last linearisation: App. B diagonal floored at 1e-6 of its block maximum, times exp(r) on
+ * the object part. */
+ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_precond, void* stream);
+/* Register a network for ptlm_lm_step with params->precond == 2: after every linearisation
+ * the step recomputes features -> network -> learned diagonal.  d = NULL unregisters.  The
+ * desc must be n = 1, h x w = the object shape, cin = 3, cout = 2; d_params and d_ws
+ * (ptlm_cnn_workspace_bytes) stay owned by the caller and must outlive their use. */
+ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float* d_params, void* d_ws,
+                            size_t ws_bytes);
 
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* ptlm_last_error(void);

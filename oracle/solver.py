@@ -190,12 +190,13 @@ class LMResult:
 
 
 def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
-             learned_diag=None, loss_fn=None) -> LMResult:
+             learned_diag=None, loss_fn=None, progress=None) -> LMResult:
     """Truncated matrix-free LM, alg:lm_inexact, step by step.
 
-    ``learned_diag`` is a real-coordinate diagonal (n, 2) used as the PCG
-    preconditioner (plus lambda) when ``params.precond == 2``.  ``loss_fn``
+    ``learned_diag`` is a real-coordinate diagonal (n, 2) that replaces Dg(G) in
+    the Jacobi preconditioner Dg(G + lambda D) when ``params.precond == 2``.  ``loss_fn``
     overrides the trial-loss evaluation (used to force branches in tests).
+    ``progress(t, f_t)`` is called at the start of every outer iteration.
     """
     p = params
     O = np.array(O0, dtype=np.complex128)
@@ -211,6 +212,8 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
         lin = ptycho.linearize(O, P, pos, y, b, metric, joint)
         f_t = lin.f
         res.f_per_iter.append(f_t)
+        if progress is not None:
+            progress(t, f_t)
         gO, gP = ptycho.gradient(lin)
         g = pack(gO, gP)
         gnorm = rnorm(g)
@@ -239,7 +242,8 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
                 m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
                 pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
             elif p.precond == 2:
-                m = learned_diag + lam
+                # learned stand-in for Dg(G) inside Dg(G + lambda D)
+                m = learned_diag + lam * (dg if scaled else 1.0)
                 pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
             else:
                 pc = None

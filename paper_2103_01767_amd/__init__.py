@@ -48,6 +48,10 @@ class ptlm_lm_params(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
 
 
+class ptlm_cnn_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("n", "h", "w", "cin", "cmid", "cout", "layers")]
+
+
 _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
                   "rz", "rr", "alpha", "beta_cg", "pap"]
 _STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
@@ -79,6 +83,16 @@ _sig = {
     "ptlm_lm_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp, _vp]),
     "ptlm_lm_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), ctypes.c_int32,
                                      _vp, _vp, _vp]),
+    "ptlm_cnn_param_count": (ctypes.c_int, [ctypes.POINTER(ptlm_cnn_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "ptlm_cnn_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ptlm_cnn_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "ptlm_cnn_forward": (ctypes.c_int, [ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ptlm_cnn_loss_grad": (ctypes.c_int, [ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
+    "ptlm_cnn_adam": (ctypes.c_int, [ctypes.c_size_t, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
+    "ptlm_cnn_features": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ptlm_learned_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ptlm_lm_set_cnn": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, ctypes.c_size_t]),
     "ptlm_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -258,6 +272,85 @@ class Problem:
         return _check(_lib.ptlm_lm_solve(self.handle, self._o(O), self._p(P), self._m(y, "y"),
                                          ctypes.byref(params), int(T), _vp(state.data_ptr()), pc, _stream()),
                       allow=(PTLM_OK, PTLM_ENOTACCEPTED))
+
+
+class Cnn:
+    """Preconditioner network on one GPU: parameters, Adam moments and workspace."""
+
+    def __init__(self, n, h, w, cin=3, cmid=32, cout=2, layers=4, device="cuda", params=None):
+        self.desc = ptlm_cnn_desc(n, h, w, cin, cmid, cout, layers)
+        cnt = ctypes.c_size_t(0)
+        _check(_lib.ptlm_cnn_param_count(ctypes.byref(self.desc), ctypes.byref(cnt)))
+        self.count = int(cnt.value)
+        nb = ctypes.c_size_t(0)
+        _check(_lib.ptlm_cnn_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.params = (torch.zeros(self.count, dtype=torch.float32, device=self.device) if params is None
+                       else params.to(self.device, torch.float32).contiguous())
+        assert self.params.numel() == self.count
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    @property
+    def shape_in(self):
+        d = self.desc
+        return (d.n, d.cin, d.h, d.w)
+
+    @property
+    def shape_out(self):
+        d = self.desc
+        return (d.n, d.cout, d.h, d.w)
+
+    def forward(self, x):
+        out = torch.empty(self.shape_out, dtype=torch.float32, device=self.device)
+        _check(_lib.ptlm_cnn_forward(ctypes.byref(self.desc), _ptr(self.params, torch.float32),
+                                     _ptr(x, torch.float32, self.shape_in, "x"), _ptr(out, torch.float32),
+                                     _vp(self.ws.data_ptr()), self.ws_bytes, _stream()))
+        return out
+
+    def loss_grad(self, x, t, mask):
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        grad = torch.empty_like(self.params)
+        _check(_lib.ptlm_cnn_loss_grad(ctypes.byref(self.desc), _ptr(self.params, torch.float32),
+                                       _ptr(x, torch.float32, self.shape_in, "x"),
+                                       _ptr(t, torch.float32, self.shape_out, "t"),
+                                       _ptr(mask, torch.float32, self.shape_out, "mask"),
+                                       _ptr(loss, torch.float64), _ptr(grad, torch.float32),
+                                       _vp(self.ws.data_ptr()), self.ws_bytes, _stream()))
+        return loss, grad
+
+    def adam(self, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _check(_lib.ptlm_cnn_adam(self.count, _ptr(self.params, torch.float32), _ptr(grad, torch.float32),
+                                  _ptr(self.m, torch.float32), _ptr(self.v, torch.float32), self.step,
+                                  lr, b1, b2, eps, _stream()))
+
+
+def cnn_features(prob: "Problem"):
+    out = torch.empty((3,) + prob.obj_shape, dtype=torch.float32, device=prob.device)
+    _check(_lib.ptlm_cnn_features(prob.handle, _ptr(out, torch.float32), _stream()))
+    return out
+
+
+def learned_precond(prob: "Problem", r):
+    n = prob.obj_shape[0] * prob.obj_shape[1] + (prob.probe_shape[0] * prob.probe_shape[1] if prob.joint else 0)
+    out = torch.empty(2 * n, dtype=torch.float32, device=prob.device)
+    _check(_lib.ptlm_learned_precond(prob.handle, _ptr(r, torch.float32, (2,) + prob.obj_shape, "r"),
+                                     _ptr(out, torch.float32), _stream()))
+    return out
+
+
+def lm_set_cnn(prob: "Problem", cnn: "Cnn | None"):
+    if cnn is None:
+        _check(_lib.ptlm_lm_set_cnn(prob.handle, None, None, None, 0))
+        prob._cnn = None
+        return
+    _check(_lib.ptlm_lm_set_cnn(prob.handle, ctypes.byref(cnn.desc), _ptr(cnn.params, torch.float32),
+                                _vp(cnn.ws.data_ptr()), cnn.ws_bytes))
+    prob._cnn = cnn  # keep the network's buffers alive while registered
 
 
 def lib():

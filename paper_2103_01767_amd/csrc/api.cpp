@@ -173,7 +173,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   p.off.strips = take((size_t)p.strip_elems * sizeof(float2));
   p.off.probe_part = take((size_t)p.nseg * M * sizeof(float2));
   p.off.partials = take((size_t)std::max(p.grid, 1024) * 4 * sizeof(double));
-  p.off.scal = take(64 * sizeof(double));
+  p.off.scal = take(64 * sizeof(double));  // [0..7] LM scalars, [8..11] feature / learned-diagonal scratch
   // LM / PCG vectors (complex entries of R^(2n)) and real diagonals
   p.off.g = take(n2 * sizeof(float2));
   p.off.dx = take(n2 * sizeof(float2));
@@ -184,6 +184,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   p.off.Ap = take(n2 * sizeof(float2));
   p.off.diag = take(n2 * sizeof(float2));
   p.off.ztrial = take(n2 * sizeof(float2));
+  p.off.learned = take(n2 * sizeof(float2));
   p.off.lmstate = take(sizeof(ptlm_lm_state));
   p.ws_bytes = o;
   return PTLM_OK;

@@ -11,7 +11,7 @@ namespace ptlm {
 struct Offsets {
   size_t tw, pos, seg_start, seg_box, seg_off, otile_ptr, otile_seg, ptile_ptr, ptile_pos;
   size_t O_lin, P_lin, afield, w2, trace, strips, probe_part, partials, scal;
-  size_t g, dx, prev, r, z, p, Ap, diag, ztrial, lmstate;
+  size_t g, dx, prev, r, z, p, Ap, diag, ztrial, learned, lmstate;
 };
 
 // Everything derived on the host from the description and the positions.
@@ -38,6 +38,9 @@ struct ptlm_handle {
   ptlm::Geometry g{};
   char* ws = nullptr;
   bool prev_valid = false;  // an accepted LM step exists (PCG warm start)
+  ptlm_cnn_desc cnn{};      // registered preconditioner network (ptlm_lm_set_cnn)
+  const float* cnn_params = nullptr;
+  char* cnn_ws = nullptr;
 };
 
 namespace ptlm {
@@ -51,4 +54,5 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
                       const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
                       int stage = 3);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s);
+ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s);
 }  // namespace ptlm

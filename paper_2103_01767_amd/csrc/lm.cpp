@@ -81,6 +81,12 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
     LM_HIP(launch_fin(F_DIAGMAX, a, LM_BLOCKS, s), "lm diag max fin");
     LM_HIP(launch_vec(V_DIAGFLOOR, a, s), "lm diag floor");
   }
+  if (prm->precond == 2 && h->cnn_params) {
+    float2* lbuf = (float2*)(h->ws + h->plan.off.learned);
+    stt = learned_from_cnn(h, (float*)lbuf, s);
+    if (stt != PTLM_OK) return stt;
+    a.learned = lbuf;
+  }
   ptlm_lm_state hs;
   LM_HIP(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "lm read state");
   LM_HIP(hipStreamSynchronize(s), "lm sync");
@@ -154,7 +160,8 @@ ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_
   if (!h || !d_O || !d_P || !d_y || !d_state) return fail(PTLM_EINVAL, "null argument");
   ptlm_status st = check_params(params);
   if (st != PTLM_OK) return st;
-  if (params->precond == 2 && !d_precond) return fail(PTLM_EINVAL, "precond == 2 needs d_precond");
+  if (params->precond == 2 && !d_precond && !h->cnn_params)
+    return fail(PTLM_EINVAL, "precond == 2 needs d_precond or a registered network");
   return lm_step_impl(h, (float2*)d_O, (float2*)d_P, d_y, params, d_state, d_precond, (hipStream_t)stream);
 }
 

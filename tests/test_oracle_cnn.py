@@ -1,0 +1,57 @@
+"""Pins of the FP64 CNN oracle: convolution against SciPy's correlation, the backward pass
+against central finite differences, Adam's first step against its closed form."""
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import cnn
+
+RNG = np.random.default_rng(4)
+
+
+def test_conv3x3_is_zero_padded_correlation():
+    x = RNG.standard_normal((2, 3, 7, 9))
+    W = RNG.standard_normal((4, 3, 3, 3))
+    b = RNG.standard_normal(4)
+    y = cnn.conv3x3(x, W, b)
+    for n in range(2):
+        for o in range(4):
+            ref = b[o] + sum(signal.correlate2d(x[n, c], W[o, c], mode="same", boundary="fill")
+                             for c in range(3))
+            np.testing.assert_allclose(y[n, o], ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("layers", [1, 2, 3])
+def test_gradient_matches_finite_differences(layers):
+    cin, cmid, cout = 3, 4, 2
+    x = RNG.standard_normal((2, cin, 6, 5))
+    t = RNG.standard_normal((2, cout, 6, 5))
+    mask = (RNG.uniform(size=t.shape) > 0.3).astype(float)
+    p = cnn.init_params(RNG, cin, cmid, cout, layers) + 0.1 * RNG.standard_normal(cnn.param_count(cin, cmid, cout, layers))
+    L, g = cnn.grad(p, x, t, mask, cin, cmid, cout, layers)
+    assert L == pytest.approx(cnn.loss(p, x, t, mask, cin, cmid, cout, layers))
+    h = 1e-6
+    idx = RNG.choice(len(p), size=min(40, len(p)), replace=False)
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (cnn.loss(p + e, x, t, mask, cin, cmid, cout, layers) -
+              cnn.loss(p - e, x, t, mask, cin, cmid, cout, layers)) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    p = RNG.standard_normal(10)
+    g = RNG.standard_normal(10)
+    p1, m, v = cnn.adam(p, g, np.zeros(10), np.zeros(10), 1, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(p1, p - 0.01 * np.sign(g), rtol=1e-12)
+
+
+def test_features_and_learned_diag_shapes():
+    P = RNG.standard_normal((4, 4)) + 1j * RNG.standard_normal((4, 4))
+    pos = np.array([[0, 0], [2, 3], [4, 4]])
+    f = cnn.features(P, pos, (9, 9))
+    assert f.shape == (3, 9, 9) and f[0].max() == pytest.approx(1.0)
+    assert np.all(f[0][8, 0:3] == 0.0) and np.all(np.abs(f[2]) <= 1.0 + 1e-12)
+    d = cnn.learned_diag(np.ones((9, 9, 2)), np.ones((4, 4, 2)), np.zeros((2, 9, 9)))
+    assert d.shape == (81 + 16, 2) and np.all(d == 1.0)
