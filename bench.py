@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--calls", type=int, default=50, help="isolated GGN-vector product calls")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-calls", type=int, default=3)
+    ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
+    ap.add_argument("--lm-iters", type=int, default=60)
     return ap.parse_args()
 
 
@@ -67,12 +69,9 @@ def main():
     prob = pt.Problem((ny, nx), (my, mx), pr.pos, metric="gauss", mode="joint", background=pr.background,
                       device=dev)
 
-    # synthetic Poisson data from the model itself (expected counts = zeta^2)
-    zeta = prob.forward(c64(pr.O_true), c64(pr.P_true))
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(1001)
-    y = torch.poisson((zeta.double() ** 2).float(), generator=gen).contiguous()
-    del zeta
+    # synthetic Poisson counts of the workload (generated once by tests/golden/make_golden.py)
+    counts = np.load(os.path.join(HERE, "tests", "golden", "c1_counts.npz"))["y"]
+    y = torch.from_numpy(counts.astype(np.float32)).to(dev)
 
     O = c64(pr.O_init)
     P = c64(pr.P_init)
@@ -128,6 +127,8 @@ def main():
     fft_flops = 2 * 5 * M * math.log2(M) * K  # two 2D FFTs per position (5 M log2 M convention)
     fft_tflops = fft_flops / (kern_ms * 1e-3) / 1e12
 
+    lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pr, O, P, y, vO, vP, args.cpu_calls)
@@ -159,9 +160,52 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
+        "lm_time_to_target": lm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def lm_comparison(prob, pr, dev, iters):
+    """LM wall time to f <= 1.01 f_oracle, for plain (unpreconditioned), Jacobi and learned PCG.
+
+    Data: the stored Poisson counts of the workload; f_oracle: the FP64 oracle's loss after its
+    stored number of outer iterations (D = Dg(G), Jacobi PCG) on the same data.  Each variant
+    runs from the workload's initial guess for at most ``iters`` outer iterations.
+    """
+    import torch
+    import paper_2103_01767_amd as pt
+    from paper_2103_01767_amd import learned
+    gold = os.path.join(HERE, "tests", "golden")
+    ref = json.load(open(os.path.join(gold, "c1_oracle_lm.json")))
+    y = torch.from_numpy(np.load(os.path.join(gold, "c1_counts.npz"))["y"].astype(np.float32)).to(dev)
+    target = 1.01 * ref["f_final"]
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    net = learned.lm_net(learned.load(dev), pr.O_true.shape, dev)
+    out = {"target_loss": target, "oracle_final_loss": ref["f_final"], "oracle_iters": ref["T"],
+           "max_iters": iters}
+    for name, prec in (("plain", 0), ("jacobi", 1), ("learned", 2)):
+        pt.lm_set_cnn(prob, net if prec == 2 else None)
+        params = pt.default_params(scaling=1, precond=prec, cg_max=10)
+        st = prob.new_state()
+        O, P = c64(pr.O_init), c64(pr.P_init)
+        prob.lm_init(params, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hit = None
+        for t in range(iters):
+            prob.lm_step(O, P, y, params, st)
+            f = float(prob.loss(O, P, y).cpu()[0])     # also synchronises
+            if f <= target:
+                hit = t + 1
+                break
+        el = time.perf_counter() - t0
+        s = pt.state_from_tensor(st)
+        out[name] = {"reached": hit is not None, "iters": hit if hit is not None else iters,
+                     "seconds": round(el, 4), "final_loss": f, "ggnv_products": s.products,
+                     "attempts": s.attempts}
+    pt.lm_set_cnn(prob, None)
+    return out
 
 
 def cpu_baseline(pr, O, P, y, vO, vP, calls):
