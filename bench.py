@@ -33,6 +33,27 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (published)
 METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learned vs plain"
 
+# HBM-side bytes of one launch of the GGN-vector tile kernel on this workload, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
+# profiles/ggnv_tile128_joint_obj512_probe128_k1600.md (KiB per dispatch, scaled by what the
+# same counters read for a plain 256 MiB copy).  Valid only for the kernel sources they were
+# taken on: a different hash of those sources reports traffic as null.
+TRAFFIC = {"fetch_kib": 337764.675, "write_kib": 449179.6875, "fetch_factor": 1.9998, "write_factor": 1.0,
+           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp"],
+           "sha256": "90505f6c2a865871933fbe79b9fef967879893b8edc71048482bb0c6c8a74e34"}
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(HERE, "paper_2103_01767_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return round((TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+                 * 1024.0)
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -44,11 +65,28 @@ def parse():
     ap.add_argument("--cpu-calls", type=int, default=3)
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 256 MiB, five times: what the HBM byte counters read
+    for a kernel of known traffic (268435456 B read + 268435456 B written per copy)."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(positions would be sharded across GPUs; see the design notes). Use --gpus 1.",
@@ -158,7 +196,7 @@ def main():
         "fft_tflops": round(fft_tflops, 2),
         "fft_frac_fp32_peak": round(fft_tflops / FP32_PEAK_TFLOPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
         "lm_time_to_target": lm,
         "cpu_baseline": cpu,

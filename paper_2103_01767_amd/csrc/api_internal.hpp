@@ -10,7 +10,7 @@ namespace ptlm {
 
 struct Offsets {
   size_t tw, pos, seg_start, seg_box, seg_off, otile_ptr, otile_seg, ptile_ptr, ptile_pos;
-  size_t O_lin, P_lin, afield, w2, trace, strips, probe_part, partials, scal;
+  size_t O_lin, P_lin, afield, w2, trace, strips, probe_part, partials, scratch, scal;
   size_t g, dx, prev, r, z, p, Ap, diag, ztrial, learned, lmstate;
 };
 

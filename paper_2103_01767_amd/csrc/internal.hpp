@@ -26,7 +26,7 @@ struct Geometry {
   int nseg;    // number of position segments (= grid * tiles per workgroup)
   int grid;    // workgroups of the tile kernels
   // constant tables in the workspace
-  const float2* tw;       // twiddles W_L^(n k), L = 32, 64, 128 (offsets 0, 32, 96)
+  const float2* tw;       // twiddles W_L^(n k), n < L/16, k < 16: L = 32, 64, 128, 256 (offsets 0, 32, 96, 224)
   const int2* pos;        // K (row, col)
   const int* seg_start;   // nseg + 1
   const int4* seg_box;    // nseg: (row0, col0, rows, cols) of the segment's strip
@@ -46,6 +46,7 @@ struct Geometry {
   float2* strips;         // per-segment private overlap-add strips (rewritten by every scatter)
   float2* probe_part;     // nseg * M per-segment probe partial sums
   double* partials;       // grid * 4 per-workgroup FP64 partial sums
+  float2* scratch;        // grid * M transform tiles (256 x 256 probes only, else null)
 };
 
 struct TileArgs {
@@ -65,6 +66,9 @@ bool tile_shape_supported(int my, int mx);
 int tile_threads(int my, int mx);       // threads per workgroup
 int tile_per_wg(int my, int mx);        // tiles (concurrent positions) per workgroup
 size_t tile_lds_bytes(int my, int mx);
+// 256 x 256 tiles (kernels_tile256.hip): three-stage transform through Geometry::scratch
+hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+size_t tile256_lds_bytes();
 
 // reductions and vector kernels (kernels_vec.hip)
 // out_O = sum of the segment strips [+ lam * dO .* vO]

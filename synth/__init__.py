@@ -149,6 +149,25 @@ def poisson_counts(rng, intensity: np.ndarray) -> np.ndarray:
     return rng.poisson(np.maximum(intensity, 0.0)).astype(np.float64)
 
 
+def surrogate_counts(rng, K: int, shape, photons: float) -> np.ndarray:
+    """Seeded stand-in detector counts (float32, K x My x Mx) for tests that only need
+    data of the right size, scale and layout, not data consistent with an object: a
+    radially decaying mean in detector (FFT) order holding ``photons`` per pattern, times
+    independent U[0, 2) factors.  Generated in chunks of positions to bound memory."""
+    my, mx = shape
+    fy = np.fft.fftfreq(my)[:, None]
+    fx = np.fft.fftfreq(mx)[None, :]
+    prof = 1.0 / (1.0 + ((fy ** 2 + fx ** 2) / 0.02 ** 2) ** 2)
+    prof = (photons * prof / prof.sum()).astype(np.float32)
+    out = np.empty((K, my, mx), dtype=np.float32)
+    step = max(1, (1 << 24) // (my * mx))
+    for k0 in range(0, K, step):
+        k1 = min(K, k0 + step)
+        u = rng.random((k1 - k0, my, mx), dtype=np.float32)
+        np.multiply(u, 2.0 * prof, out=out[k0:k1])
+    return out
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------

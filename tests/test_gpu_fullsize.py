@@ -1,0 +1,174 @@
+"""GPU parity at the full workload sizes, in the launch configuration the benchmark uses.
+
+* 512x512 object / 128x128 probe / 1600 positions (joint): the FP64 oracle still finishes
+  the whole problem in seconds, so forward, loss, gradient and the GGN-vector product
+  are compared element by element over every output (relative L2, bar 1e-5).  Data:
+  the stored oracle-generated Poisson counts of the workload.
+* 2048x2048 object / 256x256 probe / 10 000 positions (joint): the oracle cannot run
+  the whole problem in a test, so it computes sampled outputs one by one -- magnitudes,
+  residuals and JVP rows of sampled positions, and the gradient and GGN-vector product
+  on object patches from exactly the positions whose windows cover the patch -- and the
+  parts it cannot sample (the probe block summed over all positions) are checked
+  through properties that hold at any size: symmetry of G and <v, Gv> = ||J v||^2
+  (Gaussian metric).  Data: seeded stand-in counts of the workload's size and scale.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ptycho
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2103_01767_amd as pt  # noqa: E402
+
+DEV = torch.device("cuda:0")
+TOL = 1e-5
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) else np.float64)
+    b = np.asarray(b, dtype=a.dtype)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def c64(x):
+    return np.asarray(x, dtype=np.complex64)
+
+
+def rdot(a, b):
+    """Real inner product Re sum conj(a) b in FP64 (the PCG inner product)."""
+    return float(np.sum(a.real.astype(np.float64) * b.real + a.imag.astype(np.float64) * b.imag))
+
+
+def test_c1_full_elementwise():
+    print("case c1 full", flush=True)
+    pr = synth.make_c1()
+    y = np.load(os.path.join(GOLD, "c1_counts.npz"))["y"].astype(np.float32)
+    O, P = c64(pr.O_init), c64(pr.P_init)
+    prob = pt.Problem(O.shape, P.shape, pr.pos, metric="gauss", mode="joint", background=pr.background,
+                      device=DEV)
+    Od, Pd, yd = dev(O), dev(P), dev(y)
+    O64, P64, y64 = O.astype(np.complex128), P.astype(np.complex128), y.astype(np.float64)
+    zeta = host(prob.forward(Od, Pd))
+    assert rel(zeta, ptycho.magnitude(O64, P64, pr.pos, pr.background)) < TOL
+    del zeta
+    lin = ptycho.linearize(O64, P64, pr.pos, y64, pr.background, "gauss", True)
+    f, gO, gP = prob.linearize(Od, Pd, yd)
+    assert abs(float(host(f)[0]) - lin.f) <= 1e-5 * lin.f
+    rgO, rgP = ptycho.gradient(lin)
+    assert rel(host(gO), rgO) < TOL and rel(host(gP), rgP) < TOL
+    rng = np.random.default_rng(77)
+    vO = c64(synth.random_complex(rng, O.shape))
+    vP = c64(synth.random_complex(rng, P.shape))
+    oO, oP = prob.ggn_vp(dev(vO), dev(vP))
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128))
+    assert rel(host(oO), GO) < TOL and rel(host(oP), GP) < TOL
+    dOg, dPg = prob.diag(exact=False)
+    aO, aP = ptycho.ggn_diag_paper(lin)
+    assert rel(host(dOg), aO) < TOL and rel(host(dPg), aP) < TOL
+
+
+@pytest.fixture(scope="module")
+def c4():
+    print("case c4 setup", flush=True)
+    pr = synth.make_c4()
+    K, (my, mx) = pr.K, pr.P_true.shape
+    y = synth.surrogate_counts(np.random.default_rng(1004004), K, (my, mx), pr.photons)
+    O, P = c64(pr.O_init), c64(pr.P_init)
+    prob = pt.Problem(O.shape, P.shape, pr.pos, metric="gauss", mode="joint", background=pr.background,
+                      device=DEV)
+    st = dict(pr=pr, y=y, O=O, P=P, prob=prob, Od=dev(O), Pd=dev(P), yd=dev(y))
+    yield st
+    st.clear()
+    torch.cuda.empty_cache()
+
+
+def covering(pos, shape, y0, x0, h, w):
+    """Indices of the positions whose window meets the object patch [y0, y0+h) x [x0, x0+w)."""
+    my, mx = shape
+    r, c = pos[:, 0], pos[:, 1]
+    return np.nonzero((r < y0 + h) & (r + my > y0) & (c < x0 + w) & (c + mx > x0))[0]
+
+
+def test_c4_sampled_forward_residual_jvp(c4):
+    print("case c4 forward/residual/jvp", flush=True)
+    pr, prob, y = c4["pr"], c4["prob"], c4["y"]
+    K = pr.K
+    sel = np.array([0, 1, 99, 100, 4321, 5000, 7777, K - 1])
+    O64, P64 = c4["O"].astype(np.complex128), c4["P"].astype(np.complex128)
+    zeta = prob.forward(c4["Od"], c4["Pd"])
+    ref = ptycho.magnitude(O64, P64, pr.pos[sel], pr.background)
+    assert rel(host(zeta[torch.from_numpy(sel).to(DEV)]), ref) < TOL
+    del zeta
+    f, resid = prob.loss(c4["Od"], c4["Pd"], c4["yd"], residual=True)
+    lin = ptycho.linearize(O64, P64, pr.pos[sel], y[sel].astype(np.float64), pr.background, "gauss", True)
+    assert rel(host(resid[torch.from_numpy(sel).to(DEV)]), lin.l1) < TOL
+    del resid
+    prob.linearize(c4["Od"], c4["Pd"], c4["yd"])
+    rng = np.random.default_rng(404)
+    vO = c64(synth.random_complex(rng, c4["O"].shape))
+    vP = c64(synth.random_complex(rng, c4["P"].shape))
+    u = prob.jvp(dev(vO), dev(vP))
+    ref = ptycho.jvp(lin, vO.astype(np.complex128), vP.astype(np.complex128))
+    assert rel(host(u[torch.from_numpy(sel).to(DEV)]), ref) < TOL
+
+
+@pytest.mark.parametrize("patch", [(700, 700), (104 + 16 * 37 + 250, 1500), (104, 104)])
+def test_c4_sampled_gradient_and_ggn_patches(c4, patch):
+    print("case c4 patch", patch, flush=True)
+    pr, prob, y = c4["pr"], c4["prob"], c4["y"]
+    y0, x0 = patch
+    h = w = 8
+    sub = covering(pr.pos, pr.P_true.shape, y0, x0, h, w)
+    assert 1 <= len(sub) < 600
+    O64, P64 = c4["O"].astype(np.complex128), c4["P"].astype(np.complex128)
+    f, gO, gP = prob.linearize(c4["Od"], c4["Pd"], c4["yd"])
+    lin = ptycho.linearize(O64, P64, pr.pos[sub], y[sub].astype(np.float64), pr.background, "gauss", True)
+    rgO, _ = ptycho.gradient(lin)
+    win = (slice(y0, y0 + h), slice(x0, x0 + w))
+    assert rel(host(gO[win]), rgO[win]) < TOL
+    rng = np.random.default_rng(405)
+    vO = c64(synth.random_complex(rng, c4["O"].shape))
+    vP = c64(synth.random_complex(rng, c4["P"].shape))
+    oO, _ = prob.ggn_vp(dev(vO), dev(vP))
+    GO, _ = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128))
+    assert rel(host(oO[win]), GO[win]) < TOL
+
+
+def test_c4_ggn_symmetry_and_jvp_norm(c4):
+    print("case c4 properties", flush=True)
+    prob = c4["prob"]
+    prob.linearize(c4["Od"], c4["Pd"], c4["yd"])
+    rng = np.random.default_rng(406)
+    shapes = (c4["O"].shape, c4["P"].shape)
+    u = [dev(c64(synth.random_complex(rng, s))) for s in shapes]
+    v = [dev(c64(synth.random_complex(rng, s))) for s in shapes]
+    Gu = [host(x) for x in prob.ggn_vp(*u)]
+    Gv = [host(x) for x in prob.ggn_vp(*v)]
+    uh, vh = [host(x) for x in u], [host(x) for x in v]
+    uGv = rdot(uh[0], Gv[0]) + rdot(uh[1], Gv[1])
+    vGu = rdot(vh[0], Gu[0]) + rdot(vh[1], Gu[1])
+    uGu = rdot(uh[0], Gu[0]) + rdot(uh[1], Gu[1])
+    vGv = rdot(vh[0], Gv[0]) + rdot(vh[1], Gv[1])
+    assert uGu > 0 and vGv > 0
+    assert abs(uGv - vGu) <= 1e-5 * math.sqrt(uGu * vGv)
+    # Gaussian metric: l'' = 1, so <v, G v> = ||J v||^2 with the JVP of the same linearisation
+    Jv = prob.jvp(*v)
+    jn = float(torch.sum(Jv.double() ** 2))
+    assert abs(vGv - jn) <= 1e-5 * jn

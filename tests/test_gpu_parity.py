@@ -78,10 +78,10 @@ def problem(case):
                       mode="joint" if case["joint"] else "object", background=1e-8, device=DEV)
 
 
-SHAPES = [(16, 16), (32, 32), (64, 64), (128, 128), (16, 64), (64, 32), (128, 32), (32, 128)]
+SHAPES = [(16, 16), (32, 32), (64, 64), (128, 128), (16, 64), (64, 32), (128, 32), (32, 128), (256, 256)]
 
 
-@pytest.mark.parametrize("probe", SHAPES)
+@pytest.mark.parametrize("probe", SHAPES, ids=lambda p: "%dx%d" % p)
 def test_forward_and_loss(probe):
     print("case forward", probe, flush=True)
     n = 6 if probe[0] * probe[1] >= 4096 else 7
@@ -102,7 +102,7 @@ def test_forward_and_loss(probe):
 
 @pytest.mark.parametrize("metric", ["gauss", "poisson"])
 @pytest.mark.parametrize("joint", [False, True])
-@pytest.mark.parametrize("probe", [(16, 16), (64, 64), (128, 128), (32, 64)])
+@pytest.mark.parametrize("probe", [(16, 16), (64, 64), (128, 128), (32, 64), (256, 256)], ids=lambda p: "%dx%d" % p)
 def test_linear_products(probe, joint, metric):
     print("case products", probe, joint, metric, flush=True)
     case = make_case(probe, 5, 6, max(probe) // 4, metric=metric, joint=joint, seed=3 + probe[0])
@@ -132,23 +132,28 @@ def test_linear_products(probe, joint, metric):
     assert rel(host(oO), rO) < TOL
     if joint:
         assert rel(host(oP), rP) < TOL
-    # GGN-vector product, plain and damped with a diagonal
+    # GGN-vector product, plain and damped with a diagonal.  Poisson weights l'' = 2 + 2y/h at
+    # pixels with y >= 1 and h << 1 multiply the single-precision error floor of the transform
+    # (about 1e-9 of the peak, measured equal to NumPy's single-precision FFT); at 256 x 256 and
+    # 0.03 photons per pixel the same arithmetic done with NumPy in single precision already
+    # lands at 0.7-0.9e-5 from the FP64 result, so that one case is held to 2e-5.
+    tol_g = 2 * TOL if (metric == "poisson" and probe[0] * probe[1] >= 65536) else TOL
     GO, GP = ptycho.ggn_vp(lin, vO64, vP64)
     oO, oP = prob.ggn_vp(vOd, vPd)
-    assert rel(host(oO), GO) < TOL
+    assert rel(host(oO), GO) < tol_g
     if joint:
-        assert rel(host(oP), GP) < TOL
+        assert rel(host(oP), GP) < tol_g
     lam = 0.37
     dO = rng.uniform(0.5, 2.0, case["O"].shape + (2,)).astype(np.float32)
     dP = rng.uniform(0.5, 2.0, case["P"].shape + (2,)).astype(np.float32) if joint else None
     oO, oP = prob.ggn_vp(vOd, vPd, lam=lam, dO=to_dev(dO), dP=to_dev(dP) if joint else None)
     refO = GO + lam * solver.apply_diag(dO.reshape(-1, 2).astype(np.float64), vO64.ravel()).reshape(GO.shape)
-    assert rel(host(oO), refO) < TOL
+    assert rel(host(oO), refO) < tol_g
     if joint:
         refP = GP + lam * solver.apply_diag(dP.reshape(-1, 2).astype(np.float64), vP64.ravel()).reshape(GP.shape)
-        assert rel(host(oP), refP) < TOL
+        assert rel(host(oP), refP) < tol_g
     oO, _ = prob.ggn_vp(vOd, vPd, lam=lam)
-    assert rel(host(oO), GO + lam * vO64) < TOL
+    assert rel(host(oO), GO + lam * vO64) < tol_g
     # diagonals
     dOg, dPg = prob.diag(exact=False)
     aO, aP = ptycho.ggn_diag_paper(lin)
@@ -178,9 +183,10 @@ def test_ggn_null_vector_and_determinism():
     assert float(torch.linalg.vector_norm(nO)) < 1e-5 * scale * float(torch.linalg.vector_norm(O))
 
 
-def test_segments_longer_than_one_position():
+@pytest.mark.parametrize("probe", [(128, 128), (256, 256)], ids=lambda p: "%dx%d" % p)
+def test_segments_longer_than_one_position(probe):
     """K > workgroups: each segment walks several positions (strip read-modify-write)."""
-    probe = (128, 128)
+    print("case segments", probe, flush=True)
     case = make_case(probe, 17, 19, 8, joint=True, seed=5)   # 323 positions over 256 segments
     prob = problem(case)
     O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
@@ -203,6 +209,8 @@ def test_invalid_arguments():
     assert e.value.status == pt.PTLM_EINVAL
     with pytest.raises(pt.PtlmError):
         pt.Problem(case["O"].shape, (48, 16), case["pos"], device=DEV)
+    with pytest.raises(pt.PtlmError):  # 256 only as a square probe
+        pt.Problem((300, 300), (256, 128), np.zeros((1, 2), np.int32), device=DEV)
     prob = problem(case)
     with pytest.raises(TypeError):
         prob.forward(to_dev(case["O"]).to(torch.complex128), to_dev(case["P"]))
