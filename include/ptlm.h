@@ -56,7 +56,7 @@ typedef enum {
 typedef enum { PTLM_GAUSS = 0, PTLM_POISSON = 1 } ptlm_metric; /* eq:ell_magnitude */
 typedef enum { PTLM_OBJECT = 0, PTLM_JOINT = 1 } ptlm_mode;    /* SPR eq:cdp / BPR eq:bp */
 
-/* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128, or both 256. */
+/* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128, or both 48, 96 or 256. */
 typedef struct {
   int32_t ny, nx;     /* object shape */
   int32_t my, mx;     /* probe shape */

@@ -48,7 +48,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   if (!h_pos && d->K > 0) return fail(PTLM_EINVAL, "positions are null");
   if (d->K < 1) return fail(PTLM_EINVAL, "K must be >= 1");
   if (!tile_shape_supported(d->my, d->mx))
-    return fail(PTLM_EINVAL, "probe sides must each be 16, 32, 64 or 128, or both 256");
+    return fail(PTLM_EINVAL, "probe sides must each be 16, 32, 64 or 128, or both 48, 96 or 256");
   if (d->ny < d->my || d->nx < d->mx) return fail(PTLM_EINVAL, "object smaller than probe");
   if (d->metric != PTLM_GAUSS && d->metric != PTLM_POISSON) return fail(PTLM_EINVAL, "unknown metric");
   if (d->mode != PTLM_OBJECT && d->mode != PTLM_JOINT) return fail(PTLM_EINVAL, "unknown mode");
@@ -133,10 +133,10 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
       },
       K, p.ptile_ptr, p.ptile_pos);
 
-  // twiddles W_L^(n k) = exp(-2 pi i n k / L), n < L/16, k < 16, L = 32, 64, 128, 256
-  p.tw.assign(480, make_float2(0.f, 0.f));
+  // twiddles W_L^(n k) = exp(-2 pi i n k / L), n < L/16, k < 16, L = 32, 64, 128, 256, 48, 96
+  p.tw.assign(624, make_float2(0.f, 0.f));
   int base = 0;
-  for (int L : {32, 64, 128, 256}) {
+  for (int L : {32, 64, 128, 256, 48, 96}) {
     for (int n = 0; n < L / 16; ++n)
       for (int k = 0; k < 16; ++k) {
         const double ang = -2.0 * M_PI * (double)(n * k) / (double)L;

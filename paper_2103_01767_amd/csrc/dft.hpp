@@ -1,6 +1,6 @@
 // Register-level DFT building blocks for gfx950 wavefronts.
 //
-// Small DFTs of length 2, 4, 8 and 16 on complex values held in registers,
+// Small DFTs of length 2, 3, 4, 6, 8 and 16 on complex values held in registers,
 // natural order in and out, unnormalised:
 //   forward  X[k] = sum_n x[n] exp(-2 pi i n k / R)
 //   inverse  X[k] = sum_n x[n] exp(+2 pi i n k / R)
@@ -111,11 +111,41 @@ __device__ __forceinline__ void dft16(float2* v) {
   }
 }
 
-// DFT of compile-time length R in {1, 2, 4, 8, 16} on v[0..R)
+// 3-point DFT: X1,2 = a - (b + c)/2 -+ i (sqrt(3)/2) (b - c) (forward; signs swap for inverse)
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  constexpr float H = 0.86602540378443865f;  // sqrt(3) / 2
+  const float2 s = cadd(b, c), d = csub(b, c);
+  const float2 m = make_float2(fmaf(-0.5f, s.x, a.x), fmaf(-0.5f, s.y, a.y));
+  const float2 r = rot90<INV>(make_float2(H * d.x, H * d.y));  // -+ i (sqrt(3)/2) d
+  a = cadd(a, s);
+  b = cadd(m, r);
+  c = csub(m, r);
+}
+
+// 6 = 2 x 3 (decimation in time): even and odd 3-point DFTs, then W6^k and a butterfly
+template <bool INV>
+__device__ __forceinline__ void dft6(float2* v) {
+  constexpr float H = 0.86602540378443865f;
+  float2 e0 = v[0], e1 = v[2], e2 = v[4];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5];
+  dft3<INV>(e0, e1, e2);
+  dft3<INV>(o0, o1, o2);
+  // W6^1 = 1/2 -+ i sqrt(3)/2, W6^2 = -1/2 -+ i sqrt(3)/2
+  o1 = cmul(o1, make_float2(0.5f, INV ? H : -H));
+  o2 = cmul(o2, make_float2(-0.5f, INV ? H : -H));
+  v[0] = cadd(e0, o0); v[3] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[4] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[5] = csub(e2, o2);
+}
+
+// DFT of compile-time length R in {1, 2, 3, 4, 6, 8, 16} on v[0..R)
 template <int R, bool INV>
 __device__ __forceinline__ void dftR(float2* v) {
   if constexpr (R == 2) dft2<INV>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 6) dft6<INV>(v);
   else if constexpr (R == 8) dft8<INV>(v);
   else if constexpr (R == 16) dft16<INV>(v);
 }

@@ -26,7 +26,8 @@ struct Geometry {
   int nseg;    // number of position segments (= grid * tiles per workgroup)
   int grid;    // workgroups of the tile kernels
   // constant tables in the workspace
-  const float2* tw;       // twiddles W_L^(n k), n < L/16, k < 16: L = 32, 64, 128, 256 (offsets 0, 32, 96, 224)
+  const float2* tw;       // twiddles W_L^(n k), n < L/16, k < 16: L = 32, 64, 128, 256, 48, 96
+                          // (offsets 0, 32, 96, 224, 480, 528)
   const int2* pos;        // K (row, col)
   const int* seg_start;   // nseg + 1
   const int4* seg_box;    // nseg: (row0, col0, rows, cols) of the segment's strip
@@ -69,6 +70,10 @@ size_t tile_lds_bytes(int my, int mx);
 // 256 x 256 tiles (kernels_tile256.hip): three-stage transform through Geometry::scratch
 hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
 size_t tile256_lds_bytes();
+// 48 x 48 and 96 x 96 tiles (kernels_tile3.hip): radix 16 x 3 and 16 x 6 transforms
+hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+size_t tile3_lds_bytes(int L);
+int tile3_per_wg(int L);
 
 // reductions and vector kernels (kernels_vec.hip)
 // out_O = sum of the segment strips [+ lam * dO .* vO]

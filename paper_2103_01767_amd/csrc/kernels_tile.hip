@@ -664,6 +664,7 @@ static hipError_t launch_mx(const Geometry& g, int op, const TileArgs& a, hipStr
 
 hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
   if (g.my == 256 && g.mx == 256) return launch_tile256(g, op, a, s);
+  if (g.my == g.mx && (g.my == 48 || g.my == 96)) return launch_tile3(g, op, a, s);
   switch (g.my) {
     case 16: return launch_mx<16>(g, op, a, s);
     case 32: return launch_mx<32>(g, op, a, s);
@@ -674,7 +675,9 @@ hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t
 }
 
 static bool side_ok(int m) { return m == 16 || m == 32 || m == 64 || m == 128; }
-bool tile_shape_supported(int my, int mx) { return (side_ok(my) && side_ok(mx)) || (my == 256 && mx == 256); }
+bool tile_shape_supported(int my, int mx) {
+  return (side_ok(my) && side_ok(mx)) || (my == mx && (my == 48 || my == 96 || my == 256));
+}
 
 template <int MY, int MX>
 static void cfg_of(int* wg, int* tpw, size_t* lds) {
@@ -690,6 +693,7 @@ static void cfg_dispatch(int my, int mx, int* wg, int* tpw, size_t* lds) {
   PTLM_CFG(128, 16) PTLM_CFG(128, 32) PTLM_CFG(128, 64) PTLM_CFG(128, 128)
 #undef PTLM_CFG
   if (my == 256 && mx == 256) { *wg = 1024; *tpw = 1; *lds = tile256_lds_bytes(); return; }
+  if (my == mx && (my == 48 || my == 96)) { *wg = 576; *tpw = tile3_per_wg(my); *lds = tile3_lds_bytes(my); return; }
   *wg = 0; *tpw = 0; *lds = 0;
 }
 int tile_threads(int my, int mx) { int w, t; size_t l; cfg_dispatch(my, mx, &w, &t, &l); return w; }

@@ -54,14 +54,17 @@ def test_workspace_validation():
 
 
 def test_large_probe_shapes():
-    """256 x 256 probes are planned with a per-workgroup transform tile; 256 only as a square."""
+    """48, 96 and 256 are planned as square probes only; 256 x 256 adds per-workgroup transform tiles."""
     pos = np.array([[0, 0], [16, 16], [32, 0]], np.int32)
     d = pt.ptlm_desc(300, 300, 256, 256, 3, pt.GAUSS, pt.JOINT, 1e-8)
     st, n = _ws(d, pos)
     assert st == pt.PTLM_OK
     # phasor field + probe slots + transform tiles: at least 3 * 3 tiles of 512 KiB
     assert n >= 9 * 256 * 256 * 8
-    for my, mx in ((256, 128), (128, 256), (256, 64)):
+    for side in (48, 96):
+        d1 = pt.ptlm_desc(300, 300, side, side, 3, pt.GAUSS, pt.JOINT, 1e-8)
+        assert _ws(d1, pos)[0] == pt.PTLM_OK
+    for my, mx in ((256, 128), (128, 256), (256, 64), (48, 96), (96, 32), (48, 16)):
         d2 = pt.ptlm_desc(300, 300, my, mx, 3, pt.GAUSS, pt.JOINT, 1e-8)
         assert _ws(d2, pos)[0] == pt.PTLM_EINVAL
 

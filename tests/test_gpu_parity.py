@@ -78,7 +78,8 @@ def problem(case):
                       mode="joint" if case["joint"] else "object", background=1e-8, device=DEV)
 
 
-SHAPES = [(16, 16), (32, 32), (64, 64), (128, 128), (16, 64), (64, 32), (128, 32), (32, 128), (256, 256)]
+SHAPES = [(16, 16), (32, 32), (64, 64), (128, 128), (16, 64), (64, 32), (128, 32), (32, 128), (256, 256),
+          (48, 48), (96, 96)]
 
 
 @pytest.mark.parametrize("probe", SHAPES, ids=lambda p: "%dx%d" % p)
@@ -102,7 +103,8 @@ def test_forward_and_loss(probe):
 
 @pytest.mark.parametrize("metric", ["gauss", "poisson"])
 @pytest.mark.parametrize("joint", [False, True])
-@pytest.mark.parametrize("probe", [(16, 16), (64, 64), (128, 128), (32, 64), (256, 256)], ids=lambda p: "%dx%d" % p)
+@pytest.mark.parametrize("probe", [(16, 16), (64, 64), (128, 128), (32, 64), (256, 256), (48, 48), (96, 96)],
+                         ids=lambda p: "%dx%d" % p)
 def test_linear_products(probe, joint, metric):
     print("case products", probe, joint, metric, flush=True)
     case = make_case(probe, 5, 6, max(probe) // 4, metric=metric, joint=joint, seed=3 + probe[0])
@@ -183,11 +185,12 @@ def test_ggn_null_vector_and_determinism():
     assert float(torch.linalg.vector_norm(nO)) < 1e-5 * scale * float(torch.linalg.vector_norm(O))
 
 
-@pytest.mark.parametrize("probe", [(128, 128), (256, 256)], ids=lambda p: "%dx%d" % p)
-def test_segments_longer_than_one_position(probe):
-    """K > workgroups: each segment walks several positions (strip read-modify-write)."""
-    print("case segments", probe, flush=True)
-    case = make_case(probe, 17, 19, 8, joint=True, seed=5)   # 323 positions over 256 segments
+@pytest.mark.parametrize("probe,n,step", [((128, 128), 17, 8), ((256, 256), 17, 8), ((48, 48), 48, 4),
+                                          ((96, 96), 23, 8)], ids=lambda p: "%dx%d" % p if isinstance(p, tuple) else str(p))
+def test_segments_longer_than_one_position(probe, n, step):
+    """K > segments: each segment walks several positions (strip read-modify-write)."""
+    print("case segments", probe, n, step, flush=True)
+    case = make_case(probe, n, n + 2, step, joint=True, seed=5)
     prob = problem(case)
     O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
     lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "gauss", True)
