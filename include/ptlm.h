@@ -96,6 +96,14 @@ typedef struct {
   int32_t nonfinite; /* a non-finite value was met */
   int32_t products;  /* GGN-vector products since ptlm_lm_init (PCG and warm starts) */
   int32_t attempts;  /* LM attempts (trial points) since ptlm_lm_init */
+  int32_t need_lin;  /* internal: the next attempt starts by linearising */
+  int32_t lin_now;   /* internal: the current attempt linearises */
+  int32_t use_warm;  /* internal: the current solve starts from the last accepted step */
+  int32_t alive;     /* internal: the current attempt runs (t < t_max, no numeric failure) */
+  int32_t prev_valid;/* an accepted step exists (PCG warm start) */
+  int32_t t_max;     /* outer iterations to run: INT32_MAX after ptlm_lm_init, T in batches */
+  int32_t status;    /* PTLM_OK, PTLM_ENOTACCEPTED (last outer iteration) or PTLM_ENUMERIC */
+  int32_t iter_done; /* internal: the last attempt ended an outer iteration */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;
@@ -223,6 +231,45 @@ ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_prec
  * (ptlm_cnn_workspace_bytes) stay owned by the caller and must outlive their use. */
 ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float* d_params, void* d_ws,
                             size_t ws_bytes);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched LM over independent problems of uneven sizes (a project addition: many
+ * reconstructions share the GPU; the method per problem is alg:lm_inexact unchanged).
+ * Each problem keeps its own plan, workspace region and LM state, and its handle
+ * (ptlm_batch_problem) serves every single-problem call.  One attempt of the batch launches
+ * each step of an LM attempt once for all problems (tile kernels once per probe shape
+ * present); a problem's blocks and reduction order are those it has alone, so its iterates
+ * in a batch equal those of ptlm_lm_step on it alone.
+ * ------------------------------------------------------------------------------------- */
+typedef struct ptlm_batch ptlm_batch;
+
+/* Host only.  Bytes of device workspace for n problems (descs[i], positions h_pos[i]). */
+ptlm_status ptlm_batch_workspace_bytes(int32_t n, const ptlm_desc* descs, const int32_t* const* h_pos,
+                                       size_t* bytes);
+/* Create the batch on d_ws (caller-owned, valid until ptlm_batch_destroy).  Uploads every
+ * problem's tables on `stream`.  PTLM_EINVAL names the first invalid problem. */
+ptlm_status ptlm_batch_create(int32_t n, const ptlm_desc* descs, const int32_t* const* h_pos, void* d_ws,
+                              size_t ws_bytes, void* stream, ptlm_batch** out);
+/* Handle of problem i (owned by the batch), NULL when out of range. */
+ptlm_handle* ptlm_batch_problem(ptlm_batch* b, int32_t i);
+/* Fix every problem's iterate d_O[i] / d_P[i] (updated in place), data d_y[i] and state
+ * d_states[i] (n consecutive device states), the shared LM parameters and the number T of
+ * outer iterations, and reset the states (mu = mu0, t = 0).  use_graph = 1: attempts after
+ * the first are replayed from one captured HIP graph.  With params->precond == 2 every
+ * problem needs a registered network (ptlm_lm_set_cnn on its handle).  Pointers must stay
+ * valid until the next bind or ptlm_batch_destroy. */
+ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P, const float* const* d_y,
+                            ptlm_lm_state* d_states, const ptlm_lm_params* params, int32_t T, int32_t use_graph,
+                            void* stream);
+/* Enqueue one LM attempt for every problem still running (no host synchronisation). */
+ptlm_status ptlm_batch_attempt(ptlm_batch* b, void* stream);
+/* Attempts until every problem has run T outer iterations (or met a non-finite value),
+ * reading the states every check_every attempts, at most max_attempts.  Returns PTLM_OK,
+ * PTLM_ENUMERIC (some problem failed; the others finished) or PTLM_ENOTACCEPTED (budget
+ * spent).  *attempts_done (nullable) receives the attempts enqueued. */
+ptlm_status ptlm_batch_solve(ptlm_batch* b, int32_t max_attempts, int32_t check_every, int32_t* attempts_done,
+                             void* stream);
+ptlm_status ptlm_batch_destroy(ptlm_batch* b);
 
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* ptlm_last_error(void);

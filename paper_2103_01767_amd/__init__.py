@@ -55,7 +55,7 @@ class ptlm_cnn_desc(ctypes.Structure):
 _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
                   "rz", "rr", "alpha", "beta_cg", "pap"]
 _STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
-               "attempts"]
+               "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done"]
 
 
 class ptlm_lm_state(ctypes.Structure):
@@ -93,6 +93,16 @@ _sig = {
     "ptlm_cnn_features": (ctypes.c_int, [_vp, _vp, _vp]),
     "ptlm_learned_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ptlm_lm_set_cnn": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, ctypes.c_size_t]),
+    "ptlm_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "ptlm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp, _vp, ctypes.c_size_t, _vp,
+                                         ctypes.POINTER(_vp)]),
+    "ptlm_batch_problem": (_vp, [_vp, ctypes.c_int32]),
+    "ptlm_batch_bind": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), ctypes.c_int32,
+                                       ctypes.c_int32, _vp]),
+    "ptlm_batch_attempt": (ctypes.c_int, [_vp, _vp]),
+    "ptlm_batch_solve": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
+    "ptlm_batch_destroy": (ctypes.c_int, [_vp]),
     "ptlm_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -149,33 +159,52 @@ def state_from_tensor(buf: torch.Tensor) -> ptlm_lm_state:
     return ptlm_lm_state.from_buffer_copy(raw[:STATE_BYTES])
 
 
+def _desc(obj_shape, probe_shape, K, metric, mode, background):
+    joint = mode in ("joint", JOINT)
+    return ptlm_desc(int(obj_shape[0]), int(obj_shape[1]), int(probe_shape[0]), int(probe_shape[1]), int(K),
+                     POISSON if metric in ("poisson", POISSON) else GAUSS, JOINT if joint else OBJECT,
+                     float(background))
+
+
 class Problem:
     """One ptychography problem on one GPU: handle + workspace + positions."""
 
     def __init__(self, obj_shape, probe_shape, positions, metric="gauss", mode="object",
-                 background=1e-8, device="cuda"):
+                 background=1e-8, device="cuda", _handle=None, _owner=None):
         pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
         self.obj_shape = tuple(int(v) for v in obj_shape)
         self.probe_shape = tuple(int(v) for v in probe_shape)
         self.K = int(pos.shape[0])
         self.joint = mode in ("joint", JOINT)
-        self.desc = ptlm_desc(self.obj_shape[0], self.obj_shape[1], self.probe_shape[0], self.probe_shape[1],
-                              self.K, POISSON if metric in ("poisson", POISSON) else GAUSS,
-                              JOINT if self.joint else OBJECT, float(background))
+        self.desc = _desc(obj_shape, probe_shape, self.K, metric, mode, background)
         self._pos = pos
+        self.device = torch.device(device)
+        if _handle is not None:  # a problem of a batch: the batch owns handle and workspace
+            self.handle = None
+            self._borrowed = _handle
+            self._owner = _owner
+            return
         nbytes = ctypes.c_size_t(0)
         _check(_lib.ptlm_workspace_bytes(ctypes.byref(self.desc), pos.ctypes.data_as(_vp), ctypes.byref(nbytes)))
         self.ws_bytes = int(nbytes.value)
-        self.device = torch.device(device)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
         h = _vp()
         _check(_lib.ptlm_create(ctypes.byref(self.desc), pos.ctypes.data_as(_vp), _vp(self.ws.data_ptr()),
                                 self.ws_bytes, _stream(), ctypes.byref(h)))
         self.handle = h
 
+    def __getattribute__(self, name):
+        if name == "handle":
+            b = object.__getattribute__(self, "__dict__").get("_borrowed")
+            if b is not None:
+                return b
+        return object.__getattribute__(self, name)
+
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if self.__dict__.get("_borrowed") is not None:
+            return
+        h = self.__dict__.get("handle")
+        if h is not None and h.value and _lib is not None:
             _lib.ptlm_destroy(h)
             self.handle = None
 
@@ -351,6 +380,74 @@ def lm_set_cnn(prob: "Problem", cnn: "Cnn | None"):
     _check(_lib.ptlm_lm_set_cnn(prob.handle, ctypes.byref(cnn.desc), _ptr(cnn.params, torch.float32),
                                 _vp(cnn.ws.data_ptr()), cnn.ws_bytes))
     prob._cnn = cnn  # keep the network's buffers alive while registered
+
+
+class Batch:
+    """Independent problems solved together (ptlm_batch_*): one workspace, one launch per step
+    of an LM attempt for all problems, optionally replayed from a captured HIP graph.
+
+    ``specs``: list of dicts with obj_shape, probe_shape, positions and optional metric, mode,
+    background.  ``problem(i)`` is a Problem view on the i-th handle (all single-problem calls)."""
+
+    def __init__(self, specs, device="cuda"):
+        self.device = torch.device(device)
+        self.n = len(specs)
+        self._pos = [np.ascontiguousarray(np.asarray(sp["positions"], dtype=np.int32).reshape(-1, 2))
+                     for sp in specs]
+        self.specs = specs
+        descs = (ptlm_desc * self.n)(*[
+            _desc(sp["obj_shape"], sp["probe_shape"], len(p), sp.get("metric", "gauss"), sp.get("mode", "joint"),
+                  sp.get("background", 1e-8)) for sp, p in zip(specs, self._pos)])
+        self._descs = descs
+        self._pos_ptrs = (_vp * self.n)(*[p.ctypes.data_as(_vp) for p in self._pos])
+        nb = ctypes.c_size_t(0)
+        _check(_lib.ptlm_batch_workspace_bytes(self.n, descs, self._pos_ptrs, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.ptlm_batch_create(self.n, descs, self._pos_ptrs, _vp(self.ws.data_ptr()), self.ws_bytes,
+                                      _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.problems = []
+        for i, sp in enumerate(specs):
+            ph = _vp(_lib.ptlm_batch_problem(h, i))
+            self.problems.append(Problem(sp["obj_shape"], sp["probe_shape"], self._pos[i],
+                                         sp.get("metric", "gauss"), sp.get("mode", "joint"),
+                                         sp.get("background", 1e-8), device, _handle=ph, _owner=self))
+        self.states = torch.zeros(self.n * STATE_BYTES, dtype=torch.uint8, device=self.device)
+        self._bound = None
+
+    def problem(self, i):
+        return self.problems[i]
+
+    def bind(self, Os, Ps, ys, params, T, use_graph=True):
+        pr = self.problems
+        oq = [pr[i]._o(Os[i]) for i in range(self.n)]
+        pq = [pr[i]._p(Ps[i]) for i in range(self.n)]
+        yq = [pr[i]._m(ys[i], "y") for i in range(self.n)]
+        self._bound = (list(Os), list(Ps), list(ys), params)  # keep the buffers alive
+        arr = lambda v: (_vp * self.n)(*v)
+        _check(_lib.ptlm_batch_bind(self.handle, arr(oq), arr(pq), arr(yq), _vp(self.states.data_ptr()),
+                                    ctypes.byref(params), int(T), 1 if use_graph else 0, _stream()))
+
+    def attempt(self):
+        _check(_lib.ptlm_batch_attempt(self.handle, _stream()))
+
+    def solve(self, max_attempts, check_every=4):
+        done = ctypes.c_int32(0)
+        st = _check(_lib.ptlm_batch_solve(self.handle, int(max_attempts), int(check_every), ctypes.byref(done),
+                                          _stream()), allow=(PTLM_OK, PTLM_ENOTACCEPTED, PTLM_ENUMERIC))
+        return st, int(done.value)
+
+    def state(self, i):
+        raw = self.states.detach().cpu().numpy().tobytes()
+        return ptlm_lm_state.from_buffer_copy(raw[i * STATE_BYTES:(i + 1) * STATE_BYTES])
+
+    def __del__(self):
+        h = self.__dict__.get("handle")
+        if h is not None and h.value and _lib is not None:
+            _lib.ptlm_batch_destroy(h)
+            self.handle = None
 
 
 def lib():

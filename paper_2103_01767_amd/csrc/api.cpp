@@ -244,56 +244,17 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
   return PTLM_OK;
 }
 
-}  // namespace ptlm
-
-using namespace ptlm;
-
-extern "C" {
-
-void ptlm_lm_default_params(ptlm_lm_params* p) {
-  if (!p) return;
-  p->mu0 = 1e-5;
-  p->mu_min = 1e-8;
-  p->kappa = 4.0;
-  p->nu = 1.0;
-  p->rho_min = 1e-4;
-  p->beta = 0.1;
-  p->diag_floor = 1e-6;
-  p->cg_max = 10;
-  p->retry_max = 10;
-  p->scaling = 0;
-  p->precond = 0;
-  p->warm_start = 1;
-}
-
-ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {
-  if (!bytes) return fail(PTLM_EINVAL, "bytes is null");
-  Plan p;
-  ptlm_status st = make_plan(desc, h_pos, p);
-  if (st != PTLM_OK) return st;
-  *bytes = p.ws_bytes;
-  return PTLM_OK;
-}
-
-ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes, void* stream,
-                        ptlm_handle** out) {
-  if (!out) return fail(PTLM_EINVAL, "out is null");
-  *out = nullptr;
-  ptlm_handle* h = new ptlm_handle();
+ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
+                        hipStream_t s) {
   ptlm_status st = make_plan(desc, h_pos, h->plan);
-  if (st != PTLM_OK) {
-    delete h;
-    return st;
-  }
+  if (st != PTLM_OK) return st;
   Plan& p = h->plan;
   if (!d_ws || ws_bytes < p.ws_bytes) {
-    delete h;
     char buf[128];
     snprintf(buf, sizeof buf, "workspace of %zu bytes, %zu needed", ws_bytes, p.ws_bytes);
     return fail(PTLM_EWORKSPACE, buf);
   }
   h->ws = (char*)d_ws;
-  hipStream_t s = (hipStream_t)stream;
   Geometry& g = h->g;
   const ptlm_desc& d = p.d;
   g.ny = d.ny; g.nx = d.nx; g.my = d.my; g.mx = d.mx; g.K = d.K;
@@ -341,8 +302,51 @@ ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws,
       (e = hipMemsetAsync(at(p.off.strips), 0, (size_t)p.strip_elems * sizeof(float2), s)) != hipSuccess ||
       (e = hipMemsetAsync(at(p.off.probe_part), 0, (size_t)p.nseg * d.my * d.mx * sizeof(float2), s)) !=
           hipSuccess) {
-    delete h;
     return hip_fail(e, "ptlm_create upload");
+  }
+  return PTLM_OK;
+}
+
+}  // namespace ptlm
+
+using namespace ptlm;
+
+extern "C" {
+
+void ptlm_lm_default_params(ptlm_lm_params* p) {
+  if (!p) return;
+  p->mu0 = 1e-5;
+  p->mu_min = 1e-8;
+  p->kappa = 4.0;
+  p->nu = 1.0;
+  p->rho_min = 1e-4;
+  p->beta = 0.1;
+  p->diag_floor = 1e-6;
+  p->cg_max = 10;
+  p->retry_max = 10;
+  p->scaling = 0;
+  p->precond = 0;
+  p->warm_start = 1;
+}
+
+ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {
+  if (!bytes) return fail(PTLM_EINVAL, "bytes is null");
+  Plan p;
+  ptlm_status st = make_plan(desc, h_pos, p);
+  if (st != PTLM_OK) return st;
+  *bytes = p.ws_bytes;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes, void* stream,
+                        ptlm_handle** out) {
+  if (!out) return fail(PTLM_EINVAL, "out is null");
+  *out = nullptr;
+  ptlm_handle* h = new ptlm_handle();
+  const ptlm_status st = init_handle(h, desc, h_pos, d_ws, ws_bytes, (hipStream_t)stream);
+  if (st != PTLM_OK) {
+    delete h;
+    return st;
   }
   *out = h;
   return PTLM_OK;

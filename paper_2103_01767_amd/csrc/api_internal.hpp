@@ -37,7 +37,6 @@ struct ptlm_handle {
   ptlm::Plan plan;
   ptlm::Geometry g{};
   char* ws = nullptr;
-  bool prev_valid = false;  // an accepted LM step exists (PCG warm start)
   ptlm_cnn_desc cnn{};      // registered preconditioner network (ptlm_lm_set_cnn)
   const float* cnn_params = nullptr;
   char* cnn_ws = nullptr;
@@ -55,4 +54,6 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
                       int stage = 3);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s);
 ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s);
+ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
+                        hipStream_t s);
 }  // namespace ptlm

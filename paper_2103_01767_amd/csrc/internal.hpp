@@ -61,17 +61,56 @@ struct TileArgs {
   const int* predicate;   // if non-null and *predicate == 0 the launch does nothing
 };
 
+// One problem's part of a batched launch: its geometry, its arguments and the first block
+// of the launch that belongs to it.  Blocks are dealt out in runs of whole multiples of 8
+// (one per XCD), so a problem's local block index has the XCD of the global one.
+struct TileJob {
+  Geometry g;
+  TileArgs a;
+  int block0;
+  int nblk;
+};
+
+// One problem's part of a batched reduction / diagonal launch.  For the object-side kernels a
+// job has otiles_x * otiles_y blocks, for the probe-side ones ceil(M / 64), for the partial
+// sums one.  The diagonal kernels write their (Re, Im) weights to outO / outP as floats.
+struct RedJob {
+  Geometry g;
+  float2 *outO, *outP;
+  const float2 *vO, *vP;
+  const float *dO, *dP;
+  const double* lam_dev;  // damping read from the device (null: none)
+  const int* pred;        // skip when *pred == 0
+  double* sums;           // partial-sum output (sum kernels)
+  int block0;
+  int nblk;
+};
+
+struct CopyJob {
+  const float2* src;
+  float2* dst;
+  size_t n;
+  const int* pred;
+  int block0;
+  int nblk;
+};
+
 // tile kernels (kernels_tile.hip)
 hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+// Batched launch over jobs of one probe shape: block b runs job job_of_block[b].
+hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const int* job_of_block, int nblocks,
+                             hipStream_t s);
 bool tile_shape_supported(int my, int mx);
 int tile_threads(int my, int mx);       // threads per workgroup
 int tile_per_wg(int my, int mx);        // tiles (concurrent positions) per workgroup
 size_t tile_lds_bytes(int my, int mx);
 // 256 x 256 tiles (kernels_tile256.hip): three-stage transform through Geometry::scratch
 hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+hipError_t launch_tile256_batch(int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
 size_t tile256_lds_bytes();
 // 48 x 48 and 96 x 96 tiles (kernels_tile3.hip): radix 16 x 3 and 16 x 6 transforms
 hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+hipError_t launch_tile3_batch(int L, int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
 size_t tile3_lds_bytes(int L);
 int tile3_per_wg(int L);
 
@@ -84,8 +123,19 @@ hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const 
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* predicate, hipStream_t s);
 // out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)
-hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s);
+hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s,
+                               const int* pred = nullptr);
 // paper's App. B diagonal from the stored traces
-hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s);
+hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
+// dst[i] = src[i], i < n, unless *pred == 0 (copy_blocks(n) blocks)
+hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s);
+int copy_blocks(size_t n);
+// batched forms (job tables in device memory)
+hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
+hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
+hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hipStream_t s);
+hipError_t launch_diag_paper_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
+                                   const int* prbjb, int nbp, hipStream_t s);
+hipError_t launch_copy_batch(const CopyJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
 
 }  // namespace ptlm

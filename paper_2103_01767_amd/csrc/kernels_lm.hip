@@ -3,9 +3,11 @@
 // and leave per-block FP64 partial sums; one-block finalize kernels reduce
 // them in a fixed order and run the scalar logic in FP64 (CG alpha/beta,
 // stopping test, damping lambda, forcing term eta, gain ratio rho, mu update,
-// acceptance).  Kernels inside the PCG loop read the device flag cg_active and
-// return at once when the solve has stopped, so a fixed launch sequence serves
-// every solve without host synchronisation.
+// acceptance, the end of an outer iteration).  Every launch of an LM attempt
+// can be predicated on a flag of the device state (linearising now, attempt
+// running, PCG still running, warm start, step accepted) and returns at once
+// when it is clear, so one fixed launch sequence serves every attempt of every
+// problem without host synchronisation (and can be captured in a graph).
 #include <cmath>
 
 #include "lm_internal.hpp"
@@ -42,16 +44,20 @@ __device__ __forceinline__ float2 apply_D(const LMArgs& a, size_t i, float2 v) {
   return v;
 }
 
+__device__ __forceinline__ bool flag_clear(const LMArgs& a, int flag) {
+  return flag >= 0 && reinterpret_cast<const int*>(a.st)[flag] == 0;
+}
+
 template <int OP>
-__global__ __launch_bounds__(256) void vec_kernel(LMArgs a) {
-  constexpr bool PRED = OP == V_PAP || OP == V_CG_UPDATE || OP == V_PUPDATE;
-  if (PRED && a.st->cg_active == 0) return;
+__device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int nblk) {
+  if (flag_clear(a, flag)) return;
   const double lam = a.st->lambda;
   const float alpha = (float)a.st->alpha;
   const float beta = (float)a.st->beta_cg;
+  const bool warm = a.st->use_warm != 0;
   double acc0 = 0.0, acc1 = 0.0;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+  const size_t stride = (size_t)nblk * blockDim.x;
+  for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < a.n; i += stride) {
     if constexpr (OP == V_GNORM) {
       const float2 g = a.g[i];
       acc0 += rdot(g, g);
@@ -67,7 +73,7 @@ __global__ __launch_bounds__(256) void vec_kernel(LMArgs a) {
     } else if constexpr (OP == V_CG_INIT) {
       const float2 g = a.g[i];
       float2 r;
-      if (a.use_warm) {
+      if (warm) {
         const float2 ap = a.Ap[i];
         a.dx[i] = a.prev[i];
         r = make_float2(-g.x - ap.x, -g.y - ap.y);
@@ -128,19 +134,30 @@ __global__ __launch_bounds__(256) void vec_kernel(LMArgs a) {
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      a.partials[blockIdx.x * 4 + 0] = sh[0][0];
-      a.partials[blockIdx.x * 4 + 1] = sh[0][1];
+      a.partials[bid * 4 + 0] = sh[0][0];
+      a.partials[bid * 4 + 1] = sh[0][1];
     }
   }
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void vec_kernel(LMArgs a, int flag) {
+  vec_body<OP>(a, flag, blockIdx.x, gridDim.x);
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void vec_batch_kernel(const LMJob* __restrict__ jobs,
+                                                        const int* __restrict__ job_of_block, int flag) {
+  const LMJob& J = jobs[job_of_block[blockIdx.x]];
+  vec_body<OP>(J.a, flag, (int)blockIdx.x - J.block0, J.a.vec_blocks);
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // One block: reduce `count` partials (fixed order), then run the scalar step.
 template <int OP>
-__global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
-  constexpr bool PRED = OP == F_PAP || OP == F_CG_UPDATE;
-  if (PRED && a.st->cg_active == 0) return;
+__device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
+  if (flag_clear(a, flag)) return;
   __shared__ double sh[256][2];
   double acc0 = 0.0, acc1 = 0.0;
   for (int i = threadIdx.x; i < count; i += 256) {
@@ -171,28 +188,47 @@ __global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
   const double s0 = sh[0][0], s1 = sh[0][1];
   ptlm_lm_state& st = *a.st;
   const ptlm_lm_params& p = a.prm;
-  if constexpr (OP == F_LIN) {
+  if constexpr (OP == F_ATTEMPT) {
+    // an attempt runs while the outer-iteration budget lasts and no non-finite value was met;
+    // it linearises first when the previous attempt was accepted (or at the start)
+    st.alive = (st.t < st.t_max && st.status != PTLM_ENUMERIC) ? 1 : 0;
+    st.lin_now = (st.alive && st.need_lin) ? 1 : 0;
+    if (st.alive && st.iter_done) {  // a new outer iteration starts: no rejected attempts yet
+      st.retries = 0;
+      st.iter_done = 0;
+    }
+    st.cg_active = 0;
+    st.accepted = 0;
+    st.use_warm = 0;
+  } else if constexpr (OP == F_LIN) {
     // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM
     st.f = a.scal[SC_F];
     st.resid_norm = sqrt(a.scal[SC_L1SQ]);
     st.gnorm = sqrt(s0);
     st.nonfinite = (finite_d(st.f) && finite_d(st.gnorm)) ? 0 : 1;
+    if (st.nonfinite) {
+      st.status = PTLM_ENUMERIC;
+      st.alive = 0;
+    }
+    st.need_lin = 0;
     st.retries = 0;
   } else if constexpr (OP == F_DIAGMAX) {
     a.scal[SC_DMAX_O] = s0;
     a.scal[SC_DMAX_P] = s1;
   } else if constexpr (OP == F_BEGIN) {
     // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
-    // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).
+    // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).  The first attempt
+    // of an outer iteration starts PCG from the last accepted step, a retry from zero.
     st.lambda = p.scaling ? st.mu : st.mu * pow(st.resid_norm, p.nu);
     st.eta = fmin(p.beta, sqrt(st.gnorm));
     st.cg_iters = 0;
-    st.cg_active = 1;
+    st.cg_active = 0;
     st.accepted = 0;
     st.alpha = 0.0;
     st.beta_cg = 0.0;
+    st.use_warm = (p.warm_start && st.prev_valid && st.retries == 0) ? 1 : 0;
   } else if constexpr (OP == F_CG_INIT) {
-    if (a.use_warm) st.products += 1;
+    if (st.use_warm) st.products += 1;
     st.rz = s0;
     st.rr = s1;
     st.cg_active = (p.cg_max > 0 && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
@@ -239,51 +275,101 @@ __global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count) {
       st.retries += 1;
     }
     st.cg_active = 0;
-  } else if constexpr (OP == F_STEP_END) {
-    st.t += 1;
+    if (st.accepted) {
+      // the outer iteration ends with a step; the next attempt re-linearises at z + Delta
+      st.need_lin = 1;
+      st.prev_valid = 1;
+      st.t += 1;
+      st.iter_done = 1;
+      st.status = PTLM_OK;
+    } else if (st.retries >= p.retry_max) {
+      // every retry rejected: the outer iteration ends without moving (linearisation kept)
+      st.t += 1;
+      st.iter_done = 1;
+      st.status = PTLM_ENOTACCEPTED;
+    }
   } else if constexpr (OP == F_INIT) {
     st = ptlm_lm_state{};
     st.mu = p.mu0;
+    st.need_lin = 1;
+    st.t_max = a.t_max;
+    st.status = PTLM_OK;
   }
 }
 
 template <int OP>
-static hipError_t vlaunch(const LMArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(vec_kernel<OP>, dim3(LM_BLOCKS), dim3(256), 0, s, a);
+__global__ __launch_bounds__(256) void fin_kernel(LMArgs a, int count, int flag) {
+  fin_body<OP>(a, count, flag);
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void fin_batch_kernel(const LMJob* __restrict__ jobs, int count_kind, int flag) {
+  const LMJob& J = jobs[blockIdx.x];
+  const int count = count_kind == 1 ? J.a.vec_blocks : (count_kind == 2 ? J.a.tile_grid : 0);
+  fin_body<OP>(J.a, count, flag);
+}
+
+template <int OP>
+static hipError_t vlaunch(const LMArgs& a, int flag, hipStream_t s) {
+  hipLaunchKernelGGL(vec_kernel<OP>, dim3(a.vec_blocks), dim3(256), 0, s, a, flag);
   return hipGetLastError();
 }
 template <int OP>
-static hipError_t flaunch(const LMArgs& a, int count, hipStream_t s) {
-  hipLaunchKernelGGL(fin_kernel<OP>, dim3(1), dim3(256), 0, s, a, count);
+static hipError_t flaunch(const LMArgs& a, int count, int flag, hipStream_t s) {
+  hipLaunchKernelGGL(fin_kernel<OP>, dim3(1), dim3(256), 0, s, a, count, flag);
+  return hipGetLastError();
+}
+template <int OP>
+static hipError_t vblaunch(const LMJob* jobs, const int* jb, int nb, int flag, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_batch_kernel<OP>, dim3(nb), dim3(256), 0, s, jobs, jb, flag);
+  return hipGetLastError();
+}
+template <int OP>
+static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStream_t s) {
+  if (nj <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fin_batch_kernel<OP>, dim3(nj), dim3(256), 0, s, jobs, kind, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_vec(int op, const LMArgs& a, hipStream_t s) {
+#define PTLM_VEC_CASES(X)                                                                                 \
+  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL)
+#define PTLM_FIN_CASES(X)                                                                                 \
+  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
+  X(F_INIT)
+
+hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s) {
   switch (op) {
-    case V_GNORM: return vlaunch<V_GNORM>(a, s);
-    case V_DIAGMAX: return vlaunch<V_DIAGMAX>(a, s);
-    case V_DIAGFLOOR: return vlaunch<V_DIAGFLOOR>(a, s);
-    case V_CG_INIT: return vlaunch<V_CG_INIT>(a, s);
-    case V_PAP: return vlaunch<V_PAP>(a, s);
-    case V_CG_UPDATE: return vlaunch<V_CG_UPDATE>(a, s);
-    case V_PUPDATE: return vlaunch<V_PUPDATE>(a, s);
-    case V_TRIAL: return vlaunch<V_TRIAL>(a, s);
+#define C_(OP) case OP: return vlaunch<OP>(a, flag, s);
+    PTLM_VEC_CASES(C_)
+#undef C_
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fin(int op, const LMArgs& a, int count, hipStream_t s) {
+hipError_t launch_fin(int op, const LMArgs& a, int count, int flag, hipStream_t s) {
   switch (op) {
-    case F_LIN: return flaunch<F_LIN>(a, count, s);
-    case F_DIAGMAX: return flaunch<F_DIAGMAX>(a, count, s);
-    case F_BEGIN: return flaunch<F_BEGIN>(a, count, s);
-    case F_CG_INIT: return flaunch<F_CG_INIT>(a, count, s);
-    case F_PAP: return flaunch<F_PAP>(a, count, s);
-    case F_CG_UPDATE: return flaunch<F_CG_UPDATE>(a, count, s);
-    case F_PRED: return flaunch<F_PRED>(a, count, s);
-    case F_TRIAL_END: return flaunch<F_TRIAL_END>(a, count, s);
-    case F_STEP_END: return flaunch<F_STEP_END>(a, count, s);
-    case F_INIT: return flaunch<F_INIT>(a, count, s);
+#define C_(OP) case OP: return flaunch<OP>(a, count, flag, s);
+    PTLM_FIN_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* jb, int nb, int flag, hipStream_t s) {
+  switch (op) {
+#define C_(OP) case OP: return vblaunch<OP>(jobs, jb, nb, flag, s);
+    PTLM_VEC_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fin_batch(int op, const LMJob* jobs, int nj, int kind, int flag, hipStream_t s) {
+  switch (op) {
+#define C_(OP) case OP: return fblaunch<OP>(jobs, nj, kind, flag, s);
+    PTLM_FIN_CASES(C_)
+#undef C_
     default: return hipErrorInvalidValue;
   }
 }

@@ -84,7 +84,7 @@ __device__ __forceinline__ double tile_sum(double x, double* red, int col, int s
 }
 
 template <int MY, int MX, int OP>
-__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
+__device__ __forceinline__ void tile_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
   using C = Cfg<MY, MX>;
   constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
   constexpr bool FWD_FFT = OP != OP_VJP;
@@ -102,7 +102,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x % NT;
   float2* lds = smem + slot * C::TILE;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int blk = xcd_block(bid, nblk);
   const int seg = blk * C::TPW + slot;
   const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
   int maxlen = 0;
@@ -605,12 +605,27 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, Til
         a0 += red[w * 2];
         a1 += red[w * 2 + 1];
       }
-      g.partials[blockIdx.x * 4 + 0] = a0;
-      g.partials[blockIdx.x * 4 + 1] = a1;
-      g.partials[blockIdx.x * 4 + 2] = 0.0;
-      g.partials[blockIdx.x * 4 + 3] = 0.0;
+      g.partials[bid * 4 + 0] = a0;
+      g.partials[bid * 4 + 1] = a1;
+      g.partials[bid * 4 + 2] = 0.0;
+      g.partials[bid * 4 + 3] = 0.0;
     }
   }
+}
+
+template <int MY, int MX, int OP>
+__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
+  tile_body<MY, MX, OP>(g, a, blockIdx.x, gridDim.x);
+}
+
+// batched: block b belongs to job job_of_block[b]; trailing blocks of a job's run exit
+template <int MY, int MX, int OP>
+__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_batch_kernel(const TileJob* __restrict__ jobs,
+                                                                       const int* __restrict__ job_of_block) {
+  const TileJob& J = jobs[job_of_block[blockIdx.x]];
+  const int b = (int)blockIdx.x - J.block0;
+  if (b >= J.g.grid) return;
+  tile_body<MY, MX, OP>(J.g, J.a, b, J.g.grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,6 +650,32 @@ static hipError_t launch_one(const Geometry& g, const TileArgs& a, hipStream_t s
   }
   hipLaunchKernelGGL((tile_kernel<MY, MX, OP>), dim3(g.grid), dim3(C::WG), lds, s, g, a);
   return hipGetLastError();
+}
+
+template <int MY, int MX, int OP>
+static hipError_t launch_one_batch(const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s) {
+  using C = Cfg<MY, MX>;
+  const size_t lds = lds_bytes<MY, MX>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile_batch_kernel<MY, MX, OP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile_batch_kernel<MY, MX, OP>), dim3(nblocks), dim3(C::WG), lds, s, jobs, job_of_block);
+  return hipGetLastError();
+}
+
+// the batched LM attempt uses the linearisation, the GGN-vector product and the trial loss
+template <int MY, int MX>
+static hipError_t launch_op_batch(int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  switch (op) {
+    case OP_LOSS: return launch_one_batch<MY, MX, OP_LOSS>(jobs, jb, nb, s);
+    case OP_LINEARIZE: return launch_one_batch<MY, MX, OP_LINEARIZE>(jobs, jb, nb, s);
+    case OP_GGNV: return launch_one_batch<MY, MX, OP_GGNV>(jobs, jb, nb, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int MY, int MX>
@@ -672,6 +713,19 @@ hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t
     case 128: return launch_mx<128>(g, op, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (my == 256 && mx == 256) return launch_tile256_batch(op, jobs, jb, nb, s);
+  if (my == mx && (my == 48 || my == 96)) return launch_tile3_batch(my, op, jobs, jb, nb, s);
+#define PTLM_B(A, B) if (my == A && mx == B) return launch_op_batch<A, B>(op, jobs, jb, nb, s);
+  PTLM_B(16, 16) PTLM_B(16, 32) PTLM_B(16, 64) PTLM_B(16, 128)
+  PTLM_B(32, 16) PTLM_B(32, 32) PTLM_B(32, 64) PTLM_B(32, 128)
+  PTLM_B(64, 16) PTLM_B(64, 32) PTLM_B(64, 64) PTLM_B(64, 128)
+  PTLM_B(128, 16) PTLM_B(128, 32) PTLM_B(128, 64) PTLM_B(128, 128)
+#undef PTLM_B
+  return hipErrorInvalidValue;
 }
 
 static bool side_ok(int m) { return m == 16 || m == 32 || m == 64 || m == 128; }

@@ -66,7 +66,7 @@ __device__ __forceinline__ double wg_sum(double x, double* red, int col) {
 }  // namespace
 
 template <int OP>
-__global__ __launch_bounds__(WG) void tile256_kernel(Geometry g, TileArgs a) {
+__device__ __forceinline__ void tile256_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
   constexpr bool FWD_FFT = OP != OP_VJP;
   constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
@@ -82,9 +82,9 @@ __global__ __launch_bounds__(WG) void tile256_kernel(Geometry g, TileArgs a) {
   const int t = threadIdx.x;
   const int rr = t >> 4, rc = t & 15;  // row stages: row in block, residue / frequency index
   const int cc = t & 63, cs = t >> 6;  // column stage: column in block, residue / frequency index
-  const int seg = xcd_map(blockIdx.x, gridDim.x);
+  const int seg = xcd_map(bid, nblk);
   const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
-  float2* scr = g.scratch + (size_t)blockIdx.x * M256;
+  float2* scr = g.scratch + (size_t)bid * M256;
   float2* lrow = smem + rr * LDR;
   const float isq = 1.0f / 256.0f;
   const bool joint = g.joint != 0;
@@ -383,12 +383,26 @@ __global__ __launch_bounds__(WG) void tile256_kernel(Geometry g, TileArgs a) {
         a0 += red[w * 2];
         a1 += red[w * 2 + 1];
       }
-      g.partials[blockIdx.x * 4 + 0] = a0;
-      g.partials[blockIdx.x * 4 + 1] = a1;
-      g.partials[blockIdx.x * 4 + 2] = 0.0;
-      g.partials[blockIdx.x * 4 + 3] = 0.0;
+      g.partials[bid * 4 + 0] = a0;
+      g.partials[bid * 4 + 1] = a1;
+      g.partials[bid * 4 + 2] = 0.0;
+      g.partials[bid * 4 + 3] = 0.0;
     }
   }
+}
+
+template <int OP>
+__global__ __launch_bounds__(WG) void tile256_kernel(Geometry g, TileArgs a) {
+  tile256_body<OP>(g, a, blockIdx.x, gridDim.x);
+}
+
+template <int OP>
+__global__ __launch_bounds__(WG) void tile256_batch_kernel(const TileJob* __restrict__ jobs,
+                                                           const int* __restrict__ job_of_block) {
+  const TileJob& J = jobs[job_of_block[blockIdx.x]];
+  const int b = (int)blockIdx.x - J.block0;
+  if (b >= J.g.grid) return;
+  tile256_body<OP>(J.g, J.a, b, J.g.grid);
 }
 
 size_t tile256_lds_bytes() { return (size_t)LDS_C * sizeof(float2) + NWAVE * 2 * sizeof(double) + 256 * sizeof(float2); }
@@ -406,6 +420,29 @@ static hipError_t launch256(const Geometry& g, const TileArgs& a, hipStream_t s)
   }
   hipLaunchKernelGGL((tile256_kernel<OP>), dim3(g.grid), dim3(WG), lds, s, g, a);
   return hipGetLastError();
+}
+
+template <int OP>
+static hipError_t launch256_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  const size_t lds = tile256_lds_bytes();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile256_batch_kernel<OP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile256_batch_kernel<OP>), dim3(nb), dim3(WG), lds, s, jobs, jb);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile256_batch(int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  switch (op) {
+    case OP_LOSS: return launch256_batch<OP_LOSS>(jobs, jb, nb, s);
+    case OP_LINEARIZE: return launch256_batch<OP_LINEARIZE>(jobs, jb, nb, s);
+    case OP_GGNV: return launch256_batch<OP_GGNV>(jobs, jb, nb, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {

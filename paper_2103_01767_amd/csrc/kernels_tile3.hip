@@ -38,7 +38,7 @@ __device__ __forceinline__ int xcd_map3(int b, int n) {
 }  // namespace
 
 template <int L, int OP>
-__global__ __launch_bounds__(576) void tile3_kernel(Geometry g, TileArgs a) {
+__device__ __forceinline__ void tile3_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
   using C = Cfg3<L>;
   constexpr int R = C::R, NT = C::NT, LDX = C::LDX, GMAX = C::GMAX;
   constexpr bool FWD_FFT = OP != OP_VJP;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(576) void tile3_kernel(Geometry g, TileArgs a) {
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x % NT;
   float2* lds = smem + slot * C::TILE;
-  const int blk = xcd_map3(blockIdx.x, gridDim.x);
+  const int blk = xcd_map3(bid, nblk);
   const int seg = blk * C::TPW + slot;
   const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
   int maxlen = 0;
@@ -386,12 +386,26 @@ __global__ __launch_bounds__(576) void tile3_kernel(Geometry g, TileArgs a) {
         a0 += red[w * 2];
         a1 += red[w * 2 + 1];
       }
-      g.partials[blockIdx.x * 4 + 0] = a0;
-      g.partials[blockIdx.x * 4 + 1] = a1;
-      g.partials[blockIdx.x * 4 + 2] = 0.0;
-      g.partials[blockIdx.x * 4 + 3] = 0.0;
+      g.partials[bid * 4 + 0] = a0;
+      g.partials[bid * 4 + 1] = a1;
+      g.partials[bid * 4 + 2] = 0.0;
+      g.partials[bid * 4 + 3] = 0.0;
     }
   }
+}
+
+template <int L, int OP>
+__global__ __launch_bounds__(576) void tile3_kernel(Geometry g, TileArgs a) {
+  tile3_body<L, OP>(g, a, blockIdx.x, gridDim.x);
+}
+
+template <int L, int OP>
+__global__ __launch_bounds__(576) void tile3_batch_kernel(const TileJob* __restrict__ jobs,
+                                                          const int* __restrict__ job_of_block) {
+  const TileJob& J = jobs[job_of_block[blockIdx.x]];
+  const int b = (int)blockIdx.x - J.block0;
+  if (b >= J.g.grid) return;
+  tile3_body<L, OP>(J.g, J.a, b, J.g.grid);
 }
 
 template <int L>
@@ -430,6 +444,36 @@ static hipError_t launch3_op(const Geometry& g, int op, const TileArgs& a, hipSt
     case OP_DIAG_EXACT: return launch3<L, OP_DIAG_EXACT>(g, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int L, int OP>
+static hipError_t launch3_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  const size_t lds = tile3_lds<L>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile3_batch_kernel<L, OP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile3_batch_kernel<L, OP>), dim3(nb), dim3(576), lds, s, jobs, jb);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch3_op_batch(int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  switch (op) {
+    case OP_LOSS: return launch3_batch<L, OP_LOSS>(jobs, jb, nb, s);
+    case OP_LINEARIZE: return launch3_batch<L, OP_LINEARIZE>(jobs, jb, nb, s);
+    case OP_GGNV: return launch3_batch<L, OP_GGNV>(jobs, jb, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile3_batch(int L, int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (L == 48) return launch3_op_batch<48>(op, jobs, jb, nb, s);
+  if (L == 96) return launch3_op_batch<96>(op, jobs, jb, nb, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {

@@ -11,16 +11,16 @@ namespace ptlm {
 // One block per 16x16 object tile: the tile's segment list (boxes, offsets) is staged in
 // LDS, then every thread sums its pixel over the list with independent loads.
 constexpr int OBJ_LIST = 256;
-__global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
-                                                         const float* d, const float2* v, const int* pred) {
+__device__ __forceinline__ void obj_reduce_body(const Geometry& g, float2* out, float lam_h, const double* lam_dev,
+                                                const float* d, const float2* v, const int* pred, int bx, int by) {
   if (pred && *pred == 0) return;
   __shared__ int4 s_box[OBJ_LIST];
   __shared__ long long s_off[OBJ_LIST];
   const float lam = lam_dev ? (float)*lam_dev : lam_h;
-  const int X = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int Y = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int X = bx * 16 + (threadIdx.x & 15);
+  const int Y = by * 16 + (threadIdx.x >> 4);
   const bool in = X < g.nx && Y < g.ny;
-  const int tile = blockIdx.y * g.otiles_x + blockIdx.x;
+  const int tile = by * g.otiles_x + bx;
   const int b = g.otile_ptr[tile], e = g.otile_ptr[tile + 1];
   float2 acc = make_float2(0.f, 0.f);
   for (int c0 = b; c0 < e; c0 += OBJ_LIST) {
@@ -68,16 +68,28 @@ __global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out
   out[n] = acc;
 }
 
+__global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
+                                                         const float* d, const float2* v, const int* pred) {
+  obj_reduce_body(g, out, lam_h, lam_dev, d, v, pred, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void obj_reduce_batch_kernel(const RedJob* __restrict__ jobs,
+                                                               const int* __restrict__ job_of_block) {
+  const RedJob& J = jobs[job_of_block[blockIdx.x]];
+  const int l = (int)blockIdx.x - J.block0;
+  obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
+}
+
 // out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v]; 64 pixels per block, the segment
 // sum split four ways and combined in LDS in a fixed order.
-__global__ __launch_bounds__(256) void probe_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
-                                                           const float* d, const float2* v, const int* pred) {
+__device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out, float lam_h, const double* lam_dev,
+                                                  const float* d, const float2* v, const int* pred, int bx) {
   if (pred && *pred == 0) return;
   __shared__ float2 sh[4][64];
   const float lam = lam_dev ? (float)*lam_dev : lam_h;
   const int M = g.my * g.mx;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int m = blockIdx.x * 64 + lane;
+  const int m = bx * 64 + lane;
   float2 acc = make_float2(0.f, 0.f);
   if (m < M) {
     const float2* p = g.probe_part + m;
@@ -105,9 +117,19 @@ __global__ __launch_bounds__(256) void probe_reduce_kernel(Geometry g, float2* o
   out[m] = acc;
 }
 
+__global__ __launch_bounds__(256) void probe_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
+                                                           const float* d, const float2* v, const int* pred) {
+  probe_reduce_body(g, out, lam_h, lam_dev, d, v, pred, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void probe_reduce_batch_kernel(const RedJob* __restrict__ jobs,
+                                                                 const int* __restrict__ job_of_block) {
+  const RedJob& J = jobs[job_of_block[blockIdx.x]];
+  probe_reduce_body(J.g, J.outP, 0.f, J.lam_dev, J.dP, J.vP, J.pred, (int)blockIdx.x - J.block0);
+}
+
 // out[j] = sum_i partials[i*4 + j], j < nout, fixed-order tree
-__global__ __launch_bounds__(256) void sum_partials_kernel(const double* partials, int count, double* out,
-                                                           int nout) {
+__device__ __forceinline__ void sum_partials_body(const double* partials, int count, double* out, int nout) {
   __shared__ double sh[256][4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < count; i += 256)
@@ -122,15 +144,28 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* partial
   if (threadIdx.x < nout) out[threadIdx.x] = sh[0][threadIdx.x];
 }
 
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* partials, int count, double* out,
+                                                           int nout, const int* pred) {
+  if (pred && *pred == 0) return;
+  sum_partials_body(partials, count, out, nout);
+}
+
+// one block per job: the tile kernel's partials of that problem
+__global__ __launch_bounds__(256) void sum_partials_batch_kernel(const RedJob* __restrict__ jobs, int nout) {
+  const RedJob& J = jobs[blockIdx.x];
+  if (J.pred && *J.pred == 0) return;
+  sum_partials_body(J.g.partials, J.g.grid, J.sums, nout);
+}
+
 // App. B diagonal, object part: d_n = (1/2M) sum_{k covering n} trace_k |P[n - r_k]|^2,
 // the same weight for the Re and Im coordinates.  The tile's position list is staged in LDS.
-__global__ __launch_bounds__(256) void diag_paper_obj_kernel(Geometry g, float* dO) {
+__device__ __forceinline__ void diag_paper_obj_body(const Geometry& g, float* dO, int bx, int by) {
   __shared__ int2 s_pos[OBJ_LIST];
   __shared__ double s_tr[OBJ_LIST];
-  const int X = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int Y = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int X = bx * 16 + (threadIdx.x & 15);
+  const int Y = by * 16 + (threadIdx.x >> 4);
   const bool in = X < g.nx && Y < g.ny;
-  const int tile = blockIdx.y * g.otiles_x + blockIdx.x;
+  const int tile = by * g.otiles_x + bx;
   const int b = g.ptile_ptr[tile], e = g.ptile_ptr[tile + 1];
   double acc = 0.0;
   for (int c0 = b; c0 < e; c0 += OBJ_LIST) {
@@ -161,13 +196,26 @@ __global__ __launch_bounds__(256) void diag_paper_obj_kernel(Geometry g, float* 
   dO[2 * n + 1] = val;
 }
 
+__global__ __launch_bounds__(256) void diag_paper_obj_kernel(Geometry g, float* dO, const int* pred) {
+  if (pred && *pred == 0) return;
+  diag_paper_obj_body(g, dO, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void diag_paper_obj_batch_kernel(const RedJob* __restrict__ jobs,
+                                                                   const int* __restrict__ job_of_block) {
+  const RedJob& J = jobs[job_of_block[blockIdx.x]];
+  if (J.pred && *J.pred == 0) return;
+  const int l = (int)blockIdx.x - J.block0;
+  diag_paper_obj_body(J.g, (float*)J.outO, l % J.g.otiles_x, l / J.g.otiles_x);
+}
+
 // App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; 64 pixels per
 // block, the position sum split four ways and combined in a fixed order.
-__global__ __launch_bounds__(256) void diag_paper_probe_kernel(Geometry g, float* dP) {
+__device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* dP, int bx) {
   __shared__ double sh[4][64];
   const int M = g.my * g.mx;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int m = blockIdx.x * 64 + lane;
+  const int m = bx * 64 + lane;
   double acc = 0.0;
   if (m < M) {
     const int my = m / g.mx, mx = m % g.mx;
@@ -187,6 +235,64 @@ __global__ __launch_bounds__(256) void diag_paper_probe_kernel(Geometry g, float
   dP[2 * m + 1] = val;
 }
 
+__global__ __launch_bounds__(256) void diag_paper_probe_kernel(Geometry g, float* dP, const int* pred) {
+  if (pred && *pred == 0) return;
+  diag_paper_probe_body(g, dP, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const float2* __restrict__ src, float2* __restrict__ dst, size_t n,
+                                                   const int* pred) {
+  if (pred && *pred == 0) return;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void diag_paper_probe_batch_kernel(const RedJob* __restrict__ jobs,
+                                                                     const int* __restrict__ job_of_block) {
+  const RedJob& J = jobs[job_of_block[blockIdx.x]];
+  if (J.pred && *J.pred == 0) return;
+  diag_paper_probe_body(J.g, (float*)J.outP, (int)blockIdx.x - J.block0);
+}
+
+// predicated batched copies: block b copies part of job job_of_block[b]
+__global__ __launch_bounds__(256) void copy_batch_kernel(const CopyJob* __restrict__ jobs,
+                                                         const int* __restrict__ job_of_block) {
+  const CopyJob& J = jobs[job_of_block[blockIdx.x]];
+  if (J.pred && *J.pred == 0) return;
+  const size_t stride = (size_t)J.nblk * 256;
+  for (size_t i = (size_t)((int)blockIdx.x - J.block0) * 256 + threadIdx.x; i < J.n; i += stride)
+    J.dst[i] = J.src[i];
+}
+
+hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(obj_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
+  return hipGetLastError();
+}
+hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(probe_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
+  return hipGetLastError();
+}
+hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_partials_batch_kernel, dim3(njobs), dim3(256), 0, s, jobs, nout);
+  return hipGetLastError();
+}
+hipError_t launch_diag_paper_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
+                                   const int* prbjb, int nbp, hipStream_t s) {
+  if (nbo > 0) hipLaunchKernelGGL(diag_paper_obj_batch_kernel, dim3(nbo), dim3(256), 0, s, objjobs, objjb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nbp <= 0) return e;
+  hipLaunchKernelGGL(diag_paper_probe_batch_kernel, dim3(nbp), dim3(256), 0, s, prbjobs, prbjb);
+  return hipGetLastError();
+}
+hipError_t launch_copy_batch(const CopyJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
+  return hipGetLastError();
+}
+
 hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const double* lam_dev, const float* dO,
                              const float2* vO, const int* pred, hipStream_t s) {
   hipLaunchKernelGGL(obj_reduce_kernel, dim3(g.otiles_x, g.otiles_y), dim3(256), 0, s, g, outO, (float)lam, lam_dev,
@@ -202,17 +308,28 @@ hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, cons
   return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, count, out, nout);
+hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s,
+                               const int* pred) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, count, out, nout, pred);
   return hipGetLastError();
 }
 
-hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s) {
-  hipLaunchKernelGGL(diag_paper_obj_kernel, dim3(g.otiles_x, g.otiles_y), dim3(256), 0, s, g, dO);
+hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred) {
+  hipLaunchKernelGGL(diag_paper_obj_kernel, dim3(g.otiles_x, g.otiles_y), dim3(256), 0, s, g, dO, pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !dP) return e;
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, dP);
+  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, dP, pred);
+  return hipGetLastError();
+}
+
+int copy_blocks(size_t n) {
+  const size_t b = (n + 2047) / 2048;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(copy_blocks(n)), dim3(256), 0, s, src, dst, n, pred);
   return hipGetLastError();
 }
 

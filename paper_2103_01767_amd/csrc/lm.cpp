@@ -1,20 +1,21 @@
-// Host driver of the truncated LM iteration (alg:lm_inexact).
+// Host driver of the truncated LM iteration (alg:lm_inexact) for one problem.
 //
-// One outer iteration: linearise (f, g, weighted phasors, D), then attempts.
-// Each attempt is a fixed launch sequence -- lambda/eta, PCG start, cg_max
-// predicated PCG iterations, trial point, trial loss, gain ratio and damping
-// update -- followed by one stream synchronisation to read the acceptance flag.
-// All scalars of the method live in FP64 in the device state.
+// An outer iteration is a sequence of attempts; each attempt is the fixed launch sequence of
+// lm_attempt.hpp (linearise when the previous attempt was accepted, lambda/eta, PCG start,
+// cg_max predicated PCG iterations, trial point, trial loss, gain ratio and damping update,
+// accept copies), followed by one stream synchronisation to read the device state.  All
+// scalars of the method live in FP64 in the device state.
+#include <climits>
 #include <cmath>
 #include <cstring>
 
 #include "api_internal.hpp"
-#include "lm_internal.hpp"
+#include "lm_attempt.hpp"
 
 namespace ptlm {
 
-static LMArgs make_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st, const float2* O,
-                        const float2* P, const float* learned) {
+LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st, const float2* O,
+                    const float2* P, const float* learned) {
   Plan& p = h->plan;
   auto at = [&](size_t o) { return (float2*)(h->ws + o); };
   LMArgs a{};
@@ -33,10 +34,12 @@ static LMArgs make_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state
   a.n = p.nvec;
   a.nobj = (size_t)p.d.ny * p.d.nx;
   a.st = st;
-  a.prm = *prm;
+  if (prm) a.prm = *prm;
   a.partials = h->g.partials;
   a.scal = (double*)(h->ws + p.off.scal);
-  a.use_warm = 0;
+  a.vec_blocks = lm_vec_blocks(a.n);
+  a.tile_grid = h->g.grid;
+  a.t_max = INT_MAX;
   return a;
 }
 
@@ -46,7 +49,7 @@ static LMArgs make_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
-static ptlm_status check_params(const ptlm_lm_params* p) {
+ptlm_status check_lm_params(const ptlm_lm_params* p) {
   if (!p) return fail(PTLM_EINVAL, "params is null");
   if (!(p->mu0 > 0) || !(p->mu_min > 0) || !(p->kappa > 1) || !(p->nu >= 0) || !(p->rho_min > 0) ||
       !(p->beta > 0) || !(p->diag_floor >= 0) || p->cg_max < 0 || p->retry_max < 1 ||
@@ -55,87 +58,118 @@ static ptlm_status check_params(const ptlm_lm_params* p) {
   return PTLM_OK;
 }
 
-// One GGN-vector product with the damping term lambda D read from the device state.
-static ptlm_status ggnv_lm(ptlm_handle* h, const LMArgs& a, const float2* v, float2* out, const int* pred,
-                           hipStream_t s) {
-  const size_t N = a.nobj;
-  const float* dO = a.prm.scaling ? (const float*)a.diag : nullptr;
-  const float* dP = a.prm.scaling ? (const float*)(a.diag + N) : nullptr;
-  return ggnv_impl(h, v, h->g.joint ? v + N : nullptr, 0.0, &a.st->lambda, dO, dP, out,
-                   h->g.joint ? out + N : nullptr, pred, s);
+// Launches of one attempt for a single problem, with its arguments passed directly.
+struct SingleOps {
+  ptlm_handle* h;
+  LMArgs a;
+  float2* O;
+  float2* P;
+  const float* y;
+  const float* user_learned;  // caller's learned diagonal (precond 2 without a network)
+  bool lin_expected;          // host view: this attempt linearises (network refresh)
+  hipStream_t s;
+
+  int* flag(int f) const { return reinterpret_cast<int*>(a.st) + f; }
+
+  ptlm_status fin(int op, int kind, int fl) {
+    const int count = kind == 1 ? a.vec_blocks : (kind == 2 ? a.tile_grid : 0);
+    LM_HIP(launch_fin(op, a, count, fl, s), "lm finalize");
+    return PTLM_OK;
+  }
+  ptlm_status vec(int op, int fl) {
+    LM_HIP(launch_vec(op, a, fl, s), "lm vector");
+    return PTLM_OK;
+  }
+  ptlm_status copy_lin() {
+    Geometry& g = h->g;
+    LM_HIP(launch_copy(O, g.O_lin, (size_t)g.ny * g.nx, flag(FL_LIN), s), "lm copy O");
+    LM_HIP(launch_copy(P, g.P_lin, (size_t)g.my * g.mx, flag(FL_LIN), s), "lm copy P");
+    return PTLM_OK;
+  }
+  ptlm_status linearize() {
+    Geometry& g = h->g;
+    TileArgs ta{};
+    ta.O = g.O_lin;
+    ta.P = g.P_lin;
+    ta.y = y;
+    ta.predicate = flag(FL_LIN);
+    LM_HIP(launch_tile(g, OP_LINEARIZE, ta, s), "lm linearize");
+    LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_LIN)), "lm linearize sum");
+    LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_LIN), s), "lm gradient O");
+    if (g.joint)
+      LM_HIP(launch_probe_reduce(g, a.g + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_LIN), s), "lm gradient P");
+    return PTLM_OK;
+  }
+  ptlm_status diag_paper() {
+    Geometry& g = h->g;
+    LM_HIP(launch_diag_paper(g, (float*)a.diag, g.joint ? (float*)(a.diag + a.nobj) : nullptr, s, flag(FL_LIN)),
+           "lm diag");
+    return PTLM_OK;
+  }
+  ptlm_status learned() {
+    if (h->cnn_params) {
+      float2* lbuf = (float2*)(h->ws + h->plan.off.learned);
+      if (lin_expected) {
+        const ptlm_status st = learned_from_cnn(h, (float*)lbuf, s);
+        if (st != PTLM_OK) return st;
+      }
+      a.learned = lbuf;
+    } else {
+      a.learned = (const float2*)user_learned;
+    }
+    return PTLM_OK;
+  }
+  ptlm_status ggnv(int which) {
+    const float2* v = which == GG_WARM ? a.prev : a.p;
+    const int* pred = which == GG_WARM ? flag(FL_WARM) : flag(FL_CG);
+    const size_t N = a.nobj;
+    const float* dO = a.prm.scaling ? (const float*)a.diag : nullptr;
+    const float* dP = a.prm.scaling ? (const float*)(a.diag + N) : nullptr;
+    return ggnv_impl(h, v, h->g.joint ? v + N : nullptr, 0.0, &a.st->lambda, dO, dP, a.Ap,
+                     h->g.joint ? a.Ap + N : nullptr, pred, s);
+  }
+  ptlm_status trial_loss() {
+    Geometry& g = h->g;
+    TileArgs ta{};
+    ta.O = a.ztrial;
+    ta.P = g.joint ? a.ztrial + a.nobj : P;
+    ta.y = y;
+    ta.predicate = flag(FL_ALIVE);
+    LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
+    return PTLM_OK;
+  }
+  ptlm_status copy_accept() {
+    Geometry& g = h->g;
+    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_ACCEPTED), s), "lm accept O");
+    if (g.joint) LM_HIP(launch_copy(a.ztrial + a.nobj, P, (size_t)g.my * g.mx, flag(FL_ACCEPTED), s), "lm accept P");
+    LM_HIP(launch_copy(a.dx, a.prev, a.n, flag(FL_ACCEPTED), s), "lm keep step");
+    return PTLM_OK;
+  }
+};
+
+static ptlm_status read_state(ptlm_lm_state* d, ptlm_lm_state* hs, hipStream_t s) {
+  LM_HIP(hipMemcpyAsync(hs, d, sizeof *hs, hipMemcpyDeviceToHost, s), "lm read state");
+  LM_HIP(hipStreamSynchronize(s), "lm sync");
+  return PTLM_OK;
 }
 
 static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const float* y, const ptlm_lm_params* prm,
                                 ptlm_lm_state* st, const float* learned, hipStream_t s) {
-  Geometry& g = h->g;
-  LMArgs a = make_args(h, prm, st, O, P, learned);
-  const size_t N = a.nobj, M = (size_t)g.my * g.mx;
-  // ---- linearisation of the outer iteration (reused by every retry)
-  ptlm_status stt = linearize_impl(h, O, P, y, a.scal + SC_F, a.g, g.joint ? a.g + N : nullptr, s);
-  if (stt != PTLM_OK) return stt;
-  LM_HIP(launch_vec(V_GNORM, a, s), "lm gnorm");
-  LM_HIP(launch_fin(F_LIN, a, LM_BLOCKS, s), "lm lin");
-  if (prm->scaling == 1 || prm->precond == 1) {
-    LM_HIP(launch_diag_paper(g, (float*)a.diag, g.joint ? (float*)(a.diag + N) : nullptr, s), "lm diag");
-    LM_HIP(launch_vec(V_DIAGMAX, a, s), "lm diag max");
-    LM_HIP(launch_fin(F_DIAGMAX, a, LM_BLOCKS, s), "lm diag max fin");
-    LM_HIP(launch_vec(V_DIAGFLOOR, a, s), "lm diag floor");
-  }
-  if (prm->precond == 2 && h->cnn_params) {
-    float2* lbuf = (float2*)(h->ws + h->plan.off.learned);
-    stt = learned_from_cnn(h, (float*)lbuf, s);
-    if (stt != PTLM_OK) return stt;
-    a.learned = lbuf;
-  }
   ptlm_lm_state hs;
-  LM_HIP(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "lm read state");
-  LM_HIP(hipStreamSynchronize(s), "lm sync");
-  if (hs.nonfinite) {
-    LM_HIP(launch_fin(F_STEP_END, a, 0, s), "lm step end");
-    return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
+  PTLM_TRY(read_state(st, &hs, s));
+  if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
+  if (hs.t >= hs.t_max) return fail(PTLM_EINVAL, "the state has run its outer iterations (t_max)");
+  const int t0 = hs.t;
+  SingleOps o{h, make_lm_args(h, prm, st, O, P, learned), O, P, y, learned, false, s};
+  for (int attempt = 0; attempt <= prm->retry_max; ++attempt) {
+    o.lin_expected = hs.need_lin != 0;
+    PTLM_TRY(enqueue_attempt(o, *prm));
+    PTLM_TRY(read_state(st, &hs, s));
+    if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
+    if (hs.t > t0) break;
   }
-
-  bool accepted = false;
-  for (int retry = 0; retry < prm->retry_max && !accepted; ++retry) {
-    a.use_warm = (prm->warm_start && retry == 0 && h->prev_valid) ? 1 : 0;
-    LM_HIP(launch_fin(F_BEGIN, a, 0, s), "lm begin");
-    if (a.use_warm) {
-      stt = ggnv_lm(h, a, a.prev, a.Ap, nullptr, s);
-      if (stt != PTLM_OK) return stt;
-    }
-    LM_HIP(launch_vec(V_CG_INIT, a, s), "cg init");
-    LM_HIP(launch_fin(F_CG_INIT, a, LM_BLOCKS, s), "cg init fin");
-    for (int i = 0; i < prm->cg_max; ++i) {
-      stt = ggnv_lm(h, a, a.p, a.Ap, &st->cg_active, s);
-      if (stt != PTLM_OK) return stt;
-      LM_HIP(launch_vec(V_PAP, a, s), "cg pap");
-      LM_HIP(launch_fin(F_PAP, a, LM_BLOCKS, s), "cg pap fin");
-      LM_HIP(launch_vec(V_CG_UPDATE, a, s), "cg update");
-      LM_HIP(launch_fin(F_CG_UPDATE, a, LM_BLOCKS, s), "cg update fin");
-      LM_HIP(launch_vec(V_PUPDATE, a, s), "cg p");
-    }
-    // ---- trial point z + Delta, predicted and actual reductions, rho, mu
-    LM_HIP(launch_vec(V_TRIAL, a, s), "lm trial");
-    LM_HIP(launch_fin(F_PRED, a, LM_BLOCKS, s), "lm pred");
-    TileArgs ta{};
-    ta.O = a.ztrial;
-    ta.P = g.joint ? a.ztrial + N : P;
-    ta.y = y;
-    LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
-    LM_HIP(launch_fin(F_TRIAL_END, a, g.grid, s), "lm trial end");
-    LM_HIP(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "lm read state");
-    LM_HIP(hipStreamSynchronize(s), "lm sync");
-    if (hs.accepted) {
-      accepted = true;
-      LM_HIP(hipMemcpyAsync(O, a.ztrial, N * sizeof(float2), hipMemcpyDeviceToDevice, s), "lm accept O");
-      if (g.joint)
-        LM_HIP(hipMemcpyAsync(P, a.ztrial + N, M * sizeof(float2), hipMemcpyDeviceToDevice, s), "lm accept P");
-      LM_HIP(hipMemcpyAsync(a.prev, a.dx, a.n * sizeof(float2), hipMemcpyDeviceToDevice, s), "lm keep step");
-      h->prev_valid = true;
-    }
-  }
-  LM_HIP(launch_fin(F_STEP_END, a, 0, s), "lm step end");
-  if (!accepted) return fail(PTLM_ENOTACCEPTED, "every retry of this outer iteration was rejected");
+  if (hs.t == t0) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
+  if (hs.status == PTLM_ENOTACCEPTED) return fail(PTLM_ENOTACCEPTED, "every retry of this outer iteration was rejected");
   return PTLM_OK;
 }
 
@@ -147,18 +181,17 @@ extern "C" {
 
 ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_state* d_state, void* stream) {
   if (!h || !d_state) return fail(PTLM_EINVAL, "null handle or state");
-  ptlm_status st = check_params(params);
+  ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
-  LMArgs a = make_args(h, params, d_state, nullptr, nullptr, nullptr);
-  h->prev_valid = false;
-  LM_HIP(launch_fin(F_INIT, a, 0, (hipStream_t)stream), "lm init");
+  LMArgs a = make_lm_args(h, params, d_state, nullptr, nullptr, nullptr);
+  LM_HIP(launch_fin(F_INIT, a, 0, FL_NONE, (hipStream_t)stream), "lm init");
   return PTLM_OK;
 }
 
 ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_y, const ptlm_lm_params* params,
                          ptlm_lm_state* d_state, const float* d_precond, void* stream) {
   if (!h || !d_O || !d_P || !d_y || !d_state) return fail(PTLM_EINVAL, "null argument");
-  ptlm_status st = check_params(params);
+  ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (params->precond == 2 && !d_precond && !h->cnn_params)
     return fail(PTLM_EINVAL, "precond == 2 needs d_precond or a registered network");

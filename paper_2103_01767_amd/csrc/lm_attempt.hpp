@@ -1,0 +1,60 @@
+// One LM attempt (alg:lm_inexact) as a fixed launch sequence, shared by the single-problem
+// driver (direct launches with one problem's arguments) and the batched driver (one launch
+// per step for every problem of a batch, from job tables in device memory).  Every launch is
+// predicated on a flag of the device LM state, so the same sequence serves the first attempt
+// of an outer iteration (which linearises) and its retries (which reuse the linearisation,
+// reading C4), and the host never has to look at the state in between.
+#pragma once
+#include "lm_internal.hpp"
+
+namespace ptlm {
+
+// which direction / output a GGN-vector product of the attempt uses
+enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
+
+#define PTLM_TRY(x)                              \
+  do {                                           \
+    const ptlm_status st_ = (x);                 \
+    if (st_ != PTLM_OK) return st_;              \
+  } while (0)
+
+// Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
+// diag_paper(), learned(), ggnv(which), trial_loss(), copy_accept().
+template <class Ops>
+ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
+  PTLM_TRY(o.fin(F_ATTEMPT, 0, FL_NONE));
+  // ---- linearisation at z_t (only after an accepted step or at the start)
+  PTLM_TRY(o.copy_lin());
+  PTLM_TRY(o.linearize());  // f, ||grad_zeta ell||^2, g, phasor field, traces
+  PTLM_TRY(o.vec(V_GNORM, FL_LIN));
+  PTLM_TRY(o.fin(F_LIN, 1, FL_LIN));
+  if (prm.scaling == 1 || prm.precond == 1) {
+    PTLM_TRY(o.diag_paper());  // App. B diagonal, then the floor of C17
+    PTLM_TRY(o.vec(V_DIAGMAX, FL_LIN));
+    PTLM_TRY(o.fin(F_DIAGMAX, 1, FL_LIN));
+    PTLM_TRY(o.vec(V_DIAGFLOOR, FL_LIN));
+  }
+  if (prm.precond == 2) PTLM_TRY(o.learned());
+  // ---- lambda, eta, PCG on (G + lambda D) Delta = -g
+  PTLM_TRY(o.fin(F_BEGIN, 0, FL_ALIVE));
+  PTLM_TRY(o.ggnv(GG_WARM));  // A Delta_0 for the warm start
+  PTLM_TRY(o.vec(V_CG_INIT, FL_ALIVE));
+  PTLM_TRY(o.fin(F_CG_INIT, 1, FL_ALIVE));
+  for (int i = 0; i < prm.cg_max; ++i) {
+    PTLM_TRY(o.ggnv(GG_P));
+    PTLM_TRY(o.vec(V_PAP, FL_CG));
+    PTLM_TRY(o.fin(F_PAP, 1, FL_CG));
+    PTLM_TRY(o.vec(V_CG_UPDATE, FL_CG));
+    PTLM_TRY(o.fin(F_CG_UPDATE, 1, FL_CG));
+    PTLM_TRY(o.vec(V_PUPDATE, FL_CG));
+  }
+  // ---- trial point, predicted and actual reductions, gain ratio, damping, acceptance
+  PTLM_TRY(o.vec(V_TRIAL, FL_ALIVE));
+  PTLM_TRY(o.fin(F_PRED, 1, FL_ALIVE));
+  PTLM_TRY(o.trial_loss());
+  PTLM_TRY(o.fin(F_TRIAL_END, 2, FL_ALIVE));
+  PTLM_TRY(o.copy_accept());
+  return PTLM_OK;
+}
+
+}  // namespace ptlm

@@ -1,32 +1,61 @@
 // Internal declarations of the LM / PCG kernels.
 #pragma once
+#include <cstddef>
+
 #include "ptlm.h"
 #include "internal.hpp"
 
 namespace ptlm {
 
-constexpr int LM_BLOCKS = 1024;  // blocks of the vector kernels (partials per call)
+// blocks of the vector kernels of a problem with n complex entries per vector (a function of
+// the problem alone, so a problem gets the same partial sums alone and in a batch)
+inline int lm_vec_blocks(size_t n) {
+  const size_t b = (n + 1023) / 1024;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
 
 // indices into the FP64 scalar scratch
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4 };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL };
-enum FinOp : int { F_LIN, F_DIAGMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_STEP_END, F_INIT };
+enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT };
+
+// Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
+enum LMFlag : int {
+  FL_NONE = -1,
+  FL_LIN = (int)(offsetof(ptlm_lm_state, lin_now) / 4),
+  FL_ALIVE = (int)(offsetof(ptlm_lm_state, alive) / 4),
+  FL_CG = (int)(offsetof(ptlm_lm_state, cg_active) / 4),
+  FL_WARM = (int)(offsetof(ptlm_lm_state, use_warm) / 4),
+  FL_ACCEPTED = (int)(offsetof(ptlm_lm_state, accepted) / 4),
+};
 
 struct LMArgs {
   float2 *g, *dx, *prev, *r, *z, *p, *Ap, *ztrial;
   float2* diag;            // (Re, Im) weights of Dg(G) per complex entry, floored
-  const float2* learned;   // caller preconditioner diagonal (precond == 2)
+  const float2* learned;   // learned preconditioner diagonal (precond == 2)
   const float2 *O, *P;     // current iterate
   size_t n, nobj;          // complex entries of a vector / of its object part
   ptlm_lm_state* st;
   ptlm_lm_params prm;
-  double* partials;        // >= LM_BLOCKS * 4
+  double* partials;        // >= vec_blocks * 4
   double* scal;
-  int use_warm;
+  int vec_blocks;          // blocks of the vector kernels (lm_vec_blocks(n))
+  int tile_grid;           // workgroups of the tile kernels (partials of the trial loss)
+  int t_max;               // outer iterations to run (ptlm_lm_init / batch binding)
 };
 
-hipError_t launch_vec(int op, const LMArgs& a, hipStream_t s);
-hipError_t launch_fin(int op, const LMArgs& a, int count, hipStream_t s);
+// One problem's part of a batched LM launch.
+struct LMJob {
+  LMArgs a;
+  int block0;
+};
+
+hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s);
+hipError_t launch_fin(int op, const LMArgs& a, int count, int flag, hipStream_t s);
+// batched: vector kernels over the blocks of every job; finalize kernels one block per job,
+// reducing count_kind = 0 (none), 1 (the job's vector partials) or 2 (its tile partials)
+hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* job_of_block, int nblocks, int flag, hipStream_t s);
+hipError_t launch_fin_batch(int op, const LMJob* jobs, int njobs, int count_kind, int flag, hipStream_t s);
 
 }  // namespace ptlm

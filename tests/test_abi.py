@@ -15,7 +15,7 @@ pt = pytest.importorskip("paper_2103_01767_amd")
 
 def header_functions():
     text = open(HEADER).read()
-    return re.findall(r"^(?:ptlm_status|void|const char\*)\s+(ptlm_\w+)\s*\(", text, re.M)
+    return re.findall(r"^(?:ptlm_status|void|const char\*|ptlm_handle\*)\s+(ptlm_\w+)\s*\(", text, re.M)
 
 
 def test_every_declared_symbol_is_exported_and_bound():
@@ -81,3 +81,20 @@ def test_default_params_are_the_papers():
     p = pt.default_params()
     assert (p.mu0, p.mu_min, p.kappa, p.nu, p.rho_min, p.beta) == (1e-5, 1e-8, 4.0, 1.0, 1e-4, 0.1)
     assert p.cg_max == 10 and p.scaling == 0 and p.precond == 0
+
+
+def test_batch_workspace_validation():
+    descs = (pt.ptlm_desc * 2)(pt.ptlm_desc(40, 40, 16, 16, 2, pt.GAUSS, pt.JOINT, 1e-8),
+                               pt.ptlm_desc(100, 100, 48, 48, 2, pt.GAUSS, pt.JOINT, 1e-8))
+    p0 = np.array([[0, 0], [10, 10]], np.int32)
+    p1 = np.array([[0, 0], [52, 52]], np.int32)
+    ptrs = (ctypes.c_void_p * 2)(p0.ctypes.data_as(ctypes.c_void_p), p1.ctypes.data_as(ctypes.c_void_p))
+    n = ctypes.c_size_t(0)
+    assert pt.lib().ptlm_batch_workspace_bytes(2, descs, ptrs, ctypes.byref(n)) == pt.PTLM_OK
+    # at least the two problems' own workspaces
+    one = [_ws(descs[i], p)[1] for i, p in enumerate((p0, p1))]
+    assert n.value >= sum(one)
+    p1[1] = [53, 0]  # outside the 100 x 100 object for a 48 x 48 probe
+    assert pt.lib().ptlm_batch_workspace_bytes(2, descs, ptrs, ctypes.byref(n)) == pt.PTLM_EINVAL
+    assert b"problem 1" in pt.lib().ptlm_last_error()
+    assert pt.lib().ptlm_batch_workspace_bytes(0, descs, ptrs, ctypes.byref(n)) == pt.PTLM_EINVAL

@@ -1,0 +1,128 @@
+"""Batched LM over problems of uneven sizes (probe sides 16-96, square and rectangular).
+
+* Each problem of a batch ends with exactly the iterate, loss and counters it reaches when
+  solved alone with ptlm_lm_step (same kernels, same blocks, same reduction order).
+* Attempts replayed from the captured HIP graph equal eager attempts, checked after every
+  replay, with eager work and synchronisations in between.
+* The batch reproduces the single-problem LM, which is itself checked against the FP64
+  oracle's LM (test_gpu_lm.py); the data here are Poisson draws of the oracle's intensities.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ptycho
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2103_01767_amd as pt  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+# (object side, probe shape, raster n, step, seed)
+SPECS = [(72, (32, 32), 6, 8, 11), (100, (48, 48), 6, 10, 12), (120, (64, 64), 5, 12, 13),
+         (150, (96, 96), 4, 16, 14), (40, (16, 16), 5, 5, 15), (90, (32, 64), 4, 8, 16)]
+
+
+def c64(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).to(DEV)
+
+
+def make_problems():
+    out = []
+    for side, probe, n, step, seed in SPECS:
+        rng = np.random.default_rng(seed)
+        O = synth.make_object(rng, side, amp=(0.7, 1.0), phase=(-np.pi, np.pi), phase_sigma=3.0,
+                              phase_source="gaussian")
+        P = synth.make_probe_fresnel(rng, max(probe), 0.3 * max(probe), 5.0)[:probe[0], :probe[1]]
+        P = synth.scale_probe_to_photons(P, O, 3e3)
+        base_y = 2 + step * np.arange(n)
+        base_x = 2 + step * np.arange(n)
+        ry, rx = np.meshgrid(base_y, base_x, indexing="ij")
+        pos = np.stack([ry.ravel(), rx.ravel()], 1) + rng.integers(-1, 2, size=(n * n, 2))
+        pos = np.clip(pos, 0, [side - probe[0], side - probe[1]]).astype(np.int32)
+        y = synth.poisson_counts(rng, ptycho.intensity(O, P, pos, 1e-8)).astype(np.float32)
+        O0 = synth.random_object_guess(rng, side)
+        P0 = np.abs(P)  # phaseless start with the true intensity
+        out.append(dict(obj_shape=(side, side), probe_shape=probe, positions=pos, mode="joint", y=y, O0=O0, P0=P0))
+    return out
+
+
+def run_single(p, params, T):
+    prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+    O, P = c64(p["O0"]), c64(p["P0"])
+    y = torch.from_numpy(p["y"]).to(DEV)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    for _ in range(T):
+        prob.lm_step(O, P, y, params, st)
+    torch.cuda.synchronize()
+    return O, P, pt.state_from_tensor(st)
+
+
+@pytest.mark.parametrize("precond", [1, 0])
+def test_batch_equals_problems_alone(precond):
+    print("case batch vs single precond", precond, flush=True)
+    probs = make_problems()
+    params = pt.default_params(scaling=1 if precond else 0, precond=precond, cg_max=6)
+    T = 4
+    alone = [run_single(p, params, T) for p in probs]
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, attempts = batch.solve(200, check_every=2)
+    torch.cuda.synchronize()
+    assert status in (pt.PTLM_OK,)
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        print("problem %d: t %d/%d f %.6e / %.6e products %d / %d" % (i, s1.t, s2.t, s1.f, s2.f, s1.products,
+                                                                     s2.products))
+        assert s2.t == T and s1.t == T
+        assert s2.f == s1.f and s2.products == s1.products and s2.attempts == s1.attempts
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+def test_graph_replays_equal_eager_attempts():
+    print("case graph vs eager", flush=True)
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=1, cg_max=5)
+    runs = []
+    for use_graph in (False, True):
+        b = pt.Batch(probs, device=DEV)
+        Os = [c64(p["O0"]) for p in probs]
+        Ps = [c64(p["P0"]) for p in probs]
+        ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+        b.bind(Os, Ps, ys, params, 100, use_graph=use_graph)
+        runs.append((b, Os, Ps, ys))
+    for a in range(6):
+        for b, *_ in runs:
+            b.attempt()
+        torch.cuda.synchronize()
+        # eager work between replays: a loss of every problem through its handle
+        (b0, O0s, P0s, y0s), (b1, O1s, P1s, y1s) = runs
+        for i in range(len(probs)):
+            f0 = b0.problem(i).loss(O0s[i], P0s[i], y0s[i])
+            f1 = b1.problem(i).loss(O1s[i], P1s[i], y1s[i])
+            assert torch.equal(f0, f1), (a, i)
+            assert torch.equal(O0s[i], O1s[i]) and torch.equal(P0s[i], P1s[i]), (a, i)
+        torch.cuda.synchronize()
+    for i in range(len(probs)):
+        s0, s1 = runs[0][0].state(i), runs[1][0].state(i)
+        assert (s0.t, s0.attempts, s0.products, s0.f) == (s1.t, s1.attempts, s1.products, s1.f)
+        assert s0.attempts == 6
+
+
+def test_batch_problem_handles_serve_single_calls():
+    probs = make_problems()[:3]
+    batch = pt.Batch(probs, device=DEV)
+    for i, p in enumerate(probs):
+        alone = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+        O, P = c64(p["O0"]), c64(p["P0"])
+        z1 = batch.problem(i).forward(O, P)
+        z2 = alone.forward(O, P)
+        assert torch.equal(z1, z2)
