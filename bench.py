@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-calls", type=int, default=3)
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -166,6 +168,7 @@ def main():
     fft_tflops = fft_flops / (kern_ms * 1e-3) / 1e12
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
+    batch = None if args.no_batch else batch_measure(dev, args.batch_iters)
 
     cpu = None
     if not args.no_cpu:
@@ -199,13 +202,15 @@ def main():
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
         "lm_time_to_target": lm,
+        "batch_uneven": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
 
 def lm_comparison(prob, pr, dev, iters):
-    """LM wall time to f <= 1.01 f_oracle, for plain (unpreconditioned), Jacobi and learned PCG.
+    """LM wall time to f <= 1.01 f_oracle, for plain (unpreconditioned), Jacobi and learned PCG
+    (network re-run at every linearisation, or once from the starting probe).
 
     Data: the stored Poisson counts of the workload; f_oracle: the FP64 oracle's loss after its
     stored number of outer iterations (D = Dg(G), Jacobi PCG) on the same data.  Each variant
@@ -222,8 +227,10 @@ def lm_comparison(prob, pr, dev, iters):
     net = learned.lm_net(learned.load(dev), pr.O_true.shape, dev)
     out = {"target_loss": target, "oracle_final_loss": ref["f_final"], "oracle_iters": ref["T"],
            "max_iters": iters}
-    for name, prec in (("plain", 0), ("jacobi", 1), ("learned", 2)):
+    for name, prec, every in (("plain", 0, 1), ("jacobi", 1, 1), ("learned", 2, 1), ("learned_once", 2, 0)):
         pt.lm_set_cnn(prob, net if prec == 2 else None)
+        if prec == 2:
+            pt.lm_set_cnn_refresh(prob, every)
         params = pt.default_params(scaling=1, precond=prec, cg_max=10)
         st = prob.new_state()
         O, P = c64(pr.O_init), c64(pr.P_init)
@@ -243,6 +250,93 @@ def lm_comparison(prob, pr, dev, iters):
                      "seconds": round(el, 4), "final_loss": f, "ggnv_products": s.products,
                      "attempts": s.attempts}
     pt.lm_set_cnn(prob, None)
+    return out
+
+
+def batch_measure(dev, iters):
+    """64 independent joint problems of uneven sizes (object side 128..384 enlarged to fit the
+    raster, probe side 32/48/64/96, n x n raster with n in 10..30, step = probe / 4, Poisson
+    data at 1e3..1e5 photons per pattern) solved together: one launch per LM-attempt step for
+    all problems, attempts replayed from a captured HIP graph.
+
+    Reports, for `iters` outer iterations of Jacobi PLM (D = Dg(G)): wall time and GGN-vector
+    scan-positions/s of the batch, with graph replay and with eager launches, and the same
+    problems solved one after another; then time to the plain (unpreconditioned) run's final
+    batch loss for plain, Jacobi and learned preconditioning.  Data: Poisson draws of the
+    GPU forward model at the true object and probe (seeded)."""
+    import torch
+    import synth
+    import paper_2103_01767_amd as pt
+    from paper_2103_01767_amd import learned
+    probs = [synth.make_c2_problem(p) for p in range(64)]
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    specs = [dict(obj_shape=p.O_true.shape, probe_shape=p.P_true.shape, positions=p.pos, mode="joint",
+                  background=p.background) for p in probs]
+    batch = pt.Batch(specs, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1002)
+    ys = []
+    for i, p in enumerate(probs):
+        z = batch.problem(i).forward(c64(p.O_true), c64(p.P_true))
+        ys.append(torch.poisson((z.double() ** 2).float(), generator=gen).contiguous())
+    torch.cuda.synchronize()
+    K = np.array([p.K for p in probs])
+    KM = int(np.sum(K * np.array([p.P_true.shape[0] * p.P_true.shape[1] for p in probs])))
+
+    def run(prec, use_graph, T, target=None, nets=None):
+        params = pt.default_params(scaling=1, precond=prec, cg_max=10)
+        for i in range(len(probs)):
+            pt.lm_set_cnn(batch.problem(i), nets[i] if (prec == 2 and nets) else None)
+        Os = [c64(p.O_init) for p in probs]
+        Ps = [c64(p.P_init) for p in probs]
+        batch.bind(Os, Ps, ys, params, T, use_graph=use_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hit, attempts, done = None, 0, False
+        while not done and attempts < 30 * T:
+            st, n = batch.solve(1 if target is not None else 30 * T, check_every=1 if target is not None else 4)
+            attempts += n
+            sts = batch.all_states()
+            done = all(s.t >= T for s in sts)
+            if target is not None and hit is None and sum(s.f for s in sts) <= target:
+                hit = time.perf_counter() - t0
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sts = batch.all_states()
+        f = sum(float(batch.problem(i).loss(Os[i], Ps[i], ys[i]).cpu()[0]) for i in range(len(probs)))
+        prods = sum(s.products for s in sts)
+        pos_prods = sum(s.products * int(k) for s, k in zip(sts, K))
+        return dict(seconds=round(el, 4), attempts=attempts, final_loss=f, ggnv_products=prods,
+                    ggnv_positions_per_s=round(pos_prods / el, 1), reached_s=None if hit is None else round(hit, 4))
+
+    out = {"problems": len(probs), "positions": int(K.sum()), "pixel_positions": KM, "outer_iters": iters}
+    run(1, True, 2)  # warm-up: compile-time attributes, graph capture path
+    out["jacobi_graph"] = run(1, True, iters)
+    out["jacobi_eager"] = run(1, False, iters)
+    # the same problems one after another through their own handles
+    params = pt.default_params(scaling=1, precond=1, cg_max=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, p in enumerate(probs):
+        prob = batch.problem(i)
+        O, P = c64(p.O_init), c64(p.P_init)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        prob.lm_solve(O, P, ys[i], params, iters, st)
+    torch.cuda.synchronize()
+    out["jacobi_one_by_one_seconds"] = round(time.perf_counter() - t0, 4)
+    # learned vs plain vs Jacobi: time to the plain run's final batch loss
+    plain = run(0, True, iters)
+    target = 1.01 * plain["final_loss"]
+    out["target_loss"] = target
+    out["plain"] = plain
+    out["jacobi_to_target"] = run(1, True, iters, target=target)
+    net_params = learned.load(dev)
+    nets = [learned.lm_net(net_params, p.O_true.shape, dev) for p in probs]
+    out["learned_to_target"] = run(2, True, iters, target=target, nets=nets)
+    for i in range(len(probs)):
+        pt.lm_set_cnn(batch.problem(i), None)
     return out
 
 

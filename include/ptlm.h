@@ -171,6 +171,15 @@ ptlm_status ptlm_ggn_vp_stage(ptlm_handle* h, const float* d_vO, const float* d_
  * sum_j ell''_j J_ji^2.  d_dP nullable in PTLM_OBJECT mode. */
 ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream);
 
+/* Autotuner of the tile-kernel launch (a project addition).  Times the GGN-vector product
+ * (reps calls after one warm-up) with the positions cut into 0.5x, 1x and 2x as many
+ * segments (workgroups) as the GPU keeps resident, and keeps the fastest.  Results do not
+ * depend on the choice beyond FP32 summation order.  Synchronises the stream.  h_ms (3 host
+ * doubles, nullable) receives the times per call, h_scale (nullable) the chosen scale.  The
+ * workspace of ptlm_workspace_bytes covers every candidate.  Overwrites the output buffers
+ * of the LM (call it before ptlm_lm_init or between LM runs), not the linearisation. */
+ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, void* stream);
+
 /* Truncated LM (alg:lm_inexact).  ptlm_lm_init resets d_state (mu = mu0, t = 0) on the
  * stream.  ptlm_lm_step runs one outer iteration in place on d_O (and d_P in PTLM_JOINT
  * mode): linearise, then up to retry_max attempts of {lambda, PCG solve, trial loss, gain
@@ -231,6 +240,11 @@ ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_prec
  * (ptlm_cnn_workspace_bytes) stay owned by the caller and must outlive their use. */
 ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float* d_params, void* d_ws,
                             size_t ws_bytes);
+/* How often ptlm_lm_step re-runs the registered network: every `every`-th linearisation
+ * (default 1), or only at the first one after registration (every = 0).  Between runs the
+ * learned diagonal is rebuilt from the kept network output and the new App. B diagonal.  A
+ * batch (ptlm_batch_bind) runs each network once, from the bound probe. */
+ptlm_status ptlm_lm_set_cnn_refresh(ptlm_handle* h, int32_t every);
 
 /* ---------------------------------------------------------------------------------------
  * Batched LM over independent problems of uneven sizes (a project addition: many

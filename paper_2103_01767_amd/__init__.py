@@ -93,6 +93,8 @@ _sig = {
     "ptlm_cnn_features": (ctypes.c_int, [_vp, _vp, _vp]),
     "ptlm_learned_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ptlm_lm_set_cnn": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, ctypes.c_size_t]),
+    "ptlm_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), _vp]),
     "ptlm_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp,
                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "ptlm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp, _vp, ctypes.c_size_t, _vp,
@@ -103,6 +105,7 @@ _sig = {
     "ptlm_batch_attempt": (ctypes.c_int, [_vp, _vp]),
     "ptlm_batch_solve": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ptlm_batch_destroy": (ctypes.c_int, [_vp]),
+    "ptlm_lm_set_cnn_refresh": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ptlm_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -284,6 +287,13 @@ class Problem:
                               1 if exact else 0, _stream()))
         return dO, dP
 
+    def autotune(self, reps=5):
+        """Pick the segment count of the tile kernels by timing GGN-vector products."""
+        ms = (ctypes.c_double * 3)()
+        sc = ctypes.c_double(0)
+        _check(_lib.ptlm_autotune(self.handle, int(reps), ms, ctypes.byref(sc), _stream()))
+        return float(sc.value), [float(v) for v in ms]
+
     def new_state(self):
         return torch.zeros(STATE_BYTES, dtype=torch.uint8, device=self.device)
 
@@ -443,11 +453,19 @@ class Batch:
         raw = self.states.detach().cpu().numpy().tobytes()
         return ptlm_lm_state.from_buffer_copy(raw[i * STATE_BYTES:(i + 1) * STATE_BYTES])
 
+    def all_states(self):
+        raw = self.states.detach().cpu().numpy().tobytes()
+        return [ptlm_lm_state.from_buffer_copy(raw[i * STATE_BYTES:(i + 1) * STATE_BYTES]) for i in range(self.n)]
+
     def __del__(self):
         h = self.__dict__.get("handle")
         if h is not None and h.value and _lib is not None:
             _lib.ptlm_batch_destroy(h)
             self.handle = None
+
+
+def lm_set_cnn_refresh(prob: "Problem", every: int):
+    _check(_lib.ptlm_lm_set_cnn_refresh(prob.handle, int(every)))
 
 
 def lib():

@@ -43,7 +43,81 @@ static int wgs_per_cu(int my, int mx) {
   return std::max(1, std::min(by_lds, by_waves));
 }
 
-ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
+// object 16x16 tiles -> items (segments or positions) whose box meets the tile (CSR)
+template <class Boxes>
+static void build_csr(const Plan& p, Boxes boxes, int count, std::vector<int>& ptr, std::vector<int>& idx) {
+  const int ntiles = p.oty * p.otx;
+  std::vector<int> cnt(ntiles + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    int r0, c0, h, w;
+    boxes(i, r0, c0, h, w);
+    if (h <= 0 || w <= 0) continue;
+    for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+      for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) cnt[ty * p.otx + tx + 1]++;
+  }
+  for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+  ptr = cnt;
+  idx.assign(std::max(1, cnt[ntiles]), 0);
+  std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+  for (int i = 0; i < count; ++i) {
+    int r0, c0, h, w;
+    boxes(i, r0, c0, h, w);
+    if (h <= 0 || w <= 0) continue;
+    for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+      for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) idx[fill[ty * p.otx + tx]++] = i;
+  }
+}
+
+// Workgroups of the tile kernels for a grid scale: scale x (resident workgroups of the chip),
+// at most one per tiles-per-workgroup positions.
+static int plan_grid(const Plan& p, double scale) {
+  const int resident = 256 * wgs_per_cu(p.d.my, p.d.mx);
+  const int gmax = std::max(1, (int)std::llround(resident * scale));
+  return std::max(1, std::min((p.d.K + p.tpw - 1) / p.tpw, gmax));
+}
+
+// Contiguous segments of the position list (lengths differing by at most one), their strip
+// boxes and offsets, and the object-tile -> segment map, for `grid` workgroups.
+static void segment(Plan& p, const int* h_pos, int grid) {
+  const ptlm_desc* d = &p.d;
+  const int K = d->K;
+  p.grid = grid;
+  p.nseg = p.grid * p.tpw;
+  p.seg_start.resize(p.nseg + 1);
+  for (int s = 0; s <= p.nseg; ++s) p.seg_start[s] = (int)(((long long)s * K) / p.nseg);
+  p.seg_box.assign(p.nseg, make_int4(0, 0, 0, 0));
+  p.seg_off.assign(p.nseg, 0);
+  long long off = 0;
+  for (int s = 0; s < p.nseg; ++s) {
+    const int b = p.seg_start[s], e = p.seg_start[s + 1];
+    if (b == e) {
+      p.seg_off[s] = off;
+      continue;
+    }
+    int r0 = INT32_MAX, c0 = INT32_MAX, r1 = 0, c1 = 0;
+    for (int k = b; k < e; ++k) {
+      r0 = std::min(r0, h_pos[2 * k]);
+      c0 = std::min(c0, h_pos[2 * k + 1]);
+      r1 = std::max(r1, h_pos[2 * k] + d->my);
+      c1 = std::max(c1, h_pos[2 * k + 1] + d->mx);
+    }
+    p.seg_box[s] = make_int4(r0, c0, r1 - r0, c1 - c0);
+    p.seg_off[s] = off;
+    off += (long long)(r1 - r0) * (c1 - c0);
+  }
+  p.strip_elems = off;
+  build_csr(
+      p,
+      [&](int s, int& r0, int& c0, int& h, int& w) {
+        r0 = p.seg_box[s].x; c0 = p.seg_box[s].y; h = p.seg_box[s].z; w = p.seg_box[s].w;
+      },
+      p.nseg, p.otile_ptr, p.otile_seg);
+}
+
+// grid scales the autotuner tries; the workspace holds the largest of their segment tables
+static const double kGridScales[] = {0.5, 1.0, 2.0};
+
+ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double grid_scale) {
   if (!d) return fail(PTLM_EINVAL, "desc is null");
   if (!h_pos && d->K > 0) return fail(PTLM_EINVAL, "positions are null");
   if (d->K < 1) return fail(PTLM_EINVAL, "K must be >= 1");
@@ -68,66 +142,26 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   const int K = d->K, M = d->my * d->mx;
   const long long N = (long long)d->ny * d->nx;
   p.tpw = tile_per_wg(d->my, d->mx);
-  const int gmax = 256 * wgs_per_cu(d->my, d->mx);
-  p.grid = std::max(1, std::min((K + p.tpw - 1) / p.tpw, gmax));
-  p.nseg = p.grid * p.tpw;
-
-  // contiguous segments of the position list, lengths differing by at most one
-  p.seg_start.resize(p.nseg + 1);
-  for (int s = 0; s <= p.nseg; ++s) p.seg_start[s] = (int)(((long long)s * K) / p.nseg);
-  p.seg_box.assign(p.nseg, make_int4(0, 0, 0, 0));
-  p.seg_off.assign(p.nseg, 0);
-  long long off = 0;
-  for (int s = 0; s < p.nseg; ++s) {
-    const int b = p.seg_start[s], e = p.seg_start[s + 1];
-    if (b == e) {
-      p.seg_off[s] = off;
-      continue;
-    }
-    int r0 = INT32_MAX, c0 = INT32_MAX, r1 = 0, c1 = 0;
-    for (int k = b; k < e; ++k) {
-      r0 = std::min(r0, h_pos[2 * k]);
-      c0 = std::min(c0, h_pos[2 * k + 1]);
-      r1 = std::max(r1, h_pos[2 * k] + d->my);
-      c1 = std::max(c1, h_pos[2 * k + 1] + d->mx);
-    }
-    p.seg_box[s] = make_int4(r0, c0, r1 - r0, c1 - c0);
-    p.seg_off[s] = off;
-    off += (long long)(r1 - r0) * (c1 - c0);
-  }
-  p.strip_elems = off;
-
-  // object 16x16 tiles -> segments / positions meeting them (CSR)
   p.oty = (d->ny + 15) / 16;
   p.otx = (d->nx + 15) / 16;
-  const int ntiles = p.oty * p.otx;
-  auto build_csr = [&](auto boxes, int count, std::vector<int>& ptr, std::vector<int>& idx) {
-    std::vector<int> cnt(ntiles + 1, 0);
-    for (int i = 0; i < count; ++i) {
-      int r0, c0, h, w;
-      boxes(i, r0, c0, h, w);
-      if (h <= 0 || w <= 0) continue;
-      for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
-        for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) cnt[ty * p.otx + tx + 1]++;
-    }
-    for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-    ptr = cnt;
-    idx.assign(std::max(1, cnt[ntiles]), 0);
-    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int i = 0; i < count; ++i) {
-      int r0, c0, h, w;
-      boxes(i, r0, c0, h, w);
-      if (h <= 0 || w <= 0) continue;
-      for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
-        for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) idx[fill[ty * p.otx + tx]++] = i;
-    }
-  };
+  // sizes of the segment-dependent regions over every autotuner candidate
+  int max_grid = 1;
+  size_t max_nseg = 1, max_otile = 1;
+  long long max_strip = 0;
+  for (double sc : kGridScales) {
+    segment(p, h_pos, plan_grid(p, sc));
+    max_grid = std::max(max_grid, p.grid);
+    max_nseg = std::max(max_nseg, (size_t)p.nseg);
+    max_otile = std::max(max_otile, p.otile_seg.size());
+    max_strip = std::max(max_strip, p.strip_elems);
+  }
+  if (std::find(std::begin(kGridScales), std::end(kGridScales), grid_scale) == std::end(kGridScales))
+    return fail(PTLM_EINVAL, "grid scale must be 0.5, 1 or 2");
+  p.max_grid = max_grid;
+  p.grid_scale = grid_scale;
+  segment(p, h_pos, plan_grid(p, grid_scale));
   build_csr(
-      [&](int s, int& r0, int& c0, int& h, int& w) {
-        r0 = p.seg_box[s].x; c0 = p.seg_box[s].y; h = p.seg_box[s].z; w = p.seg_box[s].w;
-      },
-      p.nseg, p.otile_ptr, p.otile_seg);
-  build_csr(
+      p,
       [&](int k, int& r0, int& c0, int& h, int& w) {
         r0 = h_pos[2 * k]; c0 = h_pos[2 * k + 1]; h = d->my; w = d->mx;
       },
@@ -158,11 +192,11 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   };
   p.off.tw = take(p.tw.size() * sizeof(float2));
   p.off.pos = take((size_t)K * sizeof(int2));
-  p.off.seg_start = take(p.seg_start.size() * sizeof(int));
-  p.off.seg_box = take(p.seg_box.size() * sizeof(int4));
-  p.off.seg_off = take(p.seg_off.size() * sizeof(long long));
+  p.off.seg_start = take((max_nseg + 1) * sizeof(int));
+  p.off.seg_box = take(max_nseg * sizeof(int4));
+  p.off.seg_off = take(max_nseg * sizeof(long long));
   p.off.otile_ptr = take(p.otile_ptr.size() * sizeof(int));
-  p.off.otile_seg = take(p.otile_seg.size() * sizeof(int));
+  p.off.otile_seg = take(max_otile * sizeof(int));
   p.off.ptile_ptr = take(p.ptile_ptr.size() * sizeof(int));
   p.off.ptile_pos = take(p.ptile_pos.size() * sizeof(int));
   p.off.O_lin = take((size_t)N * sizeof(float2));
@@ -170,10 +204,10 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p) {
   p.off.afield = take((size_t)K * M * sizeof(float2));
   p.off.w2 = d->metric == PTLM_POISSON ? take((size_t)K * M * sizeof(float)) : 0;
   p.off.trace = take((size_t)K * sizeof(double));
-  p.off.strips = take((size_t)p.strip_elems * sizeof(float2));
-  p.off.probe_part = take((size_t)p.nseg * M * sizeof(float2));
-  p.off.partials = take((size_t)std::max(p.grid, 1024) * 4 * sizeof(double));
-  p.off.scratch = d->my == 256 ? take((size_t)p.grid * M * sizeof(float2)) : 0;
+  p.off.strips = take((size_t)max_strip * sizeof(float2));
+  p.off.probe_part = take(max_nseg * M * sizeof(float2));
+  p.off.partials = take((size_t)std::max(max_grid, 1024) * 4 * sizeof(double));
+  p.off.scratch = d->my == 256 ? take((size_t)max_grid * M * sizeof(float2)) : 0;
   p.off.scal = take(64 * sizeof(double));  // [0..7] LM scalars, [8..11] feature / learned-diagonal scratch
   // LM / PCG vectors (complex entries of R^(2n)) and real diagonals
   p.off.g = take(n2 * sizeof(float2));
@@ -307,6 +341,66 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
   return PTLM_OK;
 }
 
+
+// Re-segment the handle's positions for another grid scale and upload the segment tables
+// (the stored phasor field and every other per-position array are unaffected).
+ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s) {
+  Plan& p = h->plan;
+  segment(p, p.pos.data(), plan_grid(p, scale));
+  p.grid_scale = scale;
+  h->g.nseg = p.nseg;
+  h->g.grid = p.grid;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  PTLM_HIP(up(p.off.seg_start, p.seg_start.data(), p.seg_start.size() * sizeof(int)), "resegment");
+  PTLM_HIP(up(p.off.seg_box, p.seg_box.data(), p.seg_box.size() * sizeof(int4)), "resegment");
+  PTLM_HIP(up(p.off.seg_off, p.seg_off.data(), p.seg_off.size() * sizeof(long long)), "resegment");
+  PTLM_HIP(up(p.off.otile_ptr, p.otile_ptr.data(), p.otile_ptr.size() * sizeof(int)), "resegment");
+  PTLM_HIP(up(p.off.otile_seg, p.otile_seg.data(), p.otile_seg.size() * sizeof(int)), "resegment");
+  // the host tables are rewritten by the next call: finish the copies first
+  PTLM_HIP(hipStreamSynchronize(s), "resegment sync");
+  return PTLM_OK;
+}
+
+ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, hipStream_t s) {
+  Plan& p = h->plan;
+  const size_t N = (size_t)p.d.ny * p.d.nx;
+  float2* out = (float2*)(h->ws + p.off.Ap);
+  const float2* vO = h->g.O_lin;
+  const float2* vP = h->g.joint ? h->g.P_lin : nullptr;
+  hipEvent_t e0, e1;
+  PTLM_HIP(hipEventCreate(&e0), "autotune event");
+  PTLM_HIP(hipEventCreate(&e1), "autotune event");
+  double best = 1e300;
+  int bi = 1;
+  ptlm_status st = PTLM_OK;
+  const int nc = (int)(sizeof(kGridScales) / sizeof(kGridScales[0]));
+  for (int i = 0; i < nc && st == PTLM_OK; ++i) {
+    st = resegment(h, kGridScales[i], s);
+    if (st != PTLM_OK) break;
+    st = ggnv_impl(h, vO, vP, 0.0, nullptr, nullptr, nullptr, out, h->g.joint ? out + N : nullptr, nullptr, s);
+    if (st != PTLM_OK) break;
+    hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == PTLM_OK; ++r)
+      st = ggnv_impl(h, vO, vP, 0.0, nullptr, nullptr, nullptr, out, h->g.joint ? out + N : nullptr, nullptr, s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double per = (double)ms / std::max(reps, 1);
+    if (h_ms) h_ms[i] = per;
+    if (per < best) {
+      best = per;
+      bi = i;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != PTLM_OK) return st;
+  if (h_scale) *h_scale = kGridScales[bi];
+  return resegment(h, kGridScales[bi], s);
+}
 }  // namespace ptlm
 
 using namespace ptlm;
@@ -445,6 +539,12 @@ ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, v
   if (exact) return diag_exact_impl(h, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream);
   PTLM_HIP(launch_diag_paper(h->g, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream), "diag");
   return PTLM_OK;
+}
+
+ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, void* stream) {
+  PTLM_CHECK_H(h);
+  if (reps < 1) return fail(PTLM_EINVAL, "reps must be >= 1");
+  return autotune_impl(h, reps, h_ms, h_scale, (hipStream_t)stream);
 }
 
 const char* ptlm_last_error(void) { return g_last_error.c_str(); }

@@ -18,6 +18,8 @@ struct Offsets {
 struct Plan {
   ptlm_desc d{};
   int tpw = 1, grid = 1, nseg = 1;
+  double grid_scale = 1.0;             // workgroups = scale x resident workgroups (autotuned)
+  int max_grid = 1;                    // largest grid over the autotuner's candidates
   std::vector<int> seg_start;
   std::vector<int4> seg_box;           // (row0, col0, rows, cols)
   std::vector<long long> seg_off;
@@ -40,20 +42,27 @@ struct ptlm_handle {
   ptlm_cnn_desc cnn{};      // registered preconditioner network (ptlm_lm_set_cnn)
   const float* cnn_params = nullptr;
   char* cnn_ws = nullptr;
+  int cnn_every = 1;        // network refresh period in linearisations (0: once after registration)
+  int cnn_count = 0;        // linearisations since registration
+  bool cnn_ready = false;   // the network output r in cnn_ws is current
 };
 
 namespace ptlm {
 extern thread_local std::string g_last_error;
 ptlm_status fail(ptlm_status st, const std::string& msg);
 ptlm_status hip_fail(hipError_t e, const char* where);
-ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p);
+ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double grid_scale = 1.0);
 ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
                            float2* gO, float2* gP, hipStream_t s);
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
                       const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
                       int stage = 3);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s);
+ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s);
+ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, hipStream_t s);
 ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s);
+ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s);
+ptlm_status cnn_apply(ptlm_handle* h, float* out, hipStream_t s);
 ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
                         hipStream_t s);
 }  // namespace ptlm

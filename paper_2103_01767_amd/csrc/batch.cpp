@@ -151,11 +151,12 @@ struct BatchOps {
     return PTLM_OK;
   }
   ptlm_status learned() {
-    // every problem's network, at its current linearisation (recomputing it when the
-    // linearisation is unchanged reproduces the same diagonal)
+    // every problem's learned diagonal from its network output (computed at bind from the
+    // bound probe: once per reconstruction) and its current App. B diagonal; rebuilding it
+    // when the linearisation is unchanged reproduces the same diagonal
     for (int i = 0; i < b->n; ++i) {
       ptlm_handle* h = b->hs[i];
-      PTLM_TRY(learned_from_cnn(h, (float*)(h->ws + h->plan.off.learned), s));
+      PTLM_TRY(cnn_apply(h, (float*)(h->ws + h->plan.off.learned), s));
     }
     return PTLM_OK;
   }
@@ -512,6 +513,14 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   if (e == hipSuccess) e = up(b->L.copy_lin, b->copy_lin.data(), b->copy_lin.size() * sizeof(CopyJob));
   if (e == hipSuccess) e = up(b->L.copy_acc, b->copy_acc.data(), b->copy_acc.size() * sizeof(CopyJob));
   if (e != hipSuccess) return hip_fail(e, "batch bind upload");
+  // learned preconditioner: each network's output from the bound probe (once per reconstruction)
+  if (params->precond == 2) {
+    for (int i = 0; i < n; ++i) {
+      ptlm_handle* h = b->hs[i];
+      B_HIP(launch_copy((const float2*)d_P[i], h->g.P_lin, (size_t)h->g.my * h->g.mx, nullptr, s), "batch cnn probe");
+      PTLM_TRY(cnn_refresh(h, s));
+    }
+  }
   // reset every state: mu = mu0, t = 0, t_max = T
   B_HIP(launch_fin_batch(F_INIT, b->dev<LMJob>(b->L.lm_jobs), n, 0, FL_NONE, s), "batch init");
   b->h_states.assign(n, ptlm_lm_state{});

@@ -203,22 +203,48 @@ ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float*
   h->cnn = *d;
   h->cnn_params = d_params;
   h->cnn_ws = (char*)d_ws;
+  h->cnn_ready = false;
+  h->cnn_count = 0;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_lm_set_cnn_refresh(ptlm_handle* h, int32_t every) {
+  if (!h) return fail(PTLM_EINVAL, "handle is null");
+  if (every < 0) return fail(PTLM_EINVAL, "every must be >= 0");
+  h->cnn_every = every;
+  h->cnn_count = 0;
   return PTLM_OK;
 }
 
 }  // extern "C"
 
 namespace ptlm {
-// features -> network -> learned diagonal into `out` (2n floats), at the current linearisation
-ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s) {
+// features (from the linearisation probe) -> network -> r, kept in the network workspace
+ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s) {
   const CnnLayout L = layout(h->cnn);
   float* feat = (float*)(h->cnn_ws + L.feat);
   float* r = (float*)(h->cnn_ws + L.r);
   double* scal = (double*)(h->ws + h->plan.off.scal) + 8;
   CNN_HIP(launch_features(h->g, feat, scal, s), "lm features");
-  ptlm_status st = cnn_forward_impl(h->cnn, h->cnn_params, feat, r, h->cnn_ws, s);
+  const ptlm_status st = cnn_forward_impl(h->cnn, h->cnn_params, feat, r, h->cnn_ws, s);
   if (st != PTLM_OK) return st;
+  h->cnn_ready = true;
+  return PTLM_OK;
+}
+
+// learned diagonal into `out` (2n floats) from the kept r and the current linearisation
+ptlm_status cnn_apply(ptlm_handle* h, float* out, hipStream_t s) {
+  const CnnLayout L = layout(h->cnn);
+  const float* r = (const float*)(h->cnn_ws + L.r);
+  double* scal = (double*)(h->ws + h->plan.off.scal) + 8;
   CNN_HIP(launch_learned_diag(h->g, out, r, scal + 2, 1e-6f, s), "lm learned diag");
   return PTLM_OK;
+}
+
+// features -> network -> learned diagonal into `out`, at the current linearisation
+ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s) {
+  const ptlm_status st = cnn_refresh(h, s);
+  if (st != PTLM_OK) return st;
+  return cnn_apply(h, out, s);
 }
 }  // namespace ptlm

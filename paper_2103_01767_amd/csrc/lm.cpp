@@ -110,8 +110,12 @@ struct SingleOps {
     if (h->cnn_params) {
       float2* lbuf = (float2*)(h->ws + h->plan.off.learned);
       if (lin_expected) {
-        const ptlm_status st = learned_from_cnn(h, (float*)lbuf, s);
-        if (st != PTLM_OK) return st;
+        // the network runs every cnn_every-th linearisation (0: only the first); the learned
+        // diagonal is rebuilt from its output and the new App. B diagonal every time
+        const bool due = h->cnn_every > 0 ? (h->cnn_count % h->cnn_every == 0) : !h->cnn_ready;
+        h->cnn_count += 1;
+        if (due || !h->cnn_ready) PTLM_TRY(cnn_refresh(h, s));
+        PTLM_TRY(cnn_apply(h, (float*)lbuf, s));
       }
       a.learned = lbuf;
     } else {

@@ -126,3 +126,44 @@ def test_batch_problem_handles_serve_single_calls():
         z1 = batch.problem(i).forward(O, P)
         z2 = alone.forward(O, P)
         assert torch.equal(z1, z2)
+
+
+def test_batch_learned_preconditioner_equals_alone():
+    """precond 2: every problem's network runs once from its starting probe (in the batch at
+    bind, alone at the first linearisation with refresh period 0); iterates agree bit for bit."""
+    print("case batch learned", flush=True)
+    from paper_2103_01767_amd import learned
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=2, cg_max=5)
+    T = 3
+    net_params = learned.he_params(3, DEV)
+    net_params[-2:] = 0.05  # a non-zero output bias: the learned diagonal differs from App. B
+    alone = []
+    for p in probs:
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+        net = learned.lm_net(net_params, p["obj_shape"], DEV)
+        pt.lm_set_cnn(prob, net)
+        pt.lm_set_cnn_refresh(prob, 0)
+        O, P = c64(p["O0"]), c64(p["P0"])
+        y = torch.from_numpy(p["y"]).to(DEV)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(T):
+            prob.lm_step(O, P, y, params, st)
+        torch.cuda.synchronize()
+        alone.append((O, P, pt.state_from_tensor(st)))
+    batch = pt.Batch(probs, device=DEV)
+    nets = [learned.lm_net(net_params, p["obj_shape"], DEV) for p in probs]
+    for i in range(len(probs)):
+        pt.lm_set_cnn(batch.problem(i), nets[i])
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(100, check_every=1)
+    torch.cuda.synchronize()
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        assert s2.t == T and s2.f == s1.f and s2.products == s1.products
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)

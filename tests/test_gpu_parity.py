@@ -217,3 +217,26 @@ def test_invalid_arguments():
     prob = problem(case)
     with pytest.raises(TypeError):
         prob.forward(to_dev(case["O"]).to(torch.complex128), to_dev(case["P"]))
+
+
+@pytest.mark.parametrize("probe,n,step", [((64, 64), 20, 6), ((32, 32), 30, 4)], ids=["64x64", "32x32"])
+def test_autotuned_segmentation_keeps_products(probe, n, step):
+    """The autotuner only changes how positions are cut into segments: products stay at parity."""
+    print("case autotune", probe, flush=True)
+    case = make_case(probe, n, n, step, joint=True, seed=31)
+    prob = problem(case)
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "gauss", True)
+    prob.linearize(O, P, y)
+    scale, ms = prob.autotune(reps=3)
+    print("autotune scale", scale, "ms", ms)
+    assert scale in (0.5, 1.0, 2.0) and all(m > 0 for m in ms)
+    rng = np.random.default_rng(4)
+    vO = c64(synth.random_complex(rng, case["O"].shape))
+    vP = c64(synth.random_complex(rng, case["P"].shape))
+    oO, oP = prob.ggn_vp(to_dev(vO), to_dev(vP))
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128))
+    assert rel(host(oO), GO) < TOL and rel(host(oP), GP) < TOL
+    f, gO, gP = prob.linearize(O, P, y)
+    rgO, rgP = ptycho.gradient(lin)
+    assert rel(host(gO), rgO) < TOL and rel(host(gP), rgP) < TOL
