@@ -38,9 +38,10 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # profiles/ggnv_tile128_joint_obj512_probe128_k1600.md (KiB per dispatch, scaled by what the
 # same counters read for a plain 256 MiB copy).  Valid only for the kernel sources they were
 # taken on: a different hash of those sources reports traffic as null.
-TRAFFIC = {"fetch_kib": 337764.675, "write_kib": 449179.6875, "fetch_factor": 1.9998, "write_factor": 1.0,
+TRAFFIC = {"fetch_kib": 337722.109375, "write_kib": 448747.359375, "fetch_factor": 1.9998, "write_factor": 1.0,
+           "grid_scale": 1.0,
            "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp"],
-           "sha256": "90505f6c2a865871933fbe79b9fef967879893b8edc71048482bb0c6c8a74e34"}
+           "sha256": "9a762ed9f00eb75e3eb49bc1c1d152a5ddb123405e212987c8bcc599d427fee0"}
 
 
 def measured_traffic():
@@ -66,6 +67,10 @@ def parse():
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the large-scan GGN-vector timing")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default segment count")
+    ap.add_argument("--only-large-scan", action="store_true",
+                    help="only time the large-scan GGN-vector product (one JSON line; for profiling)")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -101,6 +106,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only_large_scan:
+        print(json.dumps(large_scan(dev, args.calls)), flush=True)
+        return
     pr = synth.make_c1()
     K = pr.K
     (ny, nx), (my, mx) = pr.O_true.shape, pr.P_true.shape
@@ -137,35 +145,13 @@ def main():
     value = K * products / (t1 - t0) if t1 > t0 else float("nan")
 
     # ---------------- dominant kernel alone: per-position GGN-vector kernel (HIP events)
-    f, gO, gP = prob.linearize(O, P, y)
-    g2 = torch.Generator(device=dev)
-    g2.manual_seed(7)
-    vO = torch.randn((ny, nx), dtype=torch.complex64, device=dev, generator=g2)
-    vP = torch.randn((my, mx), dtype=torch.complex64, device=dev, generator=g2)
-    outO = torch.empty_like(vO)
-    outP = torch.empty_like(vP)
-    for _ in range(5):
-        prob.ggn_vp(vO, vP, out=(outO, outP))
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.calls)]
-    for a, b, c in ev:
-        a.record(stream)
-        prob.ggn_vp_stage(1, vO, vP)
-        b.record(stream)
-        prob.ggn_vp_stage(2, vO, vP, out=(outO, outP))
-        c.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
-    call_ms = float(np.median([a.elapsed_time(c) for a, _, c in ev]))
-    red_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-
-    # algorithmic bytes of one launch of the per-position kernel: the stored phasor field
-    # (K*M complex64) plus the object-sized and probe-sized inputs it gathers (O, vO, P, vP)
-    kern_bytes = K * M * 8 + 2 * N * 8 + 2 * M * 8
-    achieved_gbs = kern_bytes / (kern_ms * 1e-3) / 1e9
-    fft_flops = 2 * 5 * M * math.log2(M) * K  # two 2D FFTs per position (5 M log2 M convention)
-    fft_tflops = fft_flops / (kern_ms * 1e-3) / 1e12
+    prob.linearize(O, P, y)
+    tune_scale, tune_ms = prob.autotune(reps=5) if not args.no_autotune else (1.0, None)
+    iso = ggnv_isolated(prob, dev, args.calls, stream)
+    kern_ms, call_ms, red_ms = iso["kernel_ms"], iso["call_ms"], iso["reduce_ms"]
+    kern_bytes, achieved_gbs, fft_tflops = iso["bytes_per_launch"], iso["achieved_gbs"], iso["fft_tflops"]
+    vO, vP = iso["vO"], iso["vP"]
+    large = None if args.no_c4 else large_scan(dev, max(3, args.calls // 10))
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
     batch = None if args.no_batch else batch_measure(dev, args.batch_iters)
@@ -196,16 +182,81 @@ def main():
         "ggnv_positions_per_s_isolated": round(K / (call_ms * 1e-3), 1),
         "ggnv_kernel_ms": round(kern_ms, 4),
         "ggnv_reduce_ms": round(red_ms, 4),
+        "autotune": {"grid_scale": tune_scale, "ms_at_scales_0.5_1_2": tune_ms},
         "fft_tflops": round(fft_tflops, 2),
         "fft_frac_fp32_peak": round(fft_tflops / FP32_PEAK_TFLOPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if tune_scale == TRAFFIC["grid_scale"] else None,
                      "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
+        "ggnv_large_scan": large,
         "lm_time_to_target": lm,
         "batch_uneven": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def ggnv_isolated(prob, dev, calls, stream):
+    """HIP-event timing of the GGN-vector product at the current linearisation: the
+    per-position kernel alone (stage 1) and with the finishing reductions (stage 2), on the
+    stream the library launches on (torch's current stream), random seeded directions."""
+    import torch
+    (ny, nx), (my, mx) = prob.obj_shape, prob.probe_shape
+    K, M, N = prob.K, my * mx, ny * nx
+    g2 = torch.Generator(device=dev)
+    g2.manual_seed(7)
+    vO = torch.randn((ny, nx), dtype=torch.complex64, device=dev, generator=g2)
+    vP = torch.randn((my, mx), dtype=torch.complex64, device=dev, generator=g2)
+    outO = torch.empty_like(vO)
+    outP = torch.empty_like(vP)
+    for _ in range(3):
+        prob.ggn_vp(vO, vP, out=(outO, outP))
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, b, c in ev:
+        a.record(stream)
+        prob.ggn_vp_stage(1, vO, vP)
+        b.record(stream)
+        prob.ggn_vp_stage(2, vO, vP, out=(outO, outP))
+        c.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    call_ms = float(np.median([a.elapsed_time(c) for a, _, c in ev]))
+    red_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    # algorithmic bytes of one launch of the per-position kernel: the stored phasor field
+    # (K*M complex64) plus the object-sized and probe-sized inputs it gathers (O, vO, P, vP)
+    kern_bytes = K * M * 8 + 2 * N * 8 + 2 * M * 8
+    fft_flops = 2 * 5 * M * math.log2(M) * K  # two 2D FFTs per position (5 M log2 M convention)
+    return {"kernel_ms": kern_ms, "call_ms": call_ms, "reduce_ms": red_ms, "bytes_per_launch": kern_bytes,
+            "achieved_gbs": kern_bytes / (kern_ms * 1e-3) / 1e9, "fft_tflops": fft_flops / (kern_ms * 1e-3) / 1e12,
+            "positions_per_s": K / (call_ms * 1e-3), "vO": vO, "vP": vP}
+
+
+def large_scan(dev, calls):
+    """GGN-vector product on the large scan: 2048x2048 object, 256x256 probe, 100x100 raster
+    (10 000 positions), linearised at the initial guess with seeded stand-in counts of the
+    workload's size and photon budget (the product's cost does not depend on the data)."""
+    import torch
+    import synth
+    import paper_2103_01767_amd as pt
+    pr = synth.make_c4()
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, metric="gauss", mode="joint",
+                      background=pr.background, device=dev)
+    y = torch.from_numpy(synth.surrogate_counts(np.random.default_rng(1004004), pr.K, pr.P_true.shape,
+                                                pr.photons)).to(dev)
+    prob.linearize(c64(pr.O_init), c64(pr.P_init), y)
+    iso = ggnv_isolated(prob, dev, calls, torch.cuda.current_stream())
+    out = {"workload": "joint, object 2048x2048, probe 256x256, 100x100 raster step 16 +-2 (10000 positions)",
+           "kernel": "tile256_kernel<GGNV>", "kernel_ms": round(iso["kernel_ms"], 4),
+           "call_ms": round(iso["call_ms"], 4), "positions_per_s": round(iso["positions_per_s"], 1),
+           "bytes_per_launch": iso["bytes_per_launch"], "achieved_gbs": round(iso["achieved_gbs"], 1),
+           "hbm_frac": round(iso["achieved_gbs"] / HBM_PEAK_GBS, 4), "fft_tflops": round(iso["fft_tflops"], 2)}
+    del prob, y
+    torch.cuda.empty_cache()
+    return out
 
 
 def lm_comparison(prob, pr, dev, iters):

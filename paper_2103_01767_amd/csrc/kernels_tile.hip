@@ -84,7 +84,7 @@ __device__ __forceinline__ double tile_sum(double x, double* red, int col, int s
 }
 
 template <int MY, int MX, int OP>
-__device__ __forceinline__ void tile_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   using C = Cfg<MY, MX>;
   constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
   constexpr bool FWD_FFT = OP != OP_VJP;

@@ -66,7 +66,7 @@ __device__ __forceinline__ double wg_sum(double x, double* red, int col) {
 }  // namespace
 
 template <int OP>
-__device__ __forceinline__ void tile256_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   constexpr bool FWD_FFT = OP != OP_VJP;
   constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;

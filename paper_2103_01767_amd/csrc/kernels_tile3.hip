@@ -38,7 +38,7 @@ __device__ __forceinline__ int xcd_map3(int b, int n) {
 }  // namespace
 
 template <int L, int OP>
-__device__ __forceinline__ void tile3_body(const Geometry& g, const TileArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   using C = Cfg3<L>;
   constexpr int R = C::R, NT = C::NT, LDX = C::LDX, GMAX = C::GMAX;
   constexpr bool FWD_FFT = OP != OP_VJP;
