@@ -116,3 +116,65 @@ def test_first_attempt_matches_oracle_step():
         assert abs(s.cg_iters - h0.cg_iters) <= 1
         if s.cg_iters == h0.cg_iters:
             assert s.rho == pytest.approx(h0.rho, rel=1e-3, abs=1e-3)
+
+
+def _small_joint(seed=9):
+    pr = synth.make_small(seed, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(seed)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    return pr, prob, to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+
+
+def test_all_rejected_outer_iteration_keeps_iterate():
+    """Forced rejection: with no PCG iterations (and no accepted step to warm-start from) the
+    step is zero, its predicted reduction is not positive and every retry is rejected (reading
+    C9); the step reports PTLM_ENOTACCEPTED, the iterate is unchanged and t advances (C3)."""
+    pr, prob, O, P, y = _small_joint()
+    O0, P0 = O.clone(), P.clone()
+    params = pt.default_params(scaling=1, precond=1, cg_max=0, retry_max=3)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    assert prob.lm_step(O, P, y, params, st) == pt.PTLM_ENOTACCEPTED
+    s = pt.state_from_tensor(st)
+    assert s.t == 1 and s.attempts == 3 and s.retries == 3 and s.status == pt.PTLM_ENOTACCEPTED
+    assert torch.equal(O, O0) and torch.equal(P, P0)
+    assert s.mu == pytest.approx(1e-5 * 4.0 ** 3)
+    # the next outer iteration starts over (retries reset, same linearisation reused)
+    assert prob.lm_step(O, P, y, params, st) == pt.PTLM_ENOTACCEPTED
+    s = pt.state_from_tensor(st)
+    assert s.t == 2 and s.attempts == 6 and torch.equal(O, O0)
+
+
+def test_nonfinite_data_reports_enumeric_and_keeps_iterate():
+    pr, prob, O, P, y = _small_joint()
+    y[0, 3, 4] = float("nan")
+    O0, P0 = O.clone(), P.clone()
+    params = pt.default_params(scaling=1, precond=1)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    with pytest.raises(pt.PtlmError) as e:
+        prob.lm_step(O, P, y, params, st)
+    assert e.value.status == pt.PTLM_ENUMERIC
+    s = pt.state_from_tensor(st)
+    assert s.nonfinite == 1 and s.status == pt.PTLM_ENUMERIC and s.t == 0
+    assert torch.equal(O, O0) and torch.equal(P, P0)
+    with pytest.raises(pt.PtlmError):  # the state stays failed
+        prob.lm_step(O, P, y, params, st)
+
+
+def test_batch_with_one_failing_problem_finishes_the_others():
+    pr, prob, O, P, y = _small_joint(9)
+    pr2, prob2, O2, P2, y2 = _small_joint(10)
+    y2[1, 2, 2] = float("inf")
+    specs = [dict(obj_shape=p.O_true.shape, probe_shape=p.P_true.shape, positions=p.pos, mode="joint",
+                  background=p.background) for p in (pr, pr2)]
+    b = pt.Batch(specs, device=DEV)
+    params = pt.default_params(scaling=1, precond=1)
+    b.bind([O, O2], [P, P2], [y, y2], params, 3, use_graph=True)
+    status, attempts = b.solve(60, check_every=1)
+    assert status == pt.PTLM_ENUMERIC
+    s0, s1 = b.all_states()
+    assert s0.t == 3 and s0.status in (pt.PTLM_OK, pt.PTLM_ENOTACCEPTED)
+    assert s1.status == pt.PTLM_ENUMERIC and s1.t == 0
+    assert torch.equal(O2, to_dev(pr2.O_init, np.complex64))
