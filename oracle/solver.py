@@ -135,9 +135,23 @@ class LMParams:
     cg_max: int = 10
     retry_max: int = 10
     scaling: int = 0         # 0: D = I, 1: D = Dg(G) (App. B diagonal)
-    precond: int = 0         # 0: none, 1: Jacobi Dg(G + lambda D), 2: learned + lambda
+    precond: int = 0         # 0: none, 1: Jacobi Dg(G + lambda D), 2: learned + lambda D,
+                             # 3: exact diagonal of G + lambda D
     diag_floor: float = 1e-6
     warm_start: bool = True
+    surrogate_T: int = 0     # App. E surrogate Poisson metric: iterations with sigma_t > 0 (0: off)
+    surrogate_s0: float = 1.0
+
+
+def surrogate_sigma(t: int, p: "LMParams") -> float:
+    """sigma_t of the surrogate metric (App. E, eq:expected_count_surrogate): added to the
+    background, decreasing on a logarithmic grid from s0 and then 0.  The paper's grid "from
+    s0 to 0" cannot be logarithmic; read as s0 down to 1e-6 s0 over T iterations, then 0."""
+    if p.surrogate_T <= 0 or t >= p.surrogate_T:
+        return 0.0
+    if p.surrogate_T == 1:
+        return p.surrogate_s0
+    return p.surrogate_s0 * 1e-6 ** (t / (p.surrogate_T - 1))
 
 
 def gain_ratio(dfa: float, dfp: float) -> float:
@@ -194,7 +208,9 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
     """Truncated matrix-free LM, alg:lm_inexact, step by step.
 
     ``learned_diag`` is a real-coordinate diagonal (n, 2) that replaces Dg(G) in
-    the Jacobi preconditioner Dg(G + lambda D) when ``params.precond == 2``.  ``loss_fn``
+    the Jacobi preconditioner Dg(G + lambda D) when ``params.precond == 2``; precond 3 uses the
+    exact diagonal of G there.  With ``surrogate_T`` > 0 outer iteration t works on the
+    surrogate metric of App. E (background b + sigma_t), its trial loss included.  ``loss_fn``
     overrides the trial-loss evaluation (used to force branches in tests).
     ``progress(t, f_t)`` is called at the start of every outer iteration.
     """
@@ -205,11 +221,12 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
     mu = p.mu0
     prev_step = None
     res = LMResult(O=O, P=P, f=float("nan"))
-    trial_loss = loss_fn or (lambda O_, P_: ptycho.loss(O_, P_, pos, y, b, metric))
-
     for t in range(T):
+        # App. E: the surrogate metric of outer iteration t adds sigma_t to the background
+        b_t = b + surrogate_sigma(t, p)
+        trial_loss = loss_fn or (lambda O_, P_, b_t=b_t: ptycho.loss(O_, P_, pos, y, b_t, metric))
         # line "Calculate G, J, grad ell and D_t" -- once per outer iteration
-        lin = ptycho.linearize(O, P, pos, y, b, metric, joint)
+        lin = ptycho.linearize(O, P, pos, y, b_t, metric, joint)
         f_t = lin.f
         res.f_per_iter.append(f_t)
         if progress is not None:
@@ -226,6 +243,13 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
                 blocks.append(floor_block(dP.reshape(-1, 2), p.diag_floor))
             dg = np.concatenate(blocks, axis=0)
         scaled = p.scaling == 1
+        dx = None
+        if p.precond == 3:  # the exact diagonal of G in place of the App. B one, floored alike
+            eO, eP = ptycho.ggn_diag_exact(lin)
+            blocks = [floor_block(eO.reshape(-1, 2), p.diag_floor)]
+            if joint:
+                blocks.append(floor_block(eP.reshape(-1, 2), p.diag_floor))
+            dx = np.concatenate(blocks, axis=0)
 
         def apply_G(v):
             vO, vP = unpack(v, obj_shape, probe_shape, joint)
@@ -241,9 +265,9 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
             if p.precond == 1:
                 m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
                 pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
-            elif p.precond == 2:
-                # learned stand-in for Dg(G) inside Dg(G + lambda D)
-                m = learned_diag + lam * (dg if scaled else 1.0)
+            elif p.precond in (2, 3):
+                # learned or exact diagonal in place of Dg(G) inside Dg(G + lambda D)
+                m = (learned_diag if p.precond == 2 else dx) + lam * (dg if scaled else 1.0)
                 pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
             else:
                 pc = None

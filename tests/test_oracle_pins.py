@@ -426,3 +426,62 @@ def test_lm_joint_with_scaling_and_jacobi_decreases():
     res = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y, pr.background, "gauss", True, p, 8)
     assert res.f < 0.2 * res.f_per_iter[0]
     assert all(h.lam == h.mu for h in res.history)        # lambda = mu when D = Dg(G)
+
+
+# ---------------------------------------------------------------- NEXT: surrogate metric, exact Jacobi
+def test_surrogate_schedule_is_logarithmic_then_zero():
+    p = solver.LMParams(surrogate_T=5, surrogate_s0=1.0)
+    s = [solver.surrogate_sigma(t, p) for t in range(8)]
+    assert s[0] == 1.0 and s[4] == pytest.approx(1e-6) and s[5:] == [0.0, 0.0, 0.0]
+    ratios = [s[t + 1] / s[t] for t in range(4)]
+    np.testing.assert_allclose(ratios, ratios[0], rtol=1e-12)        # evenly spaced in log
+    assert solver.surrogate_sigma(0, solver.LMParams()) == 0.0          # off by default
+
+
+def test_surrogate_iterations_work_on_shifted_background():
+    """Outer iteration t linearises and judges its trial point on the metric with b + sigma_t
+    (eq:expected_count_surrogate); the loss values are recomputed here from the forward model."""
+    O, P, pos, y = tiny_problem(obj=(8, 8), probe=(4, 4), joint=False, metric="poisson")
+    b = 1e-3
+    p = solver.LMParams(surrogate_T=3, surrogate_s0=0.5, beta=0.9)
+    res = solver.lm_solve(O * 0.9, P, pos, y, b, "poisson", False, p, 4)
+    first = [h for h in res.history if h.t == 0][0]
+    h0 = ptycho.intensity(O * 0.9, P, pos, b + 0.5)
+    f0 = float(np.sum(h0 - y * np.log(h0)))                             # ell_p = zeta^2 - y log zeta^2
+    assert first.f == pytest.approx(f0, rel=1e-12)
+    assert res.f == pytest.approx(ptycho.loss(res.O, P, pos, y, b, "poisson"), rel=1e-12)
+    plain = solver.lm_solve(O * 0.9, P, pos, y, b, "poisson", False, solver.LMParams(beta=0.9), 4)
+    off = solver.lm_solve(O * 0.9, P, pos, y, b, "poisson", False, solver.LMParams(beta=0.9, surrogate_T=0), 4)
+    assert [h.f_trial for h in plain.history] == [h.f_trial for h in off.history]
+
+
+def test_exact_jacobi_first_step_matches_dense_construction():
+    """precond 3: one PCG iteration from zero with M = diag(G) + lambda (D = I); the step and
+    its trial loss are rebuilt here from the dense G of the JVP definition."""
+    O, P, pos, y = tiny_problem(obj=(6, 6), probe=(3, 3), joint=False)
+    b = 1e-3
+    p = solver.LMParams(precond=3, cg_max=1, scaling=0)
+    res = solver.lm_solve(O * 0.95, P, pos, y, b, "gauss", False, p, 1)
+    a0 = res.history[0]
+    lin = ptycho.linearize(O * 0.95, P, pos, y, b, "gauss", False)
+    n = O.size
+    # dense J from JVPs of the real unit vectors, G = J^T diag(l'') J
+    cols = []
+    for j in range(2 * n):
+        e = np.zeros(2 * n)
+        e[j] = 1.0
+        cols.append(ptycho.jvp(lin, (e[:n] + 1j * e[n:]).reshape(O.shape), None).ravel())
+    Jcols = np.stack(cols, axis=1)
+    G = Jcols.T @ (lin.l2.ravel()[:, None] * Jcols)
+    gO, _ = ptycho.gradient(lin)
+    g = np.concatenate([gO.real.ravel(), gO.imag.ravel()])
+    lam = a0.lam
+    d = np.maximum(np.diag(G), 1e-6 * np.diag(G).max())
+    m = d + lam
+    r0 = -g
+    z = r0 / m
+    Az = G @ z + lam * z
+    alpha = (r0 @ z) / (z @ Az)
+    step = alpha * z
+    Ot = O * 0.95 + (step[:n] + 1j * step[n:]).reshape(O.shape)
+    assert a0.f_trial == pytest.approx(ptycho.loss(Ot, P, pos, y, b, "gauss"), rel=1e-9)
