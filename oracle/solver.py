@@ -141,6 +141,14 @@ class LMParams:
     warm_start: bool = True
     surrogate_T: int = 0     # App. E surrogate Poisson metric: iterations with sigma_t > 0 (0: off)
     surrogate_s0: float = 1.0
+    project: bool = False    # alg:projected_LM plug-in (constrained BPR), constants of Sec. 5
+    o_max: float = 1.0       # eq:constraints: |O| <= 1
+    p_max: float = 1e8       #                 |P| <= 1e8
+    sigma_ls: float = 1e-4   # eq:armijo_criterion
+    gamma: float = 1e-6
+    tau_s: float = 1e-8
+    p_s: float = 2.1
+    ls_max: int = 30         # backtracking halvings before the iterate is kept
 
 
 def surrogate_sigma(t: int, p: "LMParams") -> float:
@@ -152,6 +160,47 @@ def surrogate_sigma(t: int, p: "LMParams") -> float:
     if p.surrogate_T == 1:
         return p.surrogate_s0
     return p.surrogate_s0 * 1e-6 ** (t / (p.surrogate_T - 1))
+
+
+def project(O, P, p: LMParams):
+    """Pi_Z of eq:projection for the separable sets of eq:constraints: the closest point with
+    |O| <= o_max and |P| <= p_max is a clamp of each entry's magnitude (phase kept)."""
+    def clamp(x, m):
+        a = np.abs(x)
+        return np.where(a > m, x * (m / np.where(a > 0, a, 1.0)), x)
+    return clamp(O, p.o_max), (clamp(P, p.p_max) if P is not None else None)
+
+
+def projected_update(O, P, step, g, f_t, loss, p: LMParams, joint):
+    """alg:projected_LM applied to an accepted LM step from the feasible point (O, P).
+
+    Reading of the garbled points: the first branch accepts the projected point
+    Pi_Z(z + Delta); otherwise a backtracking (halving) Armijo line search along
+    s = Pi_Z(z + Delta) - z when s is a sufficient descent direction (z + alpha s stays in Z
+    by convexity), else along -grad f with projection.  Returns (O, P, branch, alpha); when
+    no step size passes eq:armijo_criterion the iterate is kept (alpha = 0).
+    """
+    shapes = (O.shape, P.shape)
+    sO, sP = unpack(step, *shapes, joint)
+    Oc, Pc = project(O + sO, (P + sP) if joint else P, p)
+    if loss(Oc, Pc) < p.gamma * f_t:
+        return Oc, Pc, "lm", 1.0
+    s = pack(Oc - O, (Pc - P) if joint else None)
+    if rdot(g, s) <= -p.tau_s * rnorm(s) ** p.p_s:
+        d, proj, branch = s, False, "direction"
+    else:
+        d, proj, branch = -g, True, "gradient"
+    dn2 = rdot(d, d)
+    alpha = 1.0
+    for _ in range(p.ls_max):
+        dO, dP = unpack(alpha * d, *shapes, joint)
+        On, Pn = O + dO, (P + dP) if joint else P
+        if proj:
+            On, Pn = project(On, Pn, p)
+        if loss(On, Pn) <= f_t - p.sigma_ls * alpha * dn2:
+            return On, Pn, branch, alpha
+        alpha *= 0.5
+    return O, P, branch, 0.0
 
 
 def gain_ratio(dfa: float, dfp: float) -> float:
@@ -192,6 +241,7 @@ class Attempt:
     rho: float
     cg_iters: int
     accepted: bool
+    ls: tuple = None          # (branch, step size) of the projected plug-in, when used
 
 
 @dataclass
@@ -288,7 +338,11 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
             res.history.append(Attempt(t, f_t, f_trial, mu, lam, eta, rho, sol.iters, accepted))
             mu = mu_new
             if accepted:
-                O, P = O_t, P_t
+                if p.project:
+                    O, P, branch, alpha = projected_update(O, P, step, g, f_t, trial_loss, p, joint)
+                    res.history[-1].ls = (branch, alpha)
+                else:
+                    O, P = O_t, P_t
                 prev_step = step
                 break
             retries += 1

@@ -485,3 +485,49 @@ def test_exact_jacobi_first_step_matches_dense_construction():
     step = alpha * z
     Ot = O * 0.95 + (step[:n] + 1j * step[n:]).reshape(O.shape)
     assert a0.f_trial == pytest.approx(ptycho.loss(Ot, P, pos, y, b, "gauss"), rel=1e-9)
+
+
+# ---------------------------------------------------------------- NEXT: projected LM (constrained BPR)
+def test_projection_satisfies_the_variational_inequality():
+    """Pi_Z(x) is the Euclidean projection on {|z| <= m} iff Re(conj(x - Pi x)(y - Pi x)) <= 0
+    for every feasible y; checked on random points inside and outside and random feasible y."""
+    rng = np.random.default_rng(3)
+    p = solver.LMParams(o_max=1.0, p_max=2.5)
+    O = synth.random_complex(rng, (40,)) * 1.2
+    P = synth.random_complex(rng, (40,)) * 3.0
+    Oc, Pc = solver.project(O, P, p)
+    assert np.all(np.abs(Oc) <= 1.0 + 1e-15) and np.all(np.abs(Pc) <= 2.5 + 1e-15)
+    inside = np.abs(O) <= 1.0
+    assert np.array_equal(Oc[inside], O[inside])
+    for x, px, m in ((O, Oc, 1.0), (P, Pc, 2.5)):
+        for _ in range(50):
+            yv = m * np.sqrt(rng.uniform(size=x.shape)) * np.exp(2j * np.pi * rng.uniform(size=x.shape))
+            assert np.all(np.real(np.conj(x - px) * (yv - px)) <= 1e-12)
+
+
+def test_projected_lm_with_inactive_constraints_is_plain_lm():
+    O, P, pos, y = tiny_problem(obj=(9, 9), probe=(4, 4), joint=True)
+    b = 1e-3
+    base = dict(scaling=1, precond=1)
+    plain = solver.lm_solve(O * 0.9, P * 1.1, pos, y, b, "gauss", True, solver.LMParams(**base), 4)
+    proj = solver.lm_solve(O * 0.9, P * 1.1, pos, y, b, "gauss", True,
+                           solver.LMParams(project=True, o_max=1e30, p_max=1e30, **base), 4)
+    steps = [h.ls for h in proj.history if h.accepted]
+    assert steps and all(br == "direction" and a == 1.0 for br, a in steps)
+    np.testing.assert_allclose(proj.O, plain.O, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(proj.P, plain.P, rtol=0, atol=1e-14)
+
+
+def test_projected_lm_stays_feasible_and_descends():
+    """BPR with |O| <= 1: every accepted iterate of the plug-in is feasible and satisfies the
+    Armijo decrease, so the loss never increases (eq:armijo_criterion)."""
+    pr = synth.make_small(6, obj_side=32, probe=(8, 8), n=5, step=4, photons=1e3, mode="joint")
+    rng = np.random.default_rng(6)
+    O_true = pr.O_true / np.abs(pr.O_true).max()          # truth on the boundary of Z
+    y = synth.poisson_counts(rng, ptycho.intensity(O_true, pr.P_true, pr.pos, pr.background))
+    p = solver.LMParams(scaling=1, precond=1, project=True)
+    res = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y, pr.background, "gauss", True, p, 8)
+    assert np.abs(res.O).max() <= 1.0 + 1e-12
+    f = res.f_per_iter + [res.f]
+    assert all(f[i + 1] <= f[i] for i in range(len(f) - 1))
+    assert res.f < 0.5 * f[0]
