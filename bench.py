@@ -278,7 +278,8 @@ def lm_comparison(prob, pr, dev, iters):
     net = learned.lm_net(learned.load(dev), pr.O_true.shape, dev)
     out = {"target_loss": target, "oracle_final_loss": ref["f_final"], "oracle_iters": ref["T"],
            "max_iters": iters}
-    for name, prec, every in (("plain", 0, 1), ("jacobi", 1, 1), ("learned", 2, 1), ("learned_once", 2, 0)):
+    for name, prec, every in (("plain", 0, 1), ("jacobi", 1, 1), ("jacobi_exact", 3, 1), ("learned", 2, 1),
+                              ("learned_once", 2, 0)):
         pt.lm_set_cnn(prob, net if prec == 2 else None)
         if prec == 2:
             pt.lm_set_cnn_refresh(prob, every)

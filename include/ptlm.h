@@ -74,8 +74,16 @@ typedef struct {
   int32_t cg_max;     /* cap on PCG products per solve */
   int32_t retry_max;  /* cap on rejected attempts per outer iteration */
   int32_t scaling;    /* 0: D = I, 1: D = Dg(G) (App. B diagonal) */
-  int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: learned diagonal + lambda D */
+  int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: learned diagonal + lambda D,
+                         3: exact diagonal of G + lambda D (one more transform per linearisation) */
   int32_t warm_start; /* 1: PCG starts from the last accepted step */
+  int32_t surrogate_T;  /* App. E surrogate metric: outer iterations with sigma_t > 0 (0: off) */
+  double surrogate_s0;  /* sigma_0; sigma_t = s0 * 1e-6^(t / (T - 1)) for t < T, then 0 */
+  int32_t project;      /* 1: alg:projected_LM plug-in after every accepted step (single problems) */
+  int32_t ls_max;       /* backtracking halvings of its line search before the iterate is kept */
+  double o_max, p_max;  /* eq:constraints: |O| <= o_max (1), |P| <= p_max (1e8) */
+  double sigma_ls;      /* eq:armijo_criterion constant (1e-4) */
+  double gamma, tau_s, p_s; /* alg:projected_LM constants (1e-6, 1e-8, 2.1; Sec. 5) */
 } ptlm_lm_params;
 
 /* LM state, FP64, in DEVICE memory (written by the library, read by the caller). */
@@ -87,6 +95,8 @@ typedef struct {
   double resid_norm; /* ||grad_zeta ell|| */
   double pred;       /* predicted reduction of the last attempt */
   double rz, rr, alpha, beta_cg, pap; /* PCG scalars */
+  double sigma;      /* surrogate term added to the background in the current outer iteration */
+  double ls_alpha;   /* step size of the last projected plug-in (0: iterate kept) */
   int32_t t;         /* outer iterations completed */
   int32_t cg_iters;  /* products with A in the last solve */
   int32_t cg_total;  /* products with A since ptlm_lm_init */
@@ -104,6 +114,8 @@ typedef struct {
   int32_t t_max;     /* outer iterations to run: INT32_MAX after ptlm_lm_init, T in batches */
   int32_t status;    /* PTLM_OK, PTLM_ENOTACCEPTED (last outer iteration) or PTLM_ENUMERIC */
   int32_t iter_done; /* internal: the last attempt ended an outer iteration */
+  int32_t ls_branch; /* last projected plug-in: 0 projected LM step, 1 line search along the
+                        projected step, 2 projected gradient, -1 none */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;

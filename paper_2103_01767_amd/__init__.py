@@ -45,7 +45,11 @@ class ptlm_lm_params(ctypes.Structure):
                 ("nu", ctypes.c_double), ("rho_min", ctypes.c_double), ("beta", ctypes.c_double),
                 ("diag_floor", ctypes.c_double), ("cg_max", ctypes.c_int32),
                 ("retry_max", ctypes.c_int32), ("scaling", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("surrogate_T", ctypes.c_int32), ("surrogate_s0", ctypes.c_double),
+                ("project", ctypes.c_int32), ("ls_max", ctypes.c_int32), ("o_max", ctypes.c_double),
+                ("p_max", ctypes.c_double), ("sigma_ls", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("tau_s", ctypes.c_double), ("p_s", ctypes.c_double)]
 
 
 class ptlm_cnn_desc(ctypes.Structure):
@@ -53,9 +57,9 @@ class ptlm_cnn_desc(ctypes.Structure):
 
 
 _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
-                  "rz", "rr", "alpha", "beta_cg", "pap"]
+                  "rz", "rr", "alpha", "beta_cg", "pap", "sigma", "ls_alpha"]
 _STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
-               "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done"]
+               "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done", "ls_branch"]
 
 
 class ptlm_lm_state(ctypes.Structure):

@@ -225,16 +225,17 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   return PTLM_OK;
 }
 
-ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s) {
+ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s, const int* pred) {
   TileArgs a{};
   a.O = h->g.O_lin;
   a.P = h->g.P_lin;
+  a.predicate = pred;
   hipError_t e = launch_tile(h->g, OP_DIAG_EXACT, a, s);
   if (e != hipSuccess) return hip_fail(e, "diag exact");
-  e = launch_obj_reduce(h->g, (float2*)dO, 0.0, nullptr, nullptr, nullptr, nullptr, s);
+  e = launch_obj_reduce(h->g, (float2*)dO, 0.0, nullptr, nullptr, nullptr, pred, s);
   if (e != hipSuccess) return hip_fail(e, "diag exact O");
   if (dP) {
-    e = launch_probe_reduce(h->g, (float2*)dP, 0.0, nullptr, nullptr, nullptr, nullptr, s);
+    e = launch_probe_reduce(h->g, (float2*)dP, 0.0, nullptr, nullptr, nullptr, pred, s);
     if (e != hipSuccess) return hip_fail(e, "diag exact P");
   }
   return PTLM_OK;
@@ -421,6 +422,16 @@ void ptlm_lm_default_params(ptlm_lm_params* p) {
   p->scaling = 0;
   p->precond = 0;
   p->warm_start = 1;
+  p->surrogate_T = 0;
+  p->surrogate_s0 = 1.0;
+  p->project = 0;
+  p->ls_max = 30;
+  p->o_max = 1.0;
+  p->p_max = 1e8;
+  p->sigma_ls = 1e-4;
+  p->gamma = 1e-6;
+  p->tau_s = 1e-8;
+  p->p_s = 2.1;
 }
 
 ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {

@@ -160,6 +160,7 @@ struct BatchOps {
     }
     return PTLM_OK;
   }
+  ptlm_status exact_diag() { return fail(PTLM_EINVAL, "precond 3 is not available in batches"); }
   ptlm_status ggnv(int which) {
     PTLM_TRY(tiles(OP_GGNV, which == GG_WARM ? TK_WARM : TK_P));
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
@@ -349,6 +350,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (T < 0) return fail(PTLM_EINVAL, "T must be >= 0");
+  if (params->precond == 3) return fail(PTLM_EINVAL, "precond 3 is not available in batches");
+  if (params->project) return fail(PTLM_EINVAL, "the projected plug-in is not available in batches");
   for (int i = 0; i < b->n; ++i) {
     if (!d_O[i] || !d_P[i] || !d_y[i]) return fail(PTLM_EINVAL, "null array of problem " + std::to_string(i));
     if (params->precond == 2 && !b->hs[i]->cnn_params)
@@ -382,6 +385,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
         if (k == TK_LIN) {
           j.a.y = d_y[i];
           j.a.predicate = flags + FL_LIN;
+          j.a.bg_add = &d_states[i].sigma;
         } else if (k == TK_WARM || k == TK_P) {
           const float2* v0 = k == TK_WARM ? a.prev : a.p;
           j.a.vO = v0;
@@ -392,6 +396,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
           j.a.P = g.joint ? a.ztrial + a.nobj : (const float2*)d_P[i];
           j.a.y = d_y[i];
           j.a.predicate = flags + FL_ALIVE;
+          j.a.bg_add = &d_states[i].sigma;
         }
         v.push_back(j);
       }

@@ -59,6 +59,7 @@ struct TileArgs {
   const float* win;       // K*M real input (VJP)
   float* rout;            // K*M real output (FORWARD zeta, LOSS residual, JVP)
   const int* predicate;   // if non-null and *predicate == 0 the launch does nothing
+  const double* bg_add;   // if non-null, added to the background (surrogate metric, App. E)
 };
 
 // One problem's part of a batched launch: its geometry, its arguments and the first block

@@ -28,12 +28,22 @@ __device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r
     }
     return make_float2(r.x / (d.x + (float)lam), r.y / (d.y + (float)lam));
   }
-  if (a.prm.precond == 2) {  // learned stand-in for Dg(G), plus lambda D
+  if (a.prm.precond == 2 || a.prm.precond == 3) {  // learned or exact Dg(G), plus lambda D
     const float2 d = a.learned[i];
     const float2 D = a.prm.scaling ? a.diag[i] : make_float2(1.f, 1.f);
     return make_float2(r.x / fmaf((float)lam, D.x, d.x), r.y / fmaf((float)lam, D.y, d.y));
   }
   return r;
+}
+
+// eq:projection for the sets of eq:constraints: clamp the magnitude of an object entry to
+// o_max and of a probe entry to p_max (the phase is kept)
+__device__ __forceinline__ float2 project_entry(const LMArgs& a, size_t i, float2 v) {
+  const double m = i < a.nobj ? a.prm.o_max : a.prm.p_max;
+  const double r = sqrt((double)v.x * v.x + (double)v.y * v.y);
+  if (r <= m) return v;
+  const double s = m / r;
+  return make_float2((float)(v.x * s), (float)(v.y * s));
 }
 
 __device__ __forceinline__ float2 apply_D(const LMArgs& a, size_t i, float2 v) {
@@ -70,6 +80,37 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float f = (float)(a.prm.diag_floor * (i < a.nobj ? a.scal[SC_DMAX_O] : a.scal[SC_DMAX_P]));
       const float2 d = a.diag[i];
       a.diag[i] = make_float2(fmaxf(d.x, f), fmaxf(d.y, f));
+    } else if constexpr (OP == V_PROJ) {
+      a.ztrial[i] = project_entry(a, i, a.ztrial[i]);
+    } else if constexpr (OP == V_LS_DIR || OP == V_LS_NEG) {
+      // search direction: the projected step s = Pi(z + Delta) - z, or -grad f
+      const float2 g = a.g[i];
+      float2 d;
+      if constexpr (OP == V_LS_DIR) {
+        const float2 zt = a.ztrial[i];
+        const float2 z = i < a.nobj ? a.Olin[i] : a.Plin[i - a.nobj];
+        d = make_float2(zt.x - z.x, zt.y - z.y);
+      } else {
+        d = make_float2(-g.x, -g.y);
+      }
+      a.r[i] = d;
+      acc0 += rdot(g, d);
+      acc1 += rdot(d, d);
+    } else if constexpr (OP == V_LS_CAND) {
+      const float2 z = i < a.nobj ? a.Olin[i] : a.Plin[i - a.nobj];
+      const float2 d = a.r[i];
+      float2 c = make_float2(fmaf(a.ls_alpha, d.x, z.x), fmaf(a.ls_alpha, d.y, z.y));
+      if (a.ls_proj) c = project_entry(a, i, c);
+      a.ztrial[i] = c;
+    } else if constexpr (OP == V_XMAX) {
+      const float2 d = a.xdiag[i];
+      const double m = fmax((double)d.x, (double)d.y);
+      if (i < a.nobj) acc0 = fmax(acc0, m);
+      else acc1 = fmax(acc1, m);
+    } else if constexpr (OP == V_XFLOOR) {
+      const float f = (float)(a.prm.diag_floor * (i < a.nobj ? a.scal[SC_XMAX_O] : a.scal[SC_XMAX_P]));
+      const float2 d = a.xdiag[i];
+      a.xdiag[i] = make_float2(fmaxf(d.x, f), fmaxf(d.y, f));
     } else if constexpr (OP == V_CG_INIT) {
       const float2 g = a.g[i];
       float2 r;
@@ -114,8 +155,9 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       acc0 += (double)x.x * (lam * (double)dd.x - (double)g.x) + (double)x.y * (lam * (double)dd.y - (double)g.y);
     }
   }
-  constexpr bool SUMS = OP == V_GNORM || OP == V_DIAGMAX || OP == V_CG_INIT || OP == V_PAP ||
-                        OP == V_CG_UPDATE || OP == V_TRIAL;
+  constexpr bool MAXR = OP == V_DIAGMAX || OP == V_XMAX;
+  constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_PAP || OP == V_CG_UPDATE ||
+                        OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG;
   if constexpr (SUMS) {
     __shared__ double sh[256][2];
     sh[threadIdx.x][0] = acc0;
@@ -123,7 +165,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
       if (threadIdx.x < w) {
-        if constexpr (OP == V_DIAGMAX) {
+        if constexpr (MAXR) {
           sh[threadIdx.x][0] = fmax(sh[threadIdx.x][0], sh[threadIdx.x + w][0]);
           sh[threadIdx.x][1] = fmax(sh[threadIdx.x][1], sh[threadIdx.x + w][1]);
         } else {
@@ -154,14 +196,22 @@ __global__ __launch_bounds__(256) void vec_batch_kernel(const LMJob* __restrict_
 
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
+// sigma_t of the surrogate metric (App. E): s0 * 1e-6^(t / (T - 1)) for t < T, then 0
+__device__ __forceinline__ double surrogate_sigma(const ptlm_lm_params& p, int t) {
+  if (p.surrogate_T <= 0 || t >= p.surrogate_T) return 0.0;
+  if (p.surrogate_T == 1) return p.surrogate_s0;
+  return p.surrogate_s0 * pow(1e-6, (double)t / (double)(p.surrogate_T - 1));
+}
+
 // One block: reduce `count` partials (fixed order), then run the scalar step.
 template <int OP>
 __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   if (flag_clear(a, flag)) return;
   __shared__ double sh[256][2];
   double acc0 = 0.0, acc1 = 0.0;
+  constexpr bool MAXR = OP == F_DIAGMAX || OP == F_XMAX;
   for (int i = threadIdx.x; i < count; i += 256) {
-    if constexpr (OP == F_DIAGMAX) {
+    if constexpr (MAXR) {
       acc0 = fmax(acc0, a.partials[i * 4]);
       acc1 = fmax(acc1, a.partials[i * 4 + 1]);
     } else {
@@ -174,7 +224,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
-      if constexpr (OP == F_DIAGMAX) {
+      if constexpr (MAXR) {
         sh[threadIdx.x][0] = fmax(sh[threadIdx.x][0], sh[threadIdx.x + w][0]);
         sh[threadIdx.x][1] = fmax(sh[threadIdx.x][1], sh[threadIdx.x + w][1]);
       } else {
@@ -190,8 +240,16 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   const ptlm_lm_params& p = a.prm;
   if constexpr (OP == F_ATTEMPT) {
     // an attempt runs while the outer-iteration budget lasts and no non-finite value was met;
-    // it linearises first when the previous attempt was accepted (or at the start)
+    // it linearises first when the previous attempt was accepted (or at the start), or when
+    // the surrogate term of the metric (App. E) changed with the outer iteration
     st.alive = (st.t < st.t_max && st.status != PTLM_ENUMERIC) ? 1 : 0;
+    if (st.alive) {
+      const double sg = surrogate_sigma(p, st.t);
+      if (sg != st.sigma) {
+        st.sigma = sg;
+        st.need_lin = 1;
+      }
+    }
     st.lin_now = (st.alive && st.need_lin) ? 1 : 0;
     if (st.alive && st.iter_done) {  // a new outer iteration starts: no rejected attempts yet
       st.retries = 0;
@@ -215,6 +273,12 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   } else if constexpr (OP == F_DIAGMAX) {
     a.scal[SC_DMAX_O] = s0;
     a.scal[SC_DMAX_P] = s1;
+  } else if constexpr (OP == F_XMAX) {
+    a.scal[SC_XMAX_O] = s0;
+    a.scal[SC_XMAX_P] = s1;
+  } else if constexpr (OP == F_LS) {
+    a.scal[SC_LS0] = s0;
+    a.scal[SC_LS1] = s1;
   } else if constexpr (OP == F_BEGIN) {
     // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
     // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).  The first attempt
@@ -291,6 +355,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   } else if constexpr (OP == F_INIT) {
     st = ptlm_lm_state{};
     st.mu = p.mu0;
+    st.sigma = surrogate_sigma(p, 0);
     st.need_lin = 1;
     st.t_max = a.t_max;
     st.status = PTLM_OK;
@@ -333,10 +398,11 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 }
 
 #define PTLM_VEC_CASES(X)                                                                                 \
-  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL)
+  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL) X(V_XMAX) \
+  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND)
 #define PTLM_FIN_CASES(X)                                                                                 \
-  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
-  X(F_INIT)
+  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
+  X(F_INIT) X(F_LS)
 
 hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s) {
   switch (op) {

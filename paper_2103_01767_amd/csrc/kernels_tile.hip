@@ -115,6 +115,7 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   const float2* twy = tw_table(s_tw, MY);
   const float isq = rsqrtf((float)C::M);
   const bool joint = g.joint != 0;
+  const float bgv = a.bg_add ? (float)((double)g.background + *a.bg_add) : g.background;
 
   constexpr int VA = C::PROBE_REGS ? V : 1;
   constexpr int JA = C::PROBE_REGS ? 16 : 1;
@@ -312,7 +313,7 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
             const size_t gi = base + (size_t)ky * MX + yc;
             if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
               const float2 ps = cscale(v[u][r], isq);
-              const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, g.background));
+              const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, bgv));
               const float iz = rsqrtf(h);
               const float zeta = h * iz;
               if constexpr (OP == OP_FORWARD) {

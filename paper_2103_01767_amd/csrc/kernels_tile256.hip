@@ -88,6 +88,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
   float2* lrow = smem + rr * LDR;
   const float isq = 1.0f / 256.0f;
   const bool joint = g.joint != 0;
+  const float bgv = a.bg_add ? (float)((double)g.background + *a.bg_add) : g.background;
   float2* pslot = g.probe_part + (size_t)seg * M256;
   double s0 = 0.0, s1 = 0.0;
 
@@ -203,7 +204,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
           const size_t gi = base + (size_t)(cs + 16 * r) * S + kx;
           if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
             const float2 ps = cscale(v[r], isq);
-            const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, g.background));
+            const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, bgv));
             const float iz = rsqrtf(h);
             const float zeta = h * iz;
             if constexpr (OP == OP_FORWARD) {

@@ -70,6 +70,7 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
   const int yc = t % L, ys = t / L;  // y passes: line (column) and residue / pass-2 lane
   const float isq = 1.0f / (float)L;
   const bool joint = g.joint != 0;
+  const float bgv = a.bg_add ? (float)((double)g.background + *a.bg_add) : g.background;
   float2 accP[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) accP[j] = make_float2(0.f, 0.f);
@@ -207,7 +208,7 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
 #pragma unroll
             for (int k2 = 0; k2 < R; ++k2) {
               const size_t gi = base + (size_t)(k1 + 16 * k2) * L + yc;
-              pixel_op<OP>(g, a, gi, isq, v[gg * R + k2], s0, s1, tr);
+              pixel_op<OP>(g, a, gi, isq, bgv, v[gg * R + k2], s0, s1, tr);
             }
           }
         }

@@ -28,9 +28,12 @@ LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st
   a.Ap = at(p.off.Ap);
   a.ztrial = at(p.off.ztrial);
   a.diag = at(p.off.diag);
-  a.learned = (const float2*)learned;
+  a.xdiag = at(p.off.learned);
+  a.learned = prm && prm->precond == 3 ? a.xdiag : (const float2*)learned;
   a.O = O;
   a.P = P;
+  a.Olin = h->g.O_lin;
+  a.Plin = h->g.P_lin;
   a.n = p.nvec;
   a.nobj = (size_t)p.d.ny * p.d.nx;
   a.st = st;
@@ -53,7 +56,10 @@ ptlm_status check_lm_params(const ptlm_lm_params* p) {
   if (!p) return fail(PTLM_EINVAL, "params is null");
   if (!(p->mu0 > 0) || !(p->mu_min > 0) || !(p->kappa > 1) || !(p->nu >= 0) || !(p->rho_min > 0) ||
       !(p->beta > 0) || !(p->diag_floor >= 0) || p->cg_max < 0 || p->retry_max < 1 ||
-      (p->scaling != 0 && p->scaling != 1) || p->precond < 0 || p->precond > 2)
+      (p->scaling != 0 && p->scaling != 1) || p->precond < 0 || p->precond > 3 || p->surrogate_T < 0 ||
+      !(p->surrogate_s0 >= 0.0) || !std::isfinite(p->surrogate_s0) || (p->project != 0 && p->project != 1) ||
+      (p->project && (p->ls_max < 0 || !(p->o_max > 0) || !(p->p_max > 0) || !(p->sigma_ls >= 0) ||
+                      !(p->gamma >= 0) || !(p->tau_s >= 0) || !(p->p_s > 1))))
     return fail(PTLM_EINVAL, "invalid LM parameters");
   return PTLM_OK;
 }
@@ -93,6 +99,7 @@ struct SingleOps {
     ta.P = g.P_lin;
     ta.y = y;
     ta.predicate = flag(FL_LIN);
+    ta.bg_add = &a.st->sigma;
     LM_HIP(launch_tile(g, OP_LINEARIZE, ta, s), "lm linearize");
     LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_LIN)), "lm linearize sum");
     LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_LIN), s), "lm gradient O");
@@ -123,6 +130,9 @@ struct SingleOps {
     }
     return PTLM_OK;
   }
+  ptlm_status exact_diag() {
+    return diag_exact_impl(h, (float*)a.xdiag, h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, flag(FL_LIN));
+  }
   ptlm_status ggnv(int which) {
     const float2* v = which == GG_WARM ? a.prev : a.p;
     const int* pred = which == GG_WARM ? flag(FL_WARM) : flag(FL_CG);
@@ -139,6 +149,7 @@ struct SingleOps {
     ta.P = g.joint ? a.ztrial + a.nobj : P;
     ta.y = y;
     ta.predicate = flag(FL_ALIVE);
+    ta.bg_add = &a.st->sigma;
     LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
     return PTLM_OK;
   }
@@ -157,6 +168,89 @@ static ptlm_status read_state(ptlm_lm_state* d, ptlm_lm_state* hs, hipStream_t s
   return PTLM_OK;
 }
 
+static ptlm_status read_scal(const double* d, double* out, int count, hipStream_t s) {
+  LM_HIP(hipMemcpyAsync(out, d, count * sizeof(double), hipMemcpyDeviceToHost, s), "lm read scalars");
+  LM_HIP(hipStreamSynchronize(s), "lm sync");
+  return PTLM_OK;
+}
+
+// loss at the trial buffer (surrogate term included) into scal[SC_LSF], read back
+static ptlm_status trial_value(SingleOps& o, double* f) {
+  TileArgs ta{};
+  ta.O = o.a.ztrial;
+  ta.P = o.h->g.joint ? o.a.ztrial + o.a.nobj : o.P;
+  ta.y = o.y;
+  ta.bg_add = &o.a.st->sigma;
+  LM_HIP(launch_tile(o.h->g, OP_LOSS, ta, o.s), "projected loss");
+  LM_HIP(launch_sum_partials(o.h->g.partials, o.h->g.grid, o.a.scal + SC_LSF, 1, o.s), "projected loss sum");
+  return read_scal(o.a.scal + SC_LSF, f, 1, o.s);
+}
+
+// copy the trial buffer (or, with keep, the linearisation point) into the iterate
+static ptlm_status set_iterate(SingleOps& o, bool keep) {
+  const Geometry& g = o.h->g;
+  const float2* srcO = keep ? g.O_lin : o.a.ztrial;
+  const float2* srcP = keep ? g.P_lin : o.a.ztrial + o.a.nobj;
+  LM_HIP(launch_copy(srcO, o.O, o.a.nobj, nullptr, o.s), "projected iterate O");
+  if (g.joint) LM_HIP(launch_copy(srcP, o.P, (size_t)g.my * g.mx, nullptr, o.s), "projected iterate P");
+  return PTLM_OK;
+}
+
+// alg:projected_LM after an accepted step Delta from z_t (O_lin, P_lin), the trial buffer
+// holding z_t + Delta: accept Pi(z_t + Delta) if it cuts f below gamma f(z_t); otherwise a
+// halving Armijo line search (eq:armijo_criterion) along s = Pi(z_t + Delta) - z_t when s is a
+// sufficient descent direction, else along -grad f with projection; no passing step size
+// keeps z_t.  The outcome is written to the state (ls_branch, ls_alpha).
+static ptlm_status projected_plugin(SingleOps& o, const ptlm_lm_params& prm, double f_t) {
+  LMArgs& a = o.a;
+  double fc = 0.0, alpha = 1.0;
+  int branch = 0;
+  bool done = false;
+  LM_HIP(launch_vec(V_PROJ, a, FL_NONE, o.s), "projection");
+  PTLM_TRY(trial_value(o, &fc));
+  if (fc < prm.gamma * f_t) {
+    PTLM_TRY(set_iterate(o, false));
+    done = true;
+  } else {
+    double gs[2];
+    LM_HIP(launch_vec(V_LS_DIR, a, FL_NONE, o.s), "line-search direction");
+    LM_HIP(launch_fin(F_LS, a, a.vec_blocks, FL_NONE, o.s), "line-search direction sums");
+    PTLM_TRY(read_scal(a.scal + SC_LS0, gs, 2, o.s));
+    branch = 1;
+    a.ls_proj = 0;
+    if (!(gs[0] <= -prm.tau_s * std::pow(std::sqrt(gs[1]), prm.p_s))) {
+      branch = 2;
+      a.ls_proj = 1;
+      LM_HIP(launch_vec(V_LS_NEG, a, FL_NONE, o.s), "line-search gradient");
+      LM_HIP(launch_fin(F_LS, a, a.vec_blocks, FL_NONE, o.s), "line-search gradient sums");
+      PTLM_TRY(read_scal(a.scal + SC_LS0, gs, 2, o.s));
+    }
+    const double dn2 = gs[1];
+    for (int i = 0; i < prm.ls_max && !done; ++i) {
+      a.ls_alpha = (float)alpha;
+      LM_HIP(launch_vec(V_LS_CAND, a, FL_NONE, o.s), "line-search candidate");
+      double fn = 0.0;
+      PTLM_TRY(trial_value(o, &fn));
+      if (fn <= f_t - prm.sigma_ls * alpha * dn2) {
+        PTLM_TRY(set_iterate(o, false));
+        done = true;
+      } else {
+        alpha *= 0.5;
+      }
+    }
+  }
+  if (!done) {
+    PTLM_TRY(set_iterate(o, true));
+    alpha = 0.0;
+  }
+  // record the outcome in the device state (the stream is synchronised before return)
+  struct { double alpha; int branch; } rec{alpha, done ? branch : -1};
+  LM_HIP(hipMemcpyAsync(&a.st->ls_alpha, &rec.alpha, sizeof(double), hipMemcpyHostToDevice, o.s), "ls record");
+  LM_HIP(hipMemcpyAsync(&a.st->ls_branch, &rec.branch, sizeof(int), hipMemcpyHostToDevice, o.s), "ls record");
+  LM_HIP(hipStreamSynchronize(o.s), "ls sync");
+  return PTLM_OK;
+}
+
 static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const float* y, const ptlm_lm_params* prm,
                                 ptlm_lm_state* st, const float* learned, hipStream_t s) {
   ptlm_lm_state hs;
@@ -172,6 +266,7 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
     if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
     if (hs.t > t0) break;
   }
+  if (prm->project && hs.t > t0 && hs.accepted) PTLM_TRY(projected_plugin(o, *prm, hs.f));
   if (hs.t == t0) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
   if (hs.status == PTLM_ENOTACCEPTED) return fail(PTLM_ENOTACCEPTED, "every retry of this outer iteration was rejected");
   return PTLM_OK;

@@ -19,7 +19,7 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
   } while (0)
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
-// diag_paper(), learned(), ggnv(which), trial_loss(), copy_accept().
+// diag_paper(), learned(), exact_diag(), ggnv(which), trial_loss(), copy_accept().
 template <class Ops>
 ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.fin(F_ATTEMPT, 0, FL_NONE));
@@ -35,6 +35,12 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
     PTLM_TRY(o.vec(V_DIAGFLOOR, FL_LIN));
   }
   if (prm.precond == 2) PTLM_TRY(o.learned());
+  if (prm.precond == 3) {
+    PTLM_TRY(o.exact_diag());  // exact Dg(G) in place of the App. B one, floored alike
+    PTLM_TRY(o.vec(V_XMAX, FL_LIN));
+    PTLM_TRY(o.fin(F_XMAX, 1, FL_LIN));
+    PTLM_TRY(o.vec(V_XFLOOR, FL_LIN));
+  }
   // ---- lambda, eta, PCG on (G + lambda D) Delta = -g
   PTLM_TRY(o.fin(F_BEGIN, 0, FL_ALIVE));
   PTLM_TRY(o.ggnv(GG_WARM));  // A Delta_0 for the warm start

@@ -15,10 +15,13 @@ inline int lm_vec_blocks(size_t n) {
 }
 
 // indices into the FP64 scalar scratch
-enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4 };
+enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4, SC_XMAX_O = 5, SC_XMAX_P = 6,
+       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14 };
 
-enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL };
-enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT };
+enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL, V_XMAX, V_XFLOOR,
+                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND };
+enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT,
+                   F_LS };
 
 // Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
 enum LMFlag : int {
@@ -33,8 +36,12 @@ enum LMFlag : int {
 struct LMArgs {
   float2 *g, *dx, *prev, *r, *z, *p, *Ap, *ztrial;
   float2* diag;            // (Re, Im) weights of Dg(G) per complex entry, floored
-  const float2* learned;   // learned preconditioner diagonal (precond == 2)
+  const float2* learned;   // learned (precond 2) or exact (precond 3) diagonal standing for Dg(G)
+  float2* xdiag;           // exact-diagonal buffer (precond 3, floored in place)
   const float2 *O, *P;     // current iterate
+  const float2 *Olin, *Plin;  // linearisation point z_t (projected plug-in)
+  float ls_alpha;          // line-search step size (V_LS_CAND)
+  int ls_proj;             // 1: project the line-search candidate
   size_t n, nobj;          // complex entries of a vector / of its object part
   ptlm_lm_state* st;
   ptlm_lm_params prm;

@@ -10,7 +10,8 @@
 //   VJP        w a (divided by sqrt(ell'') for the Poisson metric)
 //
 // v holds the unnormalised transform; isq = 1/sqrt(M) applies the unitary normalisation
-// (eq:expected_count).  Gaussian ell = (zeta - sqrt y)^2 / 2, Poisson ell = zeta^2 - y log zeta^2.
+// (eq:expected_count); bgv is the background (plus the surrogate term of App. E when set).
+// Gaussian ell = (zeta - sqrt y)^2 / 2, Poisson ell = zeta^2 - y log zeta^2.
 #pragma once
 #include "dft.hpp"
 #include "internal.hpp"
@@ -23,11 +24,11 @@ __device__ __forceinline__ float2 ld_once(const float2* p) {
 }
 
 template <int OP>
-__device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, size_t gi, float isq, float2& v,
-                                         double& s0, double& s1, double& tr) {
+__device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, size_t gi, float isq, float bgv,
+                                         float2& v, double& s0, double& s1, double& tr) {
   if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
     const float2 ps = cscale(v, isq);
-    const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, g.background));
+    const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, bgv));
     const float iz = rsqrtf(h);
     const float zeta = h * iz;
     if constexpr (OP == OP_FORWARD) {

@@ -167,3 +167,35 @@ def test_batch_learned_preconditioner_equals_alone():
         s2 = batch.state(i)
         assert s2.t == T and s2.f == s1.f and s2.products == s1.products
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+def test_batch_surrogate_equals_alone():
+    """The surrogate term of App. E is read from each problem's device state by the batched
+    kernels: a Poisson batch with the schedule equals its problems solved alone."""
+    probs = make_problems()[:3]
+    for p in probs:
+        p["metric"] = "poisson"
+    params = pt.default_params(scaling=1, precond=1, beta=0.9, cg_max=5, surrogate_T=3, surrogate_s0=1.0)
+    T = 4
+    alone = []
+    for p in probs:
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], metric="poisson", mode="joint",
+                          device=DEV)
+        O, P = c64(p["O0"]), c64(p["P0"])
+        y = torch.from_numpy(p["y"]).to(DEV)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(T):
+            prob.lm_step(O, P, y, params, st)
+        alone.append((O, P, pt.state_from_tensor(st)))
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(100, check_every=1)
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        assert s2.t == T and s2.f == s1.f and s2.sigma == s1.sigma == 0.0
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)

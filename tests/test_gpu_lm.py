@@ -178,3 +178,74 @@ def test_batch_with_one_failing_problem_finishes_the_others():
     assert s0.t == 3 and s0.status in (pt.PTLM_OK, pt.PTLM_ENOTACCEPTED)
     assert s1.status == pt.PTLM_ENUMERIC and s1.t == 0
     assert torch.equal(O2, to_dev(pr2.O_init, np.complex64))
+
+
+@pytest.mark.parametrize("variant", ["surrogate_poisson", "exact_jacobi"])
+def test_lm_variants_match_oracle_final_loss(variant):
+    """The surrogate Poisson metric of App. E (PLM-S, beta = 0.9) and the exact-diagonal
+    Jacobi preconditioner: final loss within 1.01x of the oracle's LM on the same problem."""
+    print("case lm variant", variant, flush=True)
+    pr = synth.make_small(11, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(11)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    if variant == "surrogate_poisson":
+        metric, T = "poisson", 8
+        kw = dict(scaling=1, precond=1, beta=0.9, surrogate_T=5, surrogate_s0=1.0)
+    else:
+        metric, T = "gauss", 8
+        kw = dict(scaling=1, precond=3)
+    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, metric, True,
+                          solver.LMParams(**kw), T)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, metric=metric, mode="joint",
+                      background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(**kw)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    s0 = pt.state_from_tensor(st)
+    if variant == "surrogate_poisson":
+        assert s0.sigma == 1.0
+    prob.lm_solve(O, P, yd, params, T, st)
+    s = pt.state_from_tensor(st)
+    f_gpu = float(prob.loss(O, P, yd).cpu()[0])
+    print("%s oracle f=%.6e gpu f=%.6e sigma=%g" % (variant, ref.f, f_gpu, s.sigma))
+    assert s.t == T
+    # the Poisson metric is negative in general: the 1.01x bar applies above its per-pixel
+    # minimum sum(y - y log y), reached at zeta^2 = y (0 log 0 = 0)
+    yy = y.astype(np.float64)
+    f_min = float(np.sum(yy - yy * np.log(np.where(yy > 0, yy, 1.0)))) if metric == "poisson" else 0.0
+    assert f_gpu - f_min <= 1.01 * (ref.f - f_min)
+    if variant == "surrogate_poisson":
+        assert s.sigma == 0.0   # after T_s iterations the metric is the true Poisson one
+
+
+def test_projected_lm_matches_oracle():
+    """alg:projected_LM (|O| <= 1): feasible iterates, same plug-in branch as the oracle on the
+    first iteration, final loss within 1.01x of the oracle's."""
+    print("case projected lm", flush=True)
+    pr = synth.make_small(6, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(6)
+    O_true = pr.O_true / np.abs(pr.O_true).max()
+    y = synth.poisson_counts(rng, ptycho.intensity(O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    T = 8
+    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, "gauss", True,
+                          solver.LMParams(scaling=1, precond=1, project=True), T)
+    first = [h for h in ref.history if h.t == 0 and h.accepted][0]
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(scaling=1, precond=1, project=1)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_step(O, P, yd, params, st)
+    s = pt.state_from_tensor(st)
+    names = {0: "lm", 1: "direction", 2: "gradient", -1: "none"}
+    assert names[s.ls_branch] == first.ls[0]
+    assert s.ls_alpha == pytest.approx(first.ls[1])
+    fs = [float(prob.loss(O, P, yd).cpu()[0])]
+    for _ in range(T - 1):
+        prob.lm_step(O, P, yd, params, st)
+        fs.append(float(prob.loss(O, P, yd).cpu()[0]))
+        assert float(torch.abs(O).max()) <= 1.0 + 1e-6
+    print("projected oracle f=%.6e gpu f=%.6e" % (ref.f, fs[-1]))
+    assert all(fs[i + 1] <= fs[i] * (1 + 1e-6) for i in range(len(fs) - 1))
+    assert fs[-1] <= 1.01 * ref.f
