@@ -158,12 +158,17 @@ __global__ __launch_bounds__(256) void sum_partials_batch_kernel(const RedJob* _
 }
 
 // App. B diagonal, object part: d_n = (1/2M) sum_{k covering n} trace_k |P[n - r_k]|^2,
-// the same weight for the Re and Im coordinates.  The tile's position list is staged in LDS.
+// the same weight for the Re and Im coordinates.  One 1024-thread block per 16x16 object
+// tile: the tile's position list is staged in LDS, each pixel's sum is split four ways over
+// the list and the four parts are added in a fixed order.
+constexpr int DIAG_OBJ_THREADS = 1024;
 __device__ __forceinline__ void diag_paper_obj_body(const Geometry& g, float* dO, int bx, int by) {
   __shared__ int2 s_pos[OBJ_LIST];
   __shared__ double s_tr[OBJ_LIST];
-  const int X = bx * 16 + (threadIdx.x & 15);
-  const int Y = by * 16 + (threadIdx.x >> 4);
+  __shared__ double s_part[4][256];
+  const int px = threadIdx.x & 255, grp = threadIdx.x >> 8;
+  const int X = bx * 16 + (px & 15);
+  const int Y = by * 16 + (px >> 4);
   const bool in = X < g.nx && Y < g.ny;
   const int tile = by * g.otiles_x + bx;
   const int b = g.ptile_ptr[tile], e = g.ptile_ptr[tile + 1];
@@ -179,7 +184,7 @@ __device__ __forceinline__ void diag_paper_obj_body(const Geometry& g, float* dO
     __syncthreads();
     if (in) {
 #pragma unroll 4
-      for (int i = 0; i < cnt; ++i) {
+      for (int i = grp; i < cnt; i += 4) {
         const int2 r = s_pos[i];
         const int my = Y - r.x, mx = X - r.y;
         if ((unsigned)my < (unsigned)g.my && (unsigned)mx < (unsigned)g.mx) {
@@ -189,19 +194,22 @@ __device__ __forceinline__ void diag_paper_obj_body(const Geometry& g, float* dO
       }
     }
   }
-  if (!in) return;
+  s_part[grp][px] = acc;
+  __syncthreads();
+  if (!in || grp != 0) return;
+  acc = (s_part[0][px] + s_part[1][px]) + (s_part[2][px] + s_part[3][px]);
   const float val = (float)(acc / (2.0 * g.my * g.mx));
   const size_t n = (size_t)Y * g.nx + X;
   dO[2 * n] = val;
   dO[2 * n + 1] = val;
 }
 
-__global__ __launch_bounds__(256) void diag_paper_obj_kernel(Geometry g, float* dO, const int* pred) {
+__global__ __launch_bounds__(1024) void diag_paper_obj_kernel(Geometry g, float* dO, const int* pred) {
   if (pred && *pred == 0) return;
   diag_paper_obj_body(g, dO, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void diag_paper_obj_batch_kernel(const RedJob* __restrict__ jobs,
+__global__ __launch_bounds__(1024) void diag_paper_obj_batch_kernel(const RedJob* __restrict__ jobs,
                                                                    const int* __restrict__ job_of_block) {
   const RedJob& J = jobs[job_of_block[blockIdx.x]];
   if (J.pred && *J.pred == 0) return;
@@ -209,18 +217,19 @@ __global__ __launch_bounds__(256) void diag_paper_obj_batch_kernel(const RedJob*
   diag_paper_obj_body(J.g, (float*)J.outO, l % J.g.otiles_x, l / J.g.otiles_x);
 }
 
-// App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; 64 pixels per
-// block, the position sum split four ways and combined in a fixed order.
+// App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; one 1024-thread
+// block per 16 pixels, the position sum split 64 ways and combined in a fixed order.
+constexpr int DIAG_PRB_THREADS = 1024;
 __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* dP, int bx) {
-  __shared__ double sh[4][64];
+  __shared__ double sh[64][17];
   const int M = g.my * g.mx;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int m = bx * 64 + lane;
+  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int m = bx * 16 + lane;
   double acc = 0.0;
   if (m < M) {
     const int my = m / g.mx, mx = m % g.mx;
 #pragma unroll 4
-    for (int k = grp; k < g.K; k += 4) {
+    for (int k = grp; k < g.K; k += 64) {
       const int2 r = g.pos[k];
       const float2 o = g.O_lin[(size_t)(r.x + my) * g.nx + r.y + mx];
       acc += g.trace[k] * (double)fmaf(o.x, o.x, o.y * o.y);
@@ -229,13 +238,14 @@ __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* 
   sh[grp][lane] = acc;
   __syncthreads();
   if (grp != 0 || m >= M) return;
-  acc = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+  acc = 0.0;
+  for (int q = 0; q < 64; ++q) acc += sh[q][lane];
   const float val = (float)(acc / (2.0 * M));
   dP[2 * m] = val;
   dP[2 * m + 1] = val;
 }
 
-__global__ __launch_bounds__(256) void diag_paper_probe_kernel(Geometry g, float* dP, const int* pred) {
+__global__ __launch_bounds__(1024) void diag_paper_probe_kernel(Geometry g, float* dP, const int* pred) {
   if (pred && *pred == 0) return;
   diag_paper_probe_body(g, dP, blockIdx.x);
 }
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* __restrict__ sr
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-__global__ __launch_bounds__(256) void diag_paper_probe_batch_kernel(const RedJob* __restrict__ jobs,
+__global__ __launch_bounds__(1024) void diag_paper_probe_batch_kernel(const RedJob* __restrict__ jobs,
                                                                      const int* __restrict__ job_of_block) {
   const RedJob& J = jobs[job_of_block[blockIdx.x]];
   if (J.pred && *J.pred == 0) return;
@@ -281,10 +291,10 @@ hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hi
 }
 hipError_t launch_diag_paper_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
                                    const int* prbjb, int nbp, hipStream_t s) {
-  if (nbo > 0) hipLaunchKernelGGL(diag_paper_obj_batch_kernel, dim3(nbo), dim3(256), 0, s, objjobs, objjb);
+  if (nbo > 0) hipLaunchKernelGGL(diag_paper_obj_batch_kernel, dim3(nbo), dim3(DIAG_OBJ_THREADS), 0, s, objjobs, objjb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nbp <= 0) return e;
-  hipLaunchKernelGGL(diag_paper_probe_batch_kernel, dim3(nbp), dim3(256), 0, s, prbjobs, prbjb);
+  hipLaunchKernelGGL(diag_paper_probe_batch_kernel, dim3(nbp), dim3(DIAG_PRB_THREADS), 0, s, prbjobs, prbjb);
   return hipGetLastError();
 }
 hipError_t launch_copy_batch(const CopyJob* jobs, const int* jb, int nb, hipStream_t s) {
@@ -315,11 +325,11 @@ hipError_t launch_sum_partials(const double* partials, int count, double* out, i
 }
 
 hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred) {
-  hipLaunchKernelGGL(diag_paper_obj_kernel, dim3(g.otiles_x, g.otiles_y), dim3(256), 0, s, g, dO, pred);
+  hipLaunchKernelGGL(diag_paper_obj_kernel, dim3(g.otiles_x, g.otiles_y), dim3(DIAG_OBJ_THREADS), 0, s, g, dO, pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !dP) return e;
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, dP, pred);
+  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 15) / 16), dim3(DIAG_PRB_THREADS), 0, s, g, dP, pred);
   return hipGetLastError();
 }
 
