@@ -149,6 +149,7 @@ class LMParams:
     tau_s: float = 1e-8
     p_s: float = 2.1
     ls_max: int = 30         # backtracking halvings before the iterate is kept
+    alternate: bool = False  # alg:alt_LM_ptycho: object sub-step, then probe sub-step (joint only)
 
 
 def surrogate_sigma(t: int, p: "LMParams") -> float:
@@ -171,32 +172,39 @@ def project(O, P, p: LMParams):
     return clamp(O, p.o_max), (clamp(P, p.p_max) if P is not None else None)
 
 
-def projected_update(O, P, step, g, f_t, loss, p: LMParams, joint):
+def projected_update(O, P, step, g, f_t, loss, p: LMParams, joint, block="all"):
     """alg:projected_LM applied to an accepted LM step from the feasible point (O, P).
 
     Reading of the garbled points: the first branch accepts the projected point
     Pi_Z(z + Delta); otherwise a backtracking (halving) Armijo line search along
     s = Pi_Z(z + Delta) - z when s is a sufficient descent direction (z + alpha s stays in Z
     by convexity), else along -grad f with projection.  Returns (O, P, branch, alpha); when
-    no step size passes eq:armijo_criterion the iterate is kept (alpha = 0).
+    no step size passes eq:armijo_criterion the iterate is kept (alpha = 0).  ``step`` and
+    ``g`` are full vectors; with ``block`` "O" or "P" (a sub-step of the alternating update)
+    they vanish outside that block, and only that block is projected (the other is fixed).
     """
     shapes = (O.shape, P.shape)
+
+    def proj(On, Pn):
+        Oc, Pc = project(On, Pn, p)
+        return (Oc if block != "P" else On), (Pc if block != "O" else Pn)
+
     sO, sP = unpack(step, *shapes, joint)
-    Oc, Pc = project(O + sO, (P + sP) if joint else P, p)
+    Oc, Pc = proj(O + sO, (P + sP) if joint else P)
     if loss(Oc, Pc) < p.gamma * f_t:
         return Oc, Pc, "lm", 1.0
     s = pack(Oc - O, (Pc - P) if joint else None)
     if rdot(g, s) <= -p.tau_s * rnorm(s) ** p.p_s:
-        d, proj, branch = s, False, "direction"
+        d, use_proj, branch = s, False, "direction"
     else:
-        d, proj, branch = -g, True, "gradient"
+        d, use_proj, branch = -g, True, "gradient"
     dn2 = rdot(d, d)
     alpha = 1.0
     for _ in range(p.ls_max):
         dO, dP = unpack(alpha * d, *shapes, joint)
         On, Pn = O + dO, (P + dP) if joint else P
-        if proj:
-            On, Pn = project(On, Pn, p)
+        if use_proj:
+            On, Pn = proj(On, Pn)
         if loss(On, Pn) <= f_t - p.sigma_ls * alpha * dn2:
             return On, Pn, branch, alpha
         alpha *= 0.5
@@ -242,6 +250,7 @@ class Attempt:
     cg_iters: int
     accepted: bool
     ls: tuple = None          # (branch, step size) of the projected plug-in, when used
+    block: str = "all"        # variables of the attempt: "all", or "O" / "P" (alternating update)
 
 
 @dataclass
@@ -263,92 +272,125 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
     surrogate metric of App. E (background b + sigma_t), its trial loss included.  ``loss_fn``
     overrides the trial-loss evaluation (used to force branches in tests).
     ``progress(t, f_t)`` is called at the start of every outer iteration.
+
+    With ``params.alternate`` (joint problems only) an outer iteration is the alternating
+    update of alg:alt_LM_ptycho: the inner loop of alg:lm_inexact (its while loop) on the
+    object with the probe fixed, then on the probe with the new object fixed.  Each sub-step
+    linearises at its own starting point and solves with the object-object (probe-probe)
+    block of G, the block's part of g, D and the preconditioner.  Readings: each block keeps
+    its own damping mu and its own warm-start step; both sub-steps of outer iteration t use
+    the metric of that iteration (surrogate term included); a sub-step whose retries are all
+    rejected leaves its block unchanged and the other sub-step still runs.
     """
     p = params
     O = np.array(O0, dtype=np.complex128)
     P = np.array(P0, dtype=np.complex128)
-    obj_shape, probe_shape = O.shape, P.shape
-    mu = p.mu0
-    prev_step = None
+    if p.alternate and not joint:
+        raise ValueError("the alternating update needs a joint (object and probe) problem")
+    blocks = ("O", "P") if p.alternate else ("all",)
+    mu = {k: p.mu0 for k in blocks}
+    prev_step = {k: None for k in blocks}
     res = LMResult(O=O, P=P, f=float("nan"))
     for t in range(T):
         # App. E: the surrogate metric of outer iteration t adds sigma_t to the background
         b_t = b + surrogate_sigma(t, p)
         trial_loss = loss_fn or (lambda O_, P_, b_t=b_t: ptycho.loss(O_, P_, pos, y, b_t, metric))
-        # line "Calculate G, J, grad ell and D_t" -- once per outer iteration
-        lin = ptycho.linearize(O, P, pos, y, b_t, metric, joint)
-        f_t = lin.f
-        res.f_per_iter.append(f_t)
-        if progress is not None:
-            progress(t, f_t)
-        gO, gP = ptycho.gradient(lin)
-        g = pack(gO, gP)
-        gnorm = rnorm(g)
-        zres = ptycho.zeta_residual_norm(lin)
-        dg = None
-        if p.scaling == 1 or p.precond == 1:
-            dO, dP = ptycho.ggn_diag_paper(lin)
-            blocks = [floor_block(dO.reshape(-1, 2), p.diag_floor)]
-            if joint:
-                blocks.append(floor_block(dP.reshape(-1, 2), p.diag_floor))
-            dg = np.concatenate(blocks, axis=0)
-        scaled = p.scaling == 1
-        dx = None
-        if p.precond == 3:  # the exact diagonal of G in place of the App. B one, floored alike
-            eO, eP = ptycho.ggn_diag_exact(lin)
-            blocks = [floor_block(eO.reshape(-1, 2), p.diag_floor)]
-            if joint:
-                blocks.append(floor_block(eP.reshape(-1, 2), p.diag_floor))
-            dx = np.concatenate(blocks, axis=0)
-
-        def apply_G(v):
-            vO, vP = unpack(v, obj_shape, probe_shape, joint)
-            return pack(*ptycho.ggn_vp(lin, vO, vP))
-
-        retries = 0
-        while True:  # the "while rho < rho_min" loop with its reject branch
-            lam = damping(mu, zres, scaled, p)
-            if scaled:
-                A = lambda v, lam=lam: apply_G(v) + lam * apply_diag(dg, v)
-            else:
-                A = lambda v, lam=lam: apply_G(v) + lam * v
-            if p.precond == 1:
-                m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
-                pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
-            elif p.precond in (2, 3):
-                # learned or exact diagonal in place of Dg(G) inside Dg(G + lambda D)
-                m = (learned_diag if p.precond == 2 else dx) + lam * (dg if scaled else 1.0)
-                pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
-            else:
-                pc = None
-            eta = min(p.beta, math.sqrt(gnorm))
-            x0 = prev_step if (p.warm_start and retries == 0 and prev_step is not None) \
-                else np.zeros_like(g)
-            sol = pcg(A, g, x0, pc, eta, p.cg_max)
-            step = sol.x
-            sO, sP = unpack(step, obj_shape, probe_shape, joint)
-            O_t = O + sO
-            P_t = P + sP if joint else P
-            f_trial = trial_loss(O_t, P_t)
-            dfa = f_t - f_trial
-            Dstep = lam * (apply_diag(dg, step) if scaled else step)
-            dfp = 0.5 * rdot(step, Dstep - g)
-            rho = gain_ratio(dfa, dfp)
-            mu_new, accepted = mu_update(rho, mu, p)
-            res.history.append(Attempt(t, f_t, f_trial, mu, lam, eta, rho, sol.iters, accepted))
-            mu = mu_new
-            if accepted:
-                if p.project:
-                    O, P, branch, alpha = projected_update(O, P, step, g, f_t, trial_loss, p, joint)
-                    res.history[-1].ls = (branch, alpha)
-                else:
-                    O, P = O_t, P_t
-                prev_step = step
-                break
-            retries += 1
-            if retries >= p.retry_max:
-                break
+        for k in blocks:
+            # line "Calculate G, J, grad ell and D_t" -- once per outer iteration (per sub-step)
+            lin = ptycho.linearize(O, P, pos, y, b_t, metric, joint)
+            if k == blocks[0]:
+                res.f_per_iter.append(lin.f)
+                if progress is not None:
+                    progress(t, lin.f)
+            O, P, mu[k], prev_step[k] = _inner_loop(t, k, lin, O, P, mu[k], prev_step[k], joint, p,
+                                                    learned_diag, trial_loss, res.history)
 
     res.O, res.P = O, P
     res.f = ptycho.loss(O, P, pos, y, b, metric)
     return res
+
+
+def _inner_loop(t, block, lin, O, P, mu, prev_step, joint, p: LMParams, learned_diag, trial_loss, history):
+    """The while loop of alg:lm_inexact at the linearisation ``lin`` of (O, P), over the
+    variables of ``block``: "all" (the object, and the probe for joint problems), "O" or "P"
+    (the other block fixed, alg:alt_LM_ptycho).  Vectors here hold the block's entries only.
+    Returns (O, P, mu, last accepted step of the block or the previous one)."""
+    obj_shape, probe_shape = O.shape, P.shape
+    N = O.size
+    n = N + (P.size if joint else 0)
+    sel = {"all": slice(0, n), "O": slice(0, N), "P": slice(N, n)}[block]
+
+    def embed(v):  # block vector -> full vector, zero outside the block
+        full = np.zeros(n, dtype=np.complex128)
+        full[sel] = v
+        return full
+
+    f_t = lin.f
+    gO, gP = ptycho.gradient(lin)
+    g = pack(gO, gP)[sel]
+    gnorm = rnorm(g)
+    zres = ptycho.zeta_residual_norm(lin)
+    dg = None
+    if p.scaling == 1 or p.precond == 1:
+        dO, dP = ptycho.ggn_diag_paper(lin)
+        blocks = [floor_block(dO.reshape(-1, 2), p.diag_floor)]
+        if joint:
+            blocks.append(floor_block(dP.reshape(-1, 2), p.diag_floor))
+        dg = np.concatenate(blocks, axis=0)[sel]
+    scaled = p.scaling == 1
+    dx = None
+    if p.precond == 3:  # the exact diagonal of G in place of the App. B one, floored alike
+        eO, eP = ptycho.ggn_diag_exact(lin)
+        blocks = [floor_block(eO.reshape(-1, 2), p.diag_floor)]
+        if joint:
+            blocks.append(floor_block(eP.reshape(-1, 2), p.diag_floor))
+        dx = np.concatenate(blocks, axis=0)[sel]
+    ld = learned_diag[sel] if learned_diag is not None else None
+
+    def apply_G(v):  # the block of G acting on the block's variables
+        vO, vP = unpack(embed(v), obj_shape, probe_shape, joint)
+        return pack(*ptycho.ggn_vp(lin, vO, vP))[sel]
+
+    retries = 0
+    while True:  # the "while rho < rho_min" loop with its reject branch
+        lam = damping(mu, zres, scaled, p)
+        if scaled:
+            A = lambda v, lam=lam: apply_G(v) + lam * apply_diag(dg, v)
+        else:
+            A = lambda v, lam=lam: apply_G(v) + lam * v
+        if p.precond == 1:
+            m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
+            pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
+        elif p.precond in (2, 3):
+            # learned or exact diagonal in place of Dg(G) inside Dg(G + lambda D)
+            m = (ld if p.precond == 2 else dx) + lam * (dg if scaled else 1.0)
+            pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
+        else:
+            pc = None
+        eta = min(p.beta, math.sqrt(gnorm))
+        x0 = prev_step if (p.warm_start and retries == 0 and prev_step is not None) \
+            else np.zeros_like(g)
+        sol = pcg(A, g, x0, pc, eta, p.cg_max)
+        step = sol.x
+        sO, sP = unpack(embed(step), obj_shape, probe_shape, joint)
+        O_t = O + sO
+        P_t = P + sP if joint else P
+        f_trial = trial_loss(O_t, P_t)
+        dfa = f_t - f_trial
+        Dstep = lam * (apply_diag(dg, step) if scaled else step)
+        dfp = 0.5 * rdot(step, Dstep - g)
+        rho = gain_ratio(dfa, dfp)
+        mu_new, accepted = mu_update(rho, mu, p)
+        history.append(Attempt(t, f_t, f_trial, mu, lam, eta, rho, sol.iters, accepted, block=block))
+        mu = mu_new
+        if accepted:
+            if p.project:
+                O, P, branch, alpha = projected_update(O, P, embed(step), embed(g), f_t, trial_loss, p,
+                                                       joint, block)
+                history[-1].ls = (branch, alpha)
+            else:
+                O, P = O_t, P_t
+            return O, P, mu, step
+        retries += 1
+        if retries >= p.retry_max:
+            return O, P, mu, prev_step

@@ -531,3 +531,118 @@ def test_projected_lm_stays_feasible_and_descends():
     f = res.f_per_iter + [res.f]
     assert all(f[i + 1] <= f[i] for i in range(len(f) - 1))
     assert res.f < 0.5 * f[0]
+
+
+# ---------------------------------------------------------------- NEXT: alternating LM (BPR)
+def _accepted_of(history, block, t=0):
+    acc = [h for h in history if h.block == block and h.t == t and h.accepted]
+    return acc[0] if acc else None
+
+
+def _dense_block_step(O, P, pos, y, b, block, lam):
+    """-(J_B^T diag(l'') J_B + lam I)^{-1} J_B^T l' for one block B of the variables, with J_B
+    from central differences of the forward model and l', l'' of the Gaussian metric (pinned
+    by their own finite-difference test)."""
+    J = _fd_jacobian(O, P, pos, b, True)
+    n_o = 2 * O.size
+    JB = J[:, :n_o] if block == "O" else J[:, n_o:]
+    zeta = ptycho.magnitude(O, P, pos, b).ravel()
+    l1 = ptycho.ell_d1(zeta, y.ravel(), "gauss")
+    l2 = ptycho.ell_d2(zeta, y.ravel(), "gauss")
+    G = JB.T @ (l2[:, None] * JB)
+    step = np.linalg.solve(G + lam * np.eye(G.shape[0]), -(JB.T @ l1))
+    m = step.size // 2
+    shape = O.shape if block == "O" else P.shape
+    return (step[:m] + 1j * step[m:]).reshape(shape)
+
+
+def test_alternating_substeps_match_dense_block_solves():
+    """alg:alt_LM_ptycho: the object update solves with the object block of G at (O_t, P_t), the
+    probe update with the probe block at (O_{t+1}, P_t).  PCG is run to convergence and each
+    accepted step is rebuilt from a dense finite-difference Jacobian of that block alone."""
+    O, P, pos, y = tiny_problem(joint=True)
+    b = 1e-3
+    O0, P0 = O * 0.95, P * 1.05
+    p = solver.LMParams(alternate=True, beta=1e-13, cg_max=400, warm_start=False)
+    res = solver.lm_solve(O0, P0, pos, y, b, "gauss", True, p, 1)
+    assert [h.block for h in res.history][0] == "O" and res.history[-1].block == "P"
+    aO, aP = _accepted_of(res.history, "O"), _accepted_of(res.history, "P")
+    assert aO is not None and aP is not None
+    O1 = O0 + _dense_block_step(O0, P0, pos, y, b, "O", aO.lam)
+    assert aO.f_trial == pytest.approx(ptycho.loss(O1, P0, pos, y, b, "gauss"), rel=1e-7)
+    np.testing.assert_allclose(res.O, O1, rtol=0, atol=1e-6 * np.abs(O1).max())
+    P1 = P0 + _dense_block_step(res.O, P0, pos, y, b, "P", aP.lam)
+    assert aP.f_trial == pytest.approx(ptycho.loss(res.O, P1, pos, y, b, "gauss"), rel=1e-7)
+    np.testing.assert_allclose(res.P, P1, rtol=0, atol=1e-6 * np.abs(P1).max())
+    # the probe update starts at f(O_{t+1}, P_t), the object's trial value
+    assert aP.f == pytest.approx(aO.f_trial, rel=1e-12)
+
+
+def test_alternating_object_substep_is_the_object_only_step():
+    """With the probe fixed, the object sub-step of a joint problem is the LM step of the
+    object-only problem (SPR form of eq:cdp): same damping, diagonal D, Jacobi preconditioner,
+    PCG iterations and trial values."""
+    O, P, pos, y = tiny_problem(seed=11, joint=True)
+    b = 1e-3
+    kw = dict(scaling=1, precond=1)
+    alt = solver.lm_solve(O * 0.9, P, pos, y, b, "gauss", True, solver.LMParams(alternate=True, **kw), 1)
+    obj = solver.lm_solve(O * 0.9, P, pos, y, b, "gauss", False, solver.LMParams(**kw), 1)
+    a = [h for h in alt.history if h.block == "O"]
+    assert len(a) == len(obj.history)
+    for u, v in zip(a, obj.history):
+        assert (u.cg_iters, u.accepted) == (v.cg_iters, v.accepted)
+        for name in ("f", "f_trial", "mu", "lam", "eta", "rho"):
+            assert getattr(u, name) == pytest.approx(getattr(v, name), rel=1e-10, abs=1e-300), name
+    np.testing.assert_allclose(alt.O, obj.O, rtol=0, atol=1e-12)
+
+
+def test_alternating_probe_substep_mirrors_object_step():
+    """With one scan position and equal object and probe shapes the exit wave P S O = P O is
+    symmetric in O and P, so the probe sub-step (object fixed) is the object-only LM step of the
+    problem with the two swapped -- with D = Dg(G) and the Jacobi preconditioner, whose probe
+    part (eq:ggn_joint_diag) then mirrors the object part."""
+    rng = np.random.default_rng(21)
+    O = synth.random_complex(rng, (6, 6)) * 0.5 + 0.8
+    P = synth.random_complex(rng, (6, 6))
+    pos = np.zeros((1, 2), dtype=np.int32)
+    b = 1e-3
+    y = synth.poisson_counts(rng, 50 * ptycho.intensity(O, P, pos, b)) / 50
+    kw = dict(scaling=1, precond=1)
+    alt = solver.lm_solve(O * 0.9, P * 1.1, pos, y, b, "gauss", True, solver.LMParams(alternate=True, **kw), 1)
+    O1 = alt.O                                      # the probe sub-step leaves the object as it is
+    swapped = solver.lm_solve(P * 1.1, O1, pos, y, b, "gauss", False, solver.LMParams(**kw), 1)
+    a = [h for h in alt.history if h.block == "P"]
+    assert len(a) == len(swapped.history) and any(h.accepted for h in a)
+    for u, v in zip(a, swapped.history):
+        assert u.cg_iters == v.cg_iters
+        for name in ("f", "f_trial", "lam", "rho"):
+            assert getattr(u, name) == pytest.approx(getattr(v, name), rel=1e-9), name
+    np.testing.assert_allclose(alt.P, swapped.O, rtol=0, atol=1e-12)
+
+
+def test_alternating_blocks_keep_their_own_damping_and_descend():
+    """Reading: each block carries its own mu from one outer iteration to the next, and every
+    accepted sub-step lowers f (rho > rho_min > 0 with a positive predicted reduction)."""
+    pr = synth.make_small(8, obj_side=32, probe=(8, 8), n=4, step=4, photons=1e3, mode="joint")
+    rng = np.random.default_rng(8)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background))
+    p = solver.LMParams(alternate=True, scaling=1, precond=1)
+    res = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y, pr.background, "gauss", True, p, 5)
+    for blk in ("O", "P"):
+        seq = [h for h in res.history if h.block == blk]
+        assert {h.t for h in seq} == set(range(5))
+        assert seq[0].mu == p.mu0
+        for u, v in zip(seq, seq[1:]):
+            assert v.mu == solver.mu_update(u.rho, u.mu, p)[0]
+    for h in res.history:
+        if h.accepted:
+            assert h.f_trial < h.f
+    f = res.f_per_iter + [res.f]
+    assert all(f[i + 1] <= f[i] for i in range(len(f) - 1))
+    assert res.f < 0.5 * f[0]
+
+
+def test_alternating_needs_joint_problem():
+    O, P, pos, y = tiny_problem(joint=False)
+    with pytest.raises(ValueError):
+        solver.lm_solve(O, P, pos, y, 1e-3, "gauss", False, solver.LMParams(alternate=True), 1)
