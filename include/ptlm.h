@@ -84,6 +84,10 @@ typedef struct {
   double o_max, p_max;  /* eq:constraints: |O| <= o_max (1), |P| <= p_max (1e8) */
   double sigma_ls;      /* eq:armijo_criterion constant (1e-4) */
   double gamma, tau_s, p_s; /* alg:projected_LM constants (1e-6, 1e-8, 2.1; Sec. 5) */
+  int32_t alternate;    /* 1: alg:alt_LM_ptycho (joint problems only): every outer iteration
+                           runs the attempts of alg:lm_inexact on the object with the probe fixed,
+                           then on the probe with the new object fixed, each block with its own
+                           damping mu and warm start; 0: joint update */
 } ptlm_lm_params;
 
 /* LM state, FP64, in DEVICE memory (written by the library, read by the caller). */
@@ -97,12 +101,13 @@ typedef struct {
   double rz, rr, alpha, beta_cg, pap; /* PCG scalars */
   double sigma;      /* surrogate term added to the background in the current outer iteration */
   double ls_alpha;   /* step size of the last projected plug-in (0: iterate kept) */
-  int32_t t;         /* outer iterations completed */
+  double mu_alt;     /* alternating update: damping of the block not running (mu: running block) */
+  int32_t t;         /* outer iterations completed (both sub-steps, alternating update) */
   int32_t cg_iters;  /* products with A in the last solve */
   int32_t cg_total;  /* products with A since ptlm_lm_init */
   int32_t accepted;  /* last attempt accepted */
   int32_t cg_active; /* internal: PCG loop still running */
-  int32_t retries;   /* rejected attempts in the current outer iteration */
+  int32_t retries;   /* rejected attempts in the current outer iteration (sub-step) */
   int32_t nonfinite; /* a non-finite value was met */
   int32_t products;  /* GGN-vector products since ptlm_lm_init (PCG and warm starts) */
   int32_t attempts;  /* LM attempts (trial points) since ptlm_lm_init */
@@ -110,12 +115,17 @@ typedef struct {
   int32_t lin_now;   /* internal: the current attempt linearises */
   int32_t use_warm;  /* internal: the current solve starts from the last accepted step */
   int32_t alive;     /* internal: the current attempt runs (t < t_max, no numeric failure) */
-  int32_t prev_valid;/* an accepted step exists (PCG warm start) */
+  int32_t prev_valid;/* accepted steps exist for the PCG warm start: bit 0 object (all variables
+                        for the joint update), bit 1 probe (alternating update) */
   int32_t t_max;     /* outer iterations to run: INT32_MAX after ptlm_lm_init, T in batches */
   int32_t status;    /* PTLM_OK, PTLM_ENOTACCEPTED (last outer iteration) or PTLM_ENUMERIC */
   int32_t iter_done; /* internal: the last attempt ended an outer iteration */
   int32_t ls_branch; /* last projected plug-in: 0 projected LM step, 1 line search along the
                         projected step, 2 projected gradient, -1 none */
+  int32_t block;     /* alternating update: block of the current sub-step (0 object, 1 probe);
+                        0 for the joint update */
+  int32_t acc_o;     /* internal: the last attempt accepted a step of the object */
+  int32_t acc_p;     /* internal: the last attempt accepted a step of the probe */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;
@@ -198,6 +208,10 @@ ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_
  * ratio, mu update}.  It synchronises the stream once per attempt to read the acceptance
  * flag.  Returns PTLM_OK when a step was accepted, PTLM_ENOTACCEPTED when all retries were
  * rejected (iterate unchanged), PTLM_ENUMERIC on a non-finite loss (iterate unchanged).
+ * With params->alternate (PTLM_JOINT only, else PTLM_EINVAL) the outer iteration is the
+ * object sub-step and then the probe sub-step of alg:alt_LM_ptycho, each linearising at its
+ * own start and running up to retry_max attempts on its block; PTLM_ENOTACCEPTED then means
+ * that the attempts of at least one sub-step were all rejected (that block unchanged).
  * With params->precond == 2 the PCG preconditioner is d + lambda D, where d is the network's
  * learned diagonal (ptlm_lm_set_cnn, refreshed every outer iteration) or, if no network is
  * registered, the caller's d_precond (2n floats).
@@ -282,7 +296,8 @@ ptlm_handle* ptlm_batch_problem(ptlm_batch* b, int32_t i);
  * d_states[i] (n consecutive device states), the shared LM parameters and the number T of
  * outer iterations, and reset the states (mu = mu0, t = 0).  use_graph = 1: attempts after
  * the first are replayed from one captured HIP graph.  With params->precond == 2 every
- * problem needs a registered network (ptlm_lm_set_cnn on its handle).  Pointers must stay
+ * problem needs a registered network (ptlm_lm_set_cnn on its handle); with params->alternate
+ * every problem must be PTLM_JOINT.  Pointers must stay
  * valid until the next bind or ptlm_batch_destroy. */
 ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P, const float* const* d_y,
                             ptlm_lm_state* d_states, const ptlm_lm_params* params, int32_t T, int32_t use_graph,

@@ -49,7 +49,7 @@ class ptlm_lm_params(ctypes.Structure):
                 ("surrogate_T", ctypes.c_int32), ("surrogate_s0", ctypes.c_double),
                 ("project", ctypes.c_int32), ("ls_max", ctypes.c_int32), ("o_max", ctypes.c_double),
                 ("p_max", ctypes.c_double), ("sigma_ls", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("tau_s", ctypes.c_double), ("p_s", ctypes.c_double)]
+                ("tau_s", ctypes.c_double), ("p_s", ctypes.c_double), ("alternate", ctypes.c_int32)]
 
 
 class ptlm_cnn_desc(ctypes.Structure):
@@ -57,9 +57,10 @@ class ptlm_cnn_desc(ctypes.Structure):
 
 
 _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid_norm", "pred",
-                  "rz", "rr", "alpha", "beta_cg", "pap", "sigma", "ls_alpha"]
+                  "rz", "rr", "alpha", "beta_cg", "pap", "sigma", "ls_alpha", "mu_alt"]
 _STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
-               "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done", "ls_branch"]
+               "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done", "ls_branch",
+               "block", "acc_o", "acc_p"]
 
 
 class ptlm_lm_state(ctypes.Structure):

@@ -208,7 +208,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   p.off.probe_part = take(max_nseg * M * sizeof(float2));
   p.off.partials = take((size_t)std::max(max_grid, 1024) * 4 * sizeof(double));
   p.off.scratch = d->my == 256 ? take((size_t)max_grid * M * sizeof(float2)) : 0;
-  p.off.scal = take(64 * sizeof(double));  // [0..7] LM scalars, [8..11] feature / learned-diagonal scratch
+  p.off.scal = take(64 * sizeof(double));  // [0..7], [12..17] LM scalars, [8..11] feature / learned-diagonal scratch
   // LM / PCG vectors (complex entries of R^(2n)) and real diagonals
   p.off.g = take(n2 * sizeof(float2));
   p.off.dx = take(n2 * sizeof(float2));
@@ -432,6 +432,7 @@ void ptlm_lm_default_params(ptlm_lm_params* p) {
   p->gamma = 1e-6;
   p->tau_s = 1e-8;
   p->p_s = 2.1;
+  p->alternate = 0;
 }
 
 ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {

@@ -231,9 +231,11 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
   job = 0;
   for (int i = 0; i < n; ++i) {
     const Plan& p = plans[i];
+    // accepted object, object step, accepted probe, probe step
+    append_run(b.jb_copy_acc, job++, copy_blocks((size_t)p.d.ny * p.d.nx), 1);
     append_run(b.jb_copy_acc, job++, copy_blocks((size_t)p.d.ny * p.d.nx), 1);
     append_run(b.jb_copy_acc, job++, copy_blocks((size_t)p.d.my * p.d.mx), 1);
-    append_run(b.jb_copy_acc, job++, copy_blocks(p.nvec), 1);
+    append_run(b.jb_copy_acc, job++, copy_blocks((size_t)p.d.my * p.d.mx), 1);
   }
   b.nb_obj = (int)b.jb_obj.size();
   b.nb_prb = (int)b.jb_prb.size();
@@ -266,7 +268,7 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
   L.red_sum = take(n * sizeof(RedJob));
   L.lm_jobs = take(n * sizeof(LMJob));
   L.copy_lin = take(2 * n * sizeof(CopyJob));
-  L.copy_acc = take(3 * n * sizeof(CopyJob));
+  L.copy_acc = take(4 * n * sizeof(CopyJob));
   L.bytes = o;
   *total = b.tables_off + L.bytes;
   return PTLM_OK;
@@ -361,6 +363,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
     if (!d_O[i] || !d_P[i] || !d_y[i]) return fail(PTLM_EINVAL, "null array of problem " + std::to_string(i));
     if (params->precond == 2 && !b->hs[i]->cnn_params)
       return fail(PTLM_EINVAL, "precond == 2 in a batch needs a network on every problem (ptlm_lm_set_cnn)");
+    if (params->alternate && !b->hs[i]->g.joint)
+      return fail(PTLM_EINVAL, "the alternating update needs PTLM_JOINT problems (problem " + std::to_string(i) + ")");
   }
   hipStream_t s = (hipStream_t)stream;
   release_graph(b);
@@ -392,7 +396,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
           j.a.predicate = flags + FL_LIN;
           j.a.bg_add = &d_states[i].sigma;
         } else if (k == TK_WARM || k == TK_P) {
-          const float2* v0 = k == TK_WARM ? a.prev : a.p;
+          const float2* v0 = (k == TK_WARM && !params->alternate) ? a.prev : a.p;
           j.a.vO = v0;
           j.a.vP = g.joint ? v0 + a.nobj : nullptr;
           j.a.predicate = flags + (k == TK_WARM ? FL_WARM : FL_CG);
@@ -436,7 +440,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
         r.outP = a.diag + N;
         r.pred = flags + FL_LIN;
       } else {
-        const float2* v0 = k == RK_WARM ? a.prev : a.p;
+        const float2* v0 = (k == RK_WARM && !params->alternate) ? a.prev : a.p;
         r.outO = a.Ap;
         r.outP = a.Ap + N;
         r.vO = v0;
@@ -473,12 +477,16 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
     b->copy_lin.push_back(c);
     c.src = P; c.dst = h->g.P_lin; c.n = M;
     b->copy_lin.push_back(c);
-    c.pred = flags + FL_ACCEPTED;
+    // the accepted step's blocks (both, or the active one of the alternating update)
+    c.pred = flags + FL_ACC_O;
     c.src = a.ztrial; c.dst = O; c.n = N;
     b->copy_acc.push_back(c);
+    c.src = a.dx; c.dst = a.prev; c.n = N;
+    b->copy_acc.push_back(c);
+    c.pred = flags + FL_ACC_P;
     c.src = a.ztrial + N; c.dst = P; c.n = g.joint ? M : 0;
     b->copy_acc.push_back(c);
-    c.src = a.dx; c.dst = a.prev; c.n = a.n;
+    c.src = a.dx + N; c.dst = a.prev + N; c.n = g.joint ? M : 0;
     b->copy_acc.push_back(c);
   }
   // block offsets of the copy jobs (runs in job order)
@@ -495,9 +503,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
     b0 = 0;
     j = 0;
     for (CopyJob& c : b->copy_acc) {
-      ptlm_handle* h = b->hs[j / 3];
-      const size_t len = j % 3 == 0 ? (size_t)h->g.ny * h->g.nx : (j % 3 == 1 ? (size_t)h->g.my * h->g.mx
-                                                                              : h->plan.nvec);
+      ptlm_handle* h = b->hs[j / 4];
+      const size_t len = j % 4 < 2 ? (size_t)h->g.ny * h->g.nx : (size_t)h->g.my * h->g.mx;
       const int nb = copy_blocks(len);
       c.block0 = b0;
       c.nblk = nb;

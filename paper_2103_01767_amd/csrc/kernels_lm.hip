@@ -54,6 +54,17 @@ __device__ __forceinline__ float2 apply_D(const LMArgs& a, size_t i, float2 v) {
   return v;
 }
 
+// Entries [lo, hi) that the running step works on: every entry, or for the alternating
+// update (alg:alt_LM_ptycho) the block of the current sub-step (object [0, nobj), probe
+// [nobj, n)).
+struct Range {
+  size_t lo, hi;
+};
+__device__ __forceinline__ Range active_range(const LMArgs& a) {
+  if (!a.prm.alternate) return Range{0, a.n};
+  return a.st->block ? Range{a.nobj, a.n} : Range{0, a.nobj};
+}
+
 __device__ __forceinline__ bool flag_clear(const LMArgs& a, int flag) {
   return flag >= 0 && reinterpret_cast<const int*>(a.st)[flag] == 0;
 }
@@ -66,11 +77,21 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
   const float beta = (float)a.st->beta_cg;
   const bool warm = a.st->use_warm != 0;
   double acc0 = 0.0, acc1 = 0.0;
+  // steps of the PCG recurrence and of the projected plug-in touch the active block only;
+  // V_CG_INIT and V_WARM_P clear the rest of their vectors, V_TRIAL keeps it at the iterate
+  constexpr bool BLOCK = OP == V_PAP || OP == V_CG_UPDATE || OP == V_PUPDATE || OP == V_PROJ || OP == V_LS_DIR ||
+                         OP == V_LS_NEG;
+  const Range act = active_range(a);
+  const size_t lo = BLOCK ? act.lo : 0, hi = BLOCK ? act.hi : a.n;
   const size_t stride = (size_t)nblk * blockDim.x;
-  for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-    if constexpr (OP == V_GNORM) {
+  for (size_t i = lo + (size_t)bid * blockDim.x + threadIdx.x; i < hi; i += stride) {
+    if constexpr (OP == V_GNORM) {  // ||g_O||^2, ||g_P||^2
       const float2 g = a.g[i];
-      acc0 += rdot(g, g);
+      if (i < a.nobj) acc0 += rdot(g, g);
+      else acc1 += rdot(g, g);
+    } else if constexpr (OP == V_WARM_P) {  // the warm-start vector restricted to the active block
+      const bool in = i >= act.lo && i < act.hi;
+      a.p[i] = in ? a.prev[i] : make_float2(0.f, 0.f);
     } else if constexpr (OP == V_DIAGMAX) {
       const float2 d = a.diag[i];
       const double m = fmax((double)d.x, (double)d.y);
@@ -98,9 +119,12 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       acc1 += rdot(d, d);
     } else if constexpr (OP == V_LS_CAND) {
       const float2 z = i < a.nobj ? a.Olin[i] : a.Plin[i - a.nobj];
-      const float2 d = a.r[i];
-      float2 c = make_float2(fmaf(a.ls_alpha, d.x, z.x), fmaf(a.ls_alpha, d.y, z.y));
-      if (a.ls_proj) c = project_entry(a, i, c);
+      float2 c = z;
+      if (i >= act.lo && i < act.hi) {
+        const float2 d = a.r[i];
+        c = make_float2(fmaf(a.ls_alpha, d.x, z.x), fmaf(a.ls_alpha, d.y, z.y));
+        if (a.ls_proj) c = project_entry(a, i, c);
+      }
       a.ztrial[i] = c;
     } else if constexpr (OP == V_XMAX) {
       const float2 d = a.xdiag[i];
@@ -112,6 +136,14 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float2 d = a.xdiag[i];
       a.xdiag[i] = make_float2(fmaxf(d.x, f), fmaxf(d.y, f));
     } else if constexpr (OP == V_CG_INIT) {
+      if (i < act.lo || i >= act.hi) {  // outside the active block: Delta = r = z = p = 0
+        const float2 zero = make_float2(0.f, 0.f);
+        a.dx[i] = zero;
+        a.r[i] = zero;
+        a.z[i] = zero;
+        a.p[i] = zero;
+        continue;
+      }
       const float2 g = a.g[i];
       float2 r;
       if (warm) {
@@ -251,18 +283,28 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
       }
     }
     st.lin_now = (st.alive && st.need_lin) ? 1 : 0;
-    if (st.alive && st.iter_done) {  // a new outer iteration starts: no rejected attempts yet
+    if (st.alive && st.iter_done) {  // a new outer iteration (sub-step) starts: no rejections yet
       st.retries = 0;
       st.iter_done = 0;
+      if (p.alternate) {  // alg:alt_LM_ptycho: the other block, with its own damping
+        st.block ^= 1;
+        const double m = st.mu;
+        st.mu = st.mu_alt;
+        st.mu_alt = m;
+      }
     }
     st.cg_active = 0;
     st.accepted = 0;
+    st.acc_o = 0;
+    st.acc_p = 0;
     st.use_warm = 0;
   } else if constexpr (OP == F_LIN) {
     // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM
     st.f = a.scal[SC_F];
     st.resid_norm = sqrt(a.scal[SC_L1SQ]);
-    st.gnorm = sqrt(s0);
+    a.scal[SC_G2_O] = s0;
+    a.scal[SC_G2_P] = s1;
+    st.gnorm = sqrt(s0 + s1);
     st.nonfinite = (finite_d(st.f) && finite_d(st.gnorm)) ? 0 : 1;
     if (st.nonfinite) {
       st.status = PTLM_ENUMERIC;
@@ -283,6 +325,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
     // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).  The first attempt
     // of an outer iteration starts PCG from the last accepted step, a retry from zero.
+    if (p.alternate) st.gnorm = sqrt(a.scal[st.block ? SC_G2_P : SC_G2_O]);  // ||g|| of the block
     st.lambda = p.scaling ? st.mu : st.mu * pow(st.resid_norm, p.nu);
     st.eta = fmin(p.beta, sqrt(st.gnorm));
     st.cg_iters = 0;
@@ -290,7 +333,8 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.accepted = 0;
     st.alpha = 0.0;
     st.beta_cg = 0.0;
-    st.use_warm = (p.warm_start && st.prev_valid && st.retries == 0) ? 1 : 0;
+    const int bit = (p.alternate && st.block) ? 2 : 1;
+    st.use_warm = (p.warm_start && (st.prev_valid & bit) && st.retries == 0) ? 1 : 0;
   } else if constexpr (OP == F_CG_INIT) {
     if (st.use_warm) st.products += 1;
     st.rz = s0;
@@ -339,22 +383,28 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
       st.retries += 1;
     }
     st.cg_active = 0;
+    // the outer iteration ends with the sub-step of the probe in the alternating update
+    const int last = !p.alternate || st.block == 1;
     if (st.accepted) {
-      // the outer iteration ends with a step; the next attempt re-linearises at z + Delta
+      // the outer iteration (sub-step) ends with a step; the next attempt re-linearises at z + Delta
+      const int bit = (p.alternate && st.block) ? 2 : 1;
+      st.acc_o = (!p.alternate || st.block == 0) ? 1 : 0;
+      st.acc_p = (!p.alternate || st.block == 1) ? 1 : 0;
       st.need_lin = 1;
-      st.prev_valid = 1;
-      st.t += 1;
+      st.prev_valid |= bit;
+      st.t += last;
       st.iter_done = 1;
       st.status = PTLM_OK;
     } else if (st.retries >= p.retry_max) {
-      // every retry rejected: the outer iteration ends without moving (linearisation kept)
-      st.t += 1;
+      // every retry rejected: the outer iteration (sub-step) ends without moving (linearisation kept)
+      st.t += last;
       st.iter_done = 1;
       st.status = PTLM_ENOTACCEPTED;
     }
   } else if constexpr (OP == F_INIT) {
     st = ptlm_lm_state{};
     st.mu = p.mu0;
+    st.mu_alt = p.mu0;
     st.sigma = surrogate_sigma(p, 0);
     st.need_lin = 1;
     st.t_max = a.t_max;
@@ -399,7 +449,7 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 
 #define PTLM_VEC_CASES(X)                                                                                 \
   X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL) X(V_XMAX) \
-  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND)
+  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P)
 #define PTLM_FIN_CASES(X)                                                                                 \
   X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
   X(F_INIT) X(F_LS)

@@ -59,7 +59,8 @@ ptlm_status check_lm_params(const ptlm_lm_params* p) {
       (p->scaling != 0 && p->scaling != 1) || p->precond < 0 || p->precond > 3 || p->surrogate_T < 0 ||
       !(p->surrogate_s0 >= 0.0) || !std::isfinite(p->surrogate_s0) || (p->project != 0 && p->project != 1) ||
       (p->project && (p->ls_max < 0 || !(p->o_max > 0) || !(p->p_max > 0) || !(p->sigma_ls >= 0) ||
-                      !(p->gamma >= 0) || !(p->tau_s >= 0) || !(p->p_s > 1))))
+                      !(p->gamma >= 0) || !(p->tau_s >= 0) || !(p->p_s > 1))) ||
+      (p->alternate != 0 && p->alternate != 1))
     return fail(PTLM_EINVAL, "invalid LM parameters");
   return PTLM_OK;
 }
@@ -134,7 +135,7 @@ struct SingleOps {
     return diag_exact_impl(h, (float*)a.xdiag, h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, flag(FL_LIN));
   }
   ptlm_status ggnv(int which) {
-    const float2* v = which == GG_WARM ? a.prev : a.p;
+    const float2* v = (which == GG_WARM && !a.prm.alternate) ? a.prev : a.p;
     const int* pred = which == GG_WARM ? flag(FL_WARM) : flag(FL_CG);
     const size_t N = a.nobj;
     const float* dO = a.prm.scaling ? (const float*)a.diag : nullptr;
@@ -154,10 +155,15 @@ struct SingleOps {
     return PTLM_OK;
   }
   ptlm_status copy_accept() {
+    // the accepted step's blocks (both, or the active one of the alternating update)
     Geometry& g = h->g;
-    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_ACCEPTED), s), "lm accept O");
-    if (g.joint) LM_HIP(launch_copy(a.ztrial + a.nobj, P, (size_t)g.my * g.mx, flag(FL_ACCEPTED), s), "lm accept P");
-    LM_HIP(launch_copy(a.dx, a.prev, a.n, flag(FL_ACCEPTED), s), "lm keep step");
+    const size_t M = (size_t)g.my * g.mx;
+    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_ACC_O), s), "lm accept O");
+    LM_HIP(launch_copy(a.dx, a.prev, a.nobj, flag(FL_ACC_O), s), "lm keep step O");
+    if (g.joint) {
+      LM_HIP(launch_copy(a.ztrial + a.nobj, P, M, flag(FL_ACC_P), s), "lm accept P");
+      LM_HIP(launch_copy(a.dx + a.nobj, a.prev + a.nobj, M, flag(FL_ACC_P), s), "lm keep step P");
+    }
     return PTLM_OK;
   }
 };
@@ -251,6 +257,9 @@ static ptlm_status projected_plugin(SingleOps& o, const ptlm_lm_params& prm, dou
   return PTLM_OK;
 }
 
+// One outer iteration: the attempts of alg:lm_inexact until one is accepted or retry_max are
+// rejected -- once for the joint update, once per block (object, then probe) for the
+// alternating update of alg:alt_LM_ptycho.
 static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const float* y, const ptlm_lm_params* prm,
                                 ptlm_lm_state* st, const float* learned, hipStream_t s) {
   ptlm_lm_state hs;
@@ -259,16 +268,24 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
   if (hs.t >= hs.t_max) return fail(PTLM_EINVAL, "the state has run its outer iterations (t_max)");
   const int t0 = hs.t;
   SingleOps o{h, make_lm_args(h, prm, st, O, P, learned), O, P, y, learned, false, s};
-  for (int attempt = 0; attempt <= prm->retry_max; ++attempt) {
-    o.lin_expected = hs.need_lin != 0;
-    PTLM_TRY(enqueue_attempt(o, *prm));
-    PTLM_TRY(read_state(st, &hs, s));
-    if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
-    if (hs.t > t0) break;
+  bool rejected = false;
+  const int subs = prm->alternate ? 2 : 1;
+  for (int sub = 0; sub < subs; ++sub) {
+    bool ended = false;
+    for (int attempt = 0; attempt <= prm->retry_max && !ended; ++attempt) {
+      o.lin_expected = hs.need_lin != 0;
+      PTLM_TRY(enqueue_attempt(o, *prm));
+      PTLM_TRY(read_state(st, &hs, s));
+      if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
+      ended = hs.iter_done != 0;
+    }
+    if (!ended) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
+    // the plug-in runs on the block of the sub-step just ended (the state still names it)
+    if (prm->project && hs.accepted) PTLM_TRY(projected_plugin(o, *prm, hs.f));
+    rejected = rejected || hs.status == PTLM_ENOTACCEPTED;
   }
-  if (prm->project && hs.t > t0 && hs.accepted) PTLM_TRY(projected_plugin(o, *prm, hs.f));
-  if (hs.t == t0) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
-  if (hs.status == PTLM_ENOTACCEPTED) return fail(PTLM_ENOTACCEPTED, "every retry of this outer iteration was rejected");
+  if (hs.t != t0 + 1) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
+  if (rejected) return fail(PTLM_ENOTACCEPTED, "every retry of this outer iteration (or of one sub-step) was rejected");
   return PTLM_OK;
 }
 
@@ -282,6 +299,7 @@ ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_s
   if (!h || !d_state) return fail(PTLM_EINVAL, "null handle or state");
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
+  if (params->alternate && !h->g.joint) return fail(PTLM_EINVAL, "the alternating update needs a PTLM_JOINT problem");
   LMArgs a = make_lm_args(h, params, d_state, nullptr, nullptr, nullptr);
   LM_HIP(launch_fin(F_INIT, a, 0, FL_NONE, (hipStream_t)stream), "lm init");
   return PTLM_OK;
@@ -292,6 +310,7 @@ ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_
   if (!h || !d_O || !d_P || !d_y || !d_state) return fail(PTLM_EINVAL, "null argument");
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
+  if (params->alternate && !h->g.joint) return fail(PTLM_EINVAL, "the alternating update needs a PTLM_JOINT problem");
   if (params->precond == 2 && !d_precond && !h->cnn_params)
     return fail(PTLM_EINVAL, "precond == 2 needs d_precond or a registered network");
   return lm_step_impl(h, (float2*)d_O, (float2*)d_P, d_y, params, d_state, d_precond, (hipStream_t)stream);

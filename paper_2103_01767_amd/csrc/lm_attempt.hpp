@@ -20,6 +20,7 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
 // diag_paper(), learned(), exact_diag(), ggnv(which), trial_loss(), copy_accept().
+// ggnv(GG_WARM) multiplies the last accepted step, or p when params.alternate is set.
 template <class Ops>
 ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.fin(F_ATTEMPT, 0, FL_NONE));
@@ -43,7 +44,10 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   }
   // ---- lambda, eta, PCG on (G + lambda D) Delta = -g
   PTLM_TRY(o.fin(F_BEGIN, 0, FL_ALIVE));
-  PTLM_TRY(o.ggnv(GG_WARM));  // A Delta_0 for the warm start
+  // A Delta_0 for the warm start; the alternating update multiplies the last step of the
+  // active block alone, staged in p (free until V_CG_INIT)
+  if (prm.alternate) PTLM_TRY(o.vec(V_WARM_P, FL_WARM));
+  PTLM_TRY(o.ggnv(GG_WARM));
   PTLM_TRY(o.vec(V_CG_INIT, FL_ALIVE));
   PTLM_TRY(o.fin(F_CG_INIT, 1, FL_ALIVE));
   for (int i = 0; i < prm.cg_max; ++i) {

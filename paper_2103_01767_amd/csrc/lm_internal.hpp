@@ -16,10 +16,10 @@ inline int lm_vec_blocks(size_t n) {
 
 // indices into the FP64 scalar scratch
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4, SC_XMAX_O = 5, SC_XMAX_P = 6,
-       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14 };
+       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17 };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL, V_XMAX, V_XFLOOR,
-                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND };
+                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P };
 enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT,
                    F_LS };
 
@@ -31,6 +31,8 @@ enum LMFlag : int {
   FL_CG = (int)(offsetof(ptlm_lm_state, cg_active) / 4),
   FL_WARM = (int)(offsetof(ptlm_lm_state, use_warm) / 4),
   FL_ACCEPTED = (int)(offsetof(ptlm_lm_state, accepted) / 4),
+  FL_ACC_O = (int)(offsetof(ptlm_lm_state, acc_o) / 4),
+  FL_ACC_P = (int)(offsetof(ptlm_lm_state, acc_p) / 4),
 };
 
 struct LMArgs {

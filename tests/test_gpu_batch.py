@@ -199,3 +199,27 @@ def test_batch_surrogate_equals_alone():
         s2 = batch.state(i)
         assert s2.t == T and s2.f == s1.f and s2.sigma == s1.sigma == 0.0
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+def test_batch_alternating_equals_alone():
+    """The alternating update (alg:alt_LM_ptycho) in a batch: each problem's active block,
+    damping pair and per-block warm starts live in its own device state, so the batch equals
+    its problems solved alone."""
+    print("case batch alternating", flush=True)
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=1, cg_max=6, alternate=1)
+    T = 3
+    alone = [run_single(p, params, T) for p in probs]
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(200, check_every=2)
+    torch.cuda.synchronize()
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        assert s2.t == T and s1.t == T and s2.block == s1.block == 1
+        assert s2.f == s1.f and s2.mu == s1.mu and s2.mu_alt == s1.mu_alt and s2.products == s1.products
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)

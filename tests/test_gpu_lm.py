@@ -249,3 +249,79 @@ def test_projected_lm_matches_oracle():
     print("projected oracle f=%.6e gpu f=%.6e" % (ref.f, fs[-1]))
     assert all(fs[i + 1] <= fs[i] * (1 + 1e-6) for i in range(len(fs) - 1))
     assert fs[-1] <= 1.01 * ref.f
+
+
+# ---------------------------------------------------------------- alternating update (alg:alt_LM_ptycho)
+@pytest.mark.parametrize("scaling,precond", [(0, 0), (1, 1)])
+def test_alternating_step_matches_oracle_substeps(scaling, precond):
+    """One outer iteration of the alternating update from the same point: the state after it
+    holds the probe sub-step's last attempt (lambda, eta, PCG products, rho) and both blocks'
+    damping values as the oracle's."""
+    print("case alternating step", scaling, precond, flush=True)
+    pr = synth.make_small(7, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(7)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    p_or = solver.LMParams(scaling=scaling, precond=precond, alternate=True)
+    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, "gauss", True, p_or, 1)
+    hO = [h for h in ref.history if h.block == "O"]
+    hP = [h for h in ref.history if h.block == "P"]
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(scaling=scaling, precond=precond, alternate=1)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_step(O, P, yd, params, st)
+    s = pt.state_from_tensor(st)
+    h0 = hP[-1]
+    print("oracle P", h0.lam, h0.eta, h0.cg_iters, h0.rho, h0.f, "gpu", s.lambda_, s.eta, s.cg_iters, s.rho, s.f)
+    assert s.t == 1 and s.block == 1
+    assert s.f == pytest.approx(h0.f, rel=1e-5)               # f at (O_{t+1}, P_t)
+    assert s.eta == pytest.approx(h0.eta, rel=1e-5)
+    assert s.lambda_ == pytest.approx(h0.lam, rel=1e-5)
+    assert abs(s.cg_iters - h0.cg_iters) <= 1
+    if s.cg_iters == h0.cg_iters:
+        assert s.rho == pytest.approx(h0.rho, rel=1e-3, abs=1e-3)
+    mu_o = solver.mu_update(hO[-1].rho, hO[-1].mu, p_or)[0]
+    mu_p = solver.mu_update(hP[-1].rho, hP[-1].mu, p_or)[0]
+    assert s.mu_alt == pytest.approx(mu_o, rel=1e-12) and s.mu == pytest.approx(mu_p, rel=1e-12)
+    # the object is the oracle's after its sub-step (the probe sub-step leaves it as it is)
+    Og = O.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(Og - ref.O) <= 1e-3 * np.linalg.norm(ref.O)
+
+
+@pytest.mark.parametrize("variant", ["plain", "scaled_jacobi", "projected"])
+def test_alternating_lm_matches_oracle(variant):
+    """LM-A and PLM-A: final loss within 1.01x of the oracle's alternating LM."""
+    print("case alternating lm", variant, flush=True)
+    pr = synth.make_small(5, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(5)
+    O_true = pr.O_true / np.abs(pr.O_true).max() if variant == "projected" else pr.O_true
+    y = synth.poisson_counts(rng, ptycho.intensity(O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    kw = {"plain": {}, "scaled_jacobi": dict(scaling=1, precond=1),
+          "projected": dict(scaling=1, precond=1, project=True)}[variant]
+    T = 10
+    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, "gauss", True,
+                          solver.LMParams(alternate=True, **kw), T)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(alternate=1, **{k: int(v) for k, v in kw.items()})
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_solve(O, P, yd, params, T, st)
+    s = pt.state_from_tensor(st)
+    f_gpu = float(prob.loss(O, P, yd).cpu()[0])
+    print("alternating %s oracle f=%.6e gpu f=%.6e (start %.3e)" % (variant, ref.f, f_gpu, ref.f_per_iter[0]))
+    assert s.t == T
+    assert f_gpu <= 1.01 * ref.f
+    assert f_gpu < 0.5 * ref.f_per_iter[0]
+    if variant == "projected":
+        assert float(torch.abs(O).max()) <= 1.0 + 1e-6
+
+
+def test_alternating_needs_joint_problem():
+    pr = synth.make_small(3, obj_side=40, probe=(16, 16), n=4, step=6, photons=1e3, mode="object")
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="object", background=pr.background, device=DEV)
+    st = prob.new_state()
+    with pytest.raises(pt.PtlmError) as e:
+        prob.lm_init(pt.default_params(alternate=1), st)
+    assert e.value.status == pt.PTLM_EINVAL
