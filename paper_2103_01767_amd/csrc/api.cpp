@@ -463,6 +463,15 @@ ptlm_status ptlm_destroy(ptlm_handle* h) {
   return PTLM_OK;
 }
 
+}  // extern "C"
+
+ptlm_handle::~ptlm_handle() {
+  for (hipEvent_t e : cg_events) (void)hipEventDestroy(e);
+  if (cg_flags) (void)hipHostFree(cg_flags);
+}
+
+extern "C" {
+
 ptlm_status ptlm_forward(ptlm_handle* h, const float* d_O, const float* d_P, float* d_zeta, void* stream) {
   PTLM_CHECK_H(h);
   if (!d_O || !d_P || !d_zeta) return fail(PTLM_EINVAL, "null array");

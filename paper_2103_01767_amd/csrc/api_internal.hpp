@@ -45,6 +45,12 @@ struct ptlm_handle {
   int cnn_every = 1;        // network refresh period in linearisations (0: once after registration)
   int cnn_count = 0;        // linearisations since registration
   bool cnn_ready = false;   // the network output r in cnn_ws is current
+  // PCG look-ahead of ptlm_lm_step: pinned host slots the finalize kernels write the PCG
+  // continuation flag to, and one event per slot
+  int* cg_flags = nullptr;
+  int cg_slots = 0;
+  std::vector<hipEvent_t> cg_events;
+  ~ptlm_handle();
 };
 
 namespace ptlm {

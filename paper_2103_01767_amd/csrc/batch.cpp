@@ -166,6 +166,12 @@ struct BatchOps {
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
   }
   ptlm_status trial_loss() { return tiles(OP_LOSS, TK_TRIAL); }
+  // the batch keeps one fixed launch sequence (graph capture): every PCG iteration is enqueued
+  ptlm_status cg_mark(int) { return PTLM_OK; }
+  ptlm_status cg_gate(int, bool* go) {
+    *go = true;
+    return PTLM_OK;
+  }
   ptlm_status copy_accept() {
     B_HIP(launch_copy_batch(b->dev<CopyJob>(b->L.copy_acc), b->dev<int>(b->L.jb_copy_acc), b->nb_copy_acc, s),
           "batch accept");

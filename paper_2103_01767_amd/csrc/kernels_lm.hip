@@ -340,6 +340,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.rz = s0;
     st.rr = s1;
     st.cg_active = (p.cg_max > 0 && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
+    if (a.cg_flags) __hip_atomic_store(a.cg_flags, st.cg_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   } else if constexpr (OP == F_PAP) {
     st.products += 1;
     st.pap = s0;
@@ -355,6 +356,8 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.cg_iters += 1;
     st.cg_total += 1;
     st.cg_active = (st.cg_iters < p.cg_max && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
+    if (a.cg_flags)
+      __hip_atomic_store(a.cg_flags + st.cg_iters, st.cg_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   } else if constexpr (OP == F_PRED) {
     st.pred = 0.5 * s0;  // 1/2 Delta^T (lambda D Delta - g)
   } else if constexpr (OP == F_TRIAL_END) {

@@ -17,6 +17,7 @@
 // kernels sum strips and probe partials in a fixed order.
 #include "dft.hpp"
 #include "internal.hpp"
+#include "tile_pixel.hpp"
 
 namespace ptlm {
 
@@ -54,12 +55,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ int xcd_block(int b, int n) {
   if (n % 8 != 0) return b;
   return (b % 8) * (n / 8) + b / 8;
-}
-
-// streamed (read-once) complex load that bypasses cache allocation
-__device__ __forceinline__ float2 ld_stream(const float2* p) {
-  const double d = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));
-  return __builtin_bit_cast(float2, d);
 }
 
 __device__ __forceinline__ const float2* tw_table(const float2* tw, int L) {
@@ -304,64 +299,20 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
       double tr = 0.0;
       if (act) {
         const size_t base = (size_t)k * C::M;
+        with_metric<OP>(g, [&](auto met) {
+          constexpr int MET = decltype(met)::value;
 #pragma unroll
-        for (int u = 0; u < V; ++u) {
-          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+          for (int u = 0; u < V; ++u) {
+            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int ky = ys * GY + r / RY + 16 * (r % RY);
-            const size_t gi = base + (size_t)ky * MX + yc;
-            if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
-              const float2 ps = cscale(v[u][r], isq);
-              const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, bgv));
-              const float iz = rsqrtf(h);
-              const float zeta = h * iz;
-              if constexpr (OP == OP_FORWARD) {
-                a.rout[gi] = zeta;
-              } else {
-                const float yv = a.y[gi];
-                float l, l1, l2;
-                if (g.metric == 0) {
-                  const float d = zeta - sqrtf(yv);
-                  l = 0.5f * d * d;
-                  l1 = d;
-                  l2 = 1.0f;
-                } else {
-                  l = h - yv * logf(h);
-                  l1 = 2.0f * zeta - 2.0f * yv * iz;
-                  l2 = 2.0f + 2.0f * yv / h;
-                }
-                s0 += (double)l;
-                s1 += (double)l1 * (double)l1;
-                if constexpr (OP == OP_LOSS) {
-                  if (a.rout) a.rout[gi] = l1;
-                } else {
-                  tr += (double)l2;
-                  const float w = sqrtf(l2);
-                  const float2 e = cscale(ps, iz);
-                  g.afield[gi] = cscale(e, w * isq);
-                  if (g.w2) g.w2[gi] = w;
-                  v[u][r] = cscale(e, l1 * isq);
-                }
-              }
-            } else if constexpr (OP == OP_JVP) {
-              const float2 as = ld_stream(g.afield + gi);
-              float val = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
-              if (g.w2) val /= g.w2[gi];
-              a.rout[gi] = val;
-            } else if constexpr (OP == OP_GGNV) {
-              const float2 as = ld_stream(g.afield + gi);
-              const float tt = fmaf(as.x, v[u][r].x, as.y * v[u][r].y);
-              v[u][r] = cscale(as, tt);
-            } else if constexpr (OP == OP_VJP) {
-              const float2 as = ld_stream(g.afield + gi);
-              float w = a.win[gi];
-              if (g.w2) w /= g.w2[gi];
-              v[u][r] = cscale(as, w);
+            for (int r = 0; r < 16; ++r) {
+              const int ky = ys * GY + r / RY + 16 * (r % RY);
+              const size_t gi = base + (size_t)ky * MX + yc;
+              pixel_op<OP, MET>(g, a, gi, isq, bgv, v[u][r], s0, s1, tr);
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        });
       }
       if constexpr (OP == OP_LINEARIZE) {
         // per-position trace of the metric Hessian (App. B), reduced over the tile

@@ -22,6 +22,7 @@
 // smaller tile kernels.
 #include "dft.hpp"
 #include "internal.hpp"
+#include "tile_pixel.hpp"
 
 namespace ptlm {
 
@@ -198,60 +199,19 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
           dft16<false>(v);
         }
         // per-pixel work at (ky, kx) = (cs + 16 r, kx), in groups of four pixels
+        if constexpr (OP == OP_DIAG_EXACT) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (r % 4 == 0) __builtin_amdgcn_sched_barrier(0);
-          const size_t gi = base + (size_t)(cs + 16 * r) * S + kx;
-          if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
-            const float2 ps = cscale(v[r], isq);
-            const float h = fmaf(ps.x, ps.x, fmaf(ps.y, ps.y, bgv));
-            const float iz = rsqrtf(h);
-            const float zeta = h * iz;
-            if constexpr (OP == OP_FORWARD) {
-              a.rout[gi] = zeta;
-            } else {
-              const float yv = a.y[gi];
-              float l, l1, l2;
-              if (g.metric == 0) {
-                const float d = zeta - sqrtf(yv);
-                l = 0.5f * d * d;
-                l1 = d;
-                l2 = 1.0f;
-              } else {
-                l = h - yv * logf(h);
-                l1 = 2.0f * zeta - 2.0f * yv * iz;
-                l2 = 2.0f + 2.0f * yv / h;
-              }
-              s0 += (double)l;
-              s1 += (double)l1 * (double)l1;
-              if constexpr (OP == OP_LOSS) {
-                if (a.rout) a.rout[gi] = l1;
-              } else {
-                tr += (double)l2;
-                const float w = sqrtf(l2);
-                const float2 e = cscale(ps, iz);
-                g.afield[gi] = cscale(e, w * isq);
-                if (g.w2) g.w2[gi] = w;
-                v[r] = cscale(e, l1 * isq);
-              }
+          for (int r = 0; r < 16; ++r) scr[(cs + 16 * r) * S + kx] = v[r];  // B_k = DFT(conj(a)^2), frequency order
+        } else {
+          with_metric<OP>(g, [&](auto met) {
+            constexpr int MET = decltype(met)::value;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              if (r % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+              const size_t gi = base + (size_t)(cs + 16 * r) * S + kx;
+              pixel_op<OP, MET>(g, a, gi, isq, bgv, v[r], s0, s1, tr);
             }
-          } else if constexpr (OP == OP_JVP) {
-            const float2 as = ld_nt(g.afield + gi);
-            float val = fmaf(as.x, v[r].x, as.y * v[r].y);
-            if (g.w2) val /= g.w2[gi];
-            a.rout[gi] = val;
-          } else if constexpr (OP == OP_GGNV) {
-            const float2 as = ld_nt(g.afield + gi);
-            const float tt = fmaf(as.x, v[r].x, as.y * v[r].y);
-            v[r] = cscale(as, tt);
-          } else if constexpr (OP == OP_VJP) {
-            const float2 as = ld_nt(g.afield + gi);
-            float w = a.win[gi];
-            if (g.w2) w /= g.w2[gi];
-            v[r] = cscale(as, w);
-          } else if constexpr (OP == OP_DIAG_EXACT) {
-            scr[(cs + 16 * r) * S + kx] = v[r];  // B_k = DFT(conj(a)^2), frequency order
-          }
+          });
         }
         if constexpr (INV_FFT) {
           // inverse y pass 2: DFT16 over k2 -> n1, conjugate twiddle W_256^(-n1 cs)

@@ -208,7 +208,7 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
 #pragma unroll
             for (int k2 = 0; k2 < R; ++k2) {
               const size_t gi = base + (size_t)(k1 + 16 * k2) * L + yc;
-              pixel_op<OP>(g, a, gi, isq, bgv, v[gg * R + k2], s0, s1, tr);
+              pixel_op<OP, -1>(g, a, gi, isq, bgv, v[gg * R + k2], s0, s1, tr);
             }
           }
         }

@@ -154,6 +154,22 @@ struct SingleOps {
     LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
     return PTLM_OK;
   }
+  // PCG look-ahead: iteration i is enqueued once the decision on iteration i - 1 is known
+  // (the GPU is then still busy with iteration i - 1), so at most one iteration past the
+  // end of the solve is launched, predicated off.  Without pinned slots every iteration is
+  // enqueued.
+  ptlm_status cg_mark(int j) {
+    if (!a.cg_flags) return PTLM_OK;
+    LM_HIP(hipEventRecord(h->cg_events[j], s), "lm pcg mark");
+    return PTLM_OK;
+  }
+  ptlm_status cg_gate(int i, bool* go) {
+    *go = true;
+    if (!a.cg_flags || i < 1) return PTLM_OK;
+    LM_HIP(hipEventSynchronize(h->cg_events[i - 1]), "lm pcg gate");
+    *go = __atomic_load_n(a.cg_flags + (i - 1), __ATOMIC_ACQUIRE) != 0;
+    return PTLM_OK;
+  }
   ptlm_status copy_accept() {
     // the accepted step's blocks (both, or the active one of the alternating update)
     Geometry& g = h->g;
@@ -257,6 +273,24 @@ static ptlm_status projected_plugin(SingleOps& o, const ptlm_lm_params& prm, dou
   return PTLM_OK;
 }
 
+// Pinned host slots (and their events) for the PCG look-ahead, grown on demand.
+static ptlm_status cg_slots(ptlm_handle* h, int n) {
+  if (h->cg_flags && h->cg_slots >= n) return PTLM_OK;
+  if (h->cg_flags) LM_HIP(hipHostFree(h->cg_flags), "lm pcg slots");
+  h->cg_flags = nullptr;
+  h->cg_slots = 0;
+  void* p = nullptr;
+  LM_HIP(hipHostMalloc(&p, (size_t)n * sizeof(int), hipHostMallocCoherent), "lm pcg slots");
+  h->cg_flags = (int*)p;
+  h->cg_slots = n;
+  while ((int)h->cg_events.size() < n) {
+    hipEvent_t e;
+    LM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "lm pcg events");
+    h->cg_events.push_back(e);
+  }
+  return PTLM_OK;
+}
+
 // One outer iteration: the attempts of alg:lm_inexact until one is accepted or retry_max are
 // rejected -- once for the joint update, once per block (object, then probe) for the
 // alternating update of alg:alt_LM_ptycho.
@@ -268,12 +302,16 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
   if (hs.t >= hs.t_max) return fail(PTLM_EINVAL, "the state has run its outer iterations (t_max)");
   const int t0 = hs.t;
   SingleOps o{h, make_lm_args(h, prm, st, O, P, learned), O, P, y, learned, false, s};
+  PTLM_TRY(cg_slots(h, prm->cg_max + 1));
+  o.a.cg_flags = h->cg_flags;
   bool rejected = false;
   const int subs = prm->alternate ? 2 : 1;
   for (int sub = 0; sub < subs; ++sub) {
     bool ended = false;
     for (int attempt = 0; attempt <= prm->retry_max && !ended; ++attempt) {
       o.lin_expected = hs.need_lin != 0;
+      // no kernel of an earlier attempt is in flight (its state was read back)
+      for (int j = 0; j <= prm->cg_max; ++j) __atomic_store_n(h->cg_flags + j, 0, __ATOMIC_RELAXED);
       PTLM_TRY(enqueue_attempt(o, *prm));
       PTLM_TRY(read_state(st, &hs, s));
       if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");

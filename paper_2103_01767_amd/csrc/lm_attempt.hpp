@@ -19,7 +19,10 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
   } while (0)
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
-// diag_paper(), learned(), exact_diag(), ggnv(which), trial_loss(), copy_accept().
+// diag_paper(), learned(), exact_diag(), ggnv(which), trial_loss(), copy_accept(),
+// cg_mark(j) (after the launch that decides whether PCG iteration j runs) and
+// cg_gate(i, &go) (before PCG iteration i is enqueued; go = false ends the enqueueing, every
+// later iteration being predicated off anyway).
 // ggnv(GG_WARM) multiplies the last accepted step, or p when params.alternate is set.
 template <class Ops>
 ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
@@ -50,12 +53,17 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.ggnv(GG_WARM));
   PTLM_TRY(o.vec(V_CG_INIT, FL_ALIVE));
   PTLM_TRY(o.fin(F_CG_INIT, 1, FL_ALIVE));
+  PTLM_TRY(o.cg_mark(0));
   for (int i = 0; i < prm.cg_max; ++i) {
+    bool go = true;
+    PTLM_TRY(o.cg_gate(i, &go));
+    if (!go) break;
     PTLM_TRY(o.ggnv(GG_P));
     PTLM_TRY(o.vec(V_PAP, FL_CG));
     PTLM_TRY(o.fin(F_PAP, 1, FL_CG));
     PTLM_TRY(o.vec(V_CG_UPDATE, FL_CG));
     PTLM_TRY(o.fin(F_CG_UPDATE, 1, FL_CG));
+    PTLM_TRY(o.cg_mark(i + 1));
     PTLM_TRY(o.vec(V_PUPDATE, FL_CG));
   }
   // ---- trial point, predicted and actual reductions, gain ratio, damping, acceptance

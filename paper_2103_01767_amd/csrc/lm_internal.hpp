@@ -52,6 +52,7 @@ struct LMArgs {
   int vec_blocks;          // blocks of the vector kernels (lm_vec_blocks(n))
   int tile_grid;           // workgroups of the tile kernels (partials of the trial loss)
   int t_max;               // outer iterations to run (ptlm_lm_init / batch binding)
+  int* cg_flags;           // nullable, pinned host memory: slot j <- whether PCG iteration j runs
 };
 
 // One problem's part of a batched LM launch.

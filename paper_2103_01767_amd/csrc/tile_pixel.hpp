@@ -11,8 +11,11 @@
 //
 // v holds the unnormalised transform; isq = 1/sqrt(M) applies the unitary normalisation
 // (eq:expected_count); bgv is the background (plus the surrogate term of App. E when set).
+// The metric is a template parameter, so pixel loops carry no per-pixel branch on it.
 // Gaussian ell = (zeta - sqrt y)^2 / 2, Poisson ell = zeta^2 - y log zeta^2.
 #pragma once
+#include <type_traits>
+
 #include "dft.hpp"
 #include "internal.hpp"
 
@@ -23,7 +26,16 @@ __device__ __forceinline__ float2 ld_once(const float2* p) {
   return __builtin_bit_cast(float2, d);
 }
 
+// Whether the per-pixel work of OP depends on the metric (the caller then dispatches the
+// metric once, outside its pixel loop, so the loop has no per-pixel branches).
 template <int OP>
+constexpr bool metric_dependent() {
+  return OP == OP_LOSS || OP == OP_LINEARIZE || OP == OP_JVP || OP == OP_VJP;
+}
+
+// MET: 0 Gaussian, 1 Poisson (g.w2 holds sqrt(ell'') for the Poisson metric only), -1 read
+// from g per pixel (for loops where two specialised copies cost more registers than the branch)
+template <int OP, int MET>
 __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, size_t gi, float isq, float bgv,
                                          float2& v, double& s0, double& s1, double& tr) {
   if constexpr (OP == OP_FORWARD || OP == OP_LOSS || OP == OP_LINEARIZE) {
@@ -36,7 +48,7 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
     } else {
       const float yv = a.y[gi];
       float l, l1, l2;
-      if (g.metric == 0) {
+      if (MET == 0 || (MET < 0 && g.metric == 0)) {
         const float d = zeta - sqrtf(yv);
         l = 0.5f * d * d;
         l1 = d;
@@ -55,14 +67,20 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
         const float w = sqrtf(l2);
         const float2 e = cscale(ps, iz);
         g.afield[gi] = cscale(e, w * isq);
-        if (g.w2) g.w2[gi] = w;
+        if constexpr (MET == 1) g.w2[gi] = w;
+        if constexpr (MET < 0) {
+          if (g.w2) g.w2[gi] = w;
+        }
         v = cscale(e, l1 * isq);
       }
     }
   } else if constexpr (OP == OP_JVP) {
     const float2 as = ld_once(g.afield + gi);
     float val = fmaf(as.x, v.x, as.y * v.y);
-    if (g.w2) val /= g.w2[gi];
+    if constexpr (MET == 1) val /= g.w2[gi];
+    if constexpr (MET < 0) {
+      if (g.w2) val /= g.w2[gi];
+    }
     a.rout[gi] = val;
   } else if constexpr (OP == OP_GGNV) {
     const float2 as = ld_once(g.afield + gi);
@@ -71,8 +89,23 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
   } else if constexpr (OP == OP_VJP) {
     const float2 as = ld_once(g.afield + gi);
     float w = a.win[gi];
-    if (g.w2) w /= g.w2[gi];
+    if constexpr (MET == 1) w /= g.w2[gi];
+    if constexpr (MET < 0) {
+      if (g.w2) w /= g.w2[gi];
+    }
     v = cscale(as, w);
+  }
+}
+
+// Run body(std::integral_constant<int, MET>) with the problem's metric as a constant (once
+// for metric-independent ops).
+template <int OP, class F>
+__device__ __forceinline__ void with_metric(const Geometry& g, F&& body) {
+  if constexpr (metric_dependent<OP>()) {
+    if (g.metric == 0) body(std::integral_constant<int, 0>{});
+    else body(std::integral_constant<int, 1>{});
+  } else {
+    body(std::integral_constant<int, 0>{});
   }
 }
 
