@@ -120,6 +120,25 @@ def ell_d2(zeta, y, metric=GAUSS):
     raise ValueError(metric)
 
 
+def big_ell(h, y, metric=GAUSS):
+    """Intensity-based form L(h, y) of the same metric (eq:error_metric_magnitude): L(zeta^2, y)
+    equals ell(zeta, y)."""
+    if metric == GAUSS:
+        return 0.5 * (np.sqrt(h) - np.sqrt(y)) ** 2
+    if metric == POISSON:
+        return h - y * np.log(h)
+    raise ValueError(metric)
+
+
+def big_ell_d2(h, y, metric=GAUSS):
+    """d^2 L / d h^2, the Hessian of the intensity-based metric in eq:ggn_intensity."""
+    if metric == GAUSS:
+        return np.sqrt(y) / (4.0 * h ** 1.5)
+    if metric == POISSON:
+        return y / h ** 2
+    raise ValueError(metric)
+
+
 def loss(O, P, pos, y, b, metric=GAUSS) -> float:
     """f = sum_k sum_m ell(zeta_km, y_km)  (eq:error_metric_magnitude)."""
     return float(np.sum(ell(magnitude(O, P, pos, b), y, metric)))
@@ -142,7 +161,9 @@ class Linearization:
     zeta: np.ndarray
     e: np.ndarray         # psi_hat / zeta: d zeta = Re(conj(e) d psi_hat)
     l1: np.ndarray        # ell'(zeta)
-    l2: np.ndarray        # ell''(zeta)
+    l2: np.ndarray        # GGN weight in zeta: ell''(zeta) (magnitude-based GGN, eq:ggn_magnitude)
+                          # or 4 zeta^2 L''(zeta^2) (intensity-based GGN, eq:ggn_intensity)
+    ggn: str = "magnitude"
 
     @property
     def f(self) -> float:
@@ -153,13 +174,25 @@ class Linearization:
         return self.P.size
 
 
-def linearize(O, P, pos, y, b, metric=GAUSS, joint=False) -> Linearization:
-    """Evaluate the forward model and the metric derivatives at (O, P)."""
+def linearize(O, P, pos, y, b, metric=GAUSS, joint=False, ggn="magnitude") -> Linearization:
+    """Evaluate the forward model and the metric derivatives at (O, P).
+
+    ``ggn`` chooses the GGN matrix of the LM model: "magnitude" (eq:ggn_magnitude, the paper's
+    choice) or "intensity" (eq:ggn_intensity, the ablation of App. C).  Since h = zeta^2,
+    J_h = diag(2 zeta) J_zeta, so G^L = J_zeta^T diag(4 zeta^2 L''(h)) J_zeta: only the weight
+    between the two Jacobians differs; f and the gradient are the same.
+    """
     psi_hat = far_field(O, P, pos)
     zeta = np.sqrt(np.abs(psi_hat) ** 2 + b)
+    if ggn == "magnitude":
+        l2 = ell_d2(zeta, y, metric)
+    elif ggn == "intensity":
+        l2 = 4.0 * zeta ** 2 * big_ell_d2(zeta ** 2, y, metric)
+    else:
+        raise ValueError(ggn)
     return Linearization(O=O, P=P, pos=pos, y=y, b=b, metric=metric, joint=joint,
                          psi_hat=psi_hat, zeta=zeta, e=psi_hat / zeta,
-                         l1=ell_d1(zeta, y, metric), l2=ell_d2(zeta, y, metric))
+                         l1=ell_d1(zeta, y, metric), l2=l2, ggn=ggn)
 
 
 def jvp(lin: Linearization, vO, vP=None) -> np.ndarray:

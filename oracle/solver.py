@@ -150,6 +150,8 @@ class LMParams:
     p_s: float = 2.1
     ls_max: int = 30         # backtracking halvings before the iterate is kept
     alternate: bool = False  # alg:alt_LM_ptycho: object sub-step, then probe sub-step (joint only)
+    ggn: str = "magnitude"   # GGN of the LM model: "magnitude" (eq:ggn_magnitude) or "intensity"
+                             # (eq:ggn_intensity, the App. C ablation)
 
 
 def surrogate_sigma(t: int, p: "LMParams") -> float:
@@ -297,7 +299,7 @@ def lm_solve(O0, P0, pos, y, b, metric, joint, params: LMParams, T: int,
         trial_loss = loss_fn or (lambda O_, P_, b_t=b_t: ptycho.loss(O_, P_, pos, y, b_t, metric))
         for k in blocks:
             # line "Calculate G, J, grad ell and D_t" -- once per outer iteration (per sub-step)
-            lin = ptycho.linearize(O, P, pos, y, b_t, metric, joint)
+            lin = ptycho.linearize(O, P, pos, y, b_t, metric, joint, p.ggn)
             if k == blocks[0]:
                 res.f_per_iter.append(lin.f)
                 if progress is not None:
