@@ -55,6 +55,7 @@ typedef enum {
 
 typedef enum { PTLM_GAUSS = 0, PTLM_POISSON = 1 } ptlm_metric; /* eq:ell_magnitude */
 typedef enum { PTLM_OBJECT = 0, PTLM_JOINT = 1 } ptlm_mode;    /* SPR eq:cdp / BPR eq:bp */
+typedef enum { PTLM_GGN_MAGNITUDE = 0, PTLM_GGN_INTENSITY = 1 } ptlm_ggn;
 
 /* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128, or both 48, 96 or 256. */
 typedef struct {
@@ -64,6 +65,10 @@ typedef struct {
   int32_t metric;     /* ptlm_metric */
   int32_t mode;       /* ptlm_mode: PTLM_JOINT optimises object and probe */
   float background;   /* b > 0 of eq:expected_count, per detector pixel */
+  int32_t ggn;        /* GGN of the LM model: PTLM_GGN_MAGNITUDE (eq:ggn_magnitude, the paper's
+                         choice) or PTLM_GGN_INTENSITY (eq:ggn_intensity, the ablation of App. C:
+                         the same f and gradient, the Hessian of the metric taken in the
+                         intensity h; its weight is floored at 1e-30 where it vanishes, y = 0) */
 } ptlm_desc;
 
 /* LM hyper-parameters (alg:lm_inexact; defaults of Sec. 5 via ptlm_lm_default_params). */

@@ -125,6 +125,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
     return fail(PTLM_EINVAL, "probe sides must each be 16, 32, 64 or 128, or both 48, 96 or 256");
   if (d->ny < d->my || d->nx < d->mx) return fail(PTLM_EINVAL, "object smaller than probe");
   if (d->metric != PTLM_GAUSS && d->metric != PTLM_POISSON) return fail(PTLM_EINVAL, "unknown metric");
+  if (d->ggn != PTLM_GGN_MAGNITUDE && d->ggn != PTLM_GGN_INTENSITY) return fail(PTLM_EINVAL, "unknown GGN kind");
   if (d->mode != PTLM_OBJECT && d->mode != PTLM_JOINT) return fail(PTLM_EINVAL, "unknown mode");
   if (!(d->background > 0.0f) || !std::isfinite(d->background))
     return fail(PTLM_EINVAL, "background must be finite and > 0");
@@ -202,7 +203,9 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   p.off.O_lin = take((size_t)N * sizeof(float2));
   p.off.P_lin = take((size_t)M * sizeof(float2));
   p.off.afield = take((size_t)K * M * sizeof(float2));
-  p.off.w2 = d->metric == PTLM_POISSON ? take((size_t)K * M * sizeof(float)) : 0;
+  // sqrt of the GGN weight, kept where it is not 1 (the JVP / VJP divide it out of the phasors)
+  const bool weighted = d->metric == PTLM_POISSON || d->ggn == PTLM_GGN_INTENSITY;
+  p.off.w2 = weighted ? take((size_t)K * M * sizeof(float)) : 0;
   p.off.trace = take((size_t)K * sizeof(double));
   p.off.strips = take((size_t)max_strip * sizeof(float2));
   p.off.probe_part = take(max_nseg * M * sizeof(float2));
@@ -294,6 +297,7 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
   const ptlm_desc& d = p.d;
   g.ny = d.ny; g.nx = d.nx; g.my = d.my; g.mx = d.mx; g.K = d.K;
   g.metric = d.metric;
+  g.ggn = d.ggn;
   g.joint = d.mode == PTLM_JOINT;
   g.background = d.background;
   g.nseg = p.nseg;
@@ -313,7 +317,7 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
   g.O_lin = (float2*)at(p.off.O_lin);
   g.P_lin = (float2*)at(p.off.P_lin);
   g.afield = (float2*)at(p.off.afield);
-  g.w2 = d.metric == PTLM_POISSON ? (float*)at(p.off.w2) : nullptr;
+  g.w2 = (d.metric == PTLM_POISSON || d.ggn == PTLM_GGN_INTENSITY) ? (float*)at(p.off.w2) : nullptr;
   g.trace = (double*)at(p.off.trace);
   g.strips = (float2*)at(p.off.strips);
   g.probe_part = (float2*)at(p.off.probe_part);

@@ -21,6 +21,7 @@ enum TileOp : int {
 struct Geometry {
   int ny, nx, my, mx, K;
   int metric;  // 0 Gauss, 1 Poisson
+  int ggn;     // 0 magnitude-based GGN weight ell''(zeta), 1 intensity-based 4 zeta^2 L''(zeta^2)
   int joint;   // 1: probe part is computed
   float background;
   int nseg;    // number of position segments (= grid * tiles per workgroup)
@@ -41,7 +42,7 @@ struct Geometry {
   float2* O_lin;          // N
   float2* P_lin;          // M
   float2* afield;         // K*M: sqrt(ell'') e / sqrt(M), detector order
-  float* w2;              // K*M: sqrt(ell'') (Poisson only, else null)
+  float* w2;              // K*M: sqrt of the GGN weight (Poisson or intensity-based GGN, else null)
   double* trace;          // K: sum_m ell''_km
   // scratch
   float2* strips;         // per-segment private overlap-add strips (rewritten by every scatter)

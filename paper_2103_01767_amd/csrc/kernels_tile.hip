@@ -78,7 +78,9 @@ __device__ __forceinline__ double tile_sum(double x, double* red, int col, int s
   return x;
 }
 
-template <int MY, int MX, int OP>
+// MET: the metric / GGN-weight code of the per-pixel op (tile_pixel.hpp); -1 reads it from g
+// per pixel (batched launches mix problems)
+template <int MY, int MX, int OP, int MET>
 __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   using C = Cfg<MY, MX>;
   constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
@@ -299,20 +301,17 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
       double tr = 0.0;
       if (act) {
         const size_t base = (size_t)k * C::M;
-        with_metric<OP>(g, [&](auto met) {
-          constexpr int MET = decltype(met)::value;
 #pragma unroll
-          for (int u = 0; u < V; ++u) {
-            const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
+        for (int u = 0; u < V; ++u) {
+          const int tv = t + u * NT, yc = tv % MX, ys = tv / MX;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int ky = ys * GY + r / RY + 16 * (r % RY);
-              const size_t gi = base + (size_t)ky * MX + yc;
-              pixel_op<OP, MET>(g, a, gi, isq, bgv, v[u][r], s0, s1, tr);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+          for (int r = 0; r < 16; ++r) {
+            const int ky = ys * GY + r / RY + 16 * (r % RY);
+            const size_t gi = base + (size_t)ky * MX + yc;
+            pixel_op<OP, MET>(g, a, gi, isq, bgv, v[u][r], s0, s1, tr);
           }
-        });
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
       if constexpr (OP == OP_LINEARIZE) {
         // per-position trace of the metric Hessian (App. B), reduced over the tile
@@ -565,9 +564,9 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   }
 }
 
-template <int MY, int MX, int OP>
+template <int MY, int MX, int OP, int MET>
 __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
-  tile_body<MY, MX, OP>(g, a, blockIdx.x, gridDim.x);
+  tile_body<MY, MX, OP, MET>(g, a, blockIdx.x, gridDim.x);
 }
 
 // batched: block b belongs to job job_of_block[b]; trailing blocks of a job's run exit
@@ -577,7 +576,7 @@ __global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_batch_kernel(const Til
   const TileJob& J = jobs[job_of_block[blockIdx.x]];
   const int b = (int)blockIdx.x - J.block0;
   if (b >= J.g.grid) return;
-  tile_body<MY, MX, OP>(J.g, J.a, b, J.g.grid);
+  tile_body<MY, MX, OP, -1>(J.g, J.a, b, J.g.grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -589,19 +588,39 @@ static size_t lds_bytes() {
   return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)C::NWAVE * 2 * sizeof(double) + 224 * sizeof(float2);
 }
 
-template <int MY, int MX, int OP>
-static hipError_t launch_one(const Geometry& g, const TileArgs& a, hipStream_t s) {
+template <int MY, int MX, int OP, int MET>
+static hipError_t launch_met(const Geometry& g, const TileArgs& a, hipStream_t s) {
   using C = Cfg<MY, MX>;
   const size_t lds = lds_bytes<MY, MX>();
   static bool attr_set = false;  // per instantiation, host-side
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<MY, MX, OP>,
+    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<MY, MX, OP, MET>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((tile_kernel<MY, MX, OP>), dim3(g.grid), dim3(C::WG), lds, s, g, a);
+  hipLaunchKernelGGL((tile_kernel<MY, MX, OP, MET>), dim3(g.grid), dim3(C::WG), lds, s, g, a);
   return hipGetLastError();
+}
+
+// one kernel per metric / GGN-weight code, so each variant gets its own register allocation
+template <int MY, int MX, int OP>
+static hipError_t launch_one(const Geometry& g, const TileArgs& a, hipStream_t s) {
+  switch (met_code(OP, g)) {
+    case 0: return launch_met<MY, MX, OP, 0>(g, a, s);
+    case 1:
+      if constexpr (OP == OP_LOSS || OP == OP_LINEARIZE || OP == OP_JVP || OP == OP_VJP)
+        return launch_met<MY, MX, OP, 1>(g, a, s);
+      break;
+    case 2:
+      if constexpr (OP == OP_LINEARIZE) return launch_met<MY, MX, OP, 2>(g, a, s);
+      break;
+    case 3:
+      if constexpr (OP == OP_LINEARIZE) return launch_met<MY, MX, OP, 3>(g, a, s);
+      break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int MY, int MX, int OP>

@@ -203,15 +203,13 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
 #pragma unroll
           for (int r = 0; r < 16; ++r) scr[(cs + 16 * r) * S + kx] = v[r];  // B_k = DFT(conj(a)^2), frequency order
         } else {
-          with_metric<OP>(g, [&](auto met) {
-            constexpr int MET = decltype(met)::value;
+          // the metric is read per pixel: specialised copies of this loop spill more
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              if (r % 4 == 0) __builtin_amdgcn_sched_barrier(0);
-              const size_t gi = base + (size_t)(cs + 16 * r) * S + kx;
-              pixel_op<OP, MET>(g, a, gi, isq, bgv, v[r], s0, s1, tr);
-            }
-          });
+          for (int r = 0; r < 16; ++r) {
+            if (r % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+            const size_t gi = base + (size_t)(cs + 16 * r) * S + kx;
+            pixel_op<OP, -1>(g, a, gi, isq, bgv, v[r], s0, s1, tr);
+          }
         }
         if constexpr (INV_FFT) {
           // inverse y pass 2: DFT16 over k2 -> n1, conjugate twiddle W_256^(-n1 cs)

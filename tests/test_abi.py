@@ -43,10 +43,16 @@ def test_workspace_validation():
         p2[2] = bad
         assert _ws(d, p2)[0] == pt.PTLM_EINVAL
         assert b"position 2" in pt.lib().ptlm_last_error()
-    for field, val in (("my", 48), ("mx", 24), ("K", 0), ("metric", 7), ("mode", 3), ("background", 0.0)):
+    for field, val in (("my", 48), ("mx", 24), ("K", 0), ("metric", 7), ("mode", 3), ("background", 0.0),
+                       ("ggn", 2)):
         d2 = pt.ptlm_desc(48, 40, 32, 16, 3, pt.GAUSS, pt.JOINT, 1e-8)
         setattr(d2, field, val)
         assert _ws(d2, pos)[0] == pt.PTLM_EINVAL, field
+    # the intensity-based GGN keeps the square root of its weight per measurement, as Poisson does
+    d_int = pt.ptlm_desc(48, 40, 32, 16, 3, pt.GAUSS, pt.JOINT, 1e-8, pt.GGN_INTENSITY)
+    d_poi = pt.ptlm_desc(48, 40, 32, 16, 3, pt.POISSON, pt.JOINT, 1e-8)
+    n_int, n_poi = _ws(d_int, pos)[1], _ws(d_poi, pos)[1]
+    assert n_int == n_poi >= n + 3 * 32 * 16 * 4
     # more positions need more workspace (stored phasor field grows with K)
     many = np.array([[i % 17, i % 25] for i in range(40)], np.int32)
     d3 = pt.ptlm_desc(48, 40, 32, 16, 40, pt.GAUSS, pt.JOINT, 1e-8)

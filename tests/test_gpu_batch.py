@@ -223,3 +223,35 @@ def test_batch_alternating_equals_alone():
         assert s2.t == T and s1.t == T and s2.block == s1.block == 1
         assert s2.f == s1.f and s2.mu == s1.mu and s2.mu_alt == s1.mu_alt and s2.products == s1.products
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+def test_batch_mixed_ggn_equals_alone():
+    """Problems with the intensity-based GGN (App. C) and the magnitude-based one in one batch:
+    the batched kernels read each problem's GGN kind, so the batch equals them solved alone."""
+    print("case batch mixed ggn", flush=True)
+    probs = make_problems()[:4]
+    for i, p in enumerate(probs):
+        p["ggn"] = "intensity" if i % 2 == 0 else "magnitude"
+    params = pt.default_params(scaling=1, precond=1, cg_max=6)
+    T = 3
+    alone = []
+    for p in probs:
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV, ggn=p["ggn"])
+        O, P = c64(p["O0"]), c64(p["P0"])
+        y = torch.from_numpy(p["y"]).to(DEV)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(T):
+            prob.lm_step(O, P, y, params, st)
+        alone.append((O, P, pt.state_from_tensor(st)))
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(100, check_every=1)
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        assert s2.t == T and s2.f == s1.f and s2.products == s1.products
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)

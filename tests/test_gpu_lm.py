@@ -325,3 +325,36 @@ def test_alternating_needs_joint_problem():
     with pytest.raises(pt.PtlmError) as e:
         prob.lm_init(pt.default_params(alternate=1), st)
     assert e.value.status == pt.PTLM_EINVAL
+
+
+# ---------------------------------------------------------------- intensity-based GGN (App. C ablation)
+@pytest.mark.parametrize("mode", ["object", "joint"])
+def test_intensity_ggn_lm_matches_oracle(mode):
+    """LM on the intensity-based GGN (eq:ggn_intensity): final loss within 1.01x of the oracle's
+    LM on the same GGN; on the object problem it ends above the magnitude-based LM (Fig. 1)."""
+    print("case intensity lm", mode, flush=True)
+    joint = mode == "joint"
+    pr = synth.make_small(5, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode=mode)
+    rng = np.random.default_rng(5)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    P0 = pr.P_init if joint else pr.P_true
+    kw = dict(scaling=1, precond=1) if joint else {}
+    T = 10
+    ref = solver.lm_solve(pr.O_init, P0, pr.pos, y.astype(np.float64), pr.background, "gauss", joint,
+                          solver.LMParams(ggn="intensity", **kw), T)
+    f_gpu = {}
+    for ggn in ("intensity", "magnitude"):
+        prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode=mode, background=pr.background,
+                          device=DEV, ggn=ggn)
+        O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(P0, np.complex64), to_dev(y, np.float32)
+        params = pt.default_params(**kw)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        prob.lm_solve(O, P, yd, params, T, st)
+        assert pt.state_from_tensor(st).t == T
+        f_gpu[ggn] = float(prob.loss(O, P, yd).cpu()[0])
+    print("intensity %s oracle f=%.6e gpu f=%.6e magnitude gpu f=%.6e" % (mode, ref.f, f_gpu["intensity"],
+                                                                        f_gpu["magnitude"]))
+    assert f_gpu["intensity"] <= 1.01 * ref.f
+    if not joint:
+        assert f_gpu["magnitude"] < f_gpu["intensity"]

@@ -240,3 +240,56 @@ def test_autotuned_segmentation_keeps_products(probe, n, step):
     f, gO, gP = prob.linearize(O, P, y)
     rgO, rgP = ptycho.gradient(lin)
     assert rel(host(gO), rgO) < TOL and rel(host(gP), rgP) < TOL
+
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+@pytest.mark.parametrize("probe,joint", [((16, 16), True), ((64, 64), False), ((128, 128), True), ((48, 48), True),
+                                         ((256, 256), True)], ids=lambda p: "%dx%d" % p if isinstance(p, tuple) else str(p))
+def test_intensity_ggn_products(probe, joint, metric):
+    """Intensity-based GGN (eq:ggn_intensity, App. C): the same f, gradient, JVP and VJP as the
+    magnitude-based problem, the GGN-vector product and both diagonals with the weight
+    4 zeta^2 L''(zeta^2) (zero-count pixels included: their weight vanishes)."""
+    print("case intensity ggn", probe, joint, metric, flush=True)
+    case = make_case(probe, 5, 6, max(probe) // 4, metric=metric, joint=joint, seed=5 + probe[0])
+    prob = pt.Problem(case["O"].shape, case["P"].shape, case["pos"], metric=metric,
+                      mode="joint" if joint else "object", background=1e-8, device=DEV, ggn="intensity")
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    assert np.any(case["y"] == 0)
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, metric, joint, ggn="intensity")
+    f, gO, gP = prob.linearize(O, P, y)
+    f = host(f)
+    assert abs(f[0] - lin.f) <= 1e-5 * abs(lin.f)
+    rgO, rgP = ptycho.gradient(lin)
+    assert rel(host(gO), rgO) < TOL
+    if joint:
+        assert rel(host(gP), rgP) < TOL
+    rng = np.random.default_rng(12)
+    vO = c64(synth.random_complex(rng, case["O"].shape))
+    vP = c64(synth.random_complex(rng, case["P"].shape)) if joint else None
+    vOd, vPd = to_dev(vO), (to_dev(vP) if joint else None)
+    vO64 = vO.astype(np.complex128)
+    vP64 = vP.astype(np.complex128) if joint else None
+    assert rel(host(prob.jvp(vOd, vPd)), ptycho.jvp(lin, vO64, vP64)) < TOL
+    w = rng.standard_normal(prob.meas_shape).astype(np.float32)
+    oO, oP = prob.vjp(to_dev(w))
+    rO, rP = ptycho.vjp(lin, w.astype(np.float64))
+    assert rel(host(oO), rO) < TOL
+    if joint:
+        assert rel(host(oP), rP) < TOL
+    tol_g = 2 * TOL if (metric == "poisson" and probe[0] * probe[1] >= 65536) else TOL
+    GO, GP = ptycho.ggn_vp(lin, vO64, vP64)
+    oO, oP = prob.ggn_vp(vOd, vPd)
+    print("ggn rel", rel(host(oO), GO), rel(host(oP), GP) if joint else 0.0)
+    assert rel(host(oO), GO) < tol_g
+    if joint:
+        assert rel(host(oP), GP) < tol_g
+    dOg, dPg = prob.diag(exact=False)
+    aO, aP = ptycho.ggn_diag_paper(lin)
+    assert rel(host(dOg), aO) < TOL
+    if joint:
+        assert rel(host(dPg), aP) < TOL
+    dOg, dPg = prob.diag(exact=True)
+    eO, eP = ptycho.ggn_diag_exact(lin)
+    assert rel(host(dOg), eO) < 2 * TOL
+    if joint:
+        assert rel(host(dPg), eP) < 2 * TOL
