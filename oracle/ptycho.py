@@ -315,3 +315,56 @@ def illumination_overlap(P, pos, obj_shape) -> np.ndarray:
     """sum_k S_k^T |P|^2: the illumination-overlap map."""
     K = len(pos)
     return extract_adjoint(np.broadcast_to(np.abs(P)[None] ** 2, (K,) + P.shape), pos, obj_shape)
+
+
+# ----------------------------------------------------------------------------
+# stochastic diagonal estimate (the matrix-free route the paper points to when
+# no analytic diagonal is available)
+# ----------------------------------------------------------------------------
+_U64 = np.uint64
+_GOLDEN_GAMMA = _U64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, n: np.ndarray) -> np.ndarray:
+    """Output number n >= 1 of the SplitMix64 generator seeded with ``seed`` (Steele, Lea and
+    Flood, OOPSLA 2014): the state after n steps is seed + n * gamma (mod 2^64) and the output
+    is Stafford's 64-bit finaliser ("Mix13") of it.  Counter-based: any output is computed on
+    its own.  Pinned by the generator's first outputs from seed 0."""
+    with np.errstate(over="ignore"):
+        z = _U64(seed) + np.asarray(n, dtype=_U64) * _GOLDEN_GAMMA
+        z = (z ^ (z >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U64(27))) * _U64(0x94D049BB133111EB)
+        return z ^ (z >> _U64(31))
+
+
+def rademacher(seed: int, n: np.ndarray) -> np.ndarray:
+    """+1 or -1 from the top bit of SplitMix64 output n (n >= 1)."""
+    return np.where(splitmix64(seed, n) >> _U64(63), -1.0, 1.0)
+
+
+def rademacher_field(lin: "Linearization", seed: int, draw: int) -> np.ndarray:
+    """The sign field r of draw ``draw`` over all K x M measurements: measurement j (position k,
+    detector pixel m in row-major order, j = k M + m) takes output draw K M + j + 1."""
+    KM = lin.zeta.size
+    n = np.uint64(draw) * np.uint64(KM) + np.arange(KM, dtype=np.uint64) + np.uint64(1)
+    return rademacher(seed, n).reshape(lin.zeta.shape)
+
+
+def ggn_diag_stochastic(lin: Linearization, r: np.ndarray):
+    """Unbiased estimate of diag(G) from vector-Jacobian products alone (Chapelle and Erhan
+    2011; Martens 2016): for a sign vector r over the measurements, u = J^T diag(sqrt(W)) r has
+    E[u u^T] = J^T diag(W) J = G, so the mean of u_i^2 over draws estimates G_ii.  W is the GGN
+    weight of the linearisation (ell'' or its intensity-based form).  ``r`` has shape
+    (S, K, My, Mx), entries +-1.  Returns (dO, dP) in the layout of ggn_diag_exact.  Pinned:
+    averaged over every sign pattern it is the exact diagonal; over many draws it converges
+    to it."""
+    w = np.sqrt(lin.l2)
+    accO = np.zeros(lin.O.shape + (2,))
+    accP = np.zeros(lin.P.shape + (2,)) if lin.joint else None
+    for rs in r:
+        uO, uP = vjp(lin, w * rs)
+        accO += np.stack([uO.real ** 2, uO.imag ** 2], axis=-1)
+        if lin.joint:
+            accP += np.stack([uP.real ** 2, uP.imag ** 2], axis=-1)
+    S = len(r)
+    return accO / S, (accP / S if lin.joint else None)

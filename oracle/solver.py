@@ -136,7 +136,7 @@ class LMParams:
     retry_max: int = 10
     scaling: int = 0         # 0: D = I, 1: D = Dg(G) (App. B diagonal)
     precond: int = 0         # 0: none, 1: Jacobi Dg(G + lambda D), 2: learned + lambda D,
-                             # 3: exact diagonal of G + lambda D
+                             # 3: exact diagonal of G + lambda D, 4: stochastic estimate + lambda D
     diag_floor: float = 1e-6
     warm_start: bool = True
     surrogate_T: int = 0     # App. E surrogate Poisson metric: iterations with sigma_t > 0 (0: off)
@@ -152,6 +152,8 @@ class LMParams:
     alternate: bool = False  # alg:alt_LM_ptycho: object sub-step, then probe sub-step (joint only)
     ggn: str = "magnitude"   # GGN of the LM model: "magnitude" (eq:ggn_magnitude) or "intensity"
                              # (eq:ggn_intensity, the App. C ablation)
+    stoch_samples: int = 8   # precond 4: sign-field draws of the stochastic diagonal per linearisation
+    stoch_seed: int = 0      # precond 4: SplitMix64 seed; outer iteration t uses draws t S .. t S + S - 1
 
 
 def surrogate_sigma(t: int, p: "LMParams") -> float:
@@ -341,8 +343,14 @@ def _inner_loop(t, block, lin, O, P, mu, prev_step, joint, p: LMParams, learned_
         dg = np.concatenate(blocks, axis=0)[sel]
     scaled = p.scaling == 1
     dx = None
-    if p.precond == 3:  # the exact diagonal of G in place of the App. B one, floored alike
-        eO, eP = ptycho.ggn_diag_exact(lin)
+    if p.precond in (3, 4):
+        # the exact diagonal of G, or its stochastic estimate, in place of the App. B one, floored alike
+        if p.precond == 3:
+            eO, eP = ptycho.ggn_diag_exact(lin)
+        else:
+            S = p.stoch_samples
+            r = np.stack([ptycho.rademacher_field(lin, p.stoch_seed, t * S + s) for s in range(S)])
+            eO, eP = ptycho.ggn_diag_stochastic(lin, r)
         blocks = [floor_block(eO.reshape(-1, 2), p.diag_floor)]
         if joint:
             blocks.append(floor_block(eP.reshape(-1, 2), p.diag_floor))
@@ -363,8 +371,8 @@ def _inner_loop(t, block, lin, O, P, mu, prev_step, joint, p: LMParams, learned_
         if p.precond == 1:
             m = dg * (1.0 + lam) if scaled else dg + lam      # Dg(G + lambda D)
             pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
-        elif p.precond in (2, 3):
-            # learned or exact diagonal in place of Dg(G) inside Dg(G + lambda D)
+        elif p.precond in (2, 3, 4):
+            # learned, exact or estimated diagonal in place of Dg(G) inside Dg(G + lambda D)
             m = (ld if p.precond == 2 else dx) + lam * (dg if scaled else 1.0)
             pc = lambda r, m=m: r.real / m[:, 0] + 1j * r.imag / m[:, 1]
         else:

@@ -735,3 +735,67 @@ def test_magnitude_ggn_lm_converges_faster_than_intensity_ggn_lm():
                                   solver.LMParams(ggn=ggn), 15)
             f[ggn] = res.f
         assert f["magnitude"] < 0.8 * f["intensity"], f
+
+
+# ---------------------------------------------------------------- NEXT: stochastic diagonal
+def test_splitmix64_first_outputs():
+    """The first three outputs of SplitMix64 seeded with 0, as published with the generator."""
+    out = ptycho.splitmix64(0, np.arange(1, 4, dtype=np.uint64))
+    assert [int(x) for x in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_rademacher_signs_are_balanced_and_uncorrelated():
+    n = np.arange(1, 1_000_001, dtype=np.uint64)
+    r = ptycho.rademacher(12345, n)
+    assert set(np.unique(r)) == {-1.0, 1.0}
+    assert abs(r.mean()) < 4e-3                       # 4 sigma of a fair coin over 1e6 draws
+    assert abs(np.mean(r[1:] * r[:-1])) < 4e-3        # neighbouring counters independent
+
+
+def _tiny_joint(metric="gauss"):
+    rng = np.random.default_rng(31)
+    O = synth.random_complex(rng, (4, 4)) * 0.5 + 0.8
+    P = synth.random_complex(rng, (2, 2))
+    pos = np.array([[0, 0], [0, 2], [2, 1]], dtype=np.int32)
+    y = synth.poisson_counts(rng, 30 * ptycho.intensity(O, P, pos, 1e-3)) / 30
+    return ptycho.linearize(O * 0.9, P, pos, y, 1e-3, metric, True)
+
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+def test_stochastic_diagonal_over_every_sign_pattern_is_exact(metric):
+    """E over the uniform distribution on {+-1}^m is the average over all 2^m patterns, so the
+    estimator averaged over every pattern must equal the diagonal of G exactly."""
+    lin = _tiny_joint(metric)
+    m = lin.zeta.size
+    assert m <= 14
+    bits = (np.arange(2 ** m)[:, None] >> np.arange(m)[None, :]) & 1
+    r = (1.0 - 2.0 * bits).reshape((2 ** m,) + lin.zeta.shape)
+    sO, sP = ptycho.ggn_diag_stochastic(lin, r)
+    eO, eP = ptycho.ggn_diag_exact(lin)
+    np.testing.assert_allclose(sO, eO, rtol=1e-10, atol=1e-12 * np.abs(eO).max())
+    np.testing.assert_allclose(sP, eP, rtol=1e-10, atol=1e-12 * np.abs(eP).max())
+
+
+def test_stochastic_diagonal_converges_with_generated_draws():
+    """With the generator's sign fields the estimate approaches the exact diagonal as the draws
+    grow (relative L2 error shrinking like 1/sqrt(S))."""
+    O, P, pos, y = tiny_problem(joint=True)
+    lin = ptycho.linearize(O, P, pos, y, 1e-3, "gauss", True)
+    eO, eP = ptycho.ggn_diag_exact(lin)
+    exact = np.concatenate([eO.ravel(), eP.ravel()])
+    errs = []
+    for S in (16, 1024):
+        r = np.stack([ptycho.rademacher_field(lin, 7, d) for d in range(S)])
+        sO, sP = ptycho.ggn_diag_stochastic(lin, r)
+        est = np.concatenate([sO.ravel(), sP.ravel()])
+        errs.append(np.linalg.norm(est - exact) / np.linalg.norm(exact))
+    assert errs[1] < 0.06 and errs[1] < 0.25 * errs[0], errs
+
+
+def test_lm_with_stochastic_jacobi_decreases():
+    pr = synth.make_small(5, obj_side=32, probe=(8, 8), n=4, step=4, photons=1e3, mode="joint")
+    rng = np.random.default_rng(5)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background))
+    p = solver.LMParams(scaling=1, precond=4, stoch_samples=16, stoch_seed=3)
+    res = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y, pr.background, "gauss", True, p, 6)
+    assert res.f < 0.3 * res.f_per_iter[0]
