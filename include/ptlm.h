@@ -80,7 +80,9 @@ typedef struct {
   int32_t retry_max;  /* cap on rejected attempts per outer iteration */
   int32_t scaling;    /* 0: D = I, 1: D = Dg(G) (App. B diagonal) */
   int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: learned diagonal + lambda D,
-                         3: exact diagonal of G + lambda D (one more transform per linearisation) */
+                         3: exact diagonal of G + lambda D (one more transform per linearisation),
+                         4: stochastic estimate of diag(G) + lambda D (stoch_samples inverse
+                         transforms per linearisation); 3 and 4 floored like D, single problems */
   int32_t warm_start; /* 1: PCG starts from the last accepted step */
   int32_t surrogate_T;  /* App. E surrogate metric: outer iterations with sigma_t > 0 (0: off) */
   double surrogate_s0;  /* sigma_0; sigma_t = s0 * 1e-6^(t / (T - 1)) for t < T, then 0 */
@@ -93,6 +95,9 @@ typedef struct {
                            runs the attempts of alg:lm_inexact on the object with the probe fixed,
                            then on the probe with the new object fixed, each block with its own
                            damping mu and warm start; 0: joint update */
+  int32_t stoch_samples;  /* precond 4: draws of the stochastic diagonal per linearisation */
+  uint64_t stoch_seed;    /* precond 4: SplitMix64 seed; outer iteration t uses draws
+                             t*stoch_samples .. (t+1)*stoch_samples - 1 (ptlm_diag_stochastic) */
 } ptlm_lm_params;
 
 /* LM state, FP64, in DEVICE memory (written by the library, read by the caller). */
@@ -197,6 +202,18 @@ ptlm_status ptlm_ggn_vp_stage(ptlm_handle* h, const float* d_vO, const float* d_
  * eq:ggn_coord_trans; equal Re/Im weights).  exact = 1: the exact diagonal
  * sum_j ell''_j J_ji^2.  d_dP nullable in PTLM_OBJECT mode. */
 ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream);
+
+/* Stochastic estimate of the same diagonal from vector-Jacobian products alone (the matrix-free
+ * route the paper names for problems without an analytic diagonal, end of Sec. 6): the mean
+ * over `samples` draws of the squared real coordinates of J^T diag(sqrt(W)) r, W the GGN
+ * weight of the linearisation and r a sign field over the K*M measurements; E[(J^T W^1/2 r)
+ * (J^T W^1/2 r)^T] = G, so the estimate is unbiased.  Draw d gives measurement j (position k,
+ * detector pixel m row-major, j = k*M + m) the sign of the top bit of output d*K*M + j + 1 of
+ * SplitMix64 seeded with `seed`; the call uses draws draw0 .. draw0 + samples - 1.  Output
+ * layout as ptlm_diag.  Overwrites the LM vector z of the workspace.  Costs `samples`
+ * inverse transforms per position. */
+ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed, uint64_t draw0, float* d_dO,
+                                 float* d_dP, void* stream);
 
 /* Autotuner of the tile-kernel launch (a project addition).  Times the GGN-vector product
  * (reps calls after one warm-up) with the positions cut into 0.5x, 1x and 2x as many

@@ -50,7 +50,8 @@ class ptlm_lm_params(ctypes.Structure):
                 ("surrogate_T", ctypes.c_int32), ("surrogate_s0", ctypes.c_double),
                 ("project", ctypes.c_int32), ("ls_max", ctypes.c_int32), ("o_max", ctypes.c_double),
                 ("p_max", ctypes.c_double), ("sigma_ls", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("tau_s", ctypes.c_double), ("p_s", ctypes.c_double), ("alternate", ctypes.c_int32)]
+                ("tau_s", ctypes.c_double), ("p_s", ctypes.c_double), ("alternate", ctypes.c_int32),
+                ("stoch_samples", ctypes.c_int32), ("stoch_seed", ctypes.c_uint64)]
 
 
 class ptlm_cnn_desc(ctypes.Structure):
@@ -85,6 +86,7 @@ _sig = {
     "ptlm_ggn_vp_stage": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                          _vp]),
     "ptlm_diag": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "ptlm_diag_stochastic": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp]),
     "ptlm_lm_init": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp]),
     "ptlm_lm_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp, _vp]),
     "ptlm_lm_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), ctypes.c_int32,
@@ -293,6 +295,14 @@ class Problem:
         dP = torch.empty(self.probe_shape + (2,), dtype=torch.float32, device=self.device) if self.joint else None
         _check(_lib.ptlm_diag(self.handle, _ptr(dO, torch.float32), _ptr(dP, torch.float32) if self.joint else None,
                               1 if exact else 0, _stream()))
+        return dO, dP
+
+    def diag_stochastic(self, samples, seed, draw0=0):
+        """Unbiased estimate of the GGN diagonal from `samples` sign-field VJPs (ptlm_diag_stochastic)."""
+        dO = torch.empty(self.obj_shape + (2,), dtype=torch.float32, device=self.device)
+        dP = torch.empty(self.probe_shape + (2,), dtype=torch.float32, device=self.device) if self.joint else None
+        _check(_lib.ptlm_diag_stochastic(self.handle, int(samples), int(seed), int(draw0), _ptr(dO, torch.float32),
+                                         _ptr(dP, torch.float32) if self.joint else None, _stream()))
         return dO, dP
 
     def autotune(self, reps=5):

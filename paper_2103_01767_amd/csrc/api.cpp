@@ -244,6 +244,36 @@ ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s,
   return PTLM_OK;
 }
 
+// Stochastic estimate of diag(G): the mean over `samples` draws of the squared real coordinates
+// of J^T diag(sqrt(W)) r, r a sign field per draw.  Draw s of the call is draw0 + s, plus
+// (*draw_t) * samples when draw_t is set (the LM's outer iteration).  The LM vector z serves
+// as the per-draw scratch.
+ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long seed, unsigned long long draw0,
+                                 const int* draw_t, float* dO, float* dP, hipStream_t s, const int* pred) {
+  Geometry& g = h->g;
+  const size_t N = (size_t)g.ny * g.nx, M = (size_t)g.my * g.mx;
+  float2* u = (float2*)(h->ws + h->plan.off.z);
+  const float scale = 1.0f / (float)samples;
+  for (int k = 0; k < samples; ++k) {
+    TileArgs a{};
+    a.O = g.O_lin;
+    a.P = g.P_lin;
+    a.predicate = pred;
+    a.rseed = seed;
+    a.rdraw = draw0 + (unsigned long long)k;
+    a.rdraw_t = draw_t;
+    a.rdraw_mul = samples;
+    hipError_t e = launch_tile(g, OP_VJP_RAND, a, s);
+    if (e != hipSuccess) return hip_fail(e, "stochastic diag");
+    e = launch_obj_reduce(g, u, 0.0, nullptr, nullptr, nullptr, pred, s);
+    if (e == hipSuccess) e = launch_sq_accum(u, (float2*)dO, N, scale, k == 0, pred, s);
+    if (e == hipSuccess && dP) e = launch_probe_reduce(g, u + N, 0.0, nullptr, nullptr, nullptr, pred, s);
+    if (e == hipSuccess && dP) e = launch_sq_accum(u + N, (float2*)dP, M, scale, k == 0, pred, s);
+    if (e != hipSuccess) return hip_fail(e, "stochastic diag accumulate");
+  }
+  return PTLM_OK;
+}
+
 ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
                            float2* gO, float2* gP, hipStream_t s) {
   Geometry& g = h->g;
@@ -437,6 +467,8 @@ void ptlm_lm_default_params(ptlm_lm_params* p) {
   p->tau_s = 1e-8;
   p->p_s = 2.1;
   p->alternate = 0;
+  p->stoch_samples = 8;
+  p->stoch_seed = 0;
 }
 
 ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, size_t* bytes) {
@@ -564,6 +596,16 @@ ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, v
   if (exact) return diag_exact_impl(h, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream);
   PTLM_HIP(launch_diag_paper(h->g, d_dO, h->g.joint ? d_dP : nullptr, (hipStream_t)stream), "diag");
   return PTLM_OK;
+}
+
+ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed, uint64_t draw0, float* d_dO,
+                                 float* d_dP, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_dO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && !d_dP) return fail(PTLM_EINVAL, "joint mode needs d_dP");
+  if (samples < 1) return fail(PTLM_EINVAL, "samples must be >= 1");
+  return diag_stochastic_impl(h, samples, seed, draw0, nullptr, d_dO, h->g.joint ? d_dP : nullptr,
+                              (hipStream_t)stream);
 }
 
 ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, void* stream) {

@@ -64,6 +64,8 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
                       const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
                       int stage = 3);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
+ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long seed, unsigned long long draw0,
+                                 const int* draw_t, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
 ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s);
 ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, hipStream_t s);
 ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s);

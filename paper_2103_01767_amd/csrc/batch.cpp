@@ -161,6 +161,7 @@ struct BatchOps {
     return PTLM_OK;
   }
   ptlm_status exact_diag() { return fail(PTLM_EINVAL, "precond 3 is not available in batches"); }
+  ptlm_status stoch_diag() { return fail(PTLM_EINVAL, "precond 4 is not available in batches"); }
   ptlm_status ggnv(int which) {
     PTLM_TRY(tiles(OP_GGNV, which == GG_WARM ? TK_WARM : TK_P));
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
@@ -363,7 +364,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (T < 0) return fail(PTLM_EINVAL, "T must be >= 0");
-  if (params->precond == 3) return fail(PTLM_EINVAL, "precond 3 is not available in batches");
+  if (params->precond == 3 || params->precond == 4)
+    return fail(PTLM_EINVAL, "precond 3 and 4 are not available in batches");
   if (params->project) return fail(PTLM_EINVAL, "the projected plug-in is not available in batches");
   for (int i = 0; i < b->n; ++i) {
     if (!d_O[i] || !d_P[i] || !d_y[i]) return fail(PTLM_EINVAL, "null array of problem " + std::to_string(i));

@@ -14,7 +14,8 @@ enum TileOp : int {
   OP_JVP = 3,      // gather d psi, F, Re(conj(e) .)
   OP_VJP = 4,      // w e, F^H, overlap-add
   OP_GGNV = 5,     // gather d psi, F, Re(conj(a) .) a, F^H, overlap-add
-  OP_DIAG_EXACT = 6// conj(a)^2, F, read at 2m', overlap-add of the exact diagonal terms
+  OP_DIAG_EXACT = 6,// conj(a)^2, F, read at 2m', overlap-add of the exact diagonal terms
+  OP_VJP_RAND = 7  // r a for a generated sign field r, F^H, overlap-add (stochastic diagonal)
 };
 
 // Geometry and buffers of one problem as the kernels see them.
@@ -61,6 +62,12 @@ struct TileArgs {
   float* rout;            // K*M real output (FORWARD zeta, LOSS residual, JVP)
   const int* predicate;   // if non-null and *predicate == 0 the launch does nothing
   const double* bg_add;   // if non-null, added to the background (surrogate metric, App. E)
+  // OP_VJP_RAND: sign field of draw rdraw + (*rdraw_t) * rdraw_mul (rdraw_t nullable) from
+  // SplitMix64 seeded with rseed
+  unsigned long long rseed;
+  unsigned long long rdraw;
+  const int* rdraw_t;
+  int rdraw_mul;
 };
 
 // One problem's part of a batched launch: its geometry, its arguments and the first block
@@ -131,6 +138,8 @@ hipError_t launch_sum_partials(const double* partials, int count, double* out, i
 hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
 // dst[i] = src[i], i < n, unless *pred == 0 (copy_blocks(n) blocks)
 hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s);
+hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, int first, const int* pred,
+                           hipStream_t s);
 int copy_blocks(size_t n);
 // batched forms (job tables in device memory)
 hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);

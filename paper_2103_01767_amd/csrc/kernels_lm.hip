@@ -28,7 +28,7 @@ __device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r
     }
     return make_float2(r.x / (d.x + (float)lam), r.y / (d.y + (float)lam));
   }
-  if (a.prm.precond == 2 || a.prm.precond == 3) {  // learned or exact Dg(G), plus lambda D
+  if (a.prm.precond >= 2) {  // learned, exact or estimated Dg(G), plus lambda D
     const float2 d = a.learned[i];
     const float2 D = a.prm.scaling ? a.diag[i] : make_float2(1.f, 1.f);
     return make_float2(r.x / fmaf((float)lam, D.x, d.x), r.y / fmaf((float)lam, D.y, d.y));

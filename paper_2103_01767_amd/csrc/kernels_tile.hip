@@ -84,8 +84,8 @@ template <int MY, int MX, int OP, int MET>
 __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   using C = Cfg<MY, MX>;
   constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
-  constexpr bool FWD_FFT = OP != OP_VJP;
-  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
+  constexpr bool FWD_FFT = OP != OP_VJP && OP != OP_VJP_RAND;
+  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV || OP == OP_VJP_RAND;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
   constexpr bool SUMS = OP == OP_LOSS || OP == OP_LINEARIZE;
   if (a.predicate && *a.predicate == 0) return;
@@ -657,6 +657,7 @@ static hipError_t launch_op(const Geometry& g, int op, const TileArgs& a, hipStr
     case OP_LINEARIZE: return launch_one<MY, MX, OP_LINEARIZE>(g, a, s);
     case OP_JVP: return launch_one<MY, MX, OP_JVP>(g, a, s);
     case OP_VJP: return launch_one<MY, MX, OP_VJP>(g, a, s);
+    case OP_VJP_RAND: return launch_one<MY, MX, OP_VJP_RAND>(g, a, s);
     case OP_GGNV: return launch_one<MY, MX, OP_GGNV>(g, a, s);
     case OP_DIAG_EXACT: return launch_one<MY, MX, OP_DIAG_EXACT>(g, a, s);
     default: return hipErrorInvalidValue;

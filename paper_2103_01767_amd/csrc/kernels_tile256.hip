@@ -68,8 +68,8 @@ __device__ __forceinline__ double wg_sum(double x, double* red, int col) {
 
 template <int OP>
 __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a, int bid, int nblk) {
-  constexpr bool FWD_FFT = OP != OP_VJP;
-  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
+  constexpr bool FWD_FFT = OP != OP_VJP && OP != OP_VJP_RAND;
+  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV || OP == OP_VJP_RAND;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
   constexpr bool SUMS = OP == OP_LOSS || OP == OP_LINEARIZE;
   if (a.predicate && *a.predicate == 0) return;
@@ -412,6 +412,7 @@ hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStrea
     case OP_LINEARIZE: return launch256<OP_LINEARIZE>(g, a, s);
     case OP_JVP: return launch256<OP_JVP>(g, a, s);
     case OP_VJP: return launch256<OP_VJP>(g, a, s);
+    case OP_VJP_RAND: return launch256<OP_VJP_RAND>(g, a, s);
     case OP_GGNV: return launch256<OP_GGNV>(g, a, s);
     case OP_DIAG_EXACT: return launch256<OP_DIAG_EXACT>(g, a, s);
     default: return hipErrorInvalidValue;

@@ -41,8 +41,8 @@ template <int L, int OP>
 __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, int bid, int nblk) {
   using C = Cfg3<L>;
   constexpr int R = C::R, NT = C::NT, LDX = C::LDX, GMAX = C::GMAX;
-  constexpr bool FWD_FFT = OP != OP_VJP;
-  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV;
+  constexpr bool FWD_FFT = OP != OP_VJP && OP != OP_VJP_RAND;
+  constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV || OP == OP_VJP_RAND;
   constexpr bool SCATTER = INV_FFT || OP == OP_DIAG_EXACT;
   constexpr bool SUMS = OP == OP_LOSS || OP == OP_LINEARIZE;
   if (a.predicate && *a.predicate == 0) return;
@@ -441,6 +441,7 @@ static hipError_t launch3_op(const Geometry& g, int op, const TileArgs& a, hipSt
     case OP_LINEARIZE: return launch3<L, OP_LINEARIZE>(g, a, s);
     case OP_JVP: return launch3<L, OP_JVP>(g, a, s);
     case OP_VJP: return launch3<L, OP_VJP>(g, a, s);
+    case OP_VJP_RAND: return launch3<L, OP_VJP_RAND>(g, a, s);
     case OP_GGNV: return launch3<L, OP_GGNV>(g, a, s);
     case OP_DIAG_EXACT: return launch3<L, OP_DIAG_EXACT>(g, a, s);
     default: return hipErrorInvalidValue;

@@ -338,6 +338,30 @@ int copy_blocks(size_t n) {
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
+// d = (first ? 0 : d) + scale (Re u, Im u)^2 per complex entry: one draw's share of the
+// stochastic diagonal estimate
+__global__ __launch_bounds__(256) void sq_accum_kernel(const float2* __restrict__ u, float2* __restrict__ d, size_t n,
+                                                       float scale, int first, const int* pred) {
+  if (pred && *pred == 0) return;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const float2 x = u[i];
+    const float2 q = make_float2(scale * x.x * x.x, scale * x.y * x.y);
+    if (first) {
+      d[i] = q;
+    } else {
+      const float2 c = d[i];
+      d[i] = make_float2(c.x + q.x, c.y + q.y);
+    }
+  }
+}
+
+hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, int first, const int* pred,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(sq_accum_kernel, dim3(copy_blocks(n)), dim3(256), 0, s, u, d, n, scale, first, pred);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(copy_blocks(n)), dim3(256), 0, s, src, dst, n, pred);
   return hipGetLastError();

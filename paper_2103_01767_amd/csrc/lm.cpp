@@ -29,7 +29,7 @@ LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st
   a.ztrial = at(p.off.ztrial);
   a.diag = at(p.off.diag);
   a.xdiag = at(p.off.learned);
-  a.learned = prm && prm->precond == 3 ? a.xdiag : (const float2*)learned;
+  a.learned = prm && (prm->precond == 3 || prm->precond == 4) ? a.xdiag : (const float2*)learned;
   a.O = O;
   a.P = P;
   a.Olin = h->g.O_lin;
@@ -56,7 +56,8 @@ ptlm_status check_lm_params(const ptlm_lm_params* p) {
   if (!p) return fail(PTLM_EINVAL, "params is null");
   if (!(p->mu0 > 0) || !(p->mu_min > 0) || !(p->kappa > 1) || !(p->nu >= 0) || !(p->rho_min > 0) ||
       !(p->beta > 0) || !(p->diag_floor >= 0) || p->cg_max < 0 || p->retry_max < 1 ||
-      (p->scaling != 0 && p->scaling != 1) || p->precond < 0 || p->precond > 3 || p->surrogate_T < 0 ||
+      (p->scaling != 0 && p->scaling != 1) || p->precond < 0 || p->precond > 4 ||
+      (p->precond == 4 && p->stoch_samples < 1) || p->surrogate_T < 0 ||
       !(p->surrogate_s0 >= 0.0) || !std::isfinite(p->surrogate_s0) || (p->project != 0 && p->project != 1) ||
       (p->project && (p->ls_max < 0 || !(p->o_max > 0) || !(p->p_max > 0) || !(p->sigma_ls >= 0) ||
                       !(p->gamma >= 0) || !(p->tau_s >= 0) || !(p->p_s > 1))) ||
@@ -133,6 +134,10 @@ struct SingleOps {
   }
   ptlm_status exact_diag() {
     return diag_exact_impl(h, (float*)a.xdiag, h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, flag(FL_LIN));
+  }
+  ptlm_status stoch_diag() {
+    return diag_stochastic_impl(h, a.prm.stoch_samples, a.prm.stoch_seed, 0, &a.st->t, (float*)a.xdiag,
+                                h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, flag(FL_LIN));
   }
   ptlm_status ggnv(int which) {
     const float2* v = (which == GG_WARM && !a.prm.alternate) ? a.prev : a.p;

@@ -19,7 +19,7 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
   } while (0)
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
-// diag_paper(), learned(), exact_diag(), ggnv(which), trial_loss(), copy_accept(),
+// diag_paper(), learned(), exact_diag(), stoch_diag(), ggnv(which), trial_loss(), copy_accept(),
 // cg_mark(j) (after the launch that decides whether PCG iteration j runs) and
 // cg_gate(i, &go) (before PCG iteration i is enqueued; go = false ends the enqueueing, every
 // later iteration being predicated off anyway).
@@ -39,8 +39,10 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
     PTLM_TRY(o.vec(V_DIAGFLOOR, FL_LIN));
   }
   if (prm.precond == 2) PTLM_TRY(o.learned());
-  if (prm.precond == 3) {
-    PTLM_TRY(o.exact_diag());  // exact Dg(G) in place of the App. B one, floored alike
+  if (prm.precond == 3 || prm.precond == 4) {
+    // exact Dg(G) or its stochastic estimate in place of the App. B one, floored alike
+    if (prm.precond == 3) PTLM_TRY(o.exact_diag());
+    else PTLM_TRY(o.stoch_diag());
     PTLM_TRY(o.vec(V_XMAX, FL_LIN));
     PTLM_TRY(o.fin(F_XMAX, 1, FL_LIN));
     PTLM_TRY(o.vec(V_XFLOOR, FL_LIN));

@@ -38,8 +38,8 @@ enum LMFlag : int {
 struct LMArgs {
   float2 *g, *dx, *prev, *r, *z, *p, *Ap, *ztrial;
   float2* diag;            // (Re, Im) weights of Dg(G) per complex entry, floored
-  const float2* learned;   // learned (precond 2) or exact (precond 3) diagonal standing for Dg(G)
-  float2* xdiag;           // exact-diagonal buffer (precond 3, floored in place)
+  const float2* learned;   // learned (2), exact (3) or estimated (4) diagonal standing for Dg(G)
+  float2* xdiag;           // exact / estimated diagonal buffer (precond 3, 4; floored in place)
   const float2 *O, *P;     // current iterate
   const float2 *Olin, *Plin;  // linearisation point z_t (projected plug-in)
   float ls_alpha;          // line-search step size (V_LS_CAND)

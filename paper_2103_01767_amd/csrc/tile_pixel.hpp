@@ -9,6 +9,7 @@
 //   JVP        Re(conj(e) F dpsi) (a divided by sqrt(W) where W is not 1)
 //   GGNV       Re(conj(a) F dpsi) a   (loss-Hessian weighting of the GGN-vector product)
 //   VJP        w a (divided by sqrt(W) where W is not 1)
+//   VJP_RAND   r a for a generated sign field r (stochastic estimate of diag(G))
 //
 // v holds the unnormalised transform; isq = 1/sqrt(M) applies the unitary normalisation
 // (eq:expected_count); bgv is the background (plus the surrogate term of App. E when set).
@@ -22,6 +23,16 @@ namespace ptlm {
 __device__ __forceinline__ float2 ld_once(const float2* p) {
   const double d = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));
   return __builtin_bit_cast(float2, d);
+}
+
+// Output n >= 1 of the SplitMix64 generator seeded with `seed` (Steele, Lea and Flood 2014):
+// Stafford's 64-bit finaliser of seed + n * golden gamma.  Counter-based, so every measurement
+// draws its own sign independently.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed, unsigned long long n) {
+  unsigned long long z = seed + n * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
 // MET (a constant, so pixel loops can carry no per-pixel branch on it): bit 0 the metric
@@ -87,6 +98,13 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
     const float2 as = ld_once(g.afield + gi);
     const float tt = fmaf(as.x, v.x, as.y * v.y);
     v = cscale(as, tt);
+  } else if constexpr (OP == OP_VJP_RAND) {
+    // r a with r = +-1 from the top bit of output draw * K * M + gi + 1: one draw of
+    // J^T diag(sqrt(W)) r, whose squares estimate diag(G) without bias
+    const unsigned long long draw = a.rdraw + (a.rdraw_t ? (unsigned long long)(*a.rdraw_t) * a.rdraw_mul : 0ull);
+    const unsigned long long n = draw * ((unsigned long long)g.K * (unsigned long long)g.my * g.mx) + gi + 1ull;
+    const float2 as = ld_once(g.afield + gi);
+    v = (splitmix64(a.rseed, n) >> 63) ? make_float2(-as.x, -as.y) : as;
   } else if constexpr (OP == OP_VJP) {
     const float2 as = ld_once(g.afield + gi);
     float w = a.win[gi];

@@ -358,3 +358,27 @@ def test_intensity_ggn_lm_matches_oracle(mode):
     assert f_gpu["intensity"] <= 1.01 * ref.f
     if not joint:
         assert f_gpu["magnitude"] < f_gpu["intensity"]
+
+
+def test_stochastic_jacobi_lm_matches_oracle():
+    """precond 4: the PCG preconditioner built from the stochastic diagonal estimate, drawn per
+    outer iteration from the same counter-based signs as the oracle: final loss within 1.01x."""
+    print("case stochastic lm", flush=True)
+    pr = synth.make_small(11, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(11)
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    kw = dict(scaling=1, precond=4, stoch_samples=6, stoch_seed=99)
+    T = 8
+    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, "gauss", True,
+                          solver.LMParams(**kw), T)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(**kw)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_solve(O, P, yd, params, T, st)
+    s = pt.state_from_tensor(st)
+    f_gpu = float(prob.loss(O, P, yd).cpu()[0])
+    print("stochastic oracle f=%.6e gpu f=%.6e (start %.3e)" % (ref.f, f_gpu, ref.f_per_iter[0]))
+    assert s.t == T
+    assert f_gpu <= 1.01 * ref.f

@@ -293,3 +293,23 @@ def test_intensity_ggn_products(probe, joint, metric):
     assert rel(host(dOg), eO) < 2 * TOL
     if joint:
         assert rel(host(dPg), eP) < 2 * TOL
+
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+@pytest.mark.parametrize("probe", [(16, 16), (128, 128), (48, 48), (256, 256), (32, 64)], ids=lambda p: "%dx%d" % p)
+def test_stochastic_diagonal(probe, metric):
+    """ptlm_diag_stochastic against the oracle's estimator on the oracle's own sign fields (the
+    SplitMix64 draws agree bit for bit, so any sign slip would show as an O(1) error)."""
+    print("case stochastic diag", probe, metric, flush=True)
+    case = make_case(probe, 4, 5, max(probe) // 4, metric=metric, joint=True, seed=9 + probe[0])
+    prob = problem(case)
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    prob.linearize(O, P, y)
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, metric, True)
+    S, seed, draw0 = 3, 0x5EED1234ABCD, 7
+    dO, dP = prob.diag_stochastic(S, seed, draw0)
+    r = np.stack([ptycho.rademacher_field(lin, seed, draw0 + s) for s in range(S)])
+    sO, sP = ptycho.ggn_diag_stochastic(lin, r)
+    print("stoch rel", rel(host(dO), sO), rel(host(dP), sP))
+    assert rel(host(dO), sO) < 2 * TOL
+    assert rel(host(dP), sP) < 2 * TOL
