@@ -136,6 +136,8 @@ typedef struct {
                         0 for the joint update */
   int32_t acc_o;     /* internal: the last attempt accepted a step of the object */
   int32_t acc_p;     /* internal: the last attempt accepted a step of the probe */
+  int32_t tile_now;  /* internal: the current attempt evaluates the linearisation (0 when it
+                        adopts the one computed at the accepted trial point) */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;
@@ -230,6 +232,12 @@ ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_
  * ratio, mu update}.  It synchronises the stream once per attempt to read the acceptance
  * flag.  Returns PTLM_OK when a step was accepted, PTLM_ENOTACCEPTED when all retries were
  * rejected (iterate unchanged), PTLM_ENUMERIC on a non-finite loss (iterate unchanged).
+ * Without params->project the trial point of every attempt is evaluated as a full
+ * linearisation into spare buffers; when the step is accepted the next outer iteration adopts
+ * it instead of linearising again (same kernels on the same values: results are unchanged).
+ * It is not adopted when O or P differ from the accepted point at the next call (the caller
+ * changed them), when d_y is another pointer, after ptlm_linearize on the handle, or when the
+ * surrogate term changes; the contents of d_y must not change between calls of one run.
  * With params->alternate (PTLM_JOINT only, else PTLM_EINVAL) the outer iteration is the
  * object sub-step and then the probe sub-step of alg:alt_LM_ptycho, each linearising at its
  * own start and running up to retry_max attempts on its block; PTLM_ENOTACCEPTED then means

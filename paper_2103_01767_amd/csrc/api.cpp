@@ -224,6 +224,10 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   p.off.ztrial = take(n2 * sizeof(float2));
   p.off.learned = take(n2 * sizeof(float2));
   p.off.lmstate = take(sizeof(ptlm_lm_state));
+  p.off.afield2 = take((size_t)K * M * sizeof(float2));
+  p.off.w2_2 = weighted ? take((size_t)K * M * sizeof(float)) : 0;
+  p.off.trace2 = take((size_t)K * sizeof(double));
+  p.off.g2 = take(n2 * sizeof(float2));
   p.ws_bytes = o;
   return PTLM_OK;
 }
@@ -277,6 +281,7 @@ ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long
 ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
                            float2* gO, float2* gP, hipStream_t s) {
   Geometry& g = h->g;
+  h->lin_gen += 1;  // the LM may no longer adopt a linearisation it kept
   const size_t N = (size_t)g.ny * g.nx, M = (size_t)g.my * g.mx;
   if ((const void*)O != (const void*)g.O_lin)
     PTLM_HIP(hipMemcpyAsync(g.O_lin, O, N * sizeof(float2), hipMemcpyDeviceToDevice, s), "linearize copy O");
@@ -353,6 +358,12 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
   g.probe_part = (float2*)at(p.off.probe_part);
   g.partials = (double*)at(p.off.partials);
   g.scratch = d.my == 256 ? (float2*)at(p.off.scratch) : nullptr;
+  h->lm_g = (float2*)at(p.off.g);
+  h->lm_g_alt = (float2*)at(p.off.g2);
+  h->afield_alt = (float2*)at(p.off.afield2);
+  h->w2_alt = g.w2 ? (float*)at(p.off.w2_2) : nullptr;
+  h->trace_alt = (double*)at(p.off.trace2);
+  h->lin_gen += 1;
 
   hipError_t e;
   auto up = [&](size_t off, const void* src, size_t bytes) {

@@ -12,6 +12,7 @@ struct Offsets {
   size_t tw, pos, seg_start, seg_box, seg_off, otile_ptr, otile_seg, ptile_ptr, ptile_pos;
   size_t O_lin, P_lin, afield, w2, trace, strips, probe_part, partials, scratch, scal;
   size_t g, dx, prev, r, z, p, Ap, diag, ztrial, learned, lmstate;
+  size_t afield2, w2_2, trace2, g2;  // spare linearisation (trial point of the LM)
 };
 
 // Everything derived on the host from the description and the positions.
@@ -50,6 +51,18 @@ struct ptlm_handle {
   int* cg_flags = nullptr;
   int cg_slots = 0;
   std::vector<hipEvent_t> cg_events;
+  // Linearisation at the LM's trial point, computed into spare buffers and swapped in when the
+  // step is accepted: the LM gradient in use and its spare, the spare phasors / weights /
+  // traces, the linearisation generation (bumped by ptlm_linearize) when the swap was made and
+  // the data pointer it used.
+  float2* lm_g = nullptr;
+  float2* lm_g_alt = nullptr;
+  float2* afield_alt = nullptr;
+  float* w2_alt = nullptr;
+  double* trace_alt = nullptr;
+  unsigned lin_gen = 0;
+  unsigned kept_gen = ~0u;
+  const float* kept_y = nullptr;
   ~ptlm_handle();
 };
 

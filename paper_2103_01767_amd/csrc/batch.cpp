@@ -167,6 +167,7 @@ struct BatchOps {
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
   }
   ptlm_status trial_loss() { return tiles(OP_LOSS, TK_TRIAL); }
+  ptlm_status trial_finish() { return PTLM_OK; }  // batched trials are losses only
   // the batch keeps one fixed launch sequence (graph capture): every PCG iteration is enqueued
   ptlm_status cg_mark(int) { return PTLM_OK; }
   ptlm_status cg_gate(int, bool* go) {

@@ -89,6 +89,10 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float2 g = a.g[i];
       if (i < a.nobj) acc0 += rdot(g, g);
       else acc1 += rdot(g, g);
+    } else if constexpr (OP == V_SAME) {  // entries of the iterate that differ from the last trial point
+      const float2 z = i < a.nobj ? a.O[i] : a.P[i - a.nobj];
+      const float2 t = a.ztrial[i];
+      acc0 += (z.x != t.x || z.y != t.y) ? 1.0 : 0.0;
     } else if constexpr (OP == V_WARM_P) {  // the warm-start vector restricted to the active block
       const bool in = i >= act.lo && i < act.hi;
       a.p[i] = in ? a.prev[i] : make_float2(0.f, 0.f);
@@ -187,9 +191,19 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       acc0 += (double)x.x * (lam * (double)dd.x - (double)g.x) + (double)x.y * (lam * (double)dd.y - (double)g.y);
     }
   }
+  if constexpr (OP == V_SAME) {
+    // object-only problems: the probe the trial used is P_lin's copy of the caller's probe
+    if (a.Pcur) {
+      const size_t M = (size_t)a.nprobe;
+      for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < M; i += stride) {
+        const float2 x = a.Pcur[i], y = a.Plin[i];
+        acc0 += (x.x != y.x || x.y != y.y) ? 1.0 : 0.0;
+      }
+    }
+  }
   constexpr bool MAXR = OP == V_DIAGMAX || OP == V_XMAX;
   constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_PAP || OP == V_CG_UPDATE ||
-                        OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG;
+                        OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG || OP == V_SAME;
   if constexpr (SUMS) {
     __shared__ double sh[256][2];
     sh[threadIdx.x][0] = acc0;
@@ -275,14 +289,19 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     // it linearises first when the previous attempt was accepted (or at the start), or when
     // the surrogate term of the metric (App. E) changed with the outer iteration
     st.alive = (st.t < st.t_max && st.status != PTLM_ENUMERIC) ? 1 : 0;
+    bool sigma_changed = false;
     if (st.alive) {
       const double sg = surrogate_sigma(p, st.t);
       if (sg != st.sigma) {
         st.sigma = sg;
         st.need_lin = 1;
+        sigma_changed = true;
       }
     }
     st.lin_now = (st.alive && st.need_lin) ? 1 : 0;
+    // a linearisation kept from the accepted trial point is adopted unless the surrogate term
+    // changed (F_ADOPT also checks that the iterate is that point)
+    st.tile_now = (st.lin_now && !(a.adopt_ok && !sigma_changed)) ? 1 : 0;
     if (st.alive && st.iter_done) {  // a new outer iteration (sub-step) starts: no rejections yet
       st.retries = 0;
       st.iter_done = 0;
@@ -318,6 +337,8 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   } else if constexpr (OP == F_XMAX) {
     a.scal[SC_XMAX_O] = s0;
     a.scal[SC_XMAX_P] = s1;
+  } else if constexpr (OP == F_ADOPT) {
+    if (st.lin_now && s0 != 0.0) st.tile_now = 1;  // the iterate is not the kept point
   } else if constexpr (OP == F_LS) {
     a.scal[SC_LS0] = s0;
     a.scal[SC_LS1] = s1;
@@ -452,10 +473,10 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 
 #define PTLM_VEC_CASES(X)                                                                                 \
   X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL) X(V_XMAX) \
-  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P)
+  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME)
 #define PTLM_FIN_CASES(X)                                                                                 \
   X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
-  X(F_INIT) X(F_LS)
+  X(F_INIT) X(F_LS) X(F_ADOPT)
 
 hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s) {
   switch (op) {

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "api_internal.hpp"
 #include "lm_attempt.hpp"
@@ -19,7 +20,7 @@ LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st
   Plan& p = h->plan;
   auto at = [&](size_t o) { return (float2*)(h->ws + o); };
   LMArgs a{};
-  a.g = at(p.off.g);
+  a.g = h->lm_g;
   a.dx = at(p.off.dx);
   a.prev = at(p.off.prev);
   a.r = at(p.off.r);
@@ -36,6 +37,7 @@ LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st
   a.Plin = h->g.P_lin;
   a.n = p.nvec;
   a.nobj = (size_t)p.d.ny * p.d.nx;
+  a.nprobe = (size_t)p.d.my * p.d.mx;
   a.st = st;
   if (prm) a.prm = *prm;
   a.partials = h->g.partials;
@@ -76,6 +78,7 @@ struct SingleOps {
   const float* user_learned;  // caller's learned diagonal (precond 2 without a network)
   bool lin_expected;          // host view: this attempt linearises (network refresh)
   hipStream_t s;
+  bool spec = false;          // the trial point is evaluated as a linearisation (spare buffers)
 
   int* flag(int f) const { return reinterpret_cast<int*>(a.st) + f; }
 
@@ -90,6 +93,10 @@ struct SingleOps {
   }
   ptlm_status copy_lin() {
     Geometry& g = h->g;
+    if (a.adopt_ok) {  // adopt the kept linearisation only if the iterate is the point it was made at
+      LM_HIP(launch_vec(V_SAME, a, FL_LIN, s), "lm same point");
+      LM_HIP(launch_fin(F_ADOPT, a, a.vec_blocks, FL_LIN, s), "lm adopt");
+    }
     LM_HIP(launch_copy(O, g.O_lin, (size_t)g.ny * g.nx, flag(FL_LIN), s), "lm copy O");
     LM_HIP(launch_copy(P, g.P_lin, (size_t)g.my * g.mx, flag(FL_LIN), s), "lm copy P");
     return PTLM_OK;
@@ -100,14 +107,22 @@ struct SingleOps {
     ta.O = g.O_lin;
     ta.P = g.P_lin;
     ta.y = y;
-    ta.predicate = flag(FL_LIN);
+    ta.predicate = flag(FL_TILE);
     ta.bg_add = &a.st->sigma;
     LM_HIP(launch_tile(g, OP_LINEARIZE, ta, s), "lm linearize");
-    LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_LIN)), "lm linearize sum");
-    LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_LIN), s), "lm gradient O");
+    LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_TILE)), "lm linearize sum");
+    LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_TILE), s), "lm gradient O");
     if (g.joint)
-      LM_HIP(launch_probe_reduce(g, a.g + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_LIN), s), "lm gradient P");
+      LM_HIP(launch_probe_reduce(g, a.g + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_TILE), s), "lm gradient P");
     return PTLM_OK;
+  }
+  // geometry whose linearisation buffers are the spares (the trial's linearisation)
+  Geometry spare_geometry() const {
+    Geometry gs = h->g;
+    gs.afield = h->afield_alt;
+    gs.w2 = h->w2_alt;
+    gs.trace = h->trace_alt;
+    return gs;
   }
   ptlm_status diag_paper() {
     Geometry& g = h->g;
@@ -156,7 +171,21 @@ struct SingleOps {
     ta.y = y;
     ta.predicate = flag(FL_ALIVE);
     ta.bg_add = &a.st->sigma;
-    LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
+    // the loss partials of a linearisation are those of the loss, so F_TRIAL_END reads either
+    if (spec) LM_HIP(launch_tile(spare_geometry(), OP_LINEARIZE, ta, s), "lm trial linearize");
+    else LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
+    return PTLM_OK;
+  }
+  // after an accepted trial evaluated as a linearisation: its f and ||ell'||^2 for F_LIN of the
+  // next outer iteration, and its gradient into the spare gradient buffer
+  ptlm_status trial_finish() {
+    if (!spec) return PTLM_OK;
+    const Geometry gs = spare_geometry();
+    LM_HIP(launch_sum_partials(gs.partials, gs.grid, a.scal + SC_F, 2, s, flag(FL_ACCEPTED)), "lm trial sums");
+    LM_HIP(launch_obj_reduce(gs, h->lm_g_alt, 0.0, nullptr, nullptr, nullptr, flag(FL_ACCEPTED), s), "lm trial grad O");
+    if (gs.joint)
+      LM_HIP(launch_probe_reduce(gs, h->lm_g_alt + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_ACCEPTED), s),
+             "lm trial grad P");
     return PTLM_OK;
   }
   // PCG look-ahead: iteration i is enqueued once the decision on iteration i - 1 is known
@@ -309,16 +338,31 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
   SingleOps o{h, make_lm_args(h, prm, st, O, P, learned), O, P, y, learned, false, s};
   PTLM_TRY(cg_slots(h, prm->cg_max + 1));
   o.a.cg_flags = h->cg_flags;
+  // trial points are evaluated as linearisations (kept for the next outer iteration when the
+  // step is accepted) unless the projected plug-in may move the iterate off the trial point
+  o.spec = !prm->project;
+  o.a.Pcur = h->g.joint ? nullptr : P;
   bool rejected = false;
   const int subs = prm->alternate ? 2 : 1;
   for (int sub = 0; sub < subs; ++sub) {
     bool ended = false;
     for (int attempt = 0; attempt <= prm->retry_max && !ended; ++attempt) {
       o.lin_expected = hs.need_lin != 0;
+      o.a.adopt_ok = (o.spec && h->kept_gen == h->lin_gen && h->kept_y == y) ? 1 : 0;
       // no kernel of an earlier attempt is in flight (its state was read back)
       for (int j = 0; j <= prm->cg_max; ++j) __atomic_store_n(h->cg_flags + j, 0, __ATOMIC_RELAXED);
       PTLM_TRY(enqueue_attempt(o, *prm));
       PTLM_TRY(read_state(st, &hs, s));
+      if (o.spec && hs.accepted) {
+        // the trial's linearisation becomes the current one (its point is the new iterate)
+        std::swap(h->g.afield, h->afield_alt);
+        std::swap(h->g.w2, h->w2_alt);
+        std::swap(h->g.trace, h->trace_alt);
+        std::swap(h->lm_g, h->lm_g_alt);
+        o.a.g = h->lm_g;
+        h->kept_gen = h->lin_gen;
+        h->kept_y = y;
+      }
       if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
       ended = hs.iter_done != 0;
     }
@@ -343,6 +387,7 @@ ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_s
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (params->alternate && !h->g.joint) return fail(PTLM_EINVAL, "the alternating update needs a PTLM_JOINT problem");
+  h->lin_gen += 1;  // a new run linearises afresh
   LMArgs a = make_lm_args(h, params, d_state, nullptr, nullptr, nullptr);
   LM_HIP(launch_fin(F_INIT, a, 0, FL_NONE, (hipStream_t)stream), "lm init");
   return PTLM_OK;

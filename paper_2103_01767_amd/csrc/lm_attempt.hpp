@@ -19,7 +19,8 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
   } while (0)
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
-// diag_paper(), learned(), exact_diag(), stoch_diag(), ggnv(which), trial_loss(), copy_accept(),
+// diag_paper(), learned(), exact_diag(), stoch_diag(), ggnv(which), trial_loss(), trial_finish(),
+// copy_accept(),
 // cg_mark(j) (after the launch that decides whether PCG iteration j runs) and
 // cg_gate(i, &go) (before PCG iteration i is enqueued; go = false ends the enqueueing, every
 // later iteration being predicated off anyway).
@@ -73,6 +74,7 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.fin(F_PRED, 1, FL_ALIVE));
   PTLM_TRY(o.trial_loss());
   PTLM_TRY(o.fin(F_TRIAL_END, 2, FL_ALIVE));
+  PTLM_TRY(o.trial_finish());  // gradient and sums of a trial evaluated as a linearisation
   PTLM_TRY(o.copy_accept());
   return PTLM_OK;
 }

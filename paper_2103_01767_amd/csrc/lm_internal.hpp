@@ -19,9 +19,9 @@ enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4, SC_XM
        SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17 };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL, V_XMAX, V_XFLOOR,
-                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P };
+                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME };
 enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT,
-                   F_LS };
+                   F_LS, F_ADOPT };
 
 // Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
 enum LMFlag : int {
@@ -33,6 +33,7 @@ enum LMFlag : int {
   FL_ACCEPTED = (int)(offsetof(ptlm_lm_state, accepted) / 4),
   FL_ACC_O = (int)(offsetof(ptlm_lm_state, acc_o) / 4),
   FL_ACC_P = (int)(offsetof(ptlm_lm_state, acc_p) / 4),
+  FL_TILE = (int)(offsetof(ptlm_lm_state, tile_now) / 4),
 };
 
 struct LMArgs {
@@ -45,6 +46,7 @@ struct LMArgs {
   float ls_alpha;          // line-search step size (V_LS_CAND)
   int ls_proj;             // 1: project the line-search candidate
   size_t n, nobj;          // complex entries of a vector / of its object part
+  size_t nprobe;           // complex entries of the probe
   ptlm_lm_state* st;
   ptlm_lm_params prm;
   double* partials;        // >= vec_blocks * 4
@@ -53,6 +55,9 @@ struct LMArgs {
   int tile_grid;           // workgroups of the tile kernels (partials of the trial loss)
   int t_max;               // outer iterations to run (ptlm_lm_init / batch binding)
   int* cg_flags;           // nullable, pinned host memory: slot j <- whether PCG iteration j runs
+  const float2* Pcur;      // the caller's probe (V_SAME, object-only problems)
+  int adopt_ok;            // host: the linearisation buffers hold the one made at the last accepted
+                           // trial point, unless O / P changed since (checked by V_SAME / F_ADOPT)
 };
 
 // One problem's part of a batched LM launch.

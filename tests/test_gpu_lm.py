@@ -382,3 +382,33 @@ def test_stochastic_jacobi_lm_matches_oracle():
     print("stochastic oracle f=%.6e gpu f=%.6e (start %.3e)" % (ref.f, f_gpu, ref.f_per_iter[0]))
     assert s.t == T
     assert f_gpu <= 1.01 * ref.f
+
+
+# ---------------------------------------------------------------- trial-point linearisation kept
+def test_kept_trial_linearisation_is_adopted_only_at_the_same_point():
+    """An accepted trial point's linearisation is adopted by the next outer iteration (no
+    linearisation launch); after the caller moves O, or linearises the handle elsewhere, the
+    next step linearises afresh: its f is the loss at the caller's current iterate."""
+    print("case kept linearisation", flush=True)
+    pr, prob, O, P, yd = _small_joint(13)
+    params = pt.default_params(scaling=1, precond=1)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_step(O, P, yd, params, st)
+    s1 = pt.state_from_tensor(st)
+    prob.lm_step(O, P, yd, params, st)
+    s2 = pt.state_from_tensor(st)
+    assert s1.accepted and s2.tile_now == 0          # adopted: f_t of step 2 is step 1's trial value
+    assert s2.f == pytest.approx(s1.f_trial, rel=1e-12)
+    # the caller moves the object: the next step must linearise at the moved point
+    O.mul_(0.97)
+    f_moved = float(prob.loss(O, P, yd).cpu()[0])
+    prob.lm_step(O, P, yd, params, st)
+    s3 = pt.state_from_tensor(st)
+    assert s3.f == pytest.approx(f_moved, rel=1e-5)
+    # a linearisation of the handle at another point between steps is not adopted either
+    f_here = float(prob.loss(O, P, yd).cpu()[0])
+    prob.linearize(O * 0.9, P, yd)
+    prob.lm_step(O, P, yd, params, st)
+    s4 = pt.state_from_tensor(st)
+    assert s4.f == pytest.approx(f_here, rel=1e-5)
