@@ -40,7 +40,7 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # taken on: a different hash of those sources reports traffic as null.
 TRAFFIC = {"fetch_kib": 337722.109375, "write_kib": 448747.359375, "fetch_factor": 1.9998, "write_factor": 1.0,
            "grid_scale": 1.0,
-           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp"],
+           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp"],
            "sha256": "9a762ed9f00eb75e3eb49bc1c1d152a5ddb123405e212987c8bcc599d427fee0"}
 
 

@@ -113,8 +113,8 @@ struct BatchOps {
     B_HIP(launch_fin_batch(op, b->dev<LMJob>(b->L.lm_jobs), b->n, kind, fl, s), "batch finalize");
     return PTLM_OK;
   }
-  ptlm_status vec(int op, int fl) {
-    B_HIP(launch_vec_batch(op, b->dev<LMJob>(b->L.lm_jobs), b->dev<int>(b->L.jb_vec), b->nb_vec, fl, s),
+  ptlm_status vec(int op, int fl, int iter = 0) {
+    B_HIP(launch_vec_batch(op, b->dev<LMJob>(b->L.lm_jobs), b->dev<int>(b->L.jb_vec), b->nb_vec, fl, s, iter),
           "batch vector");
     return PTLM_OK;
   }

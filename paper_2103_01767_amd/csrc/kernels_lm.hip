@@ -69,17 +69,71 @@ __device__ __forceinline__ bool flag_clear(const LMArgs& a, int flag) {
   return flag >= 0 && reinterpret_cast<const int*>(a.st)[flag] == 0;
 }
 
+// Sum of partials[i * 4 + col], i < count, over one 256-thread block in a fixed order: each
+// thread sums a strided share, then a tree through LDS.  Every block that calls it, and the
+// one-block finalize kernels, obtain the same value bit for bit.
+__device__ __forceinline__ double block_sum_partials(const double* partials, int count, int col) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) acc += partials[i * 4 + col];
+  __syncthreads();
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// PCG iteration `iter` keeps r.z in scal[SC_RZ + iter % 2] (no block of a kernel overwrites
+// what another block of it still reads).
 template <int OP>
-__device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int nblk) {
+__device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int nblk, int iter) {
   if (flag_clear(a, flag)) return;
   const double lam = a.st->lambda;
-  const float alpha = (float)a.st->alpha;
-  const float beta = (float)a.st->beta_cg;
   const bool warm = a.st->use_warm != 0;
+  // V_CG_STEP: alpha = r.z / p^T A p from V_PAP's partials (what a finalize kernel would do)
+  // V_P_STEP:  beta = r'.z' / r.z from V_CG_STEP's partials, and the PCG stopping test
+  float alpha = 0.f, beta = 0.f;
+  if constexpr (OP == V_CG_STEP) {
+    const double pap = block_sum_partials(a.partials, a.vec_blocks, 0);
+    const bool curv = pap > 0.0 && isfinite(pap);
+    const double al = curv ? a.scal[SC_RZ + (iter & 1)] / pap : 0.0;
+    if (bid == 0 && threadIdx.x == 0) {
+      ptlm_lm_state& st = *a.st;
+      st.products += 1;
+      st.pap = pap;
+      if (curv) st.alpha = al;
+      else st.cg_active = 0;  // non-positive curvature: keep the current iterate
+    }
+    if (!curv) return;
+    alpha = (float)al;
+  } else if constexpr (OP == V_P_STEP) {
+    const double rz = block_sum_partials(a.partials, a.vec_blocks, 2);
+    const double rr = block_sum_partials(a.partials, a.vec_blocks, 3);
+    const double be = rz / a.scal[SC_RZ + (iter & 1)];
+    if (bid == 0 && threadIdx.x == 0) {
+      ptlm_lm_state& st = *a.st;
+      const ptlm_lm_params& p = a.prm;
+      a.scal[SC_RZ + ((iter + 1) & 1)] = rz;
+      st.beta_cg = be;
+      st.rz = rz;
+      st.rr = rr;
+      st.cg_iters += 1;
+      st.cg_total += 1;
+      st.cg_active = (st.cg_iters < p.cg_max && sqrt(rr) > st.eta * st.gnorm) ? 1 : 0;
+      if (a.cg_flags)
+        __hip_atomic_store(a.cg_flags + st.cg_iters, st.cg_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    beta = (float)be;
+  }
   double acc0 = 0.0, acc1 = 0.0;
   // steps of the PCG recurrence and of the projected plug-in touch the active block only;
   // V_CG_INIT and V_WARM_P clear the rest of their vectors, V_TRIAL keeps it at the iterate
-  constexpr bool BLOCK = OP == V_PAP || OP == V_CG_UPDATE || OP == V_PUPDATE || OP == V_PROJ || OP == V_LS_DIR ||
+  constexpr bool BLOCK = OP == V_PAP || OP == V_CG_STEP || OP == V_P_STEP || OP == V_PROJ || OP == V_LS_DIR ||
                          OP == V_LS_NEG;
   const Range act = active_range(a);
   const size_t lo = BLOCK ? act.lo : 0, hi = BLOCK ? act.hi : a.n;
@@ -166,7 +220,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       acc1 += rdot(r, r);
     } else if constexpr (OP == V_PAP) {
       acc0 += rdot(a.p[i], a.Ap[i]);
-    } else if constexpr (OP == V_CG_UPDATE) {
+    } else if constexpr (OP == V_CG_STEP) {
       const float2 p = a.p[i], ap = a.Ap[i];
       float2 x = a.dx[i], r = a.r[i];
       x.x = fmaf(alpha, p.x, x.x);
@@ -179,7 +233,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       a.z[i] = z;
       acc0 += rdot(r, z);
       acc1 += rdot(r, r);
-    } else if constexpr (OP == V_PUPDATE) {
+    } else if constexpr (OP == V_P_STEP) {
       const float2 z = a.z[i], p = a.p[i];
       a.p[i] = make_float2(fmaf(beta, p.x, z.x), fmaf(beta, p.y, z.y));
     } else if constexpr (OP == V_TRIAL) {
@@ -202,7 +256,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
     }
   }
   constexpr bool MAXR = OP == V_DIAGMAX || OP == V_XMAX;
-  constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_PAP || OP == V_CG_UPDATE ||
+  constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_PAP || OP == V_CG_STEP ||
                         OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG || OP == V_SAME;
   if constexpr (SUMS) {
     __shared__ double sh[256][2];
@@ -222,22 +276,24 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      a.partials[bid * 4 + 0] = sh[0][0];
-      a.partials[bid * 4 + 1] = sh[0][1];
+      // V_CG_STEP leaves its sums in columns 2, 3: every block still reads V_PAP's in column 0
+      constexpr int c = OP == V_CG_STEP ? 2 : 0;
+      a.partials[bid * 4 + c] = sh[0][0];
+      a.partials[bid * 4 + c + 1] = sh[0][1];
     }
   }
 }
 
 template <int OP>
-__global__ __launch_bounds__(256) void vec_kernel(LMArgs a, int flag) {
-  vec_body<OP>(a, flag, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void vec_kernel(LMArgs a, int flag, int iter) {
+  vec_body<OP>(a, flag, blockIdx.x, gridDim.x, iter);
 }
 
 template <int OP>
 __global__ __launch_bounds__(256) void vec_batch_kernel(const LMJob* __restrict__ jobs,
-                                                        const int* __restrict__ job_of_block, int flag) {
+                                                        const int* __restrict__ job_of_block, int flag, int iter) {
   const LMJob& J = jobs[job_of_block[blockIdx.x]];
-  vec_body<OP>(J.a, flag, (int)blockIdx.x - J.block0, J.a.vec_blocks);
+  vec_body<OP>(J.a, flag, (int)blockIdx.x - J.block0, J.a.vec_blocks, iter);
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
@@ -361,24 +417,8 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.rz = s0;
     st.rr = s1;
     st.cg_active = (p.cg_max > 0 && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
+    a.scal[SC_RZ] = s0;
     if (a.cg_flags) __hip_atomic_store(a.cg_flags, st.cg_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  } else if constexpr (OP == F_PAP) {
-    st.products += 1;
-    st.pap = s0;
-    if (s0 > 0.0 && finite_d(s0)) {
-      st.alpha = st.rz / s0;
-    } else {
-      st.cg_active = 0;  // non-positive curvature: keep the current iterate
-    }
-  } else if constexpr (OP == F_CG_UPDATE) {
-    st.beta_cg = s0 / st.rz;
-    st.rz = s0;
-    st.rr = s1;
-    st.cg_iters += 1;
-    st.cg_total += 1;
-    st.cg_active = (st.cg_iters < p.cg_max && sqrt(s1) > st.eta * st.gnorm) ? 1 : 0;
-    if (a.cg_flags)
-      __hip_atomic_store(a.cg_flags + st.cg_iters, st.cg_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   } else if constexpr (OP == F_PRED) {
     st.pred = 0.5 * s0;  // 1/2 Delta^T (lambda D Delta - g)
   } else if constexpr (OP == F_TRIAL_END) {
@@ -449,8 +489,8 @@ __global__ __launch_bounds__(256) void fin_batch_kernel(const LMJob* __restrict_
 }
 
 template <int OP>
-static hipError_t vlaunch(const LMArgs& a, int flag, hipStream_t s) {
-  hipLaunchKernelGGL(vec_kernel<OP>, dim3(a.vec_blocks), dim3(256), 0, s, a, flag);
+static hipError_t vlaunch(const LMArgs& a, int flag, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(vec_kernel<OP>, dim3(a.vec_blocks), dim3(256), 0, s, a, flag, iter);
   return hipGetLastError();
 }
 template <int OP>
@@ -459,9 +499,9 @@ static hipError_t flaunch(const LMArgs& a, int count, int flag, hipStream_t s) {
   return hipGetLastError();
 }
 template <int OP>
-static hipError_t vblaunch(const LMJob* jobs, const int* jb, int nb, int flag, hipStream_t s) {
+static hipError_t vblaunch(const LMJob* jobs, const int* jb, int nb, int flag, int iter, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(vec_batch_kernel<OP>, dim3(nb), dim3(256), 0, s, jobs, jb, flag);
+  hipLaunchKernelGGL(vec_batch_kernel<OP>, dim3(nb), dim3(256), 0, s, jobs, jb, flag, iter);
   return hipGetLastError();
 }
 template <int OP>
@@ -472,15 +512,15 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 }
 
 #define PTLM_VEC_CASES(X)                                                                                 \
-  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_UPDATE) X(V_PUPDATE) X(V_TRIAL) X(V_XMAX) \
+  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
   X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME)
 #define PTLM_FIN_CASES(X)                                                                                 \
-  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PAP) X(F_CG_UPDATE) X(F_PRED) X(F_TRIAL_END) \
+  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \
   X(F_INIT) X(F_LS) X(F_ADOPT)
 
-hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s) {
+hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s, int iter) {
   switch (op) {
-#define C_(OP) case OP: return vlaunch<OP>(a, flag, s);
+#define C_(OP) case OP: return vlaunch<OP>(a, flag, iter, s);
     PTLM_VEC_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -496,9 +536,9 @@ hipError_t launch_fin(int op, const LMArgs& a, int count, int flag, hipStream_t 
   }
 }
 
-hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* jb, int nb, int flag, hipStream_t s) {
+hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* jb, int nb, int flag, hipStream_t s, int iter) {
   switch (op) {
-#define C_(OP) case OP: return vblaunch<OP>(jobs, jb, nb, flag, s);
+#define C_(OP) case OP: return vblaunch<OP>(jobs, jb, nb, flag, iter, s);
     PTLM_VEC_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;

@@ -87,8 +87,8 @@ struct SingleOps {
     LM_HIP(launch_fin(op, a, count, fl, s), "lm finalize");
     return PTLM_OK;
   }
-  ptlm_status vec(int op, int fl) {
-    LM_HIP(launch_vec(op, a, fl, s), "lm vector");
+  ptlm_status vec(int op, int fl, int iter = 0) {
+    LM_HIP(launch_vec(op, a, fl, s, iter), "lm vector");
     return PTLM_OK;
   }
   ptlm_status copy_lin() {

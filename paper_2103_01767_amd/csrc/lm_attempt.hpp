@@ -62,12 +62,10 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
     PTLM_TRY(o.cg_gate(i, &go));
     if (!go) break;
     PTLM_TRY(o.ggnv(GG_P));
-    PTLM_TRY(o.vec(V_PAP, FL_CG));
-    PTLM_TRY(o.fin(F_PAP, 1, FL_CG));
-    PTLM_TRY(o.vec(V_CG_UPDATE, FL_CG));
-    PTLM_TRY(o.fin(F_CG_UPDATE, 1, FL_CG));
+    PTLM_TRY(o.vec(V_PAP, FL_CG, i));      // p^T A p partials
+    PTLM_TRY(o.vec(V_CG_STEP, FL_CG, i));  // alpha; Delta, r, z and the r.z, r.r partials
+    PTLM_TRY(o.vec(V_P_STEP, FL_CG, i));   // beta, stopping test; p = z + beta p
     PTLM_TRY(o.cg_mark(i + 1));
-    PTLM_TRY(o.vec(V_PUPDATE, FL_CG));
   }
   // ---- trial point, predicted and actual reductions, gain ratio, damping, acceptance
   PTLM_TRY(o.vec(V_TRIAL, FL_ALIVE));

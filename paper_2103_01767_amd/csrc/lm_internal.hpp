@@ -16,12 +16,11 @@ inline int lm_vec_blocks(size_t n) {
 
 // indices into the FP64 scalar scratch
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4, SC_XMAX_O = 5, SC_XMAX_P = 6,
-       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17 };
+       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
-enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_UPDATE, V_PUPDATE, V_TRIAL, V_XMAX, V_XFLOOR,
+enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
                    V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME };
-enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PAP, F_CG_UPDATE, F_PRED, F_TRIAL_END, F_INIT,
-                   F_LS, F_ADOPT };
+enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_LS, F_ADOPT };
 
 // Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
 enum LMFlag : int {
@@ -66,11 +65,13 @@ struct LMJob {
   int block0;
 };
 
-hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s);
+// iter: the PCG iteration of V_CG_STEP / V_P_STEP (selects the r.z parity slot)
+hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s, int iter = 0);
 hipError_t launch_fin(int op, const LMArgs& a, int count, int flag, hipStream_t s);
 // batched: vector kernels over the blocks of every job; finalize kernels one block per job,
 // reducing count_kind = 0 (none), 1 (the job's vector partials) or 2 (its tile partials)
-hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* job_of_block, int nblocks, int flag, hipStream_t s);
+hipError_t launch_vec_batch(int op, const LMJob* jobs, const int* job_of_block, int nblocks, int flag, hipStream_t s,
+                            int iter = 0);
 hipError_t launch_fin_batch(int op, const LMJob* jobs, int njobs, int count_kind, int flag, hipStream_t s);
 
 }  // namespace ptlm

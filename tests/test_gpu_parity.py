@@ -313,3 +313,61 @@ def test_stochastic_diagonal(probe, metric):
     print("stoch rel", rel(host(dO), sO), rel(host(dP), sP))
     assert rel(host(dO), sO) < 2 * TOL
     assert rel(host(dP), sP) < 2 * TOL
+
+
+def _check_products(probe, O, P, pos, metric, joint, seed, tol=TOL):
+    rng = np.random.default_rng(seed)
+    O64, P64 = O.astype(np.complex128), P.astype(np.complex128)
+    y = synth.poisson_counts(rng, ptycho.intensity(O64, P64, pos, 1e-8)).astype(np.float32)
+    case = dict(O=O, P=P, pos=pos, y=y, metric=metric, joint=joint)
+    prob = problem(case)
+    Od, Pd, yd = to_dev(O), to_dev(P), to_dev(y)
+    assert rel(host(prob.forward(Od, Pd)), ptycho.magnitude(O64, P64, pos, 1e-8)) < TOL
+    lin = ptycho.linearize(O64, P64, pos, y.astype(np.float64), 1e-8, metric, joint)
+    f, gO, gP = prob.linearize(Od, Pd, yd)
+    assert abs(float(host(f)[0]) - lin.f) <= 1e-5 * abs(lin.f)
+    rgO, rgP = ptycho.gradient(lin)
+    assert rel(host(gO), rgO) < tol
+    vO = c64(synth.random_complex(rng, O.shape))
+    vP = c64(synth.random_complex(rng, P.shape)) if joint else None
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128) if joint else None)
+    oO, oP = prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None)
+    assert rel(host(oO), GO) < tol
+    if joint:
+        assert rel(host(gP), rgP) < tol
+        assert rel(host(oP), GP) < tol
+    dO, dP = prob.diag(exact=True)
+    eO, eP = ptycho.ggn_diag_exact(lin)
+    assert rel(host(dO), eO) < 2 * tol
+    if joint:
+        assert rel(host(dP), eP) < 2 * tol
+
+
+@pytest.mark.parametrize("probe", [(16, 16), (128, 128), (48, 48), (256, 256), (32, 64)], ids=lambda p: "%dx%d" % p)
+def test_single_position_covering_the_object(probe):
+    """K = 1 with the object exactly the probe's size: one segment, every other workgroup empty,
+    every object pixel covered once."""
+    print("case single position", probe, flush=True)
+    rng = np.random.default_rng(40 + probe[0])
+    O = c64(synth.random_complex(rng, probe) * 0.3 + 0.8)
+    P = c64(synth.scale_probe_to_photons(synth.make_probe_fresnel(rng, max(probe), 0.35 * max(probe), 3.0)
+                                         [:probe[0], :probe[1]], O, 2e3))
+    _check_products(probe, O, P, np.zeros((1, 2), np.int32), "gauss", True, seed=probe[0])
+
+
+@pytest.mark.parametrize("probe", [(16, 16), (128, 128), (96, 96)], ids=lambda p: "%dx%d" % p)
+def test_corner_and_repeated_positions(probe):
+    """Positions at all four extreme corners of the object, the same position repeated, and a
+    prime number of positions (ragged segments, most workgroups of a 128 x 128 launch empty);
+    Poisson metric, joint."""
+    print("case corners", probe, flush=True)
+    rng = np.random.default_rng(50 + probe[0])
+    ny, nx = probe[0] * 2 + 5, probe[1] * 2 + 3
+    O = c64(synth.make_object(rng, max(ny, nx), amp=(0.7, 1.0), phase=(-math.pi, math.pi), phase_sigma=2.0,
+                              phase_source="gaussian")[:ny, :nx])
+    P = c64(synth.scale_probe_to_photons(synth.make_probe_fresnel(rng, max(probe), 0.35 * max(probe), 3.0)
+                                         [:probe[0], :probe[1]], O, 2e3))
+    ry, rx = ny - probe[0], nx - probe[1]
+    pos = np.array([[0, 0], [0, rx], [ry, 0], [ry, rx], [ry // 2, rx // 3], [ry // 2, rx // 3], [1, rx - 1]],
+                   np.int32)
+    _check_products(probe, O, P, pos, "poisson", True, seed=probe[0] + 1)
