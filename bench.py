@@ -38,10 +38,10 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # profiles/ggnv_tile128_joint_obj512_probe128_k1600.md (KiB per dispatch, scaled by what the
 # same counters read for a plain 256 MiB copy).  Valid only for the kernel sources they were
 # taken on: a different hash of those sources reports traffic as null.
-TRAFFIC = {"fetch_kib": 337722.109375, "write_kib": 448747.359375, "fetch_factor": 1.9998, "write_factor": 1.0,
+TRAFFIC = {"fetch_kib": 337749.4140625, "write_kib": 448891.109375, "fetch_factor": 1.9998, "write_factor": 1.0,
            "grid_scale": 1.0,
            "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp"],
-           "sha256": "9a762ed9f00eb75e3eb49bc1c1d152a5ddb123405e212987c8bcc599d427fee0"}
+           "sha256": "a6915e4683f596be2915ebc12e995d6556f67da013a4bf3e4a3ff7add6f33e7b"}
 
 
 def measured_traffic():
