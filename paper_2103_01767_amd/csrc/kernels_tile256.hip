@@ -53,6 +53,12 @@ __device__ __forceinline__ float2 ld_nt(const float2* p) {
   return __builtin_bit_cast(float2, d);
 }
 
+// The transform tile is streamed through memory (512 KiB per workgroup never fits its L2
+// share): streaming stores and loads leave L2 to the windows and strips that are reused.
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double*>(p));
+}
+
 // sum of x over the workgroup, returned to every thread (two barriers)
 __device__ __forceinline__ double wg_sum(double x, double* red, int col) {
 #pragma unroll
@@ -170,7 +176,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
         dft16<false>(v);
         float2* srow = scr + row * S + rc;
 #pragma unroll
-        for (int k2 = 0; k2 < 16; ++k2) srow[16 * k2] = v[k2];
+        for (int k2 = 0; k2 < 16; ++k2) st_nt(srow + 16 * k2, v[k2]);
       }
       __syncthreads();
     }
@@ -185,7 +191,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
         if constexpr (FWD_FFT) {
           // y pass 1: DFT16 over n2 (y = cs + 16 n2), twiddle W_256^(cs k1)
 #pragma unroll
-          for (int j = 0; j < 16; ++j) v[j] = scr[(cs + 16 * j) * S + kx];
+          for (int j = 0; j < 16; ++j) v[j] = ld_nt(scr + (cs + 16 * j) * S + kx);
           dft16<false>(v);
 #pragma unroll
           for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[cs * 16 + k1]);
@@ -225,7 +231,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
           for (int k1 = 0; k1 < 16; ++k1) v[k1] = smem[(k1 * 16 + cs) * CB + cc];
           dft16<true>(v);
 #pragma unroll
-          for (int j = 0; j < 16; ++j) scr[(cs + 16 * j) * S + kx] = v[j];
+          for (int j = 0; j < 16; ++j) st_nt(scr + (cs + 16 * j) * S + kx, v[j]);
         }
       }
       if constexpr (OP == OP_LINEARIZE) {
@@ -244,7 +250,7 @@ __device__ __forceinline__ void tile256_body(const Geometry g, const TileArgs a,
         float2 v[16];
         const float2* srow = scr + row * S + rc;
 #pragma unroll
-        for (int k2 = 0; k2 < 16; ++k2) v[k2] = srow[16 * k2];
+        for (int k2 = 0; k2 < 16; ++k2) v[k2] = ld_nt(srow + 16 * k2);
         // inverse x pass 2 (this thread owns k1 = rc): DFT16 over k2 -> n1, W_256^(-n1 rc)
         dft16<true>(v);
 #pragma unroll
