@@ -491,12 +491,32 @@ ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, si
   return PTLM_OK;
 }
 
+}  // extern "C"
+
+// Pinned host slots and events of the PCG look-ahead (ptlm_lm_step), made once with the handle
+// so that no LM call allocates; solves with more than kCgSlots - 1 iterations enqueue all of them.
+static ptlm_status cg_slots_create(ptlm_handle* h) {
+  void* p = nullptr;
+  PTLM_HIP(hipHostMalloc(&p, (size_t)kCgSlots * sizeof(int), hipHostMallocCoherent), "pcg slots");
+  h->cg_flags = (int*)p;
+  h->cg_slots = kCgSlots;
+  for (int i = 0; i < kCgSlots; ++i) {
+    hipEvent_t e;
+    PTLM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "pcg events");
+    h->cg_events.push_back(e);
+  }
+  return PTLM_OK;
+}
+
+extern "C" {
+
 ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes, void* stream,
                         ptlm_handle** out) {
   if (!out) return fail(PTLM_EINVAL, "out is null");
   *out = nullptr;
   ptlm_handle* h = new ptlm_handle();
-  const ptlm_status st = init_handle(h, desc, h_pos, d_ws, ws_bytes, (hipStream_t)stream);
+  ptlm_status st = init_handle(h, desc, h_pos, d_ws, ws_bytes, (hipStream_t)stream);
+  if (st == PTLM_OK) st = cg_slots_create(h);
   if (st != PTLM_OK) {
     delete h;
     return st;

@@ -48,7 +48,7 @@ struct ptlm_handle {
   bool cnn_ready = false;   // the network output r in cnn_ws is current
   // PCG look-ahead of ptlm_lm_step: pinned host slots the finalize kernels write the PCG
   // continuation flag to, and one event per slot
-  int* cg_flags = nullptr;
+  int* cg_flags = nullptr;  // null for the handles of a batch: no look-ahead there
   int cg_slots = 0;
   std::vector<hipEvent_t> cg_events;
   // Linearisation at the LM's trial point, computed into spare buffers and swapped in when the
@@ -67,6 +67,7 @@ struct ptlm_handle {
 };
 
 namespace ptlm {
+constexpr int kCgSlots = 129;  // PCG look-ahead slots of a single-problem handle (cg_max <= 128)
 extern thread_local std::string g_last_error;
 ptlm_status fail(ptlm_status st, const std::string& msg);
 ptlm_status hip_fail(hipError_t e, const char* where);

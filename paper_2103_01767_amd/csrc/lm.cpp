@@ -307,24 +307,6 @@ static ptlm_status projected_plugin(SingleOps& o, const ptlm_lm_params& prm, dou
   return PTLM_OK;
 }
 
-// Pinned host slots (and their events) for the PCG look-ahead, grown on demand.
-static ptlm_status cg_slots(ptlm_handle* h, int n) {
-  if (h->cg_flags && h->cg_slots >= n) return PTLM_OK;
-  if (h->cg_flags) LM_HIP(hipHostFree(h->cg_flags), "lm pcg slots");
-  h->cg_flags = nullptr;
-  h->cg_slots = 0;
-  void* p = nullptr;
-  LM_HIP(hipHostMalloc(&p, (size_t)n * sizeof(int), hipHostMallocCoherent), "lm pcg slots");
-  h->cg_flags = (int*)p;
-  h->cg_slots = n;
-  while ((int)h->cg_events.size() < n) {
-    hipEvent_t e;
-    LM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "lm pcg events");
-    h->cg_events.push_back(e);
-  }
-  return PTLM_OK;
-}
-
 // One outer iteration: the attempts of alg:lm_inexact until one is accepted or retry_max are
 // rejected -- once for the joint update, once per block (object, then probe) for the
 // alternating update of alg:alt_LM_ptycho.
@@ -336,8 +318,9 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
   if (hs.t >= hs.t_max) return fail(PTLM_EINVAL, "the state has run its outer iterations (t_max)");
   const int t0 = hs.t;
   SingleOps o{h, make_lm_args(h, prm, st, O, P, learned), O, P, y, learned, false, s};
-  PTLM_TRY(cg_slots(h, prm->cg_max + 1));
-  o.a.cg_flags = h->cg_flags;
+  // PCG look-ahead when the handle has slots for every iteration (else all are enqueued)
+  const bool ahead = h->cg_flags && prm->cg_max + 1 <= h->cg_slots;
+  o.a.cg_flags = ahead ? h->cg_flags : nullptr;
   // trial points are evaluated as linearisations (kept for the next outer iteration when the
   // step is accepted) unless the projected plug-in may move the iterate off the trial point
   o.spec = !prm->project;
@@ -350,7 +333,8 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
       o.lin_expected = hs.need_lin != 0;
       o.a.adopt_ok = (o.spec && h->kept_gen == h->lin_gen && h->kept_y == y) ? 1 : 0;
       // no kernel of an earlier attempt is in flight (its state was read back)
-      for (int j = 0; j <= prm->cg_max; ++j) __atomic_store_n(h->cg_flags + j, 0, __ATOMIC_RELAXED);
+      if (ahead)
+        for (int j = 0; j <= prm->cg_max; ++j) __atomic_store_n(h->cg_flags + j, 0, __ATOMIC_RELAXED);
       PTLM_TRY(enqueue_attempt(o, *prm));
       PTLM_TRY(read_state(st, &hs, s));
       if (o.spec && hs.accepted) {
