@@ -412,3 +412,27 @@ def test_kept_trial_linearisation_is_adopted_only_at_the_same_point():
     prob.lm_step(O, P, yd, params, st)
     s4 = pt.state_from_tensor(st)
     assert s4.f == pytest.approx(f_here, rel=1e-5)
+
+
+def test_lm_at_the_solution_stays_put():
+    """Degenerate case: noise-free data and the iterate at the ground truth (f and g vanish up to
+    single-precision rounding).  No value turns non-finite, the state stays usable and the
+    iterate stays at the truth to rounding, whether the attempts are accepted or all rejected."""
+    print("case at solution", flush=True)
+    pr = synth.make_small(17, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode="joint")
+    y = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background).astype(np.float32)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_true, np.complex64), to_dev(pr.P_true, np.complex64), to_dev(y, np.float32)
+    O0, P0 = O.clone(), P.clone()
+    for kw in (dict(scaling=1, precond=1), dict()):
+        params = pt.default_params(**kw)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(3):
+            prob.lm_step(O, P, yd, params, st)
+        s = pt.state_from_tensor(st)
+        assert s.t == 3 and s.status != pt.PTLM_ENUMERIC and s.nonfinite == 0
+        assert math.isfinite(s.f) and math.isfinite(s.mu) and math.isfinite(s.lambda_)
+        assert bool(torch.isfinite(torch.view_as_real(O)).all()) and bool(torch.isfinite(torch.view_as_real(P)).all())
+        assert float(torch.linalg.norm(O - O0) / torch.linalg.norm(O0)) < 1e-4
+        assert float(torch.linalg.norm(P - P0) / torch.linalg.norm(P0)) < 1e-4
