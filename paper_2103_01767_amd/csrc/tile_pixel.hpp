@@ -20,9 +20,14 @@
 
 namespace ptlm {
 
+// Streamed accesses (read or written once per call): the nontemporal hint keeps them from
+// evicting the windows and strips that the tile kernels reuse from L2.
 __device__ __forceinline__ float2 ld_once(const float2* p) {
   const double d = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));
   return __builtin_bit_cast(float2, d);
+}
+__device__ __forceinline__ void st_once(float2* p, float2 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double*>(p));
 }
 
 // Output n >= 1 of the SplitMix64 generator seeded with `seed` (Steele, Lea and Flood 2014):
@@ -55,7 +60,7 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
     if constexpr (OP == OP_FORWARD) {
       a.rout[gi] = zeta;
     } else {
-      const float yv = a.y[gi];
+      const float yv = __builtin_nontemporal_load(a.y + gi);
       const bool poisson = MET >= 0 ? (MET & 1) != 0 : g.metric != 0;
       float l, l1;
       if (!poisson) {
@@ -78,10 +83,10 @@ __device__ __forceinline__ void pixel_op(const Geometry& g, const TileArgs& a, s
         tr += (double)l2;
         const float w = sqrtf(l2);
         const float2 e = cscale(ps, iz);
-        g.afield[gi] = cscale(e, w * isq);
-        if constexpr (MET > 0) g.w2[gi] = w;
+        st_once(g.afield + gi, cscale(e, w * isq));
+        if constexpr (MET > 0) __builtin_nontemporal_store(w, g.w2 + gi);
         if constexpr (MET < 0) {
-          if (g.w2) g.w2[gi] = w;
+          if (g.w2) __builtin_nontemporal_store(w, g.w2 + gi);
         }
         v = cscale(e, l1 * isq);
       }
