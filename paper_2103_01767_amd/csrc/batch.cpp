@@ -226,7 +226,7 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
     const int M = p.d.my * p.d.mx;
     b.obj_b0[i] = append_run(b.jb_obj, i, p.otx * p.oty, 1);
     b.prb_b0[i] = append_run(b.jb_prb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);
-    b.dprb_b0[i] = append_run(b.jb_dprb, i, p.d.mode == PTLM_JOINT ? (M + 15) / 16 : 0, 1);
+    b.dprb_b0[i] = append_run(b.jb_dprb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);  // 64 pixels a block
     b.vec_b0[i] = append_run(b.jb_vec, i, lm_vec_blocks(p.nvec), 1);
   }
   // copy jobs: linearisation (O, P) and acceptance (O, P, previous step) per problem
@@ -465,7 +465,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
       ro.block0 = b->obj_b0[i];
       ro.nblk = g.otiles_x * g.otiles_y;
       rp.block0 = k == RK_DIAG ? b->dprb_b0[i] : b->prb_b0[i];
-      rp.nblk = g.joint ? (int)(k == RK_DIAG ? (M + 15) / 16 : (M + 63) / 64) : 0;
+      rp.nblk = g.joint ? (int)((M + 63) / 64) : 0;  // 64 probe pixels per block (reduction and diagonal)
       b->red_obj[k][i] = ro;
       b->red_prb[k][i] = rp;
     }

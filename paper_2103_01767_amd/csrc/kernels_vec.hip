@@ -218,18 +218,20 @@ __global__ __launch_bounds__(1024) void diag_paper_obj_batch_kernel(const RedJob
 }
 
 // App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; one 1024-thread
-// block per 16 pixels, the position sum split 64 ways and combined in a fixed order.
+// block per 64 consecutive pixels (a wavefront reads one 512-byte run of an object row), the
+// position sum split 16 ways and combined in a fixed order.
 constexpr int DIAG_PRB_THREADS = 1024;
+constexpr int DIAG_PRB_PIX = 64;
 __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* dP, int bx) {
-  __shared__ double sh[64][17];
+  __shared__ double sh[16][DIAG_PRB_PIX + 1];
   const int M = g.my * g.mx;
-  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int m = bx * 16 + lane;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int m = bx * DIAG_PRB_PIX + lane;
   double acc = 0.0;
   if (m < M) {
     const int my = m / g.mx, mx = m % g.mx;
 #pragma unroll 4
-    for (int k = grp; k < g.K; k += 64) {
+    for (int k = grp; k < g.K; k += 16) {
       const int2 r = g.pos[k];
       const float2 o = g.O_lin[(size_t)(r.x + my) * g.nx + r.y + mx];
       acc += g.trace[k] * (double)fmaf(o.x, o.x, o.y * o.y);
@@ -238,9 +240,9 @@ __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* 
   sh[grp][lane] = acc;
   __syncthreads();
   if (grp != 0 || m >= M) return;
-  acc = 0.0;
-  for (int q = 0; q < 64; ++q) acc += sh[q][lane];
-  const float val = (float)(acc / (2.0 * M));
+  double sum = 0.0;
+  for (int q = 0; q < 16; ++q) sum += sh[q][lane];
+  const float val = (float)(sum / (2.0 * M));
   dP[2 * m] = val;
   dP[2 * m + 1] = val;
 }
@@ -329,7 +331,8 @@ hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !dP) return e;
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + 15) / 16), dim3(DIAG_PRB_THREADS), 0, s, g, dP, pred);
+  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + DIAG_PRB_PIX - 1) / DIAG_PRB_PIX), dim3(DIAG_PRB_THREADS), 0,
+                     s, g, dP, pred);
   return hipGetLastError();
 }
 

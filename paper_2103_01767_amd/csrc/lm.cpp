@@ -1,10 +1,11 @@
 // Host driver of the truncated LM iteration (alg:lm_inexact) for one problem.
 //
-// An outer iteration is a sequence of attempts; each attempt is the fixed launch sequence of
-// lm_attempt.hpp (linearise when the previous attempt was accepted, lambda/eta, PCG start,
-// cg_max predicated PCG iterations, trial point, trial loss, gain ratio and damping update,
-// accept copies), followed by one stream synchronisation to read the device state.  All
-// scalars of the method live in FP64 in the device state.
+// An outer iteration is a sequence of attempts; each attempt is the launch sequence of
+// lm_attempt.hpp (linearise when the previous attempt was accepted, unless the linearisation
+// made at the accepted trial point is adopted; lambda/eta, PCG start, predicated PCG
+// iterations enqueued one ahead of the device's stopping decision; trial point and its loss,
+// gain ratio and damping update, accept copies), followed by one stream synchronisation to
+// read the device state.  All scalars of the method live in FP64 in the device state.
 #include <climits>
 #include <cmath>
 #include <cstring>

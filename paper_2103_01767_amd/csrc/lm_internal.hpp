@@ -15,7 +15,7 @@ inline int lm_vec_blocks(size_t n) {
 }
 
 // indices into the FP64 scalar scratch
-enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_FTRIAL = 4, SC_XMAX_O = 5, SC_XMAX_P = 6,
+enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_XMAX_O = 5, SC_XMAX_P = 6,
        SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
