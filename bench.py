@@ -96,7 +96,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(positions would be sharded across GPUs; see the design notes). Use --gpus 1.",
+              "(the scan positions would be sharded over GPUs, one process each). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
