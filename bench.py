@@ -95,7 +95,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the scan positions would be sharded over GPUs, one process each). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
