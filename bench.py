@@ -38,10 +38,10 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # profiles/ggnv_tile128_joint_obj512_probe128_k1600.md (KiB per dispatch, scaled by what the
 # same counters read for a plain 256 MiB copy).  Valid only for the kernel sources they were
 # taken on: a different hash of those sources reports traffic as null.
-TRAFFIC = {"fetch_kib": 337749.4140625, "write_kib": 448891.109375, "fetch_factor": 1.9998, "write_factor": 1.0,
+TRAFFIC = {"fetch_kib": 337715.09375, "write_kib": 448956.5625, "fetch_factor": 1.9998, "write_factor": 1.0,
            "grid_scale": 1.0,
            "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp"],
-           "sha256": "a6915e4683f596be2915ebc12e995d6556f67da013a4bf3e4a3ff7add6f33e7b"}
+           "sha256": "030dbf54f3705d8526d0f5500d511eb620b19bd7d8cb4ec468d0d338755f1f35"}
 
 
 def measured_traffic():
