@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--cpu-calls", type=int, default=3)
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the projected / alternating / intensity-GGN / stochastic-diagonal / surrogate runs")
+    ap.add_argument("--poisson-iters", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the large-scan GGN-vector timing")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default segment count")
@@ -154,6 +157,7 @@ def main():
     large = None if args.no_c4 else large_scan(dev, max(3, args.calls // 10))
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
+    nxt = None if args.no_next else lm_variants(pr, dev, args.lm_iters, args.poisson_iters)
     batch = None if args.no_batch else batch_measure(dev, args.batch_iters)
 
     cpu = None
@@ -191,6 +195,7 @@ def main():
                      "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
         "ggnv_large_scan": large,
         "lm_time_to_target": lm,
+        "lm_variants": nxt,
         "batch_uneven": batch,
         "cpu_baseline": cpu,
     }
@@ -302,6 +307,82 @@ def lm_comparison(prob, pr, dev, iters):
                      "seconds": round(el, 4), "final_loss": f, "ggnv_products": s.products,
                      "attempts": s.attempts}
     pt.lm_set_cnn(prob, None)
+    return out
+
+
+def _run_lm(prob, params, O, P, y, iters, target=None, f_floor=0.0, stop=True):
+    """Outer LM iterations from (O, P) until the loss is <= target (or `iters` of them; all of them
+    when not `stop`); the loss is read after every iteration (which also synchronises), alike for
+    every variant timed."""
+    import torch
+    import paper_2103_01767_amd as pt
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hit, f = None, float("nan")
+    for t in range(iters):
+        prob.lm_step(O, P, y, params, st)
+        f = float(prob.loss(O, P, y).cpu()[0])
+        if target is not None and hit is None and f - f_floor <= target - f_floor:
+            s = pt.state_from_tensor(st)
+            hit = {"iters": t + 1, "seconds": round(time.perf_counter() - t0, 4), "ggnv_products": s.products}
+            if stop:
+                break
+    el = time.perf_counter() - t0
+    s = pt.state_from_tensor(st)
+    out = {"iters": s.t, "seconds": round(el, 4), "final_loss": f, "ggnv_products": s.products,
+           "attempts": s.attempts}
+    if target is not None:
+        out["reached"] = hit is not None
+        out["to_target"] = hit
+    return out
+
+
+def lm_variants(pr, dev, iters, poisson_iters):
+    """The method's variants on the same joint 512/128 problem, data and initial guess (Jacobi PCG
+    with the App. B diagonal unless stated, D = Dg(G), at most 10 products per solve).
+
+    Gaussian metric, time to f <= 1.01 f_oracle (the target of the LM comparison):
+      projected LM (alg:projected_LM, |O| <= 1), alternating LM (alg:alt_LM_ptycho: an object
+      step then a probe step per outer iteration), the intensity-based GGN (App. C) and the
+      stochastic diagonal estimate (8 sign-field draws per linearisation) as the preconditioner.
+    Poisson metric (beta = 0.9): `poisson_iters` outer iterations of plain Poisson LM and of the
+      App. E surrogate (sigma from 1 down over the same iterations, then 0): products and final
+      loss of both, and the surrogate's time and products to the plain run's final loss (1.01x
+      above the metric's minimum).
+    """
+    import torch
+    import paper_2103_01767_amd as pt
+    gold = os.path.join(HERE, "tests", "golden")
+    ref = json.load(open(os.path.join(gold, "c1_oracle_lm.json")))
+    yh = np.load(os.path.join(gold, "c1_counts.npz"))["y"]
+    y = torch.from_numpy(yh.astype(np.float32)).to(dev)
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    shapes = (pr.O_true.shape, pr.P_true.shape)
+    target = 1.01 * ref["f_final"]
+    out = {"target_loss": target, "max_iters": iters}
+    base = dict(scaling=1, precond=1, cg_max=10)
+    for name, ggn, kw in (("projected", "magnitude", dict(project=1)),
+                          ("alternating", "magnitude", dict(alternate=1)),
+                          ("intensity_ggn", "intensity", {}),
+                          ("stochastic_jacobi", "magnitude", dict(precond=4, stoch_samples=8, stoch_seed=7))):
+        prob = pt.Problem(*shapes, pr.pos, metric="gauss", mode="joint", background=pr.background, device=dev,
+                          ggn=ggn)
+        params = pt.default_params(**{**base, **kw})
+        out[name] = _run_lm(prob, params, c64(pr.O_init), c64(pr.P_init), y, iters, target)
+        del prob
+    # Poisson metric: plain vs the App. E surrogate
+    yy = yh.astype(np.float64)
+    f_min = float(np.sum(yy - yy * np.log(np.where(yy > 0, yy, 1.0))))
+    prob = pt.Problem(*shapes, pr.pos, metric="poisson", mode="joint", background=pr.background, device=dev)
+    plain = _run_lm(prob, pt.default_params(**base, beta=0.9), c64(pr.O_init), c64(pr.P_init), y, poisson_iters)
+    p_target = f_min + 1.01 * (plain["final_loss"] - f_min)
+    sur = _run_lm(prob, pt.default_params(**base, beta=0.9, surrogate_T=poisson_iters, surrogate_s0=1.0),
+                  c64(pr.O_init), c64(pr.P_init), y, poisson_iters, p_target, f_floor=f_min, stop=False)
+    out["poisson"] = {"iters": poisson_iters, "f_min": f_min, "target_loss": p_target, "plain": plain,
+                      "surrogate": sur}
+    del prob
     return out
 
 
