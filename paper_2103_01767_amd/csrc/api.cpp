@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -76,15 +77,42 @@ static int plan_grid(const Plan& p, double scale) {
   return std::max(1, std::min((p.d.K + p.tpw - 1) / p.tpw, gmax));
 }
 
-// Contiguous segments of the position list (lengths differing by at most one), their strip
-// boxes and offsets, and the object-tile -> segment map, for `grid` workgroups.
+// Contiguous segments of the position list, at most ceil(K / nseg) positions each, for
+// `grid` workgroups.  Where the scan jumps (consecutive windows half a side or more apart, as
+// at the end of a raster row) a segment is cut, if the cuts still leave at most nseg segments
+// of that length: a segment across a jump has a bounding box (its strip) that is mostly
+// outside its windows, which the tile kernel must clear and the gather must read.  Runs
+// between jumps are split evenly, and the segments are spread over the nseg slots so that the
+// empty ones do not bunch on one XCD.  Otherwise the list is cut evenly (lengths differing by
+// at most one).  Then the strip boxes and offsets and the object-tile -> segment map.
 static void segment(Plan& p, const int* h_pos, int grid) {
   const ptlm_desc* d = &p.d;
   const int K = d->K;
   p.grid = grid;
   p.nseg = p.grid * p.tpw;
   p.seg_start.resize(p.nseg + 1);
-  for (int s = 0; s <= p.nseg; ++s) p.seg_start[s] = (int)(((long long)s * K) / p.nseg);
+  const int L = (int)(((long long)K + p.nseg - 1) / p.nseg);
+  std::vector<int> cuts{0};  // starts of the segments cut at jumps, then K
+  int b = 0;
+  for (int k = 1; k <= K && (int)cuts.size() <= p.nseg + 1; ++k) {
+    const bool jump = k == K || std::abs(h_pos[2 * k] - h_pos[2 * k - 2]) * 2 >= d->my ||
+                      std::abs(h_pos[2 * k + 1] - h_pos[2 * k - 1]) * 2 >= d->mx;
+    if (!jump) continue;
+    const int n = k - b, m = (n + L - 1) / L;
+    for (int i = 1; i <= m; ++i) cuts.push_back(b + (int)(((long long)i * n) / m));
+    b = k;
+  }
+  const int count = (int)cuts.size() - 1;
+  if (b == K && count <= p.nseg) {
+    // segment j goes to slot floor(j nseg / count): strictly increasing, so every other slot is empty
+    int j = 0;
+    for (int s = 0; s <= p.nseg; ++s) {
+      while (j < count && (int)(((long long)j * p.nseg) / count) < s) ++j;
+      p.seg_start[s] = cuts[j];
+    }
+  } else {
+    for (int s = 0; s <= p.nseg; ++s) p.seg_start[s] = (int)(((long long)s * K) / p.nseg);
+  }
   p.seg_box.assign(p.nseg, make_int4(0, 0, 0, 0));
   p.seg_off.assign(p.nseg, 0);
   long long off = 0;
