@@ -328,7 +328,10 @@ ptlm_handle* ptlm_batch_problem(ptlm_batch* b, int32_t i);
  * outer iterations, and reset the states (mu = mu0, t = 0).  use_graph = 1: attempts after
  * the first are replayed from one captured HIP graph.  With params->precond == 2 every
  * problem needs a registered network (ptlm_lm_set_cnn on its handle); with params->alternate
- * every problem must be PTLM_JOINT.  Pointers must stay
+ * every problem must be PTLM_JOINT; params->project must be 0 (PTLM_EINVAL otherwise: the
+ * projected plug-in's line search is driven from the host).  With params->precond 3 or 4 each
+ * problem's diagonal comes from its own launches of the single-problem kernels, in the same
+ * attempt sequence (one tile launch, or one per draw, per problem).  Pointers must stay
  * valid until the next bind or ptlm_batch_destroy. */
 ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P, const float* const* d_y,
                             ptlm_lm_state* d_states, const ptlm_lm_params* params, int32_t T, int32_t use_graph,

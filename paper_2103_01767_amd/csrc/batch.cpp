@@ -160,8 +160,28 @@ struct BatchOps {
     }
     return PTLM_OK;
   }
-  ptlm_status exact_diag() { return fail(PTLM_EINVAL, "precond 3 is not available in batches"); }
-  ptlm_status stoch_diag() { return fail(PTLM_EINVAL, "precond 4 is not available in batches"); }
+  // exact diagonal / its stochastic estimate: each problem's own launches (the single-problem
+  // kernels on its handle, predicated on its linearisation flag), so a batch equals its
+  // problems alone
+  ptlm_status exact_diag() {
+    for (int i = 0; i < b->n; ++i) {
+      ptlm_handle* h = b->hs[i];
+      const LMArgs& a = b->lm_jobs[i].a;
+      const int* lin = reinterpret_cast<const int*>(b->d_states + i) + FL_LIN;
+      PTLM_TRY(diag_exact_impl(h, (float*)a.xdiag, h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, lin));
+    }
+    return PTLM_OK;
+  }
+  ptlm_status stoch_diag() {
+    for (int i = 0; i < b->n; ++i) {
+      ptlm_handle* h = b->hs[i];
+      const LMArgs& a = b->lm_jobs[i].a;
+      const int* lin = reinterpret_cast<const int*>(b->d_states + i) + FL_LIN;
+      PTLM_TRY(diag_stochastic_impl(h, a.prm.stoch_samples, a.prm.stoch_seed, 0, &b->d_states[i].t, (float*)a.xdiag,
+                                    h->g.joint ? (float*)(a.xdiag + a.nobj) : nullptr, s, lin));
+    }
+    return PTLM_OK;
+  }
   ptlm_status ggnv(int which) {
     PTLM_TRY(tiles(OP_GGNV, which == GG_WARM ? TK_WARM : TK_P));
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
@@ -365,8 +385,6 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (T < 0) return fail(PTLM_EINVAL, "T must be >= 0");
-  if (params->precond == 3 || params->precond == 4)
-    return fail(PTLM_EINVAL, "precond 3 and 4 are not available in batches");
   if (params->project) return fail(PTLM_EINVAL, "the projected plug-in is not available in batches");
   for (int i = 0; i < b->n; ++i) {
     if (!d_O[i] || !d_P[i] || !d_y[i]) return fail(PTLM_EINVAL, "null array of problem " + std::to_string(i));

@@ -255,3 +255,29 @@ def test_batch_mixed_ggn_equals_alone():
         s2 = batch.state(i)
         assert s2.t == T and s2.f == s1.f and s2.products == s1.products
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+@pytest.mark.parametrize("precond", [3, 4])
+def test_batch_exact_and_stochastic_diagonal_equal_alone(precond):
+    """The exact GGN diagonal (precond 3) and its stochastic estimate (precond 4, the sign
+    fields drawn from the outer iteration) as Jacobi diagonals in a batch: every problem's
+    diagonal comes from its own launches, so the batch equals its problems solved alone."""
+    print("case batch diagonal precond", precond, flush=True)
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=precond, cg_max=5, stoch_samples=3, stoch_seed=5)
+    T = 3
+    alone = [run_single(p, params, T) for p in probs]
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(100, check_every=2)
+    torch.cuda.synchronize()
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        print("problem %d: f %.6e / %.6e products %d / %d" % (i, s1.f, s2.f, s1.products, s2.products))
+        assert s2.t == T and s1.t == T
+        assert s2.f == s1.f and s2.products == s1.products and s2.attempts == s1.attempts
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
