@@ -219,27 +219,42 @@ __global__ __launch_bounds__(1024) void diag_paper_obj_batch_kernel(const RedJob
 
 // App. B diagonal, probe part: d_m = (1/2M) sum_k trace_k |O[r_k + m]|^2; one 1024-thread
 // block per 64 consecutive pixels (a wavefront reads one 512-byte run of an object row), the
-// position sum split 16 ways and combined in a fixed order.
+// position sum split 16 ways (k mod 16, in increasing k) and combined in a fixed order.
+// Positions and traces are staged in LDS in chunks, so the object read is the only global
+// load of the loop.
 constexpr int DIAG_PRB_THREADS = 1024;
 constexpr int DIAG_PRB_PIX = 64;
+constexpr int DIAG_PRB_CHUNK = 1024;  // a multiple of 16: a chunk keeps every group's k order
 __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* dP, int bx) {
   __shared__ double sh[16][DIAG_PRB_PIX + 1];
+  __shared__ int2 s_pos[DIAG_PRB_CHUNK];
+  __shared__ double s_tr[DIAG_PRB_CHUNK];
   const int M = g.my * g.mx;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int m = bx * DIAG_PRB_PIX + lane;
+  const bool in = m < M;
+  const float2* Om = g.O_lin + (in ? (size_t)(m / g.mx) * g.nx + m % g.mx : 0);
   double acc = 0.0;
-  if (m < M) {
-    const int my = m / g.mx, mx = m % g.mx;
-#pragma unroll 4
-    for (int k = grp; k < g.K; k += 16) {
-      const int2 r = g.pos[k];
-      const float2 o = g.O_lin[(size_t)(r.x + my) * g.nx + r.y + mx];
-      acc += g.trace[k] * (double)fmaf(o.x, o.x, o.y * o.y);
+  for (int c0 = 0; c0 < g.K; c0 += DIAG_PRB_CHUNK) {
+    const int cnt = min(DIAG_PRB_CHUNK, g.K - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      s_pos[threadIdx.x] = g.pos[c0 + threadIdx.x];
+      s_tr[threadIdx.x] = g.trace[c0 + threadIdx.x];
+    }
+    __syncthreads();
+    if (in) {
+#pragma unroll 8
+      for (int i = grp; i < cnt; i += 16) {
+        const int2 r = s_pos[i];
+        const float2 o = Om[(size_t)r.x * g.nx + r.y];
+        acc += s_tr[i] * (double)fmaf(o.x, o.x, o.y * o.y);
+      }
     }
   }
   sh[grp][lane] = acc;
   __syncthreads();
-  if (grp != 0 || m >= M) return;
+  if (grp != 0 || !in) return;
   double sum = 0.0;
   for (int q = 0; q < 16; ++q) sum += sh[q][lane];
   const float val = (float)(sum / (2.0 * M));
