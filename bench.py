@@ -36,12 +36,13 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # HBM-side bytes of one launch of the GGN-vector tile kernel on this workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
 # profiles/ggnv_tile128_joint_obj512_probe128_k1600.md (KiB per dispatch, scaled by what the
-# same counters read for a plain 256 MiB copy).  Valid only for the kernel sources they were
-# taken on: a different hash of those sources reports traffic as null.
-TRAFFIC = {"fetch_kib": 337715.09375, "write_kib": 448956.5625, "fetch_factor": 1.9998, "write_factor": 1.0,
+# same counters read for a plain 256 MiB copy).  Valid only for the kernel and plan sources they
+# were taken on (the plan sets the segments and strips): a different hash of those sources
+# reports traffic as null.
+TRAFFIC = {"fetch_kib": 340173.1953125, "write_kib": 439273.52734375, "fetch_factor": 1.9998, "write_factor": 1.0,
            "grid_scale": 1.0,
-           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp"],
-           "sha256": "030dbf54f3705d8526d0f5500d511eb620b19bd7d8cb4ec468d0d338755f1f35"}
+           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp", "api.cpp"],
+           "sha256": "18b4cc27cfbfb65426a22493b7a77a2dca1d7dd47a51618838312fa9eb0087ea"}
 
 
 def measured_traffic():
