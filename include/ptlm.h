@@ -82,11 +82,12 @@ typedef struct {
   int32_t precond;    /* 0: none, 1: Jacobi Dg(G + lambda D), 2: learned diagonal + lambda D,
                          3: exact diagonal of G + lambda D (one more transform per linearisation),
                          4: stochastic estimate of diag(G) + lambda D (stoch_samples inverse
-                         transforms per linearisation); 3 and 4 floored like D, single problems */
+                         transforms per linearisation); 3 and 4 floored like D */
   int32_t warm_start; /* 1: PCG starts from the last accepted step */
   int32_t surrogate_T;  /* App. E surrogate metric: outer iterations with sigma_t > 0 (0: off) */
   double surrogate_s0;  /* sigma_0; sigma_t = s0 * 1e-6^(t / (T - 1)) for t < T, then 0 */
-  int32_t project;      /* 1: alg:projected_LM plug-in after every accepted step (single problems) */
+  int32_t project;      /* 1: alg:projected_LM plug-in after every accepted step, decided on the
+                           device (projection, Armijo line search of at most ls_max sizes) */
   int32_t ls_max;       /* backtracking halvings of its line search before the iterate is kept */
   double o_max, p_max;  /* eq:constraints: |O| <= o_max (1), |P| <= p_max (1e8) */
   double sigma_ls;      /* eq:armijo_criterion constant (1e-4) */
@@ -138,6 +139,14 @@ typedef struct {
   int32_t acc_p;     /* internal: the last attempt accepted a step of the probe */
   int32_t tile_now;  /* internal: the current attempt evaluates the linearisation (0 when it
                         adopts the one computed at the accepted trial point) */
+  int32_t ls_dir;    /* internal, projected plug-in: the projected step is to be tested as a
+                        search direction */
+  int32_t ls_neg;    /* internal, projected plug-in: the search runs along -grad f instead */
+  int32_t ls_on;     /* internal, projected plug-in: the line search still runs */
+  int32_t ls_take;   /* internal, projected plug-in: the trial buffer becomes the iterate */
+  int32_t ls_keep;   /* internal, projected plug-in: no step size passed, z_t stays the iterate */
+  int32_t ls_proj;   /* internal, projected plug-in: candidates are projected (gradient branch) */
+  int32_t ls_iter;   /* internal, projected plug-in: step sizes tried */
 } ptlm_lm_state;
 
 typedef struct ptlm_handle ptlm_handle;
@@ -328,8 +337,7 @@ ptlm_handle* ptlm_batch_problem(ptlm_batch* b, int32_t i);
  * outer iterations, and reset the states (mu = mu0, t = 0).  use_graph = 1: attempts after
  * the first are replayed from one captured HIP graph.  With params->precond == 2 every
  * problem needs a registered network (ptlm_lm_set_cnn on its handle); with params->alternate
- * every problem must be PTLM_JOINT; params->project must be 0 (PTLM_EINVAL otherwise: the
- * projected plug-in's line search is driven from the host).  With params->precond 3 or 4 each
+ * every problem must be PTLM_JOINT.  With params->precond 3 or 4 each
  * problem's diagonal comes from its own launches of the single-problem kernels, in the same
  * attempt sequence (one tile launch, or one per draw, per problem).  Pointers must stay
  * valid until the next bind or ptlm_batch_destroy. */

@@ -62,7 +62,8 @@ _STATE_DOUBLES = ["f", "f_trial", "mu", "lambda_", "rho", "eta", "gnorm", "resid
                   "rz", "rr", "alpha", "beta_cg", "pap", "sigma", "ls_alpha", "mu_alt"]
 _STATE_INTS = ["t", "cg_iters", "cg_total", "accepted", "cg_active", "retries", "nonfinite", "products",
                "attempts", "need_lin", "lin_now", "use_warm", "alive", "prev_valid", "t_max", "status", "iter_done", "ls_branch",
-               "block", "acc_o", "acc_p", "tile_now"]
+               "block", "acc_o", "acc_p", "tile_now", "ls_dir", "ls_neg", "ls_on", "ls_take", "ls_keep", "ls_proj",
+               "ls_iter"]
 
 
 class ptlm_lm_state(ctypes.Structure):

@@ -32,7 +32,9 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-enum TileKind { TK_LIN = 0, TK_WARM = 1, TK_P = 2, TK_TRIAL = 3, TK_N = 4 };
+// TK_PJ / TK_LS: loss at the trial buffer for the projected plug-in (predicated on the
+// acceptance / on the running line search)
+enum TileKind { TK_LIN = 0, TK_WARM = 1, TK_P = 2, TK_TRIAL = 3, TK_PJ = 4, TK_LS = 5, TK_N = 6 };
 enum RedKind { RK_LIN = 0, RK_WARM = 1, RK_P = 2, RK_DIAG = 3, RK_N = 4 };
 
 // device table region of a batch (offsets from the start of the region)
@@ -41,7 +43,7 @@ struct TableLayout {
   size_t tile_jobs_off[16][TK_N];
   size_t jb_obj, jb_prb, jb_dprb, jb_vec, jb_copy_lin, jb_copy_acc;
   size_t red_obj[RK_N], red_prb[RK_N], red_sum;
-  size_t lm_jobs, copy_lin, copy_acc;
+  size_t lm_jobs, copy_lin, copy_acc, copy_take, copy_keep;
   size_t bytes;
 };
 
@@ -70,7 +72,7 @@ struct ptlm_batch {
   std::vector<std::vector<TileJob>> tile_jobs;  // [class * TK_N + kind]
   std::vector<RedJob> red_obj[RK_N], red_prb[RK_N], red_sum;
   std::vector<LMJob> lm_jobs;
-  std::vector<CopyJob> copy_lin, copy_acc;
+  std::vector<CopyJob> copy_lin, copy_acc, copy_take, copy_keep;  // take / keep: block table of copy_lin
   // binding
   bool bound = false;
   ptlm_lm_params prm{};
@@ -187,6 +189,14 @@ struct BatchOps {
     return reduce(which == GG_WARM ? RK_WARM : RK_P);
   }
   ptlm_status trial_loss() { return tiles(OP_LOSS, TK_TRIAL); }
+  ptlm_status trial_loss_if(int fl) { return tiles(OP_LOSS, fl == FL_ACCEPTED ? TK_PJ : TK_LS); }
+  ptlm_status copy_plugin() {
+    B_HIP(launch_copy_batch(b->dev<CopyJob>(b->L.copy_take), b->dev<int>(b->L.jb_copy_lin), b->nb_copy_lin, s),
+          "batch plug-in take");
+    B_HIP(launch_copy_batch(b->dev<CopyJob>(b->L.copy_keep), b->dev<int>(b->L.jb_copy_lin), b->nb_copy_lin, s),
+          "batch plug-in keep");
+    return PTLM_OK;
+  }
   ptlm_status trial_finish() { return PTLM_OK; }  // batched trials are losses only
   // the batch keeps one fixed launch sequence (graph capture): every PCG iteration is enqueued
   ptlm_status cg_mark(int) { return PTLM_OK; }
@@ -297,6 +307,8 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
   L.lm_jobs = take(n * sizeof(LMJob));
   L.copy_lin = take(2 * n * sizeof(CopyJob));
   L.copy_acc = take(4 * n * sizeof(CopyJob));
+  L.copy_take = take(2 * n * sizeof(CopyJob));
+  L.copy_keep = take(2 * n * sizeof(CopyJob));
   L.bytes = o;
   *total = b.tables_off + L.bytes;
   return PTLM_OK;
@@ -385,7 +397,6 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (T < 0) return fail(PTLM_EINVAL, "T must be >= 0");
-  if (params->project) return fail(PTLM_EINVAL, "the projected plug-in is not available in batches");
   for (int i = 0; i < b->n; ++i) {
     if (!d_O[i] || !d_P[i] || !d_y[i]) return fail(PTLM_EINVAL, "null array of problem " + std::to_string(i));
     if (params->precond == 2 && !b->hs[i]->cnn_params)
@@ -427,11 +438,11 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
           j.a.vO = v0;
           j.a.vP = g.joint ? v0 + a.nobj : nullptr;
           j.a.predicate = flags + (k == TK_WARM ? FL_WARM : FL_CG);
-        } else {
+        } else {  // TK_TRIAL, TK_PJ, TK_LS: loss at the trial buffer
           j.a.O = a.ztrial;
           j.a.P = g.joint ? a.ztrial + a.nobj : (const float2*)d_P[i];
           j.a.y = d_y[i];
-          j.a.predicate = flags + FL_ALIVE;
+          j.a.predicate = flags + (k == TK_TRIAL ? FL_ALIVE : (k == TK_PJ ? FL_ACCEPTED : FL_LS_ON));
           j.a.bg_add = &d_states[i].sigma;
         }
         v.push_back(j);
@@ -539,6 +550,25 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
       ++j;
     }
   }
+  // plug-in copies, on the blocks of the linearisation copies (same lengths, same order)
+  b->copy_take = b->copy_lin;
+  b->copy_keep = b->copy_lin;
+  for (int i = 0; i < n; ++i) {
+    ptlm_handle* h = b->hs[i];
+    const LMArgs& a = b->lm_jobs[i].a;
+    int* flags = reinterpret_cast<int*>(d_states + i);
+    CopyJob* t = &b->copy_take[2 * i];
+    CopyJob* k = &b->copy_keep[2 * i];
+    t[0].pred = t[1].pred = flags + FL_LS_TAKE;
+    k[0].pred = k[1].pred = flags + FL_LS_KEEP;
+    t[0].src = a.ztrial;
+    t[1].src = a.ztrial + a.nobj;
+    k[0].src = h->g.O_lin;
+    k[1].src = h->g.P_lin;
+    t[0].dst = k[0].dst = (float2*)d_O[i];
+    t[1].dst = k[1].dst = (float2*)d_P[i];
+    if (!h->g.joint) t[1].n = k[1].n = 0;
+  }
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return bytes ? hipMemcpyAsync(b->ws + b->tables_off + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
   };
@@ -556,6 +586,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   if (e == hipSuccess) e = up(b->L.lm_jobs, b->lm_jobs.data(), n * sizeof(LMJob));
   if (e == hipSuccess) e = up(b->L.copy_lin, b->copy_lin.data(), b->copy_lin.size() * sizeof(CopyJob));
   if (e == hipSuccess) e = up(b->L.copy_acc, b->copy_acc.data(), b->copy_acc.size() * sizeof(CopyJob));
+  if (e == hipSuccess) e = up(b->L.copy_take, b->copy_take.data(), b->copy_take.size() * sizeof(CopyJob));
+  if (e == hipSuccess) e = up(b->L.copy_keep, b->copy_keep.data(), b->copy_keep.size() * sizeof(CopyJob));
   if (e != hipSuccess) return hip_fail(e, "batch bind upload");
   // learned preconditioner: each network's output from the bound probe (once per reconstruction)
   if (params->precond == 2) {

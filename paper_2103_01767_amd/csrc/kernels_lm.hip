@@ -180,8 +180,9 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       float2 c = z;
       if (i >= act.lo && i < act.hi) {
         const float2 d = a.r[i];
-        c = make_float2(fmaf(a.ls_alpha, d.x, z.x), fmaf(a.ls_alpha, d.y, z.y));
-        if (a.ls_proj) c = project_entry(a, i, c);
+        const float al = (float)a.st->ls_alpha;
+        c = make_float2(fmaf(al, d.x, z.x), fmaf(al, d.y, z.y));
+        if (a.st->ls_proj) c = project_entry(a, i, c);
       }
       a.ztrial[i] = c;
     } else if constexpr (OP == V_XMAX) {
@@ -373,6 +374,11 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.acc_o = 0;
     st.acc_p = 0;
     st.use_warm = 0;
+    st.ls_dir = 0;
+    st.ls_neg = 0;
+    st.ls_on = 0;
+    st.ls_take = 0;
+    st.ls_keep = 0;
   } else if constexpr (OP == F_LIN) {
     // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM
     st.f = a.scal[SC_F];
@@ -395,9 +401,54 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     a.scal[SC_XMAX_P] = s1;
   } else if constexpr (OP == F_ADOPT) {
     if (st.lin_now && s0 != 0.0) st.tile_now = 1;  // the iterate is not the kept point
-  } else if constexpr (OP == F_LS) {
-    a.scal[SC_LS0] = s0;
-    a.scal[SC_LS1] = s1;
+  } else if constexpr (OP == F_PJ_CHECK) {
+    // alg:projected_LM after an accepted step Delta from z_t: the projected point
+    // Pi(z_t + Delta) (in the trial buffer, its loss reduced here) is taken when it cuts f
+    // below gamma f(z_t); otherwise the projected step is tried as a search direction
+    st.ls_iter = 0;
+    st.ls_alpha = 1.0;
+    if (s0 < p.gamma * st.f) {
+      st.ls_take = 1;
+      st.ls_branch = 0;
+    } else {
+      st.ls_dir = 1;
+    }
+  } else if constexpr (OP == F_LS_DIR) {
+    // s = Pi(z_t + Delta) - z_t: line search along s when it is a sufficient descent
+    // direction, g.s <= -tau_s ||s||^p_s; else along -grad f with projected candidates
+    st.ls_dir = 0;
+    if (s0 <= -p.tau_s * pow(sqrt(s1), p.p_s)) {
+      st.ls_branch = 1;
+      st.ls_proj = 0;
+      a.scal[SC_LS1] = s1;
+      st.ls_on = p.ls_max > 0 ? 1 : 0;
+      st.ls_keep = p.ls_max > 0 ? 0 : 1;
+    } else {
+      st.ls_branch = 2;
+      st.ls_proj = 1;
+      st.ls_neg = 1;
+    }
+  } else if constexpr (OP == F_LS_NEG) {
+    st.ls_neg = 0;
+    a.scal[SC_LS1] = s1;  // ||grad f||^2
+    st.ls_on = p.ls_max > 0 ? 1 : 0;
+    st.ls_keep = p.ls_max > 0 ? 0 : 1;
+  } else if constexpr (OP == F_LS_TEST) {
+    // eq:armijo_criterion at the candidate in the trial buffer (its loss reduced here);
+    // the step size halves until it passes or ls_max sizes were tried (then z_t is kept)
+    if (s0 <= st.f - p.sigma_ls * st.ls_alpha * a.scal[SC_LS1]) {
+      st.ls_on = 0;
+      st.ls_take = 1;
+    } else {
+      st.ls_alpha *= 0.5;
+      st.ls_iter += 1;
+      if (st.ls_iter >= p.ls_max) {
+        st.ls_on = 0;
+        st.ls_keep = 1;
+        st.ls_alpha = 0.0;
+        st.ls_branch = -1;
+      }
+    }
   } else if constexpr (OP == F_BEGIN) {
     // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
     // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).  The first attempt
@@ -516,7 +567,7 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
   X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME)
 #define PTLM_FIN_CASES(X)                                                                                 \
   X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \
-  X(F_INIT) X(F_LS) X(F_ADOPT)
+  X(F_INIT) X(F_ADOPT) X(F_PJ_CHECK) X(F_LS_DIR) X(F_LS_NEG) X(F_LS_TEST)
 
 hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s, int iter) {
   switch (op) {

@@ -205,6 +205,27 @@ struct SingleOps {
     *go = __atomic_load_n(a.cg_flags + (i - 1), __ATOMIC_ACQUIRE) != 0;
     return PTLM_OK;
   }
+  ptlm_status trial_loss_if(int fl) {
+    TileArgs ta{};
+    ta.O = a.ztrial;
+    ta.P = h->g.joint ? a.ztrial + a.nobj : P;
+    ta.y = y;
+    ta.predicate = flag(fl);
+    ta.bg_add = &a.st->sigma;
+    LM_HIP(launch_tile(h->g, OP_LOSS, ta, s), "lm plug-in loss");
+    return PTLM_OK;
+  }
+  ptlm_status copy_plugin() {
+    Geometry& g = h->g;
+    const size_t M = (size_t)g.my * g.mx;
+    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_LS_TAKE), s), "lm plug-in O");
+    LM_HIP(launch_copy(g.O_lin, O, a.nobj, flag(FL_LS_KEEP), s), "lm plug-in keep O");
+    if (g.joint) {
+      LM_HIP(launch_copy(a.ztrial + a.nobj, P, M, flag(FL_LS_TAKE), s), "lm plug-in P");
+      LM_HIP(launch_copy(g.P_lin, P, M, flag(FL_LS_KEEP), s), "lm plug-in keep P");
+    }
+    return PTLM_OK;
+  }
   ptlm_status copy_accept() {
     // the accepted step's blocks (both, or the active one of the alternating update)
     Geometry& g = h->g;
@@ -222,89 +243,6 @@ struct SingleOps {
 static ptlm_status read_state(ptlm_lm_state* d, ptlm_lm_state* hs, hipStream_t s) {
   LM_HIP(hipMemcpyAsync(hs, d, sizeof *hs, hipMemcpyDeviceToHost, s), "lm read state");
   LM_HIP(hipStreamSynchronize(s), "lm sync");
-  return PTLM_OK;
-}
-
-static ptlm_status read_scal(const double* d, double* out, int count, hipStream_t s) {
-  LM_HIP(hipMemcpyAsync(out, d, count * sizeof(double), hipMemcpyDeviceToHost, s), "lm read scalars");
-  LM_HIP(hipStreamSynchronize(s), "lm sync");
-  return PTLM_OK;
-}
-
-// loss at the trial buffer (surrogate term included) into scal[SC_LSF], read back
-static ptlm_status trial_value(SingleOps& o, double* f) {
-  TileArgs ta{};
-  ta.O = o.a.ztrial;
-  ta.P = o.h->g.joint ? o.a.ztrial + o.a.nobj : o.P;
-  ta.y = o.y;
-  ta.bg_add = &o.a.st->sigma;
-  LM_HIP(launch_tile(o.h->g, OP_LOSS, ta, o.s), "projected loss");
-  LM_HIP(launch_sum_partials(o.h->g.partials, o.h->g.grid, o.a.scal + SC_LSF, 1, o.s), "projected loss sum");
-  return read_scal(o.a.scal + SC_LSF, f, 1, o.s);
-}
-
-// copy the trial buffer (or, with keep, the linearisation point) into the iterate
-static ptlm_status set_iterate(SingleOps& o, bool keep) {
-  const Geometry& g = o.h->g;
-  const float2* srcO = keep ? g.O_lin : o.a.ztrial;
-  const float2* srcP = keep ? g.P_lin : o.a.ztrial + o.a.nobj;
-  LM_HIP(launch_copy(srcO, o.O, o.a.nobj, nullptr, o.s), "projected iterate O");
-  if (g.joint) LM_HIP(launch_copy(srcP, o.P, (size_t)g.my * g.mx, nullptr, o.s), "projected iterate P");
-  return PTLM_OK;
-}
-
-// alg:projected_LM after an accepted step Delta from z_t (O_lin, P_lin), the trial buffer
-// holding z_t + Delta: accept Pi(z_t + Delta) if it cuts f below gamma f(z_t); otherwise a
-// halving Armijo line search (eq:armijo_criterion) along s = Pi(z_t + Delta) - z_t when s is a
-// sufficient descent direction, else along -grad f with projection; no passing step size
-// keeps z_t.  The outcome is written to the state (ls_branch, ls_alpha).
-static ptlm_status projected_plugin(SingleOps& o, const ptlm_lm_params& prm, double f_t) {
-  LMArgs& a = o.a;
-  double fc = 0.0, alpha = 1.0;
-  int branch = 0;
-  bool done = false;
-  LM_HIP(launch_vec(V_PROJ, a, FL_NONE, o.s), "projection");
-  PTLM_TRY(trial_value(o, &fc));
-  if (fc < prm.gamma * f_t) {
-    PTLM_TRY(set_iterate(o, false));
-    done = true;
-  } else {
-    double gs[2];
-    LM_HIP(launch_vec(V_LS_DIR, a, FL_NONE, o.s), "line-search direction");
-    LM_HIP(launch_fin(F_LS, a, a.vec_blocks, FL_NONE, o.s), "line-search direction sums");
-    PTLM_TRY(read_scal(a.scal + SC_LS0, gs, 2, o.s));
-    branch = 1;
-    a.ls_proj = 0;
-    if (!(gs[0] <= -prm.tau_s * std::pow(std::sqrt(gs[1]), prm.p_s))) {
-      branch = 2;
-      a.ls_proj = 1;
-      LM_HIP(launch_vec(V_LS_NEG, a, FL_NONE, o.s), "line-search gradient");
-      LM_HIP(launch_fin(F_LS, a, a.vec_blocks, FL_NONE, o.s), "line-search gradient sums");
-      PTLM_TRY(read_scal(a.scal + SC_LS0, gs, 2, o.s));
-    }
-    const double dn2 = gs[1];
-    for (int i = 0; i < prm.ls_max && !done; ++i) {
-      a.ls_alpha = (float)alpha;
-      LM_HIP(launch_vec(V_LS_CAND, a, FL_NONE, o.s), "line-search candidate");
-      double fn = 0.0;
-      PTLM_TRY(trial_value(o, &fn));
-      if (fn <= f_t - prm.sigma_ls * alpha * dn2) {
-        PTLM_TRY(set_iterate(o, false));
-        done = true;
-      } else {
-        alpha *= 0.5;
-      }
-    }
-  }
-  if (!done) {
-    PTLM_TRY(set_iterate(o, true));
-    alpha = 0.0;
-  }
-  // record the outcome in the device state (the stream is synchronised before return)
-  struct { double alpha; int branch; } rec{alpha, done ? branch : -1};
-  LM_HIP(hipMemcpyAsync(&a.st->ls_alpha, &rec.alpha, sizeof(double), hipMemcpyHostToDevice, o.s), "ls record");
-  LM_HIP(hipMemcpyAsync(&a.st->ls_branch, &rec.branch, sizeof(int), hipMemcpyHostToDevice, o.s), "ls record");
-  LM_HIP(hipStreamSynchronize(o.s), "ls sync");
   return PTLM_OK;
 }
 
@@ -352,8 +290,6 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
       ended = hs.iter_done != 0;
     }
     if (!ended) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");
-    // the plug-in runs on the block of the sub-step just ended (the state still names it)
-    if (prm->project && hs.accepted) PTLM_TRY(projected_plugin(o, *prm, hs.f));
     rejected = rejected || hs.status == PTLM_ENOTACCEPTED;
   }
   if (hs.t != t0 + 1) return fail(PTLM_EHIP, "LM attempt sequence did not end the outer iteration");

@@ -20,7 +20,8 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
 
 // Ops provides: fin(op, count_kind, flag), vec(op, flag), copy_lin(), linearize(),
 // diag_paper(), learned(), exact_diag(), stoch_diag(), ggnv(which), trial_loss(), trial_finish(),
-// copy_accept(),
+// copy_accept(), trial_loss_if(flag) (loss at the trial buffer, predicated on a state flag),
+// copy_plugin() (the iterate from the trial buffer or from z_t, by the plug-in's outcome),
 // cg_mark(j) (after the launch that decides whether PCG iteration j runs) and
 // cg_gate(i, &go) (before PCG iteration i is enqueued; go = false ends the enqueueing, every
 // later iteration being predicated off anyway).
@@ -74,6 +75,22 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.fin(F_TRIAL_END, 2, FL_ALIVE));
   PTLM_TRY(o.trial_finish());  // gradient and sums of a trial evaluated as a linearisation
   PTLM_TRY(o.copy_accept());
+  // ---- alg:projected_LM plug-in after an accepted step, decided on the device
+  if (prm.project) {
+    PTLM_TRY(o.vec(V_PROJ, FL_ACCEPTED));  // trial buffer <- Pi(z_t + Delta)
+    PTLM_TRY(o.trial_loss_if(FL_ACCEPTED));
+    PTLM_TRY(o.fin(F_PJ_CHECK, 2, FL_ACCEPTED));
+    PTLM_TRY(o.vec(V_LS_DIR, FL_LS_DIR));  // s = Pi(z_t + Delta) - z_t, g.s, ||s||^2
+    PTLM_TRY(o.fin(F_LS_DIR, 1, FL_LS_DIR));
+    PTLM_TRY(o.vec(V_LS_NEG, FL_LS_NEG));  // s = -grad f
+    PTLM_TRY(o.fin(F_LS_NEG, 1, FL_LS_NEG));
+    for (int i = 0; i < prm.ls_max; ++i) {
+      PTLM_TRY(o.vec(V_LS_CAND, FL_LS_ON));  // trial buffer <- z_t + alpha s (projected)
+      PTLM_TRY(o.trial_loss_if(FL_LS_ON));
+      PTLM_TRY(o.fin(F_LS_TEST, 2, FL_LS_ON));
+    }
+    PTLM_TRY(o.copy_plugin());
+  }
   return PTLM_OK;
 }
 

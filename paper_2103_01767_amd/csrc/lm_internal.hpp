@@ -16,11 +16,12 @@ inline int lm_vec_blocks(size_t n) {
 
 // indices into the FP64 scalar scratch
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_XMAX_O = 5, SC_XMAX_P = 6,
-       SC_LS0 = 12, SC_LS1 = 13, SC_LSF = 14, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
+       SC_LS1 = 13, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
                    V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME };
-enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_LS, F_ADOPT };
+enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_ADOPT,
+                   F_PJ_CHECK, F_LS_DIR, F_LS_NEG, F_LS_TEST };
 
 // Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
 enum LMFlag : int {
@@ -33,6 +34,11 @@ enum LMFlag : int {
   FL_ACC_O = (int)(offsetof(ptlm_lm_state, acc_o) / 4),
   FL_ACC_P = (int)(offsetof(ptlm_lm_state, acc_p) / 4),
   FL_TILE = (int)(offsetof(ptlm_lm_state, tile_now) / 4),
+  FL_LS_DIR = (int)(offsetof(ptlm_lm_state, ls_dir) / 4),
+  FL_LS_NEG = (int)(offsetof(ptlm_lm_state, ls_neg) / 4),
+  FL_LS_ON = (int)(offsetof(ptlm_lm_state, ls_on) / 4),
+  FL_LS_TAKE = (int)(offsetof(ptlm_lm_state, ls_take) / 4),
+  FL_LS_KEEP = (int)(offsetof(ptlm_lm_state, ls_keep) / 4),
 };
 
 struct LMArgs {
@@ -42,8 +48,6 @@ struct LMArgs {
   float2* xdiag;           // exact / estimated diagonal buffer (precond 3, 4; floored in place)
   const float2 *O, *P;     // current iterate
   const float2 *Olin, *Plin;  // linearisation point z_t (projected plug-in)
-  float ls_alpha;          // line-search step size (V_LS_CAND)
-  int ls_proj;             // 1: project the line-search candidate
   size_t n, nobj;          // complex entries of a vector / of its object part
   size_t nprobe;           // complex entries of the probe
   ptlm_lm_state* st;

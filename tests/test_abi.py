@@ -104,3 +104,37 @@ def test_batch_workspace_validation():
     assert pt.lib().ptlm_batch_workspace_bytes(2, descs, ptrs, ctypes.byref(n)) == pt.PTLM_EINVAL
     assert b"problem 1" in pt.lib().ptlm_last_error()
     assert pt.lib().ptlm_batch_workspace_bytes(0, descs, ptrs, ctypes.byref(n)) == pt.PTLM_EINVAL
+
+
+def test_struct_mirrors_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have its sizes and field offsets (the library
+    writes the LM state in place, so a shorter or shifted mirror would be overrun or misread)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ptlm_desc": pt.ptlm_desc, "ptlm_lm_params": pt.ptlm_lm_params, "ptlm_lm_state": pt.ptlm_lm_state,
+               "ptlm_cnn_desc": pt.ptlm_cnn_desc}
+    lines = []
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            cfield = "lambda" if fname == "lambda_" else fname
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, cfield))
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ptlm.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for ln in out:
+        if not ln:
+            continue
+        cname, field, val = ln.split()
+        py = mirrors[cname]
+        want = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(val) == want, (cname, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in mirrors.values())

@@ -281,3 +281,35 @@ def test_batch_exact_and_stochastic_diagonal_equal_alone(precond):
         assert s2.t == T and s1.t == T
         assert s2.f == s1.f and s2.products == s1.products and s2.attempts == s1.attempts
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
+@pytest.mark.parametrize("gamma", [1e-6, 0.0])
+def test_batch_projected_equals_alone(gamma):
+    """alg:projected_LM in a batch: the plug-in (projection, Armijo line search, choice of the
+    iterate) is decided on the device per problem, so the batch equals its problems alone,
+    and every object stays in |O| <= 1.  gamma = 0 sends every accepted step through the
+    line search."""
+    print("case batch projected gamma", gamma, flush=True)
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=1, cg_max=6, project=1, gamma=gamma)
+    T = 4
+    alone = [run_single(p, params, T) for p in probs]
+    batch = pt.Batch(probs, device=DEV)
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(200, check_every=2)
+    torch.cuda.synchronize()
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        print("problem %d: f %.6e / %.6e branch %d / %d alpha %g / %g" % (i, s1.f, s2.f, s1.ls_branch, s2.ls_branch,
+                                                                          s1.ls_alpha, s2.ls_alpha))
+        assert s2.t == T and s1.t == T
+        assert s2.f == s1.f and s2.products == s1.products and s2.ls_branch == s1.ls_branch
+        assert s2.ls_alpha == s1.ls_alpha
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+        assert float(torch.abs(Os[i]).max()) <= 1.0 + 1e-6
+        if gamma == 0.0:
+            assert s2.ls_branch != 0
