@@ -3,7 +3,8 @@
 * 512x512 object / 128x128 probe / 1600 positions (joint): the FP64 oracle still finishes
   the whole problem in seconds, so forward, loss, gradient and the GGN-vector product
   are compared element by element over every output (relative L2, bar 1e-5).  Data:
-  the stored oracle-generated Poisson counts of the workload.
+  the stored oracle-generated Poisson counts of the workload.  The LM run of the benchmark
+  is compared with the oracle's stored LM run (final loss, bar 1.01x).
 * 2048x2048 object / 256x256 probe / 10 000 positions (joint): the oracle cannot run
   the whole problem in a test, so it computes sampled outputs one by one -- magnitudes,
   residuals and JVP rows of sampled positions, and the gradient and GGN-vector product
@@ -82,6 +83,34 @@ def test_c1_full_elementwise():
     dOg, dPg = prob.diag(exact=False)
     aO, aP = ptycho.ggn_diag_paper(lin)
     assert rel(host(dOg), aO) < TOL and rel(host(dPg), aP) < TOL
+
+
+def test_c1_lm_final_loss_matches_oracle():
+    """The benchmark's LM (D = Dg(G), Jacobi PCG, cg_max 10) on the full 512/128 workload, from
+    its initial guess and stored counts: after the oracle's number of outer iterations the
+    loss is within 1.01x of the FP64 oracle's LM (stored by tests/golden/make_golden.py), and
+    it never increases."""
+    import json
+    print("case c1 lm", flush=True)
+    ref = json.load(open(os.path.join(GOLD, "c1_oracle_lm.json")))
+    pr = synth.make_c1()
+    y = dev(np.load(os.path.join(GOLD, "c1_counts.npz"))["y"].astype(np.float32))
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, metric="gauss", mode="joint",
+                      background=pr.background, device=DEV)
+    O, P = dev(c64(pr.O_init)), dev(c64(pr.P_init))
+    params = pt.default_params(scaling=1, precond=1, cg_max=10)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    fs = []
+    for _ in range(ref["T"]):
+        prob.lm_step(O, P, y, params, st)
+        fs.append(float(prob.loss(O, P, y).cpu()[0]))
+    s = pt.state_from_tensor(st)
+    print("c1 lm: gpu f=%.6e after %d iterations (%d products), oracle f=%.6e (%d CG iterations)"
+          % (fs[-1], s.t, s.products, ref["f_final"], ref["cg_total"]))
+    assert s.t == ref["T"]
+    assert all(fs[i + 1] <= fs[i] * (1 + 1e-6) for i in range(len(fs) - 1))
+    assert fs[-1] <= 1.01 * ref["f_final"]
 
 
 @pytest.fixture(scope="module")
