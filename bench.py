@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--only-large-scan", action="store_true",
                     help="only time the large-scan GGN-vector product (one JSON line; for profiling)")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--large-lm-iters", type=int, default=3,
+                    help="timed LM outer iterations on the large scan (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -111,7 +113,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.only_large_scan:
-        print(json.dumps(large_scan(dev, args.calls)), flush=True)
+        print(json.dumps(large_scan(dev, args.calls, args.large_lm_iters)), flush=True)
         return
     pr = synth.make_c1()
     K = pr.K
@@ -155,7 +157,7 @@ def main():
     kern_ms, call_ms, red_ms = iso["kernel_ms"], iso["call_ms"], iso["reduce_ms"]
     kern_bytes, achieved_gbs, fft_tflops = iso["bytes_per_launch"], iso["achieved_gbs"], iso["fft_tflops"]
     vO, vP = iso["vO"], iso["vP"]
-    large = None if args.no_c4 else large_scan(dev, max(3, args.calls // 10))
+    large = None if args.no_c4 else large_scan(dev, max(3, args.calls // 10), args.large_lm_iters)
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
     nxt = None if args.no_next else lm_variants(pr, dev, args.lm_iters, args.poisson_iters)
@@ -240,7 +242,7 @@ def ggnv_isolated(prob, dev, calls, stream):
             "positions_per_s": K / (call_ms * 1e-3), "vO": vO, "vP": vP}
 
 
-def large_scan(dev, calls):
+def large_scan(dev, calls, lm_iters=0):
     """GGN-vector product on the large scan: 2048x2048 object, 256x256 probe, 100x100 raster
     (10 000 positions), linearised at the initial guess with seeded stand-in counts of the
     workload's size and photon budget (the product's cost does not depend on the data)."""
@@ -260,8 +262,54 @@ def large_scan(dev, calls):
            "call_ms": round(iso["call_ms"], 4), "positions_per_s": round(iso["positions_per_s"], 1),
            "bytes_per_launch": iso["bytes_per_launch"], "achieved_gbs": round(iso["achieved_gbs"], 1),
            "hbm_frac": round(iso["achieved_gbs"] / HBM_PEAK_GBS, 4), "fft_tflops": round(iso["fft_tflops"], 2)}
-    del prob, y
+    del y
+    if lm_iters > 0:
+        out["lm"] = large_scan_lm(prob, pr, dev, lm_iters)
+    del prob
     torch.cuda.empty_cache()
+    return out
+
+
+def large_scan_lm(prob, pr, dev, iters):
+    """Outer LM iterations on the large scan (D = Dg(G), at most 10 PCG products per solve),
+    with the App. B Jacobi and with the learned preconditioner (network re-run at every
+    linearisation).  Data: Poisson draws (seeded) of the forward model at the true object and
+    probe, about 1e3 photons per pattern.  One untimed iteration first, then `iters` timed ones;
+    the reported rate is scan positions through GGN-vector products per second."""
+    import torch
+    import paper_2103_01767_amd as pt
+    from paper_2103_01767_amd import learned
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    z = prob.forward(c64(pr.O_true), c64(pr.P_true))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1004005)
+    y = torch.poisson((z.double() ** 2).float(), generator=gen).contiguous()
+    del z
+    net = learned.lm_net(learned.load(dev), pr.O_true.shape, dev)
+    out = {"data": "Poisson draws of the forward model at the true object and probe", "timed_iters": iters}
+    for name, prec in (("jacobi", 1), ("learned", 2)):
+        pt.lm_set_cnn(prob, net if prec == 2 else None)
+        params = pt.default_params(scaling=1, precond=prec, cg_max=10)
+        O, P = c64(pr.O_init), c64(pr.P_init)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        f0 = float(prob.loss(O, P, y).cpu()[0])
+        prob.lm_step(O, P, y, params, st)
+        torch.cuda.synchronize()
+        s0 = pt.state_from_tensor(st)
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            prob.lm_step(O, P, y, params, st)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s1 = pt.state_from_tensor(st)
+        prods = s1.products - s0.products
+        out[name] = {"ms_per_iteration": round(el / max(iters, 1) * 1e3, 2),
+                     "products_per_iteration": round(prods / max(iters, 1), 2),
+                     "ggnv_positions_per_s": round(pr.K * prods / el, 1) if el > 0 else None,
+                     "f_start": f0, "f_end": float(prob.loss(O, P, y).cpu()[0])}
+    pt.lm_set_cnn(prob, None)
+    del y
     return out
 
 
