@@ -219,24 +219,26 @@ def test_lm_variants_match_oracle_final_loss(variant):
         assert s.sigma == 0.0   # after T_s iterations the metric is the true Poisson one
 
 
-@pytest.mark.parametrize("gamma", [1e-6, 0.0])
-def test_projected_lm_matches_oracle(gamma):
+@pytest.mark.parametrize("mode,gamma", [("joint", 1e-6), ("joint", 0.0), ("object", 0.0)])
+def test_projected_lm_matches_oracle(mode, gamma):
     """alg:projected_LM (|O| <= 1): feasible iterates, same plug-in branch and step size as the
     oracle on the first iteration, final loss within 1.01x of the oracle's.  gamma = 0 never
     takes the projected point, so every accepted step goes through the line search."""
-    print("case projected lm gamma", gamma, flush=True)
-    pr = synth.make_small(6, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    print("case projected lm", mode, "gamma", gamma, flush=True)
+    joint = mode == "joint"
+    pr = synth.make_small(6, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode=mode)
     rng = np.random.default_rng(6)
     O_true = pr.O_true / np.abs(pr.O_true).max()
     y = synth.poisson_counts(rng, ptycho.intensity(O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
     T = 8
-    ref = solver.lm_solve(pr.O_init, pr.P_init, pr.pos, y.astype(np.float64), pr.background, "gauss", True,
+    P0 = pr.P_init if joint else pr.P_true
+    ref = solver.lm_solve(pr.O_init, P0, pr.pos, y.astype(np.float64), pr.background, "gauss", joint,
                           solver.LMParams(scaling=1, precond=1, project=True, gamma=gamma), T)
     first = [h for h in ref.history if h.t == 0 and h.accepted][0]
     if gamma == 0.0:
         assert first.ls[0] != "lm"
-    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
-    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64), to_dev(y, np.float32)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode=mode, background=pr.background, device=DEV)
+    O, P, yd = to_dev(pr.O_init, np.complex64), to_dev(P0, np.complex64), to_dev(y, np.float32)
     params = pt.default_params(scaling=1, precond=1, project=1, gamma=gamma)
     st = prob.new_state()
     prob.lm_init(params, st)
