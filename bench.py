@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--calls", type=int, default=50, help="isolated GGN-vector product calls")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-calls", type=int, default=3)
+    ap.add_argument("--cpu-calls", type=int, default=12)
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
     ap.add_argument("--no-next", action="store_true",
