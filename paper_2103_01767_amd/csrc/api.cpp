@@ -521,12 +521,14 @@ ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, si
 
 }  // extern "C"
 
-// Pinned host slots and events of the PCG look-ahead (ptlm_lm_step), made once with the handle
-// so that no LM call allocates; solves with more than kCgSlots - 1 iterations enqueue all of them.
+// Pinned host slots and events of the PCG and line-search look-ahead (ptlm_lm_step), made once
+// with the handle so that no LM call allocates; solves with more than kCgSlots - 1 iterations
+// (line searches with more than kCgSlots step sizes) enqueue all of them.
 static ptlm_status cg_slots_create(ptlm_handle* h) {
   void* p = nullptr;
-  PTLM_HIP(hipHostMalloc(&p, (size_t)kCgSlots * sizeof(int), hipHostMallocCoherent), "pcg slots");
+  PTLM_HIP(hipHostMalloc(&p, (size_t)(2 * kCgSlots) * sizeof(int), hipHostMallocCoherent), "pcg slots");
   h->cg_flags = (int*)p;
+  h->ls_flags = h->cg_flags + kCgSlots;
   h->cg_slots = kCgSlots;
   for (int i = 0; i < kCgSlots; ++i) {
     hipEvent_t e;

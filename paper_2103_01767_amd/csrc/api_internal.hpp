@@ -49,6 +49,8 @@ struct ptlm_handle {
   // PCG look-ahead of ptlm_lm_step: pinned host slots the finalize kernels write the PCG
   // continuation flag to, and one event per slot
   int* cg_flags = nullptr;  // null for the handles of a batch: no look-ahead there
+  int* ls_flags = nullptr;  // the same for the projected plug-in's line search (second half of
+                            // the same pinned block; the events are shared)
   int cg_slots = 0;
   std::vector<hipEvent_t> cg_events;
   // Linearisation at the LM's trial point, computed into spare buffers and swapped in when the

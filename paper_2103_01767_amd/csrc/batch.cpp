@@ -204,6 +204,11 @@ struct BatchOps {
     *go = true;
     return PTLM_OK;
   }
+  ptlm_status ls_mark(int) { return PTLM_OK; }
+  ptlm_status ls_gate(int, bool* go) {
+    *go = true;
+    return PTLM_OK;
+  }
   ptlm_status copy_accept() {
     B_HIP(launch_copy_batch(b->dev<CopyJob>(b->L.copy_acc), b->dev<int>(b->L.jb_copy_acc), b->nb_copy_acc, s),
           "batch accept");

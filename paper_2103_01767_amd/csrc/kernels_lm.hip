@@ -436,6 +436,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   } else if constexpr (OP == F_LS_TEST) {
     // eq:armijo_criterion at the candidate in the trial buffer (its loss reduced here);
     // the step size halves until it passes or ls_max sizes were tried (then z_t is kept)
+    const int tried = st.ls_iter;
     if (s0 <= st.f - p.sigma_ls * st.ls_alpha * a.scal[SC_LS1]) {
       st.ls_on = 0;
       st.ls_take = 1;
@@ -449,6 +450,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
         st.ls_branch = -1;
       }
     }
+    if (a.ls_flags) __hip_atomic_store(a.ls_flags + tried, st.ls_on, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   } else if constexpr (OP == F_BEGIN) {
     // alg:lm_inexact: lambda = mu ||grad ell||^nu (D = I) or mu (D = Dg(G)); eta of
     // eq:lma_termination_eta read as min(beta, sqrt(||J^T grad ell||)).  The first attempt

@@ -226,6 +226,21 @@ struct SingleOps {
     }
     return PTLM_OK;
   }
+  // line-search look-ahead: step size i is enqueued once the test of size i - 2 is known (the
+  // GPU is then still busy with size i - 1), so at most two sizes past the end are launched,
+  // predicated off.  The PCG events are free again here (that solve is fully enqueued).
+  ptlm_status ls_mark(int i) {
+    if (!a.ls_flags) return PTLM_OK;
+    LM_HIP(hipEventRecord(h->cg_events[i], s), "lm line-search mark");
+    return PTLM_OK;
+  }
+  ptlm_status ls_gate(int i, bool* go) {
+    *go = true;
+    if (!a.ls_flags || i < 2) return PTLM_OK;
+    LM_HIP(hipEventSynchronize(h->cg_events[i - 2]), "lm line-search gate");
+    *go = __atomic_load_n(a.ls_flags + (i - 2), __ATOMIC_ACQUIRE) != 0;
+    return PTLM_OK;
+  }
   ptlm_status copy_accept() {
     // the accepted step's blocks (both, or the active one of the alternating update)
     Geometry& g = h->g;
@@ -260,6 +275,8 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
   // PCG look-ahead when the handle has slots for every iteration (else all are enqueued)
   const bool ahead = h->cg_flags && prm->cg_max + 1 <= h->cg_slots;
   o.a.cg_flags = ahead ? h->cg_flags : nullptr;
+  const bool ls_ahead = h->ls_flags && prm->project && prm->ls_max <= h->cg_slots;
+  o.a.ls_flags = ls_ahead ? h->ls_flags : nullptr;
   // trial points are evaluated as linearisations (kept for the next outer iteration when the
   // step is accepted) unless the projected plug-in may move the iterate off the trial point
   o.spec = !prm->project;
@@ -274,6 +291,8 @@ static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const floa
       // no kernel of an earlier attempt is in flight (its state was read back)
       if (ahead)
         for (int j = 0; j <= prm->cg_max; ++j) __atomic_store_n(h->cg_flags + j, 0, __ATOMIC_RELAXED);
+      if (ls_ahead)
+        for (int j = 0; j < prm->ls_max; ++j) __atomic_store_n(h->ls_flags + j, 0, __ATOMIC_RELAXED);
       PTLM_TRY(enqueue_attempt(o, *prm));
       PTLM_TRY(read_state(st, &hs, s));
       if (o.spec && hs.accepted) {

@@ -24,7 +24,8 @@ enum GgnWhich : int { GG_WARM = 0, GG_P = 1 };
 // copy_plugin() (the iterate from the trial buffer or from z_t, by the plug-in's outcome),
 // cg_mark(j) (after the launch that decides whether PCG iteration j runs) and
 // cg_gate(i, &go) (before PCG iteration i is enqueued; go = false ends the enqueueing, every
-// later iteration being predicated off anyway).
+// later iteration being predicated off anyway), and ls_mark(i) / ls_gate(i, &go), the same for
+// the step sizes of the projected plug-in's line search.
 // ggnv(GG_WARM) multiplies the last accepted step, or p when params.alternate is set.
 template <class Ops>
 ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
@@ -85,9 +86,13 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
     PTLM_TRY(o.vec(V_LS_NEG, FL_LS_NEG));  // s = -grad f
     PTLM_TRY(o.fin(F_LS_NEG, 1, FL_LS_NEG));
     for (int i = 0; i < prm.ls_max; ++i) {
+      bool go = true;
+      PTLM_TRY(o.ls_gate(i, &go));
+      if (!go) break;
       PTLM_TRY(o.vec(V_LS_CAND, FL_LS_ON));  // trial buffer <- z_t + alpha s (projected)
       PTLM_TRY(o.trial_loss_if(FL_LS_ON));
       PTLM_TRY(o.fin(F_LS_TEST, 2, FL_LS_ON));
+      PTLM_TRY(o.ls_mark(i));
     }
     PTLM_TRY(o.copy_plugin());
   }

@@ -58,6 +58,8 @@ struct LMArgs {
   int tile_grid;           // workgroups of the tile kernels (partials of the trial loss)
   int t_max;               // outer iterations to run (ptlm_lm_init / batch binding)
   int* cg_flags;           // nullable, pinned host memory: slot j <- whether PCG iteration j runs
+  int* ls_flags;           // nullable, pinned host memory: slot i <- whether the line search goes
+                           // on after step size i
   const float2* Pcur;      // the caller's probe (V_SAME, object-only problems)
   int adopt_ok;            // host: the linearisation buffers hold the one made at the last accepted
                            // trial point, unless O / P changed since (checked by V_SAME / F_ADOPT)
