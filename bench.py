@@ -41,8 +41,8 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # reports traffic as null.
 TRAFFIC = {"fetch_kib": 340173.1953125, "write_kib": 439273.52734375, "fetch_factor": 1.9998, "write_factor": 1.0,
            "grid_scale": 1.0,
-           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp", "api.cpp"],
-           "sha256": "18b4cc27cfbfb65426a22493b7a77a2dca1d7dd47a51618838312fa9eb0087ea"}
+           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp", "plan.cpp"],
+           "sha256": "4b487f3cacdb264b557154f81aa3081f2e28d3a1a410b5736b17c87a8518cd5a"}
 
 
 def measured_traffic():

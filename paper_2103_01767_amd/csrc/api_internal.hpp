@@ -74,6 +74,12 @@ extern thread_local std::string g_last_error;
 ptlm_status fail(ptlm_status st, const std::string& msg);
 ptlm_status hip_fail(hipError_t e, const char* where);
 ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double grid_scale = 1.0);
+// segment count scales the autotuner tries (the workspace holds the largest segment tables)
+constexpr int kNumGridScales = 3;
+extern const double kGridScales[kNumGridScales];
+// workgroups of the tile kernels at a grid scale; cut the positions into segments for them
+int plan_grid(const Plan& p, double scale);
+void segment(Plan& p, const int* h_pos, int grid);
 ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, const float* y, double* d_f,
                            float2* gO, float2* gP, hipStream_t s);
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
