@@ -301,7 +301,9 @@ ptlm_status ptlm_cnn_features(ptlm_handle* h, float* d_feat, void* stream);
  * the object part. */
 ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_precond, void* stream);
 /* Register a network for ptlm_lm_step with params->precond == 2: after every linearisation
- * the step recomputes features -> network -> learned diagonal.  d = NULL unregisters.  The
+ * the step recomputes features -> network -> learned diagonal (as ptlm_learned_precond, with
+ * the App. B diagonal floored at params->diag_floor of its block maximum, 1e-6 by default).
+ * d = NULL unregisters.  The
  * desc must be n = 1, h x w = the object shape, cin = 3, cout = 2; d_params and d_ws
  * (ptlm_cnn_workspace_bytes) stay owned by the caller and must outlive their use. */
 ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float* d_params, void* d_ws,

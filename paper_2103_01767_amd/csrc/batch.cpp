@@ -154,13 +154,8 @@ struct BatchOps {
   }
   ptlm_status learned() {
     // every problem's learned diagonal from its network output (computed at bind from the
-    // bound probe: once per reconstruction) and its current App. B diagonal; rebuilding it
-    // when the linearisation is unchanged reproduces the same diagonal
-    for (int i = 0; i < b->n; ++i) {
-      ptlm_handle* h = b->hs[i];
-      PTLM_TRY(cnn_apply(h, (float*)(h->ws + h->plan.off.learned), s));
-    }
-    return PTLM_OK;
+    // bound probe: once per reconstruction) and its new floored App. B diagonal
+    return vec(V_LEARNED, FL_LIN);
   }
   // exact diagonal / its stochastic estimate: each problem's own launches (the single-problem
   // kernels on its handle, predicated on its linearisation flag), so a batch equals its
@@ -468,7 +463,10 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
     const Geometry& g = h->g;
     LMArgs a = make_lm_args(h, params, d_states + i, (const float2*)d_O[i], (const float2*)d_P[i], nullptr);
     a.t_max = T;
-    if (params->precond == 2) a.learned = (const float2*)(h->ws + h->plan.off.learned);
+    if (params->precond == 2) {
+      a.learned = a.xdiag;
+      a.cnn_r = cnn_output(h);
+    }
     int* flags = reinterpret_cast<int*>(d_states + i);
     const size_t N = a.nobj, M = (size_t)g.my * g.mx;
     for (int k = 0; k < RK_N; ++k) {

@@ -232,19 +232,9 @@ ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s) {
   return PTLM_OK;
 }
 
-// learned diagonal into `out` (2n floats) from the kept r and the current linearisation
-ptlm_status cnn_apply(ptlm_handle* h, float* out, hipStream_t s) {
+// the kept network output r (2 maps of the object grid) of the handle's registered network
+const float* cnn_output(const ptlm_handle* h) {
   const CnnLayout L = layout(h->cnn);
-  const float* r = (const float*)(h->cnn_ws + L.r);
-  double* scal = (double*)(h->ws + h->plan.off.scal) + 8;
-  CNN_HIP(launch_learned_diag(h->g, out, r, scal + 2, 1e-6f, s), "lm learned diag");
-  return PTLM_OK;
-}
-
-// features -> network -> learned diagonal into `out`, at the current linearisation
-ptlm_status learned_from_cnn(ptlm_handle* h, float* out, hipStream_t s) {
-  const ptlm_status st = cnn_refresh(h, s);
-  if (st != PTLM_OK) return st;
-  return cnn_apply(h, out, s);
+  return (const float*)(h->cnn_ws + L.r);
 }
 }  // namespace ptlm

@@ -147,6 +147,15 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float2 z = i < a.nobj ? a.O[i] : a.P[i - a.nobj];
       const float2 t = a.ztrial[i];
       acc0 += (z.x != t.x || z.y != t.y) ? 1.0 : 0.0;
+    } else if constexpr (OP == V_LEARNED) {
+      // learned diagonal: the floored App. B diagonal, times exp(clamp(r)) per real coordinate
+      // on the object part
+      float2 d = a.diag[i];
+      if (i < a.nobj) {
+        d.x *= expf(fminf(fmaxf(a.cnn_r[i], -8.f), 8.f));
+        d.y *= expf(fminf(fmaxf(a.cnn_r[a.nobj + i], -8.f), 8.f));
+      }
+      a.xdiag[i] = d;
     } else if constexpr (OP == V_WARM_P) {  // the warm-start vector restricted to the active block
       const bool in = i >= act.lo && i < act.hi;
       a.p[i] = in ? a.prev[i] : make_float2(0.f, 0.f);
@@ -566,7 +575,7 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 
 #define PTLM_VEC_CASES(X)                                                                                 \
   X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
-  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME)
+  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME) X(V_LEARNED)
 #define PTLM_FIN_CASES(X)                                                                                 \
   X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \
   X(F_INIT) X(F_ADOPT) X(F_PJ_CHECK) X(F_LS_DIR) X(F_LS_NEG) X(F_LS_TEST)

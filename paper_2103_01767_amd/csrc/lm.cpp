@@ -133,16 +133,17 @@ struct SingleOps {
   }
   ptlm_status learned() {
     if (h->cnn_params) {
-      float2* lbuf = (float2*)(h->ws + h->plan.off.learned);
       if (lin_expected) {
-        // the network runs every cnn_every-th linearisation (0: only the first); the learned
-        // diagonal is rebuilt from its output and the new App. B diagonal every time
+        // the network runs every cnn_every-th linearisation (0: only the first)
         const bool due = h->cnn_every > 0 ? (h->cnn_count % h->cnn_every == 0) : !h->cnn_ready;
         h->cnn_count += 1;
         if (due || !h->cnn_ready) PTLM_TRY(cnn_refresh(h, s));
-        PTLM_TRY(cnn_apply(h, (float*)lbuf, s));
       }
-      a.learned = lbuf;
+      // the learned diagonal is rebuilt from the kept output and the new floored App. B
+      // diagonal at every linearisation
+      a.cnn_r = cnn_output(h);
+      LM_HIP(launch_vec(V_LEARNED, a, FL_LIN, s), "lm learned diagonal");
+      a.learned = a.xdiag;
     } else {
       a.learned = (const float2*)user_learned;
     }

@@ -2,8 +2,9 @@
 // driver (direct launches with one problem's arguments) and the batched driver (one launch
 // per step for every problem of a batch, from job tables in device memory).  Every launch is
 // predicated on a flag of the device LM state, so the same sequence serves the first attempt
-// of an outer iteration (which linearises) and its retries (which reuse the linearisation,
-// reading C4), and the host never has to look at the state in between.
+// of an outer iteration (which linearises) and its retries (which reuse the linearisation of
+// z_t, since a rejected step leaves z_t unchanged), and the host never has to look at the
+// state in between.
 #pragma once
 #include "lm_internal.hpp"
 
@@ -35,8 +36,8 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   PTLM_TRY(o.linearize());  // f, ||grad_zeta ell||^2, g, phasor field, traces
   PTLM_TRY(o.vec(V_GNORM, FL_LIN));
   PTLM_TRY(o.fin(F_LIN, 1, FL_LIN));
-  if (prm.scaling == 1 || prm.precond == 1) {
-    PTLM_TRY(o.diag_paper());  // App. B diagonal, then the floor of C17
+  if (prm.scaling == 1 || prm.precond == 1 || prm.precond == 2) {
+    PTLM_TRY(o.diag_paper());  // App. B diagonal, then its floor (diag_floor x block maximum)
     PTLM_TRY(o.vec(V_DIAGMAX, FL_LIN));
     PTLM_TRY(o.fin(F_DIAGMAX, 1, FL_LIN));
     PTLM_TRY(o.vec(V_DIAGFLOOR, FL_LIN));

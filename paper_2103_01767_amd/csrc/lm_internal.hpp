@@ -19,7 +19,7 @@ enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_XMAX_O = 5, SC_XM
        SC_LS1 = 13, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
 enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
-                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME };
+                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME, V_LEARNED };
 enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_ADOPT,
                    F_PJ_CHECK, F_LS_DIR, F_LS_NEG, F_LS_TEST };
 
@@ -61,6 +61,7 @@ struct LMArgs {
   int* ls_flags;           // nullable, pinned host memory: slot i <- whether the line search goes
                            // on after step size i
   const float2* Pcur;      // the caller's probe (V_SAME, object-only problems)
+  const float* cnn_r;      // network output r (2 maps of the object grid) for V_LEARNED
   int adopt_ok;            // host: the linearisation buffers hold the one made at the last accepted
                            // trial point, unless O / P changed since (checked by V_SAME / F_ADOPT)
 };

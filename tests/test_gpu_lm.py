@@ -128,8 +128,10 @@ def _small_joint(seed=9):
 
 def test_all_rejected_outer_iteration_keeps_iterate():
     """Forced rejection: with no PCG iterations (and no accepted step to warm-start from) the
-    step is zero, its predicted reduction is not positive and every retry is rejected (reading
-    C9); the step reports PTLM_ENOTACCEPTED, the iterate is unchanged and t advances (C3)."""
+    step is zero, its predicted reduction is not positive and every retry is rejected (the gain
+    ratio is taken as -inf when the predicted reduction is not positive); the step reports
+    PTLM_ENOTACCEPTED, the iterate is unchanged and t advances (a retry budget spent ends the
+    outer iteration without a step)."""
     pr, prob, O, P, y = _small_joint()
     O0, P0 = O.clone(), P.clone()
     params = pt.default_params(scaling=1, precond=1, cg_max=0, retry_max=3)
