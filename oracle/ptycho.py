@@ -257,10 +257,10 @@ def ggn_diag_paper(lin: Linearization):
     the probe part (eq:ggn_joint_diag).
 
     Returns (dO, dP) with a trailing axis of 2 = (Re, Im) weights; dP is None
-    for object-only problems.  Pinned only by internal consistency (equals
-    half the illumination-overlap map for the Gaussian metric; equals the
-    exact diagonal when the dropped terms vanish): parity unpinned against
-    printed values, the paper prints none.
+    for object-only problems.  Pinned by closed forms: half the
+    illumination-overlap map for the Gaussian metric (trace = M), and the
+    exact diagonal when the dropped terms vanish; the paper prints no values
+    of it to compare with.
     """
     M = lin.M
     trace = lin.l2.reshape(len(lin.pos), -1).sum(axis=1)                  # trace(grad^2_k ell)
