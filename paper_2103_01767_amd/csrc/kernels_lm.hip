@@ -315,6 +315,17 @@ __device__ __forceinline__ double surrogate_sigma(const ptlm_lm_params& p, int t
   return p.surrogate_s0 * pow(1e-6, (double)t / (double)(p.surrogate_T - 1));
 }
 
+// The projected plug-in's line search starts; with no step size to try (ls_max = 0) z_t is kept.
+__device__ __forceinline__ void ls_start(ptlm_lm_state& st, const ptlm_lm_params& p) {
+  if (p.ls_max > 0) {
+    st.ls_on = 1;
+  } else {
+    st.ls_keep = 1;
+    st.ls_alpha = 0.0;
+    st.ls_branch = -1;
+  }
+}
+
 // One block: reduce `count` partials (fixed order), then run the scalar step.
 template <int OP>
 __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
@@ -430,8 +441,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
       st.ls_branch = 1;
       st.ls_proj = 0;
       a.scal[SC_LS1] = s1;
-      st.ls_on = p.ls_max > 0 ? 1 : 0;
-      st.ls_keep = p.ls_max > 0 ? 0 : 1;
+      ls_start(st, p);
     } else {
       st.ls_branch = 2;
       st.ls_proj = 1;
@@ -440,8 +450,7 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   } else if constexpr (OP == F_LS_NEG) {
     st.ls_neg = 0;
     a.scal[SC_LS1] = s1;  // ||grad f||^2
-    st.ls_on = p.ls_max > 0 ? 1 : 0;
-    st.ls_keep = p.ls_max > 0 ? 0 : 1;
+    ls_start(st, p);
   } else if constexpr (OP == F_LS_TEST) {
     // eq:armijo_criterion at the candidate in the trial buffer (its loss reduced here);
     // the step size halves until it passes or ls_max sizes were tried (then z_t is kept)

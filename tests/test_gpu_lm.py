@@ -444,3 +444,31 @@ def test_lm_at_the_solution_stays_put():
         assert bool(torch.isfinite(torch.view_as_real(O)).all()) and bool(torch.isfinite(torch.view_as_real(P)).all())
         assert float(torch.linalg.norm(O - O0) / torch.linalg.norm(O0)) < 1e-4
         assert float(torch.linalg.norm(P - P0) / torch.linalg.norm(P0)) < 1e-4
+
+
+def test_projected_line_search_limits():
+    """The projected plug-in's line-search bounds: with no step size to try (ls_max = 0) every
+    accepted step keeps z_t (branch -1, step size 0), and a bound past the host look-ahead's
+    slots (all step sizes enqueued at once) gives the same iterates as the default bound."""
+    print("case projected limits", flush=True)
+    pr = synth.make_small(6, obj_side=48, probe=(16, 16), n=6, step=5, photons=1e3, mode="joint")
+    rng = np.random.default_rng(6)
+    O_true = pr.O_true / np.abs(pr.O_true).max()
+    y = to_dev(synth.poisson_counts(rng, ptycho.intensity(O_true, pr.P_true, pr.pos, pr.background))
+               .astype(np.float32), np.float32)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
+    runs = {}
+    for ls_max in (0, 30, 200):
+        O, P = to_dev(pr.O_init, np.complex64), to_dev(pr.P_init, np.complex64)
+        params = pt.default_params(scaling=1, precond=1, project=1, gamma=0.0, ls_max=ls_max)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(3):
+            prob.lm_step(O, P, y, params, st)
+        runs[ls_max] = (O, P, pt.state_from_tensor(st))
+    O0, P0, s0 = runs[0]
+    assert torch.equal(O0, to_dev(pr.O_init, np.complex64)) and torch.equal(P0, to_dev(pr.P_init, np.complex64))
+    assert s0.ls_branch == -1 and s0.ls_alpha == 0.0
+    (O1, P1, s1), (O2, P2, s2) = runs[30], runs[200]
+    assert s1.ls_branch in (1, 2) and s1.ls_alpha > 0
+    assert torch.equal(O1, O2) and torch.equal(P1, P2) and s1.f == s2.f and s1.ls_alpha == s2.ls_alpha
