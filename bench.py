@@ -13,6 +13,13 @@ positions pushed through GGN-vector products per second of whole-step wall
 time (inputs resident in HBM).  The dominant kernel (the per-position GGN-vector
 kernel) is also timed alone with HIP events on its stream for the roofline.
 
+Further keys of the same JSON line: the large scan (2048x2048 object, 256x256
+probe, 10 000 positions: the product and LM iterations), LM wall time to the
+oracle's final loss for plain, Jacobi, exact-Jacobi and learned PCG, the
+method's variants (projected, alternating, intensity-based GGN, stochastic
+diagonal, surrogate Poisson metric), the 64-problem uneven batch and the FP64
+oracle's product on the host (cpu_baseline).
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
