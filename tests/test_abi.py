@@ -138,3 +138,17 @@ def test_struct_mirrors_match_the_header(tmp_path):
         assert int(val) == want, (cname, field, int(val), want)
         seen += 1
     assert seen == sum(len(p._fields_) + 1 for p in mirrors.values())
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """Without the built HIP library the binding refuses to import (no silent CPU path)."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2103_01767_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2103_01767_amd", "__init__.py"), pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_2103_01767_amd"], cwd=str(tmp_path),
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)}, capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "libptlm.so is not built" in r.stderr
