@@ -31,9 +31,8 @@ static void build_csr(const Plan& p, Boxes boxes, int count, std::vector<int>& p
     int r0, c0, h, w;
     boxes(i, r0, c0, h, w);
     if (h <= 0 || w <= 0) continue;
-    const int ty1 = std::min((r0 + h - 1) / 16, p.oty - 1), tx1 = std::min((c0 + w - 1) / 16, p.otx - 1);
-    for (int ty = r0 / 16; ty <= ty1; ++ty)
-      for (int tx = c0 / 16; tx <= tx1; ++tx) cnt[ty * p.otx + tx + 1]++;
+    for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+      for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) cnt[ty * p.otx + tx + 1]++;
   }
   for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
   ptr = cnt;
@@ -43,9 +42,8 @@ static void build_csr(const Plan& p, Boxes boxes, int count, std::vector<int>& p
     int r0, c0, h, w;
     boxes(i, r0, c0, h, w);
     if (h <= 0 || w <= 0) continue;
-    const int ty1 = std::min((r0 + h - 1) / 16, p.oty - 1), tx1 = std::min((c0 + w - 1) / 16, p.otx - 1);
-    for (int ty = r0 / 16; ty <= ty1; ++ty)
-      for (int tx = c0 / 16; tx <= tx1; ++tx) idx[fill[ty * p.otx + tx]++] = i;
+    for (int ty = r0 / 16; ty <= (r0 + h - 1) / 16; ++ty)
+      for (int tx = c0 / 16; tx <= (c0 + w - 1) / 16; ++tx) idx[fill[ty * p.otx + tx]++] = i;
   }
 }
 
@@ -109,10 +107,6 @@ void segment(Plan& p, const int* h_pos, int grid) {
       r1 = std::max(r1, h_pos[2 * k] + d->my);
       c1 = std::max(c1, h_pos[2 * k + 1] + d->mx);
     }
-    // columns widened to whole 16-pixel object tiles, so every 16-pixel run the gather reads
-    // is one aligned 128-byte line (strips may extend past the object's right edge)
-    c0 = c0 / 16 * 16;
-    c1 = (c1 + 15) / 16 * 16;
     p.seg_box[s] = make_int4(r0, c0, r1 - r0, c1 - c0);
     p.seg_off[s] = off;
     off += (long long)(r1 - r0) * (c1 - c0);
