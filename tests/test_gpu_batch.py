@@ -313,3 +313,41 @@ def test_batch_projected_equals_alone(gamma):
         assert float(torch.abs(Os[i]).max()) <= 1.0 + 1e-6
         if gamma == 0.0:
             assert s2.ls_branch != 0
+
+
+def test_batch_with_large_probes_equals_alone():
+    """128 x 128 and 256 x 256 probes in a batch (their batched kernels read the metric per
+    pixel and, at 256 x 256, stage through per-workgroup transform tiles) next to a small
+    problem: every problem equals its solve alone, bit for bit."""
+    print("case batch large probes", flush=True)
+    out = []
+    for side, probe, n, step, seed in ((200, (128, 128), 3, 32, 21), (320, (256, 256), 2, 48, 22), (72, (32, 32), 5, 8, 23)):
+        rng = np.random.default_rng(seed)
+        O = synth.make_object(rng, side, amp=(0.7, 1.0), phase=(-np.pi, np.pi), phase_sigma=3.0,
+                              phase_source="gaussian")
+        P = synth.make_probe_fresnel(rng, probe[0], 0.3 * probe[0], 5.0)
+        P = synth.scale_probe_to_photons(P, O, 3e3)
+        base = 2 + step * np.arange(n)
+        ry, rx = np.meshgrid(base, base, indexing="ij")
+        pos = np.stack([ry.ravel(), rx.ravel()], 1) + rng.integers(-1, 2, size=(n * n, 2))
+        pos = np.clip(pos, 0, [side - probe[0], side - probe[1]]).astype(np.int32)
+        y = synth.poisson_counts(rng, ptycho.intensity(O, P, pos, 1e-8)).astype(np.float32)
+        out.append(dict(obj_shape=(side, side), probe_shape=probe, positions=pos, mode="joint", y=y,
+                        O0=synth.random_object_guess(rng, side), P0=np.abs(P)))
+    params = pt.default_params(scaling=1, precond=1, cg_max=5)
+    T = 2
+    alone = [run_single(p, params, T) for p in out]
+    batch = pt.Batch(out, device=DEV)
+    Os = [c64(p["O0"]) for p in out]
+    Ps = [c64(p["P0"]) for p in out]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in out]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    status, _ = batch.solve(100, check_every=1)
+    torch.cuda.synchronize()
+    assert status == pt.PTLM_OK
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        print("problem %d (probe %s): f %.6e / %.6e" % (i, out[i]["probe_shape"], s1.f, s2.f))
+        assert s2.t == T and s1.t == T
+        assert s2.f == s1.f and s2.products == s1.products and s2.attempts == s1.attempts
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
