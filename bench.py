@@ -147,8 +147,9 @@ def main():
     torch.cuda.synchronize()
     s0 = pt.state_from_tensor(state)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        prob.lm_step(O, P, y, params, state)
+    # the K outer iterations in one library call (ptlm_lm_solve runs ptlm_lm_step K times)
+    if args.steps > 0:
+        prob.lm_solve(O, P, y, params, args.steps, state)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = pt.state_from_tensor(state)
