@@ -265,10 +265,19 @@ static ptlm_status read_state(ptlm_lm_state* d, ptlm_lm_state* hs, hipStream_t s
 // One outer iteration: the attempts of alg:lm_inexact until one is accepted or retry_max are
 // rejected -- once for the joint update, once per block (object, then probe) for the
 // alternating update of alg:alt_LM_ptycho.
+// known: the device state as last read back (ptlm_lm_solve between its steps), else read here;
+// the state read after the last attempt is left in *last when it is given.
 static ptlm_status lm_step_impl(ptlm_handle* h, float2* O, float2* P, const float* y, const ptlm_lm_params* prm,
-                                ptlm_lm_state* st, const float* learned, hipStream_t s) {
+                                ptlm_lm_state* st, const float* learned, hipStream_t s,
+                                const ptlm_lm_state* known = nullptr, ptlm_lm_state* last = nullptr) {
   ptlm_lm_state hs;
-  PTLM_TRY(read_state(st, &hs, s));
+  if (known) hs = *known;
+  else PTLM_TRY(read_state(st, &hs, s));
+  struct Keep {
+    ptlm_lm_state* to;
+    const ptlm_lm_state* from;
+    ~Keep() { if (to) *to = *from; }
+  } keep{last, &hs};
   if (hs.status == PTLM_ENUMERIC) return fail(PTLM_ENUMERIC, "non-finite loss or gradient at the current iterate");
   if (hs.t >= hs.t_max) return fail(PTLM_EINVAL, "the state has run its outer iterations (t_max)");
   const int t0 = hs.t;
@@ -334,24 +343,35 @@ ptlm_status ptlm_lm_init(ptlm_handle* h, const ptlm_lm_params* params, ptlm_lm_s
   return PTLM_OK;
 }
 
-ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_y, const ptlm_lm_params* params,
-                         ptlm_lm_state* d_state, const float* d_precond, void* stream) {
+static ptlm_status check_step_args(ptlm_handle* h, float* d_O, float* d_P, const float* d_y,
+                                   const ptlm_lm_params* params, ptlm_lm_state* d_state, const float* d_precond) {
   if (!h || !d_O || !d_P || !d_y || !d_state) return fail(PTLM_EINVAL, "null argument");
   ptlm_status st = check_lm_params(params);
   if (st != PTLM_OK) return st;
   if (params->alternate && !h->g.joint) return fail(PTLM_EINVAL, "the alternating update needs a PTLM_JOINT problem");
   if (params->precond == 2 && !d_precond && !h->cnn_params)
     return fail(PTLM_EINVAL, "precond == 2 needs d_precond or a registered network");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_lm_step(ptlm_handle* h, float* d_O, float* d_P, const float* d_y, const ptlm_lm_params* params,
+                         ptlm_lm_state* d_state, const float* d_precond, void* stream) {
+  PTLM_TRY(check_step_args(h, d_O, d_P, d_y, params, d_state, d_precond));
   return lm_step_impl(h, (float2*)d_O, (float2*)d_P, d_y, params, d_state, d_precond, (hipStream_t)stream);
 }
 
 ptlm_status ptlm_lm_solve(ptlm_handle* h, float* d_O, float* d_P, const float* d_y, const ptlm_lm_params* params,
                           int32_t T, ptlm_lm_state* d_state, const float* d_precond, void* stream) {
   if (T < 0) return fail(PTLM_EINVAL, "T must be >= 0");
+  PTLM_TRY(check_step_args(h, d_O, d_P, d_y, params, d_state, d_precond));
   ptlm_status last = PTLM_OK;
+  ptlm_lm_state hs;
+  bool known = false;  // hs holds the device state read back at the end of the previous step
   for (int t = 0; t < T; ++t) {
-    last = ptlm_lm_step(h, d_O, d_P, d_y, params, d_state, d_precond, stream);
+    last = lm_step_impl(h, (float2*)d_O, (float2*)d_P, d_y, params, d_state, d_precond, (hipStream_t)stream,
+                        known ? &hs : nullptr, &hs);
     if (last != PTLM_OK && last != PTLM_ENOTACCEPTED) return last;
+    known = true;
   }
   return last;
 }
