@@ -55,3 +55,47 @@ def test_features_and_learned_diag_shapes():
     assert np.all(f[0][8, 0:3] == 0.0) and np.all(np.abs(f[2]) <= 1.0 + 1e-12)
     d = cnn.learned_diag(np.ones((9, 9, 2)), np.ones((4, 4, 2)), np.zeros((2, 9, 9)))
     assert d.shape == (81 + 16, 2) and np.all(d == 1.0)
+
+
+def _coverage_count(pos, probe_shape, obj_shape):
+    """Number of scan windows covering each object pixel, by direct counting."""
+    cnt = np.zeros(obj_shape)
+    for r, c in pos:
+        for i in range(probe_shape[0]):
+            for j in range(probe_shape[1]):
+                cnt[r + i, c + j] += 1
+    return cnt
+
+
+def test_features_of_a_flat_probe_are_coverage_count_ones_and_zero_phase():
+    pos = np.array([[0, 0], [1, 2], [3, 3], [3, 0]])
+    P = np.ones((4, 5), complex)
+    f = cnn.features(P, pos, (9, 10))
+    cnt = _coverage_count(pos, P.shape, (9, 10))
+    np.testing.assert_allclose(f[0], cnt / cnt.max(), rtol=1e-14)
+    np.testing.assert_allclose(f[1], (cnt > 0).astype(float), rtol=1e-14)
+    np.testing.assert_array_equal(f[2], 0.0)
+
+
+def test_features_of_a_constant_phase_probe_carry_that_phase():
+    pos = np.array([[0, 0], [2, 1], [1, 4]])
+    amp = RNG.uniform(0.2, 1.0, (4, 4))
+    phi = 0.7
+    f = cnn.features(amp * np.exp(1j * phi), pos, (8, 9))
+    cov = _coverage_count(pos, (4, 4), (8, 9)) > 0
+    np.testing.assert_allclose(f[2][cov], phi / np.pi, rtol=1e-13)
+    np.testing.assert_array_equal(f[2][~cov], 0.0)
+
+
+def test_features_of_one_position_are_the_probe_maps():
+    P = RNG.standard_normal((5, 4)) + 1j * RNG.standard_normal((5, 4))
+    r, c = 2, 3
+    f = cnn.features(P, np.array([[r, c]]), (9, 10))
+    q = np.abs(P) ** 2
+    win = (slice(r, r + 5), slice(c, c + 4))
+    np.testing.assert_allclose(f[0][win], q / q.max(), rtol=1e-13)
+    np.testing.assert_allclose(f[1][win], q / q.max(), rtol=1e-13)
+    np.testing.assert_allclose(f[2][win], np.angle(P) / np.pi, rtol=1e-13)
+    outside = np.ones((9, 10), bool)
+    outside[win] = False
+    assert np.all(f[:, outside] == 0.0)
