@@ -117,6 +117,13 @@ size_t tile_lds_bytes(int my, int mx);
 hipError_t launch_tile256(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
 hipError_t launch_tile256_batch(int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
 size_t tile256_lds_bytes();
+// 128 x 128 tiles (kernels_tile128.hip): every op but the exact diagonal (which stays on the
+// generic kernel); 512-thread workgroups
+bool tile128_handles(int op);
+hipError_t launch_tile128(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
+hipError_t launch_tile128_batch(int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
+size_t tile128_lds_bytes();
+int tile128_threads();
 // 48 x 48 and 96 x 96 tiles (kernels_tile3.hip): radix 16 x 3 and 16 x 6 transforms
 hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
 hipError_t launch_tile3_batch(int L, int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);

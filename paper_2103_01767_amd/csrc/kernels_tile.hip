@@ -42,21 +42,6 @@ struct Cfg {
   static constexpr bool PROBE_REGS = NT < 1024;
 };
 
-// Order this wave's LDS writes before its later LDS reads (exchanges whose readers are the
-// writers' own wavefront need no workgroup barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each
-// XCD a contiguous run of segments -- consecutive scan positions, overlapping windows -- so
-// the object windows it gathers stay in its L2.
-__device__ __forceinline__ int xcd_block(int b, int n) {
-  if (n % 8 != 0) return b;
-  return (b % 8) * (n / 8) + b / 8;
-}
-
 __device__ __forceinline__ const float2* tw_table(const float2* tw, int L) {
   return tw + (L == 32 ? 0 : (L == 64 ? 32 : 96));
 }
@@ -677,6 +662,7 @@ static hipError_t launch_mx(const Geometry& g, int op, const TileArgs& a, hipStr
 
 hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
   if (g.my == 256 && g.mx == 256) return launch_tile256(g, op, a, s);
+  if (g.my == 128 && g.mx == 128 && tile128_handles(op)) return launch_tile128(g, op, a, s);
   if (g.my == g.mx && (g.my == 48 || g.my == 96)) return launch_tile3(g, op, a, s);
   switch (g.my) {
     case 16: return launch_mx<16>(g, op, a, s);
@@ -690,12 +676,13 @@ hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t
 hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   if (my == 256 && mx == 256) return launch_tile256_batch(op, jobs, jb, nb, s);
+  if (my == 128 && mx == 128) return launch_tile128_batch(op, jobs, jb, nb, s);
   if (my == mx && (my == 48 || my == 96)) return launch_tile3_batch(my, op, jobs, jb, nb, s);
 #define PTLM_B(A, B) if (my == A && mx == B) return launch_op_batch<A, B>(op, jobs, jb, nb, s);
   PTLM_B(16, 16) PTLM_B(16, 32) PTLM_B(16, 64) PTLM_B(16, 128)
   PTLM_B(32, 16) PTLM_B(32, 32) PTLM_B(32, 64) PTLM_B(32, 128)
   PTLM_B(64, 16) PTLM_B(64, 32) PTLM_B(64, 64) PTLM_B(64, 128)
-  PTLM_B(128, 16) PTLM_B(128, 32) PTLM_B(128, 64) PTLM_B(128, 128)
+  PTLM_B(128, 16) PTLM_B(128, 32) PTLM_B(128, 64)
 #undef PTLM_B
   return hipErrorInvalidValue;
 }
@@ -712,11 +699,12 @@ static void cfg_of(int* wg, int* tpw, size_t* lds) {
   *lds = lds_bytes<MY, MX>();
 }
 static void cfg_dispatch(int my, int mx, int* wg, int* tpw, size_t* lds) {
+  if (my == 128 && mx == 128) { *wg = tile128_threads(); *tpw = 1; *lds = tile128_lds_bytes(); return; }
 #define PTLM_CFG(A, B) if (my == A && mx == B) { cfg_of<A, B>(wg, tpw, lds); return; }
   PTLM_CFG(16, 16) PTLM_CFG(16, 32) PTLM_CFG(16, 64) PTLM_CFG(16, 128)
   PTLM_CFG(32, 16) PTLM_CFG(32, 32) PTLM_CFG(32, 64) PTLM_CFG(32, 128)
   PTLM_CFG(64, 16) PTLM_CFG(64, 32) PTLM_CFG(64, 64) PTLM_CFG(64, 128)
-  PTLM_CFG(128, 16) PTLM_CFG(128, 32) PTLM_CFG(128, 64) PTLM_CFG(128, 128)
+  PTLM_CFG(128, 16) PTLM_CFG(128, 32) PTLM_CFG(128, 64)
 #undef PTLM_CFG
   if (my == 256 && mx == 256) { *wg = 1024; *tpw = 1; *lds = tile256_lds_bytes(); return; }
   if (my == mx && (my == 48 || my == 96)) { *wg = 576; *tpw = tile3_per_wg(my); *lds = tile3_lds_bytes(my); return; }

@@ -30,6 +30,21 @@ __device__ __forceinline__ void st_once(float2* p, float2 v) {
   __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double*>(p));
 }
 
+// Order this wave's LDS writes before its later LDS reads (exchanges whose readers are the
+// writers' own wavefront need no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each
+// XCD a contiguous run of segments -- consecutive scan positions, overlapping windows -- so
+// the object windows it gathers stay in its L2.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  if (n % 8 != 0) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
 // Output n >= 1 of the SplitMix64 generator seeded with `seed` (Steele, Lea and Flood 2014):
 // Stafford's 64-bit finaliser of seed + n * golden gamma.  Counter-based, so every measurement
 // draws its own sign independently.
