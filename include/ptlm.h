@@ -162,8 +162,8 @@ ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, si
 /* Create a handle.  Validates desc and every position (0 <= r <= n - m), copies the
  * positions and constant tables into the workspace on `stream` and returns without
  * waiting.  d_ws must stay valid until ptlm_destroy; the handle owns host metadata and,
- * for ptlm_lm_step's PCG and line-search look-ahead, 258 ints of pinned host memory and
- * 129 HIP events (made here, so that no later call allocates). */
+ * for ptlm_lm_step's PCG and line-search look-ahead and for ptlm_autotune, 258 ints of
+ * pinned host memory and 131 HIP events (made here, so that no later call allocates). */
 ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
                         void* stream, ptlm_handle** out);
 ptlm_status ptlm_destroy(ptlm_handle* h);

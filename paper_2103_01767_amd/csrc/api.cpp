@@ -128,6 +128,8 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
     snprintf(buf, sizeof buf, "workspace of %zu bytes, %zu needed", ws_bytes, p.ws_bytes);
     return fail(PTLM_EWORKSPACE, buf);
   }
+  PTLM_HIP(hipEventCreate(&h->tune_ev[0]), "ptlm_create autotune events");
+  PTLM_HIP(hipEventCreate(&h->tune_ev[1]), "ptlm_create autotune events");
   h->ws = (char*)d_ws;
   Geometry& g = h->g;
   const ptlm_desc& d = p.d;
@@ -216,9 +218,7 @@ ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scal
   float2* out = (float2*)(h->ws + p.off.Ap);
   const float2* vO = h->g.O_lin;
   const float2* vP = h->g.joint ? h->g.P_lin : nullptr;
-  hipEvent_t e0, e1;
-  PTLM_HIP(hipEventCreate(&e0), "autotune event");
-  PTLM_HIP(hipEventCreate(&e1), "autotune event");
+  hipEvent_t e0 = h->tune_ev[0], e1 = h->tune_ev[1];
   double best = 1e300;
   int bi = 1;
   ptlm_status st = PTLM_OK;
@@ -242,8 +242,6 @@ ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scal
       bi = i;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (st != PTLM_OK) return st;
   if (h_scale) *h_scale = kGridScales[bi];
   return resegment(h, kGridScales[bi], s);
@@ -337,6 +335,8 @@ ptlm_status ptlm_destroy(ptlm_handle* h) {
 
 ptlm_handle::~ptlm_handle() {
   for (hipEvent_t e : cg_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (cg_flags) (void)hipHostFree(cg_flags);
 }
 

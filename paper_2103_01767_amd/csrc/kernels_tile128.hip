@@ -33,6 +33,9 @@ constexpr int L = 128, M = L * L;
 constexpr int NTH = 1024;
 constexpr int NW = NTH / 64;
 constexpr int TW_OFF = 96;  // W_128^(n k), n < 8, k < 16, in the workspace twiddle table
+// pixel pairs per lane per batch of gather loads and of overlap-add loads (batches of 2 to 8
+// measured the same)
+constexpr int NG = 2, NO = 2;
 
 // two adjacent complex values (8-byte aligned: one 16-byte global access)
 struct __attribute__((aligned(8))) c2 {
@@ -120,9 +123,9 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
           if (a.vP) {
             const c2* VPq = reinterpret_cast<const c2*>(a.vP + row * L + 2 * lc);
 #pragma unroll
-            for (int nn = 0; nn < 8; nn += 2) {
+            for (int nn = 0; nn < 8; nn += NG) {
 #pragma unroll
-              for (int n2 = nn; n2 < nn + 2; ++n2) {
+              for (int n2 = nn; n2 < nn + NG; ++n2) {
                 const c2 pp = Pq[8 * n2], vv = Vq[8 * n2], vp = VPq[8 * n2], oo = Oq[8 * n2];
                 v[n2] = cadd(cmul(pp.a, vv.a), cmul(vp.a, oo.a));
                 v[8 + n2] = cadd(cmul(pp.b, vv.b), cmul(vp.b, oo.b));
@@ -256,9 +259,9 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
           }
         } else {
 #pragma unroll
-          for (int nn = 0; nn < 8; nn += 2) {
+          for (int nn = 0; nn < 8; nn += NO) {
 #pragma unroll
-            for (int n2 = nn; n2 < nn + 2; ++n2) {
+            for (int n2 = nn; n2 < nn + NO; ++n2) {
               const c2 pp = Pq[8 * n2], cur = sq[8 * n2];
               sq[8 * n2] = c2{cadd(cur.a, cmulc(v[n2], pp.a)), cadd(cur.b, cmulc(v[8 + n2], pp.b))};
             }
@@ -268,9 +271,9 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
         if (joint) {
           const c2* Oq = reinterpret_cast<const c2*>(a.O + (size_t)Y * g.nx + rx + 2 * lc);
 #pragma unroll
-          for (int nn = 0; nn < 8; nn += 2) {
+          for (int nn = 0; nn < 8; nn += NO) {
 #pragma unroll
-            for (int n2 = nn; n2 < nn + 2; ++n2) {
+            for (int n2 = nn; n2 < nn + NO; ++n2) {
               const c2 oo = Oq[8 * n2];
               accP[n2] = cadd(accP[n2], cmulc(v[n2], oo.a));
               accP[8 + n2] = cadd(accP[8 + n2], cmulc(v[8 + n2], oo.b));
