@@ -163,7 +163,9 @@ ptlm_status ptlm_workspace_bytes(const ptlm_desc* desc, const int32_t* h_pos, si
  * positions and constant tables into the workspace on `stream` and returns without
  * waiting.  d_ws must stay valid until ptlm_destroy; the handle owns host metadata and,
  * for ptlm_lm_step's PCG and line-search look-ahead and for ptlm_autotune, 258 ints of
- * pinned host memory and 131 HIP events (made here, so that no later call allocates). */
+ * pinned host memory and 131 HIP events (made here, so that no later call allocates).  On
+ * the first handle of a device it also takes that device's address of the static scratch
+ * of ptlm_loss_noalloc. */
 ptlm_status ptlm_create(const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
                         void* stream, ptlm_handle** out);
 ptlm_status ptlm_destroy(ptlm_handle* h);
@@ -176,6 +178,18 @@ ptlm_status ptlm_forward(ptlm_handle* h, const float* d_O, const float* d_P, flo
  * d_y: K*my*mx float counts >= 0.  d_resid (nullable): ell'(zeta), K*my*mx float. */
 ptlm_status ptlm_loss(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y,
                       double* d_f, float* d_resid, void* stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops):
+ * ptlm_loss with its only scratch -- the FP64 partial sums of the loss kernel, 4 doubles per
+ * workgroup -- in a static device array of 8192 x 4 doubles (256 KiB, held by every device
+ * the library runs on until the process ends) instead of the handle's workspace.  Same
+ * arguments, results and rounding as ptlm_loss; allocates nothing and calls no allocating
+ * routine.  The handle's device must be current.  PTLM_EINVAL for a 256 x 256 probe (its
+ * transform tiles live in the workspace) or a handle with more than 8192 workgroups.  All
+ * calls on one device share the array: calls that overlap in time on one device race (order
+ * them on one stream). */
+ptlm_status ptlm_loss_noalloc(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y,
+                              double* d_f, float* d_resid, void* stream);
 
 /* Linearise at (O, P): f (FP64, d_f[0]), ||grad_zeta ell||^2 (d_f[1]) and the gradient
  * g = J^T grad_zeta ell (App. A step 1) into d_gO (ny*nx complex) and, in PTLM_JOINT mode,

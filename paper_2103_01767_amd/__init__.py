@@ -80,6 +80,7 @@ _sig = {
     "ptlm_destroy": (ctypes.c_int, [_vp]),
     "ptlm_forward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptlm_loss": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_loss_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptlm_linearize": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptlm_jvp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptlm_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -248,6 +249,16 @@ class Problem:
         _check(_lib.ptlm_loss(self.handle, self._o(O), self._p(P), self._m(y, "y"), _ptr(f, torch.float64),
                               self._m(r, "resid") if residual else None, _stream()))
         return (f, r) if residual else f
+
+    def loss_noalloc(self, O, P, y, f=None, r=None):
+        """ptlm_loss_noalloc: the loss with its partial sums in the library's static scratch.
+        ``f`` (FP64, >= 1 entry) and ``r`` (residual, nullable) are caller-provided outputs."""
+        if f is None:
+            f = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(_lib.ptlm_loss_noalloc(self.handle, self._o(O), self._p(P), self._m(y, "y"),
+                                      _ptr(f, torch.float64), self._m(r, "resid") if r is not None else None,
+                                      _stream()))
+        return f
 
     def linearize(self, O, P, y):
         f = torch.zeros(2, dtype=torch.float64, device=self.device)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 namespace ptlm {
@@ -21,6 +22,28 @@ ptlm_status fail(ptlm_status st, const std::string& msg) {
 
 ptlm_status hip_fail(hipError_t e, const char* where) {
   return fail(PTLM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Scratch of ptlm_loss_noalloc, the one entry point for callers that cannot allocate: the
+// per-workgroup FP64 partial sums of the loss kernel (4 doubles a workgroup), in static device
+// memory instead of the handle's workspace.  Each device holds its own copy until the process
+// ends; host code reaches it only through the per-device address taken at handle creation.
+constexpr int kNoAllocMaxBlocks = 8192;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocMaxBlocks * 4];
+static double* g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+static std::once_flag g_scratch_once[kMaxDevices];
+
+// Address of `scratch` on device `dev` (which must be current), taken once per device.
+static hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? (double*)p : nullptr;
+  });
+  return g_scratch_err[dev];
 }
 
 #define PTLM_CHECK_H(h)                                    \
@@ -128,6 +151,8 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
     snprintf(buf, sizeof buf, "workspace of %zu bytes, %zu needed", ws_bytes, p.ws_bytes);
     return fail(PTLM_EWORKSPACE, buf);
   }
+  PTLM_HIP(hipGetDevice(&h->device), "ptlm_create device");
+  PTLM_HIP(scratch_setup(h->device), "ptlm_create static scratch");
   PTLM_HIP(hipEventCreate(&h->tune_ev[0]), "ptlm_create autotune events");
   PTLM_HIP(hipEventCreate(&h->tune_ev[1]), "ptlm_create autotune events");
   h->ws = (char*)d_ws;
@@ -365,6 +390,36 @@ ptlm_status ptlm_loss(ptlm_handle* h, const float* d_O, const float* d_P, const 
   a.rout = d_resid;
   PTLM_HIP(launch_tile(h->g, OP_LOSS, a, s), "loss");
   PTLM_HIP(launch_sum_partials(h->g.partials, h->g.grid, d_f, 1, s), "loss sum");
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_loss_noalloc(ptlm_handle* h, const float* d_O, const float* d_P, const float* d_y, double* d_f,
+                              float* d_resid, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_O || !d_P || !d_y || !d_f) return fail(PTLM_EINVAL, "null array");
+  if (h->g.my == 256 && h->g.mx == 256)
+    return fail(PTLM_EINVAL, "ptlm_loss_noalloc: 256 x 256 probes transform through the workspace; use ptlm_loss");
+  if (h->g.grid > kNoAllocMaxBlocks) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "ptlm_loss_noalloc: %d workgroups, the static scratch holds the partial sums of %d",
+             h->g.grid, kNoAllocMaxBlocks);
+    return fail(PTLM_EINVAL, buf);
+  }
+  int dev = -1;
+  PTLM_HIP(hipGetDevice(&dev), "ptlm_loss_noalloc device");
+  if (dev != h->device) return fail(PTLM_EINVAL, "ptlm_loss_noalloc: the handle's device is not current");
+  double* part = g_scratch_ptr[h->device];
+  if (!part) return fail(PTLM_EHIP, "ptlm_loss_noalloc: static scratch address unavailable");
+  hipStream_t s = (hipStream_t)stream;
+  Geometry g = h->g;
+  g.partials = part;  // every workgroup of the loss kernel writes all four of its entries
+  TileArgs a{};
+  a.O = (const float2*)d_O;
+  a.P = (const float2*)d_P;
+  a.y = d_y;
+  a.rout = d_resid;
+  PTLM_HIP(launch_tile(g, OP_LOSS, a, s), "loss_noalloc");
+  PTLM_HIP(launch_sum_partials(part, g.grid, d_f, 1, s), "loss_noalloc sum");
   return PTLM_OK;
 }
 

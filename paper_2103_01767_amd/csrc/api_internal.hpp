@@ -65,6 +65,7 @@ struct ptlm_handle {
   unsigned lin_gen = 0;
   unsigned kept_gen = ~0u;
   const float* kept_y = nullptr;
+  int device = 0;                            // device current at creation
   hipEvent_t tune_ev[2] = {nullptr, nullptr}; // timing events of ptlm_autotune
   ~ptlm_handle();
 };
