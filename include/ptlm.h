@@ -285,8 +285,11 @@ ptlm_status ptlm_lm_solve(ptlm_handle* h, float* d_O, float* d_P, const float* d
  * A small CNN of `layers` 3x3 "same" convolutions (zero padding, ReLU between layers) maps
  * 3 feature maps on the object grid -- illumination overlap sum_k S_k^T |P|^2, overlap-
  * weighted |P|^2 and overlap-weighted arg P (ptlm_cnn_features) -- to 2 maps r; the learned
- * object diagonal is d_paper * exp(r) per real coordinate (positive by construction), the
- * probe part (joint mode) stays the App. B diagonal.  Tensors are NCHW float32 device arrays;
+ * object diagonal is s * exp(r) per real coordinate (positive by construction), where the
+ * scale s is the largest entry of the App. B object diagonal: the network predicts the shape
+ * of Dg(G), trained on the exact diagonals of LM iterates (an untrained network, whose last
+ * layer is zero, gives the constant s: the iterates of unpreconditioned CG).  The probe part
+ * (joint mode) stays the App. B diagonal.  Tensors are NCHW float32 device arrays;
  * parameters are one float array: per layer W (Cout, Cin, 3, 3) then b (Cout).
  * ------------------------------------------------------------------------------------- */
 typedef struct {
@@ -297,7 +300,7 @@ typedef struct {
 
 ptlm_status ptlm_cnn_param_count(const ptlm_cnn_desc* d, size_t* count);           /* host only */
 ptlm_status ptlm_cnn_workspace_bytes(const ptlm_cnn_desc* d, size_t* bytes);        /* host only */
-/* d_out: n x cout x h x w (the log-correction r). */
+/* d_out: n x cout x h x w (the log-diagonal r). */
 ptlm_status ptlm_cnn_forward(const ptlm_cnn_desc* d, const float* d_params, const float* d_x, float* d_out,
                              void* d_ws, size_t ws_bytes, void* stream);
 /* Loss L = sum_mask (r - t)^2 / (2 count) (mask > 0 selects pixels) into d_loss[0] (FP64)
@@ -311,12 +314,12 @@ ptlm_status ptlm_cnn_adam(size_t count, float* d_params, const float* d_grad, fl
 /* The 3 input maps (3 x ny x nx floats) at the last linearisation of the handle. */
 ptlm_status ptlm_cnn_features(ptlm_handle* h, float* d_feat, void* stream);
 /* Learned PCG diagonal (2n floats, interleaved like ptlm_diag) from r (2 x ny x nx) at the
- * last linearisation: App. B diagonal floored at 1e-6 of its block maximum, times exp(r) on
- * the object part. */
+ * last linearisation: object part s * exp(r) with r clamped to [log 1e-6, 2] and s the largest
+ * App. B object entry; probe part the App. B diagonal floored at 1e-6 of its block maximum. */
 ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_precond, void* stream);
 /* Register a network for ptlm_lm_step with params->precond == 2: after every linearisation
  * the step recomputes features -> network -> learned diagonal (as ptlm_learned_precond, with
- * the App. B diagonal floored at params->diag_floor of its block maximum, 1e-6 by default).
+ * params->diag_floor, 1e-6 by default, in place of 1e-6).
  * d = NULL unregisters.  The
  * desc must be n = 1, h x w = the object shape, cin = 3, cout = 2; d_params and d_ws
  * (ptlm_cnn_workspace_bytes) stay owned by the caller and must outlive their use. */
@@ -324,7 +327,7 @@ ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float*
                             size_t ws_bytes);
 /* How often ptlm_lm_step re-runs the registered network: every `every`-th linearisation
  * (default 1), or only at the first one after registration (every = 0).  Between runs the
- * learned diagonal is rebuilt from the kept network output and the new App. B diagonal.  A
+ * learned diagonal is rebuilt from the kept network output and the new App. B scale.  A
  * batch (ptlm_batch_bind) runs each network once, from the bound probe. */
 ptlm_status ptlm_lm_set_cnn_refresh(ptlm_handle* h, int32_t every);
 

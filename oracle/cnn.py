@@ -5,11 +5,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Network (a project addition; the paper uses the analytic diagonal of App. B or
 a stochastic estimate, Sec. 6):  L layers of 3x3 "same" convolutions with zero
 padding, ReLU after every layer but the last.  Input: C_in feature maps on the
-object grid; output: C_out maps r, the log of a multiplicative correction to
-the paper's diagonal (the preconditioner is d_paper * exp(r), positive by
-construction).  Loss on a mask of illuminated pixels:
+object grid; output: C_out maps r, the log of the object block of the GGN
+diagonal relative to a per-problem scale s (the preconditioner is s * exp(r),
+positive by construction; s is the largest entry of the App. B object diagonal,
+so that only the scale, not the spatial shape, comes from the analytic formula).
+Loss on a mask of illuminated pixels:
     L = sum_mask (r - t)^2 / (2 * count)
-with t = log(d_exact / d_paper).  Gradients are written out by the chain rule.
+with t = log(d_exact / s).  Gradients are written out by the chain rule.
 
 Parameter vector layout (shared with the GPU library by definition, not code):
 for each layer l: W_l (C_out_l, C_in_l, 3, 3) row-major, then b_l (C_out_l).
@@ -136,13 +138,28 @@ def features(P, pos, obj_shape) -> np.ndarray:
     return np.stack([ov / ov.max(), f1, f2])
 
 
+def learned_scale(dO_paper) -> float:
+    """s: the largest entry of the App. B object diagonal (both real coordinates)."""
+    return float(np.max(dO_paper))
+
+
+def target(d_exact, dO_paper, floor=1e-6) -> np.ndarray:
+    """Training target t = log(d / s) of the network, (2, ny, nx): the exact object diagonal d
+    (real coordinates on the last axis, floored at floor * its largest entry as the LM floors
+    its diagonals) relative to the scale s of ``learned_scale``."""
+    d = np.maximum(d_exact, floor * d_exact.max())
+    t = np.log(d / learned_scale(dO_paper))
+    return np.stack([t[..., 0], t[..., 1]])
+
+
 def learned_diag(dO_paper, dP_paper, r, floor=1e-6):
-    """Learned PCG diagonal: App. B diagonal floored at floor * block max, times exp(r)
-    (r clamped to [-8, 8]) on the object part; the probe part stays the floored App. B one.
-    Returns the flat (n, 2) real-coordinate diagonal (object entries, then probe)."""
-    dO = np.maximum(dO_paper, floor * dO_paper.max())
-    rr = np.clip(r, -8.0, 8.0)
-    dO = dO * np.exp(np.stack([rr[0], rr[1]], axis=-1))
+    """Learned PCG diagonal: object part s * exp(r) with r clamped to [log(floor), 2] (so the
+    floor of the LM's diagonals holds) and s = ``learned_scale(dO_paper)``; the probe part
+    stays the App. B one floored at floor * its block maximum.  With r = 0 (an untrained
+    network, whose last layer starts at zero) the object part is the constant s.  Returns the
+    flat (n, 2) real-coordinate diagonal (object entries, then probe)."""
+    rr = np.clip(r, np.log(floor), 2.0)
+    dO = learned_scale(dO_paper) * np.exp(np.stack([rr[0], rr[1]], axis=-1))
     parts = [dO.reshape(-1, 2)]
     if dP_paper is not None:
         parts.append(np.maximum(dP_paper, floor * dP_paper.max()).reshape(-1, 2))

@@ -182,7 +182,7 @@ ptlm_status ptlm_cnn_features(ptlm_handle* h, float* d_feat, void* stream) {
 
 ptlm_status ptlm_learned_precond(ptlm_handle* h, const float* d_r, float* d_precond, void* stream) {
   if (!h || !d_r || !d_precond) return fail(PTLM_EINVAL, "null argument");
-  CNN_HIP(launch_learned_diag(h->g, d_precond, d_r, (double*)(h->ws + h->plan.off.scal) + 10, 1e-6f,
+  CNN_HIP(launch_learned_diag(h->g, d_precond, d_r, (double*)(h->ws + h->plan.off.scal) + 10, 1e-6,
                               (hipStream_t)stream), "learned precond");
   return PTLM_OK;
 }

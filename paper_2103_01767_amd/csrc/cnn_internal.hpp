@@ -22,7 +22,7 @@ hipError_t launch_adam(size_t n, float* p, const float* g, float* m, float* v, i
 // 3 feature maps (ny*nx each) from the handle's linearisation probe; scal: 2 doubles
 hipError_t launch_features(const Geometry& g, float* feat, double* scal, hipStream_t s);
 // learned diagonal (2n floats) from the network output r (2 x ny x nx); scal: 2 doubles
-hipError_t launch_learned_diag(const Geometry& g, float* d, const float* r, double* scal, float floor_frac,
+hipError_t launch_learned_diag(const Geometry& g, float* d, const float* r, double* scal, double floor_frac,
                                hipStream_t s);
 
 }  // namespace ptlm

@@ -280,21 +280,24 @@ __global__ void feat_norm_kernel(size_t N, float* feat, const double* scal) {
   feat[N + i] *= p;
 }
 
-// learned diagonal: object part d_paper * exp(clamp(r)), both coordinates from the two output
-// channels; the paper's diagonal is floored at floor * max first.  Probe part (joint): the
-// floored paper diagonal.  d holds the paper diagonal on entry (2n floats, interleaved).
+// learned diagonal: object part s * exp(clamp(r, log floor, 2)), both coordinates from the two
+// output channels, with s = scal[0] the largest entry of the paper's object diagonal (only the
+// scale comes from App. B; the shape is the network's).  Probe part (joint): the paper's
+// diagonal floored at floor * its block maximum scal[1].  d holds the paper diagonal on entry
+// (2n floats, interleaved).
 __global__ void learned_diag_kernel(size_t N, size_t n_all, float* d, const float* r, const double* scal,
-                                    float floor_frac) {
+                                    double floor_frac) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n_all) return;
-  const bool obj = i < N;
-  const float f = (float)(floor_frac * (obj ? scal[0] : scal[1]));
   float2 v = reinterpret_cast<float2*>(d)[i];
-  v.x = fmaxf(v.x, f);
-  v.y = fmaxf(v.y, f);
-  if (obj) {
-    v.x *= expf(fminf(fmaxf(r[i], -8.f), 8.f));
-    v.y *= expf(fminf(fmaxf(r[N + i], -8.f), 8.f));
+  if (i < N) {
+    const float sc = (float)scal[0], lo = (float)log(floor_frac);
+    v.x = sc * expf(fminf(fmaxf(r[i], lo), 2.f));
+    v.y = sc * expf(fminf(fmaxf(r[N + i], lo), 2.f));
+  } else {
+    const float f = (float)(floor_frac * scal[1]);
+    v.x = fmaxf(v.x, f);
+    v.y = fmaxf(v.y, f);
   }
   reinterpret_cast<float2*>(d)[i] = v;
 }
@@ -387,7 +390,7 @@ hipError_t launch_features(const Geometry& g, float* feat, double* scal, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_learned_diag(const Geometry& g, float* d, const float* r, double* scal, float floor_frac,
+hipError_t launch_learned_diag(const Geometry& g, float* d, const float* r, double* scal, double floor_frac,
                                hipStream_t s) {
   const size_t N = (size_t)g.ny * g.nx;
   const size_t n_all = N + (g.joint ? (size_t)g.my * g.mx : 0);

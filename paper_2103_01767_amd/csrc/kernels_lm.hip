@@ -148,12 +148,13 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float2 t = a.ztrial[i];
       acc0 += (z.x != t.x || z.y != t.y) ? 1.0 : 0.0;
     } else if constexpr (OP == V_LEARNED) {
-      // learned diagonal: the floored App. B diagonal, times exp(clamp(r)) per real coordinate
-      // on the object part
+      // learned diagonal: on the object part s * exp(clamp(r, log floor, 2)) per real coordinate,
+      // s the largest App. B object entry; the probe part is the floored App. B diagonal
       float2 d = a.diag[i];
       if (i < a.nobj) {
-        d.x *= expf(fminf(fmaxf(a.cnn_r[i], -8.f), 8.f));
-        d.y *= expf(fminf(fmaxf(a.cnn_r[a.nobj + i], -8.f), 8.f));
+        const float sc = (float)a.scal[SC_DMAX_O], lo = (float)log(a.prm.diag_floor);
+        d.x = sc * expf(fminf(fmaxf(a.cnn_r[i], lo), 2.f));
+        d.y = sc * expf(fminf(fmaxf(a.cnn_r[a.nobj + i], lo), 2.f));
       }
       a.xdiag[i] = d;
     } else if constexpr (OP == V_WARM_P) {  // the warm-start vector restricted to the active block

@@ -1,14 +1,19 @@
 """Learned diagonal PCG preconditioner: training data, training loop and evaluation helpers.
 
+The network predicts the shape of the GGN diagonal's object block from the illumination
+geometry; the learned preconditioner is s * exp(r) with s the largest App. B object entry.
 Everything runs through the library's HIP kernels:
-* samples come from LM runs (D = Dg(G), Jacobi PCG) on seeded proxies of the joint
-  512x512 / 128x128 workload (same probe recipe and scan step, 256x256 object, 8x8
-  raster); at every iterate the input maps are ``ptlm_cnn_features`` and the target is
-  t = log(d_exact / d_paper) on illuminated object pixels (``ptlm_diag`` exact and App. B);
-* training is Adam on the masked squared error with ``ptlm_cnn_loss_grad`` /
-  ``ptlm_cnn_adam``.
+* samples come from LM runs on seeded problems of two recipes: the small object-only recipe
+  with a random quadratic probe phase (``synth.make_c3``: 64x64 object, 16x16 probe, 8x8
+  raster, noise-free; plain LM, D = I) and proxies of the joint 512x512 / 128x128 workload
+  (same probe recipe and scan step, 256x256 object, 8x8 raster, Poisson data; D = Dg(G),
+  Jacobi PCG).  At every iterate the input maps are ``ptlm_cnn_features`` and the target is
+  t = log(d_exact / s) on illuminated object pixels: the exact diagonal of G (``ptlm_diag``
+  exact, floored at 1e-6 of its maximum) relative to the largest App. B object entry s;
+* training is Adam on the masked squared error with ``ptlm_cnn_loss_grad`` / ``ptlm_cnn_adam``
+  over minibatches drawn from one recipe at a time.
 
-    python -m paper_2103_01767_amd.learned train [--problems 40 --iters 5 --steps 400]
+    python -m paper_2103_01767_amd.learned train [--small 200 --proxies 40 --steps 3000]
 """
 from __future__ import annotations
 
@@ -26,11 +31,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PARAMS_PATH = os.path.join(HERE, "data", "cnn_params.npy")
 META_PATH = os.path.join(HERE, "data", "cnn_params.json")
 ARCH = dict(cin=3, cmid=32, cout=2, layers=4)
+FLOOR = 1e-6
+MASK_MIN = 1e-3   # illuminated pixels: normalised overlap above this
 
 
 def proxy(seed: int):
     import synth
     return synth.make_scaled("proxy%d" % seed, 50000 + seed, 256, 128, 8, 8, 36, 1, 40.0, 1e4, 4.0, T=10)
+
+
+def small(seed: int):
+    import synth
+    return synth.make_c3(seed)
 
 
 def _c64(a, dev):
@@ -44,19 +56,40 @@ def poisson_data(prob, pr, seed, dev):
     return torch.poisson((zeta.double() ** 2).float(), generator=g).contiguous()
 
 
-def target_from_diagonals(d_exact, d_paper, floor=1e-6):
-    """(2, ny, nx) log ratio of floored exact and App. B diagonals (object part)."""
+def clean_data(prob, pr, dev):
+    """Noise-free data h = |F(P S_k O)|^2 + b at the truth (zeta^2 of the forward model)."""
+    zeta = prob.forward(_c64(pr.O_true, dev), _c64(pr.P_true, dev))
+    return (zeta.double() ** 2).float().contiguous()
+
+
+def target_from_diagonals(d_exact, d_paper, floor=FLOOR):
+    """(2, ny, nx) target log(d / s): the exact object diagonal floored at floor * its maximum,
+    over s = the largest App. B object entry."""
     e = torch.clamp(d_exact, min=floor * float(d_exact.max()))
-    p = torch.clamp(d_paper, min=floor * float(d_paper.max()))
-    return torch.log(e / p).permute(2, 0, 1).contiguous()
+    return torch.log(e / float(d_paper.max())).permute(2, 0, 1).contiguous()
+
+
+def problem_for(pr, dev):
+    return pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, metric="gauss", mode=pr.mode,
+                      background=pr.background, device=dev)
+
+
+def lm_setup(pr, dev, seed=0):
+    """Handle, data, starting point and the LM parameters of a recipe's problem."""
+    prob = problem_for(pr, dev)
+    if pr.mode == "object":
+        y = clean_data(prob, pr, dev)
+        O, P = _c64(pr.O_init, dev), _c64(pr.P_true, dev)
+        params = pt.default_params()
+    else:
+        y = poisson_data(prob, pr, seed, dev)
+        O, P = _c64(pr.O_init, dev), _c64(pr.P_init, dev)
+        params = pt.default_params(scaling=1, precond=1)
+    return prob, y, O, P, params
 
 
 def samples_from_run(pr, iters, dev, seed=0):
-    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, metric="gauss", mode="joint",
-                      background=pr.background, device=dev)
-    y = poisson_data(prob, pr, seed, dev)
-    O, P = _c64(pr.O_init, dev), _c64(pr.P_init, dev)
-    params = pt.default_params(scaling=1, precond=1)
+    prob, y, O, P, params = lm_setup(pr, dev, seed)
     st = prob.new_state()
     prob.lm_init(params, st)
     out = []
@@ -66,21 +99,21 @@ def samples_from_run(pr, iters, dev, seed=0):
         d_ex, _ = prob.diag(exact=True)
         d_pa, _ = prob.diag(exact=False)
         t = target_from_diagonals(d_ex, d_pa)
-        mask = (feat[0:1] > 0.05).float().expand(2, -1, -1).contiguous()
+        mask = (feat[0:1] > MASK_MIN).float().expand(2, -1, -1).contiguous()
         out.append((feat, t, mask))
         prob.lm_step(O, P, y, params, st)
     return out
 
 
-def build_samples(n_problems, iters, dev):
+def build_samples(seeds, make, iters, dev):
     samples = []
-    for p in range(n_problems):
-        samples += samples_from_run(proxy(p), iters, dev, seed=p)
+    for s in seeds:
+        samples += samples_from_run(make(s), iters, dev, seed=s)
     return samples
 
 
 def he_params(seed, dev):
-    """He-normal hidden weights, zero biases, zero last layer (r = 0: the App. B diagonal)."""
+    """He-normal hidden weights, zero biases, zero last layer (r = 0: the constant scale)."""
     rng = np.random.default_rng(seed)
     chans = [ARCH["cin"]] + [ARCH["cmid"]] * (ARCH["layers"] - 1) + [ARCH["cout"]]
     parts = []
@@ -92,27 +125,36 @@ def he_params(seed, dev):
     return torch.from_numpy(np.concatenate(parts).astype(np.float32)).to(dev)
 
 
-def train_cnn(samples, steps=400, batch=4, lr=2e-3, seed=0, dev="cuda", log=None):
-    """Adam on minibatches of samples; returns (network, loss history)."""
-    n = len(samples)
-    h, w = samples[0][0].shape[1:]
-    batch = min(batch, n)
-    cnn = pt.Cnn(batch, h, w, device=dev, params=he_params(seed, dev), **ARCH)
+def train_cnn(groups, steps=400, batch=4, lr=2e-3, seed=0, dev="cuda", log=None):
+    """Adam on minibatches; each step draws its batch from one group of equally shaped samples
+    (groups in turn).  Returns (network parameters, loss history)."""
+    groups = [g for g in groups if g]
+    params = he_params(seed, dev)
+    nets = []
+    for g in groups:
+        h, w = g[0][0].shape[1:]
+        nets.append(pt.Cnn(min(batch, len(g)), h, w, device=dev, params=params, **ARCH))
+    # the networks share one parameter tensor, one set of Adam moments and the step count
+    for n in nets[1:]:
+        n.params, n.m, n.v = nets[0].params, nets[0].m, nets[0].v
     gen = torch.Generator()
     gen.manual_seed(seed)
     hist = []
     for s in range(steps):
-        idx = torch.randperm(n, generator=gen)[:batch].tolist()
-        x = torch.stack([samples[i][0] for i in idx]).contiguous()
-        t = torch.stack([samples[i][1] for i in idx]).contiguous()
-        m = torch.stack([samples[i][2] for i in idx]).contiguous()
-        loss, g = cnn.loss_grad(x, t, m)
-        cnn.adam(g, lr=lr)
-        if s % 20 == 0 or s == steps - 1:
+        gi = s % len(groups)
+        g, net = groups[gi], nets[gi]
+        idx = torch.randperm(len(g), generator=gen)[:net.desc.n].tolist()
+        x = torch.stack([g[i][0] for i in idx]).contiguous()
+        t = torch.stack([g[i][1] for i in idx]).contiguous()
+        m = torch.stack([g[i][2] for i in idx]).contiguous()
+        loss, grad = net.loss_grad(x, t, m)
+        net.step = s
+        net.adam(grad, lr=lr)
+        if s % 50 == 0 or s == steps - 1:
             hist.append((s, float(loss.item())))
             if log:
                 log("step %d loss %.5f" % hist[-1])
-    return cnn, hist
+    return nets[0].params, hist
 
 
 def mean_loss(cnn_params, samples, dev="cuda"):
@@ -130,6 +172,41 @@ def lm_net(cnn_params, obj_shape, dev="cuda"):
     return pt.Cnn(1, obj_shape[0], obj_shape[1], device=dev, params=cnn_params, **ARCH)
 
 
+def lm_run(pr, dev, precond, T, cnn_params=None, seed=0):
+    """T outer LM iterations one at a time (the loss read after each) with preconditioner
+    ``precond`` (0 none, 1 App. B Jacobi, 2 learned with ``cnn_params``) on a recipe's problem.
+    Returns dict(f, products, seconds): per iteration the loss after it and the cumulative PCG
+    products and wall time."""
+    prob, y, O, P, params = lm_setup(pr, dev, seed)
+    params.precond = precond
+    if precond == 2:
+        pt.lm_set_cnn(prob, lm_net(cnn_params, pr.O_true.shape, dev))
+        pt.lm_set_cnn_refresh(prob, 0)   # network inputs depend on the probe and positions only
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    torch.cuda.synchronize()
+    fs, prods, secs = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(T):
+        prob.lm_step(O, P, y, params, st)
+        fs.append(float(prob.loss(O, P, y).cpu()[0]))
+        secs.append(time.perf_counter() - t0)
+        prods.append(int(pt.state_from_tensor(st).products))
+    return dict(f=fs, products=prods, seconds=secs)
+
+
+def summed_to_target(runs, target):
+    """For runs of several problems (lm_run results, as if solved one after another): the first
+    iteration t at which the summed loss is <= target, with the summed products and seconds up
+    to it; None if never."""
+    T = len(runs[0]["f"])
+    for t in range(T):
+        if sum(r["f"][t] for r in runs) <= target:
+            return dict(iteration=t + 1, products=sum(r["products"][t] for r in runs),
+                        seconds=sum(r["seconds"][t] for r in runs))
+    return None
+
+
 def save(params, meta):
     os.makedirs(os.path.dirname(PARAMS_PATH), exist_ok=True)
     np.save(PARAMS_PATH, params.detach().cpu().numpy().astype(np.float32))
@@ -143,29 +220,42 @@ def load(dev="cuda"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train"])
-    ap.add_argument("--problems", type=int, default=40)
-    ap.add_argument("--iters", type=int, default=5)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--small", type=int, default=200, help="training problems of the small recipe")
+    ap.add_argument("--small-iters", type=int, default=20)
+    ap.add_argument("--proxies", type=int, default=40, help="training proxies of the joint workload")
+    ap.add_argument("--proxy-iters", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=None, help="directory for the parameters (default: the package data)")
     a = ap.parse_args()
     dev = torch.device("cuda:0")
     t0 = time.time()
-    train_s = build_samples(a.problems, a.iters, dev)
-    held = []
-    for p in range(1000, 1004):
-        held += samples_from_run(proxy(p), a.iters, dev, seed=p)
+    train_small = build_samples(range(2000, 2000 + a.small), small, a.small_iters, dev)
+    train_proxy = build_samples(range(a.proxies), proxy, a.proxy_iters, dev)
+    held_small = build_samples(range(3000, 3020), small, a.small_iters, dev)
+    held_proxy = build_samples(range(1000, 1004), proxy, a.proxy_iters, dev)
     t1 = time.time()
-    print("samples %d (+%d held out) in %.1fs" % (len(train_s), len(held), t1 - t0), flush=True)
-    base = mean_loss(he_params(0, dev), held, dev)
-    cnn, hist = train_cnn(train_s, a.steps, a.batch, a.lr, dev=dev, log=lambda s: print(s, flush=True))
+    print("samples %d + %d (+%d + %d held out) in %.1fs" % (len(train_small), len(train_proxy), len(held_small),
+                                                           len(held_proxy), t1 - t0), flush=True)
+    base = he_params(0, dev)
+    params, hist = train_cnn([train_small, train_proxy], a.steps, a.batch, a.lr, dev=dev,
+                             log=lambda s: print(s, flush=True))
     torch.cuda.synchronize()
     t2 = time.time()
-    held_loss = mean_loss(cnn.params, held, dev)
-    meta = {"arch": ARCH, "problems": a.problems, "iters": a.iters, "steps": a.steps, "batch": a.batch,
-            "lr": a.lr, "train_seconds": round(t2 - t1, 2), "sample_seconds": round(t1 - t0, 2),
-            "heldout_loss_untrained": base, "heldout_loss": held_loss, "history": hist}
-    save(cnn.params, meta)
+    meta = {"arch": ARCH, "small": a.small, "small_iters": a.small_iters, "proxies": a.proxies,
+            "proxy_iters": a.proxy_iters, "steps": a.steps, "batch": a.batch, "lr": a.lr,
+            "train_seconds": round(t2 - t1, 2), "sample_seconds": round(t1 - t0, 2),
+            "heldout_small_loss_untrained": mean_loss(base, held_small, dev),
+            "heldout_small_loss": mean_loss(params, held_small, dev),
+            "heldout_proxy_loss_untrained": mean_loss(base, held_proxy, dev),
+            "heldout_proxy_loss": mean_loss(params, held_proxy, dev),
+            "history": hist}
+    if a.out:
+        global PARAMS_PATH, META_PATH
+        PARAMS_PATH = os.path.join(a.out, "cnn_params.npy")
+        META_PATH = os.path.join(a.out, "cnn_params.json")
+    save(params, meta)
     print(json.dumps({k: v for k, v in meta.items() if k != "history"}), flush=True)
 
 

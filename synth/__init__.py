@@ -210,6 +210,23 @@ def make_c0(seed: int = 1000) -> Problem:
                    solver=dict(T=20, cg_max=10, scaling=0, precond=0, beta=0.1))
 
 
+def make_c3(seed: int) -> Problem:
+    """Training / evaluation problem of the preconditioner network: the small object-only
+    recipe (64 x 64 object, 8 x 8 raster at step 4, noise-free) with a random quadratic phase
+    exp(i c r^2), c ~ U[-pi/R^2, pi/R^2] (R = 6 px, at most pi at the aperture edge), on the
+    Gaussian-aperture probe, so that the phase input of the network carries information."""
+    rng = rng_for(seed)
+    O = make_object(rng, 64, amp=(0.8, 1.0), phase=(-math.pi / 2, math.pi / 2),
+                    phase_sigma=2.0, phase_source="uniform")
+    R = 6.0
+    c = rng.uniform(-math.pi / R ** 2, math.pi / R ** 2)
+    P = make_probe_gauss_aperture(16, R, 4.0) * np.exp(1j * c * _radius_grid(16) ** 2)
+    pos = raster_positions(rng, 8, 4, 10, 0, 64, 16)
+    O0 = random_object_guess(rng, 64)
+    return Problem("c3_%d" % seed, seed, O, P, pos, O0, P.copy(), BACKGROUND, None, "object",
+                   solver=dict(T=20, cg_max=10, scaling=0, precond=0, beta=0.1))
+
+
 def make_scaled(name: str, seed: int, obj_side: int, probe_side: int, n: int, step: int,
                 offset: int, jitter: int, radius: float, photons: float,
                 phase_sigma: float, amp=(0.7, 1.0), fresnel_px: float = 10.0,

@@ -79,30 +79,28 @@ def test_features_and_learned_diag_match_oracle():
     assert rel(dl, ref) < 1e-5
 
 
-def test_training_reduces_loss_and_lm_runs_with_network():
+def test_trained_network_beats_unpreconditioned_cg():
+    """The network trained by the library's kernels on exact GGN diagonals of LM iterates
+    carries information: on held-out problems its loss is far below the untrained network's
+    (whose constant output is the scalar preconditioner, i.e. unpreconditioned CG).  On six
+    held-out problems solved one after another (small object-only recipe, D = I, 20 outer
+    iterations), the LM preconditioned with it reaches the unpreconditioned LM's final summed
+    loss with fewer PCG products and in less wall time."""
     print("case train", flush=True)
-    samples = learned.samples_from_run(learned.proxy(0), 3, DEV, seed=0)
-    samples += learned.samples_from_run(learned.proxy(1), 3, DEV, seed=1)
-    # on real labels log(d_exact / d_paper) is tiny (the App. B diagonal is nearly exact for the
-    # Gaussian metric); a learnable synthetic target checks that the GPU training reduces the loss
-    synth_s = [(x, (0.5 * x[0:1] - 0.25 * x[1:2]).expand(2, -1, -1).contiguous(), m) for x, _, m in samples]
-    net, hist = learned.train_cnn(synth_s, steps=120, batch=2, lr=3e-3, dev=DEV)
-    assert hist[-1][1] < 0.2 * hist[0][1]
-    real_before = learned.mean_loss(learned.he_params(0, DEV), samples, DEV)
-    assert real_before < 1e-3
-    # LM on a proxy with the learned preconditioner refreshed from the network each iteration
-    pr = learned.proxy(7)
-    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background, device=DEV)
-    y = learned.poisson_data(prob, pr, 7, DEV)
-    O, P = learned._c64(pr.O_init, DEV), learned._c64(pr.P_init, DEV)
-    lm_cnn = learned.lm_net(net.params, pr.O_true.shape, DEV)
-    pt.lm_set_cnn(prob, lm_cnn)
-    params = pt.default_params(scaling=1, precond=2)
-    st = prob.new_state()
-    prob.lm_init(params, st)
-    f0 = float(prob.loss(O, P, y).cpu()[0])
-    prob.lm_solve(O, P, y, params, 5, st)
-    f1 = float(prob.loss(O, P, y).cpu()[0])
-    s = pt.state_from_tensor(st)
-    print("learned LM f %.4e -> %.4e, products %d" % (f0, f1, s.products))
-    assert s.t == 5 and f1 < 0.5 * f0
+    train = learned.build_samples(range(2000, 2032), learned.small, 10, DEV)
+    held = learned.build_samples(range(3000, 3004), learned.small, 10, DEV)
+    params, hist = learned.train_cnn([train], steps=400, batch=8, lr=3e-3, dev=DEV)
+    l0 = learned.mean_loss(learned.he_params(0, DEV), held, DEV)
+    l1 = learned.mean_loss(params, held, DEV)
+    print("held-out loss untrained %.4e trained %.4e" % (l0, l1))
+    assert l1 < 0.1 * l0
+    probs = [learned.small(s) for s in range(3000, 3006)]
+    plain = [learned.lm_run(pr, DEV, 0, 20) for pr in probs]
+    lrn = [learned.lm_run(pr, DEV, 2, 20, cnn_params=params) for pr in probs]
+    target = sum(r["f"][-1] for r in plain)
+    got = learned.summed_to_target(lrn, target)
+    p_prod = sum(r["products"][-1] for r in plain)
+    p_sec = sum(r["seconds"][-1] for r in plain)
+    print("plain: summed f %.3e after %d products %.4f s; learned: %s" % (target, p_prod, p_sec, got))
+    assert got is not None
+    assert got["products"] < p_prod and got["seconds"] < p_sec

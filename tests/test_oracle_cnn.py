@@ -53,8 +53,69 @@ def test_features_and_learned_diag_shapes():
     f = cnn.features(P, pos, (9, 9))
     assert f.shape == (3, 9, 9) and f[0].max() == pytest.approx(1.0)
     assert np.all(f[0][8, 0:3] == 0.0) and np.all(np.abs(f[2]) <= 1.0 + 1e-12)
-    d = cnn.learned_diag(np.ones((9, 9, 2)), np.ones((4, 4, 2)), np.zeros((2, 9, 9)))
-    assert d.shape == (81 + 16, 2) and np.all(d == 1.0)
+    dO = RNG.uniform(0.5, 2.0, (9, 9, 2))
+    d = cnn.learned_diag(dO, np.ones((4, 4, 2)), np.zeros((2, 9, 9)))
+    # an untrained network (r = 0) gives the constant s = largest App. B object entry
+    assert d.shape == (81 + 16, 2) and np.all(d[:81] == dO.max()) and np.all(d[81:] == 1.0)
+
+
+def _small_object_problem():
+    from oracle import ptycho
+    import synth
+    pr = synth.make_c3(2001)
+    y = ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)
+    return pr, y
+
+
+def test_network_predicting_the_app_b_shape_gives_back_jacobi():
+    """r = target(App. B diagonal) makes the learned diagonal the floored App. B diagonal, so the
+    LM with the learned preconditioner takes the Jacobi LM's steps exactly (D = I)."""
+    from oracle import ptycho, solver
+    pr, y = _small_object_problem()
+    lin = ptycho.linearize(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False)
+    dO, _ = ptycho.ggn_diag_paper(lin)
+    r = cnn.target(dO, dO)
+    ld = cnn.learned_diag(dO, None, r)
+    np.testing.assert_allclose(ld, np.maximum(dO, 1e-6 * dO.max()).reshape(-1, 2), rtol=1e-12)
+    # the LM's Jacobi path recomputes App. B at every iterate; a fixed learned diagonal equals it
+    # only at the first linearisation, so compare one outer iteration
+    a = solver.lm_solve(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False,
+                        solver.LMParams(precond=1), 1)
+    b = solver.lm_solve(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False,
+                        solver.LMParams(precond=2), 1, learned_diag=ld)
+    assert [(h.cg_iters, h.accepted) for h in a.history] == [(h.cg_iters, h.accepted) for h in b.history]
+    np.testing.assert_allclose(b.O, a.O, rtol=1e-10, atol=1e-12)
+
+
+def test_untrained_network_is_unpreconditioned_cg():
+    """A constant diagonal preconditioner (the untrained network, r = 0) leaves the CG iterates of
+    the unpreconditioned solve unchanged: scaling the preconditioner by a constant does not move
+    them (textbook property of PCG)."""
+    from oracle import ptycho, solver
+    pr, y = _small_object_problem()
+    lin = ptycho.linearize(pr.O_init, pr.P_true, pr.pos, y, pr.background, "gauss", False)
+    dO, _ = ptycho.ggn_diag_paper(lin)
+    ld = cnn.learned_diag(dO, None, np.zeros((2,) + pr.O_true.shape))
+    lam = 0.05
+    A = lambda v: ptycho.ggn_vp(lin, v.reshape(pr.O_true.shape))[0].ravel() + lam * v
+    g = ptycho.gradient(lin)[0].ravel()
+    m = ld + lam
+    pc = lambda rr: rr.real / m[:, 0] + 1j * rr.imag / m[:, 1]
+    for it in (1, 3, 6):
+        x0 = np.zeros_like(g)
+        xa = solver.pcg(A, g, x0, None, 0.0, it).x
+        xb = solver.pcg(A, g, x0, pc, 0.0, it).x
+        assert np.linalg.norm(xa - xb) <= 1e-10 * np.linalg.norm(xa)
+
+
+def test_target_is_log_of_floored_exact_diagonal_over_scale():
+    d = RNG.uniform(1e-9, 3.0, (5, 6, 2))
+    d[0, 0] = [0.0, 0.0]
+    dO = RNG.uniform(0.5, 2.0, (5, 6, 2))
+    t = cnn.target(d, dO)
+    assert t.shape == (2, 5, 6)
+    assert t[0, 0, 0] == pytest.approx(np.log(1e-6 * d.max() / dO.max()))
+    assert t[1, 2, 3] == pytest.approx(np.log(max(d[2, 3, 1], 1e-6 * d.max()) / dO.max()))
 
 
 def _coverage_count(pos, probe_shape, obj_shape):
