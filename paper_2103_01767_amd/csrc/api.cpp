@@ -116,6 +116,7 @@ ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, con
   a.P = g.P_lin;
   a.y = y;
   PTLM_HIP(launch_tile(g, OP_LINEARIZE, a, s), "linearize");
+  PTLM_HIP(launch_refine(g, a, s), "linearize refine");
   PTLM_HIP(launch_sum_partials(g.partials, g.grid, d_f, 2, s), "linearize sum");
   PTLM_HIP(launch_obj_reduce(g, gO, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gO");
   if (g.joint && gP) PTLM_HIP(launch_probe_reduce(g, gP, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gP");

@@ -143,6 +143,9 @@ struct BatchOps {
   }
   ptlm_status linearize() {
     PTLM_TRY(tiles(OP_LINEARIZE, TK_LIN));
+    // each problem's own refinement launch (as it has alone), where its weights call for one
+    for (size_t c = 0; c < b->classes.size(); ++c)
+      for (const TileJob& j : b->tile_jobs[c * TK_N + TK_LIN]) B_HIP(launch_refine(j.g, j.a, s), "batch refine");
     B_HIP(launch_sum_partials_batch(b->dev<RedJob>(b->L.red_sum), b->n, 2, s), "batch linearize sum");
     return reduce(RK_LIN);
   }

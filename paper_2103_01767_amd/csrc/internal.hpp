@@ -124,6 +124,10 @@ hipError_t launch_tile128(const Geometry& g, int op, const TileArgs& a, hipStrea
 hipError_t launch_tile128_batch(int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
 size_t tile128_lds_bytes();
 int tile128_threads();
+// FP64 refinement of the stored phasors, sqrt-weights and traces at the pixels of extreme GGN
+// weight (kernels_refine.hip); runs after a linearisation with the same geometry and arguments;
+// nothing to do (and no launch) when the geometry keeps no sqrt-weights (Gaussian magnitude GGN)
+hipError_t launch_refine(const Geometry& g, const TileArgs& a, hipStream_t s);
 // 48 x 48 and 96 x 96 tiles (kernels_tile3.hip): radix 16 x 3 and 16 x 6 transforms
 hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
 hipError_t launch_tile3_batch(int L, int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);

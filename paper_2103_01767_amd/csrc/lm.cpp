@@ -111,6 +111,7 @@ struct SingleOps {
     ta.predicate = flag(FL_TILE);
     ta.bg_add = &a.st->sigma;
     LM_HIP(launch_tile(g, OP_LINEARIZE, ta, s), "lm linearize");
+    LM_HIP(launch_refine(g, ta, s), "lm linearize refine");
     LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_TILE)), "lm linearize sum");
     LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_TILE), s), "lm gradient O");
     if (g.joint)
@@ -174,8 +175,13 @@ struct SingleOps {
     ta.predicate = flag(FL_ALIVE);
     ta.bg_add = &a.st->sigma;
     // the loss partials of a linearisation are those of the loss, so F_TRIAL_END reads either
-    if (spec) LM_HIP(launch_tile(spare_geometry(), OP_LINEARIZE, ta, s), "lm trial linearize");
-    else LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
+    if (spec) {
+      const Geometry gs = spare_geometry();
+      LM_HIP(launch_tile(gs, OP_LINEARIZE, ta, s), "lm trial linearize");
+      LM_HIP(launch_refine(gs, ta, s), "lm trial refine");
+    } else {
+      LM_HIP(launch_tile(g, OP_LOSS, ta, s), "lm trial loss");
+    }
     return PTLM_OK;
   }
   // after an accepted trial evaluated as a linearisation: its f and ||ell'||^2 for F_LIN of the

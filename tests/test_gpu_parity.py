@@ -135,27 +135,25 @@ def test_linear_products(probe, joint, metric):
     if joint:
         assert rel(host(oP), rP) < TOL
     # GGN-vector product, plain and damped with a diagonal.  Poisson weights l'' = 2 + 2y/h at
-    # pixels with y >= 1 and h << 1 multiply the single-precision error floor of the transform
-    # (about 1e-9 of the peak, measured equal to NumPy's single-precision FFT); at 256 x 256 and
-    # 0.03 photons per pixel the same arithmetic done with NumPy in single precision already
-    # lands at 0.7-0.9e-5 from the FP64 result, so that one case is held to 2e-5.
-    tol_g = 2 * TOL if (metric == "poisson" and probe[0] * probe[1] >= 65536) else TOL
+    # pixels with y >= 1 and h << 1 multiply the single-precision error of the far field; the
+    # linearisation refines the few pixels of weight above 1e4 in FP64, which holds the 256 x 256
+    # case at 0.03 photons per pixel to the bar like every other.
     GO, GP = ptycho.ggn_vp(lin, vO64, vP64)
     oO, oP = prob.ggn_vp(vOd, vPd)
-    assert rel(host(oO), GO) < tol_g
+    assert rel(host(oO), GO) < TOL
     if joint:
-        assert rel(host(oP), GP) < tol_g
+        assert rel(host(oP), GP) < TOL
     lam = 0.37
     dO = rng.uniform(0.5, 2.0, case["O"].shape + (2,)).astype(np.float32)
     dP = rng.uniform(0.5, 2.0, case["P"].shape + (2,)).astype(np.float32) if joint else None
     oO, oP = prob.ggn_vp(vOd, vPd, lam=lam, dO=to_dev(dO), dP=to_dev(dP) if joint else None)
     refO = GO + lam * solver.apply_diag(dO.reshape(-1, 2).astype(np.float64), vO64.ravel()).reshape(GO.shape)
-    assert rel(host(oO), refO) < tol_g
+    assert rel(host(oO), refO) < TOL
     if joint:
         refP = GP + lam * solver.apply_diag(dP.reshape(-1, 2).astype(np.float64), vP64.ravel()).reshape(GP.shape)
-        assert rel(host(oP), refP) < tol_g
+        assert rel(host(oP), refP) < TOL
     oO, _ = prob.ggn_vp(vOd, vPd, lam=lam)
-    assert rel(host(oO), GO + lam * vO64) < tol_g
+    assert rel(host(oO), GO + lam * vO64) < TOL
     # diagonals
     dOg, dPg = prob.diag(exact=False)
     aO, aP = ptycho.ggn_diag_paper(lin)
@@ -276,13 +274,12 @@ def test_intensity_ggn_products(probe, joint, metric):
     assert rel(host(oO), rO) < TOL
     if joint:
         assert rel(host(oP), rP) < TOL
-    tol_g = 2 * TOL if (metric == "poisson" and probe[0] * probe[1] >= 65536) else TOL
     GO, GP = ptycho.ggn_vp(lin, vO64, vP64)
     oO, oP = prob.ggn_vp(vOd, vPd)
     print("ggn rel", rel(host(oO), GO), rel(host(oP), GP) if joint else 0.0)
-    assert rel(host(oO), GO) < tol_g
+    assert rel(host(oO), GO) < TOL
     if joint:
-        assert rel(host(oP), GP) < tol_g
+        assert rel(host(oP), GP) < TOL
     dOg, dPg = prob.diag(exact=False)
     aO, aP = ptycho.ggn_diag_paper(lin)
     assert rel(host(dOg), aO) < TOL
@@ -371,3 +368,4 @@ def test_corner_and_repeated_positions(probe):
     pos = np.array([[0, 0], [0, rx], [ry, 0], [ry, rx], [ry // 2, rx // 3], [ry // 2, rx // 3], [1, rx - 1]],
                    np.int32)
     _check_products(probe, O, P, pos, "poisson", True, seed=probe[0] + 1)
+
