@@ -214,6 +214,15 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
                         const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
                         void* stream);
 
+/* The same product for 16 x 16 and 32 x 32 probes with the 2D transform done as two complex
+ * L x L matrix products (the DFT matrix of eq:expected_count) on the FP32 matrix cores
+ * (v_mfma_f32_16x16x4_f32, v_mfma_f32_32x32x2_f32) instead of the FFT: the DFT-as-MFMA
+ * variant, for the side-by-side measurement against the FFT kernels that serve ptlm_ggn_vp.
+ * Same arguments, layout and results (to rounding) as ptlm_ggn_vp; PTLM_EINVAL for other
+ * probe shapes. */
+ptlm_status ptlm_ggn_vp_mfma(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
+                             const float* d_dO, const float* d_dP, float* d_outO, float* d_outP, void* stream);
+
 /* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
  * stage = 1: per-position kernel only (accumulates into workspace strips);
  * stage = 2: the finishing reductions only (writes d_outO / d_outP and clears the strips);

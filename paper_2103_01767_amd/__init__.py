@@ -87,6 +87,7 @@ _sig = {
     "ptlm_ggn_vp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
     "ptlm_ggn_vp_stage": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                          _vp]),
+    "ptlm_ggn_vp_mfma": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
     "ptlm_diag": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
     "ptlm_diag_stochastic": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp]),
     "ptlm_lm_init": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp]),
@@ -292,6 +293,19 @@ class Problem:
         _check(_lib.ptlm_ggn_vp(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
                                 float(lam), dOp, dPp, self._o(oO, "outO"),
                                 self._p(oP, "outP") if self.joint else None, _stream()))
+        return oO, oP
+
+    def ggn_vp_mfma(self, vO, vP=None, lam=0.0, out=None):
+        """ptlm_ggn_vp_mfma: the product with the transform on the matrix cores (16 x 16 and 32 x 32
+        probes)."""
+        if out is None:
+            oO = torch.empty(self.obj_shape, dtype=torch.complex64, device=self.device)
+            oP = torch.empty(self.probe_shape, dtype=torch.complex64, device=self.device) if self.joint else None
+        else:
+            oO, oP = out
+        _check(_lib.ptlm_ggn_vp_mfma(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
+                                     float(lam), None, None, self._o(oO, "outO"),
+                                     self._p(oP, "outP") if self.joint else None, _stream()))
         return oO, oP
 
     def ggn_vp_stage(self, stage, vO, vP=None, out=None):

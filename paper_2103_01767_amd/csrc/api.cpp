@@ -479,6 +479,24 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
   return ptlm_ggn_vp_stage(h, d_vO, d_vP, lambda, d_dO, d_dP, d_outO, d_outP, 3, stream);
 }
 
+ptlm_status ptlm_ggn_vp_mfma(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda, const float* d_dO,
+                             const float* d_dP, float* d_outO, float* d_outP, void* stream) {
+  PTLM_CHECK_H(h);
+  if (!d_vO || !d_outO) return fail(PTLM_EINVAL, "null array");
+  if (h->g.joint && (!d_vP || !d_outP)) return fail(PTLM_EINVAL, "joint mode needs d_vP and d_outP");
+  if (!ggnv_mfma_supported(h->g.my, h->g.mx))
+    return fail(PTLM_EINVAL, "ptlm_ggn_vp_mfma: 16 x 16 and 32 x 32 probes only");
+  hipStream_t s = (hipStream_t)stream;
+  TileArgs a{};
+  a.O = h->g.O_lin;
+  a.P = h->g.P_lin;
+  a.vO = (const float2*)d_vO;
+  a.vP = h->g.joint ? (const float2*)d_vP : nullptr;
+  PTLM_HIP(launch_ggnv_mfma(h->g, a, s), "ggn_vp_mfma");
+  return ggnv_impl(h, (const float2*)d_vO, (const float2*)d_vP, lambda, nullptr, d_dO, d_dP, (float2*)d_outO,
+                   (float2*)d_outP, nullptr, s, 2);
+}
+
 ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream) {
   PTLM_CHECK_H(h);
   if (!d_dO) return fail(PTLM_EINVAL, "null array");

@@ -128,6 +128,10 @@ int tile128_threads();
 // weight (kernels_refine.hip); runs after a linearisation with the same geometry and arguments;
 // nothing to do (and no launch) when the geometry keeps no sqrt-weights (Gaussian magnitude GGN)
 hipError_t launch_refine(const Geometry& g, const TileArgs& a, hipStream_t s);
+// DFT-as-MFMA GGN-vector kernel for 16 x 16 and 32 x 32 probes (kernels_dft_mfma.hip), same
+// scratch as the tile kernels
+bool ggnv_mfma_supported(int my, int mx);
+hipError_t launch_ggnv_mfma(const Geometry& g, const TileArgs& a, hipStream_t s);
 // 48 x 48 and 96 x 96 tiles (kernels_tile3.hip): radix 16 x 3 and 16 x 6 transforms
 hipError_t launch_tile3(const Geometry& g, int op, const TileArgs& a, hipStream_t s);
 hipError_t launch_tile3_batch(int L, int op, const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);

@@ -369,3 +369,31 @@ def test_corner_and_repeated_positions(probe):
                    np.int32)
     _check_products(probe, O, P, pos, "poisson", True, seed=probe[0] + 1)
 
+
+@pytest.mark.parametrize("metric", ["gauss", "poisson"])
+@pytest.mark.parametrize("joint", [False, True])
+@pytest.mark.parametrize("L", [16, 32])
+def test_ggn_vp_mfma_matches_oracle(L, joint, metric):
+    """The DFT-as-MFMA product (16 x 16 and 32 x 32 probes, transform on the matrix cores)
+    against the FP64 oracle and against the FFT kernel's product, on a raster with
+    multi-position segments."""
+    print("case ggn mfma", L, joint, metric, flush=True)
+    case = make_case((L, L), 9, 10, L // 4, metric=metric, joint=joint, seed=91 + L)
+    prob = problem(case)
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, metric, joint)
+    prob.linearize(O, P, y)
+    rng = np.random.default_rng(12)
+    vO = c64(synth.random_complex(rng, case["O"].shape))
+    vP = c64(synth.random_complex(rng, case["P"].shape)) if joint else None
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128) if joint else None)
+    mO, mP = prob.ggn_vp_mfma(to_dev(vO), to_dev(vP) if joint else None)
+    fO, fP = prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None)
+    assert rel(host(mO), GO) < TOL
+    assert rel(host(mO), host(fO)) < TOL
+    if joint:
+        assert rel(host(mP), GP) < TOL
+        assert rel(host(mP), host(fP)) < TOL
+    with pytest.raises(pt.PtlmError):
+        other = problem(make_case((24, 24), 3, 3, 8, seed=92))
+        other.ggn_vp_mfma(to_dev(c64(np.zeros(other.obj_shape))), to_dev(c64(np.zeros(other.probe_shape))))
