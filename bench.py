@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--calls", type=int, default=50, help="isolated GGN-vector product calls")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-calls", type=int, default=12)
+    ap.add_argument("--cpu-calls", type=int, default=8)
     ap.add_argument("--no-lm", action="store_true", help="skip the LM time-to-target comparison")
     ap.add_argument("--lm-iters", type=int, default=60)
     ap.add_argument("--no-next", action="store_true",
@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the large-scan GGN-vector timing")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default segment count")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the DFT-as-MFMA comparison (16x16 and 32x32 probes)")
+    ap.add_argument("--only-mfma-trial", action="store_true",
+                    help="only the DFT-as-MFMA comparison (one JSON line; for profiling)")
     ap.add_argument("--only-large-scan", action="store_true",
                     help="only time the large-scan GGN-vector product (one JSON line; for profiling)")
     ap.add_argument("--batch-iters", type=int, default=20)
@@ -113,6 +116,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the CPU oracle first, while this process has no GPU state (its worker processes fork)
+    profiling_only = args.only_large_scan or args.only_mfma_trial
+    cpu = None if (args.no_cpu or profiling_only) else cpu_baseline(args.cpu_calls)
+
     import torch
     import synth
     import paper_2103_01767_amd as pt
@@ -121,6 +128,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.only_large_scan:
         print(json.dumps(large_scan(dev, args.calls, args.large_lm_iters)), flush=True)
+        return
+    if args.only_mfma_trial:
+        print(json.dumps(mfma_trial(dev, args.calls)), flush=True)
         return
     pr = synth.make_c1()
     K = pr.K
@@ -166,14 +176,15 @@ def main():
     kern_bytes, achieved_gbs, fft_tflops = iso["bytes_per_launch"], iso["achieved_gbs"], iso["fft_tflops"]
     vO, vP = iso["vO"], iso["vP"]
     large = None if args.no_c4 else large_scan(dev, max(3, args.calls // 10), args.large_lm_iters)
+    mfma = None if args.no_mfma else mfma_trial(dev, args.calls)
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
     nxt = None if args.no_next else lm_variants(pr, dev, args.lm_iters, args.poisson_iters)
     batch = None if args.no_batch else batch_measure(dev, args.batch_iters)
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(pr, O, P, y, vO, vP, args.cpu_calls)
+    if cpu is not None:
+        cpu["lm_small_object_only"].update(gpu_lm_seconds(dev, "small", 20))
+        cpu["lm_512_128"].update(gpu_lm_seconds(dev, "512_128", cpu["lm_512_128"]["iters"]))
 
     line = {
         "metric": METRIC,
@@ -203,8 +214,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if tune_scale == TRAFFIC["grid_scale"] else None,
-                     "kernel": "tile_kernel<128,128,GGNV>", "bytes_per_launch": kern_bytes},
+                     "kernel": "t128::kernel<GGNV> (128x128 tile kernel)", "bytes_per_launch": kern_bytes},
         "ggnv_large_scan": large,
+        "dft_mfma_trial": mfma,
         "lm_time_to_target": lm,
         "lm_variants": nxt,
         "batch_uneven": batch,
@@ -248,6 +260,55 @@ def ggnv_isolated(prob, dev, calls, stream):
     return {"kernel_ms": kern_ms, "call_ms": call_ms, "reduce_ms": red_ms, "bytes_per_launch": kern_bytes,
             "achieved_gbs": kern_bytes / (kern_ms * 1e-3) / 1e9, "fft_tflops": fft_flops / (kern_ms * 1e-3) / 1e12,
             "positions_per_s": K / (call_ms * 1e-3), "vO": vO, "vP": vP}
+
+
+def mfma_trial(dev, calls):
+    """The DFT-as-MFMA GGN-vector product (ptlm_ggn_vp_mfma) against the FFT tile kernel's
+    (ptlm_ggn_vp) on two small-probe scans, joint, object 512x512, raster step 4: probe 16x16
+    with a 120x120 raster (14 400 positions) and probe 32x32 with a 116x116 raster (13 456
+    positions), each linearised at a seeded random point with seeded stand-in counts (the
+    product's cost does not depend on the data).  Whole calls (per-position kernel plus the same
+    reductions), HIP events on the library's stream, median of `calls`."""
+    import torch
+    import synth
+    import paper_2103_01767_amd as pt
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    stream = torch.cuda.current_stream()
+    out_all = {}
+    for L, n in ((16, 120), (32, 116)):
+        rng = np.random.default_rng(16016 + L)
+        step, side = 4, 512
+        base = 8 + step * np.arange(n)
+        ry, rx = np.meshgrid(base, base, indexing="ij")
+        pos = np.stack([ry.ravel(), rx.ravel()], 1).astype(np.int32)
+        O = c64(synth.random_complex(rng, (side, side)))
+        P = c64(synth.make_probe_fresnel(rng, L, 0.35 * L, 2.0))
+        prob = pt.Problem((side, side), (L, L), pos, metric="gauss", mode="joint", background=1e-8, device=dev)
+        y = torch.from_numpy(synth.surrogate_counts(rng, len(pos), (L, L), 1e3)).to(dev)
+        prob.linearize(O, P, y)
+        vO, vP = c64(synth.random_complex(rng, (side, side))), c64(synth.random_complex(rng, (L, L)))
+        out = (torch.empty_like(vO), torch.empty_like(vP))
+        res = {"workload": "joint, object 512x512, probe %dx%d, %dx%d raster step 4 (%d positions)"
+               % (L, L, n, n, n * n)}
+        for name, fn in (("fft", prob.ggn_vp), ("mfma", prob.ggn_vp_mfma)):
+            for _ in range(3):
+                fn(vO, vP, out=out)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+            for a, b in ev:
+                a.record(stream)
+                fn(vO, vP, out=out)
+                b.record(stream)
+            torch.cuda.synchronize()
+            res[name + "_call_ms"] = round(float(np.median([a.elapsed_time(b) for a, b in ev])), 4)
+        f_out = prob.ggn_vp(vO, vP)
+        m_out = prob.ggn_vp_mfma(vO, vP)
+        res["rel_diff"] = float(max(torch.linalg.norm(f_out[i] - m_out[i]) / torch.linalg.norm(f_out[i])
+                                    for i in (0, 1)))
+        res["mfma_over_fft"] = round(res["mfma_call_ms"] / res["fft_call_ms"], 3)
+        out_all["%dx%d" % (L, L)] = res
+        del prob
+    return out_all
 
 
 def large_scan(dev, calls, lm_iters=0):
@@ -532,25 +593,153 @@ def batch_measure(dev, iters):
     return out
 
 
-def cpu_baseline(pr, O, P, y, vO, vP, calls):
-    """The FP64 oracle's GGN-vector product on the same linearisation point, timed on the host."""
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count()}
+
+
+def _oracle_worker(conn, O, P, pos, y, b):
+    """One process of the parallel oracle product: the linearisation of its positions, then
+    GGN-vector products on request (the unchanged oracle; positions contribute additively)."""
     from oracle import ptycho
-    Oh = O.cpu().numpy().astype(np.complex128)
-    Ph = P.cpu().numpy().astype(np.complex128)
-    yh = y.cpu().numpy().astype(np.float64)
-    vOh = vO.cpu().numpy().astype(np.complex128)
-    vPh = vP.cpu().numpy().astype(np.complex128)
+    lin = ptycho.linearize(O, P, pos, y, b, "gauss", True)
+    conn.send("ready")
+    while True:
+        msg = conn.recv()
+        if msg is None:
+            break
+        conn.send(ptycho.ggn_vp(lin, *msg))
+    conn.close()
+
+
+def cpu_baseline(calls, max_workers=16):
+    """The FP64 oracle timed on the host, before the GPU is touched (worker processes are
+    forked from a process without GPU state).  GGN-vector products of the 512/128 workload at
+    its initial guess with seeded directions: on one core, and over W = min(cores, 16)
+    processes each holding a contiguous block of the scan positions (partial products summed);
+    the small object-only workload's oracle LM (20 outer iterations) timed here, and the
+    stored 512/128 oracle LM's wall time with the host it ran on."""
+    import multiprocessing as mp
+    import synth
+    from oracle import ptycho, solver
+    pr = synth.make_c1()
+    gold = os.path.join(HERE, "tests", "golden")
+    Oh = pr.O_init.astype(np.complex64).astype(np.complex128)
+    Ph = pr.P_init.astype(np.complex64).astype(np.complex128)
+    yh = np.load(os.path.join(gold, "c1_counts.npz"))["y"].astype(np.float64)
+    rng = np.random.default_rng(7)
+    vO = synth.random_complex(rng, Oh.shape)
+    vP = synth.random_complex(rng, Ph.shape)
+    out = {"kind": "oracle", "unit": "scan-positions/s", "host": host_info()}
+
+    # one core
     lin = ptycho.linearize(Oh, Ph, pr.pos, yh, pr.background, "gauss", True)
     times = []
     for _ in range(max(calls, 1)):
         t = time.perf_counter()
-        ptycho.ggn_vp(lin, vOh, vPh)
+        ref = ptycho.ggn_vp(lin, vO, vP)
         times.append(time.perf_counter() - t)
-    per = float(np.median(times))
-    return {"value": round(pr.K / per, 2), "unit": "scan-positions/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full GGN-vector products (1600 positions, 128x128, complex128 NumPy FFT, "
-                      "single thread) at the linearisation point of the GPU run; median %.2f s each"
-                      % (len(times), per)}
+    del lin
+    per1 = float(np.median(times))
+    out["w1"] = {"value": round(pr.K / per1, 2), "cores": 1, "seconds_per_product": round(per1, 3),
+                 "products": len(times)}
+
+    # all cores (at most 16 worker processes)
+    W = max(1, min(os.cpu_count() or 1, max_workers))
+    ctx = mp.get_context("fork")
+    cuts = np.linspace(0, pr.K, W + 1).astype(int)
+    pipes, procs = [], []
+    for w in range(W):
+        a, b = cuts[w], cuts[w + 1]
+        parent, child = ctx.Pipe()
+        proc = ctx.Process(target=_oracle_worker, args=(child, Oh, Ph, pr.pos[a:b], yh[a:b], pr.background))
+        proc.start()
+        pipes.append(parent)
+        procs.append(proc)
+    for c in pipes:
+        c.recv()
+    times = []
+    err = None
+    for _ in range(max(calls, 1)):
+        t = time.perf_counter()
+        for c in pipes:
+            c.send((vO, vP))
+        parts = [c.recv() for c in pipes]
+        gO = sum(p_[0] for p_ in parts)
+        gP = sum(p_[1] for p_ in parts)
+        times.append(time.perf_counter() - t)
+        err = max(float(np.linalg.norm(gO - ref[0]) / np.linalg.norm(ref[0])),
+                  float(np.linalg.norm(gP - ref[1]) / np.linalg.norm(ref[1])))
+    for c in pipes:
+        c.send(None)
+    for proc in procs:
+        proc.join()
+    perW = float(np.median(times))
+    out["wall"] = {"value": round(pr.K / perW, 2), "cores": W, "seconds_per_product": round(perW, 3),
+                   "products": len(times), "rel_diff_vs_one_core": err}
+    out["value"] = out["wall"]["value"]
+    out["cores"] = W
+    out["sample"] = ("%d GGN-vector products of the 512/128 workload (1600 positions, 128x128, complex128 "
+                     "NumPy FFT) on 1 core and %d over %d processes (contiguous position blocks), at the "
+                     "initial guess with seeded directions; median %.2f s / %.3f s per product"
+                     % (out["w1"]["products"], len(times), W, per1, perW))
+
+    # oracle LM wall time: the small object-only workload here, the 512/128 one stored
+    pr0 = synth.make_c0()
+    P0 = pr0.P_true.astype(np.complex64).astype(np.complex128)
+    y0 = ptycho.intensity(pr0.O_true.astype(np.complex64).astype(np.complex128), P0, pr0.pos,
+                          pr0.background).astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    r0 = solver.lm_solve(pr0.O_init.astype(np.complex64).astype(np.complex128), P0, pr0.pos, y0, pr0.background,
+                         "gauss", False, solver.LMParams(), 20)
+    out["lm_small_object_only"] = {"oracle_seconds": round(time.perf_counter() - t, 3), "iters": 20,
+                                   "f_final": r0.f, "cores": 1}
+    ref1 = json.load(open(os.path.join(gold, "c1_oracle_lm.json")))
+    out["lm_512_128"] = {"oracle_seconds": ref1["seconds"], "iters": ref1["T"], "f_final": ref1["f_final"],
+                         "host": ref1.get("host"), "source": "tests/golden/c1_oracle_lm.json"}
+    return out
+
+
+def gpu_lm_seconds(dev, which, iters):
+    """GPU wall time of the LM the oracle's timed LM runs: the small object-only workload (plain
+    LM, noise-free data) or the 512/128 one (D = Dg(G), Jacobi PCG, the stored counts), from the
+    same initial guess, `iters` outer iterations in one ptlm_lm_solve call."""
+    import torch
+    import synth
+    import paper_2103_01767_amd as pt
+    c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
+    if which == "small":
+        pr = synth.make_c0()
+        P = pr.P_true
+        prob = pt.Problem(pr.O_true.shape, P.shape, pr.pos, mode="object", background=pr.background, device=dev)
+        y = prob.forward(c64(pr.O_true), c64(P))
+        y = (y.double() ** 2).float().contiguous()
+        params = pt.default_params()
+        O = c64(pr.O_init)
+        Pd = c64(P)
+    else:
+        pr = synth.make_c1()
+        prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode="joint", background=pr.background,
+                          device=dev)
+        y = torch.from_numpy(np.load(os.path.join(HERE, "tests", "golden", "c1_counts.npz"))["y"]
+                             .astype(np.float32)).to(dev)
+        params = pt.default_params(scaling=1, precond=1, cg_max=10)
+        O, Pd = c64(pr.O_init), c64(pr.P_init)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    prob.lm_solve(O, Pd, y, params, iters, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    return {"gpu_seconds": round(el, 4), "iters": iters, "f_final": float(prob.loss(O, Pd, y).cpu()[0])}
 
 
 if __name__ == "__main__":
