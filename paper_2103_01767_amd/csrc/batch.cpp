@@ -41,7 +41,7 @@ enum RedKind { RK_LIN = 0, RK_WARM = 1, RK_P = 2, RK_DIAG = 3, RK_N = 4 };
 struct TableLayout {
   size_t jb_tile_off[16];   // per shape class: int job_of_block[nb_tile]
   size_t tile_jobs_off[16][TK_N];
-  size_t jb_obj, jb_prb, jb_dprb, jb_vec, jb_copy_lin, jb_copy_acc;
+  size_t jb_obj, jb_prb, jb_prb1, jb_dprb, jb_vec, jb_copy_lin, jb_copy_acc;
   size_t red_obj[RK_N], red_prb[RK_N], red_sum;
   size_t lm_jobs, copy_lin, copy_acc, copy_take, copy_keep;
   size_t bytes;
@@ -64,11 +64,11 @@ struct ptlm_batch {
   size_t tables_off = 0;
   TableLayout L{};
   std::vector<ShapeClass> classes;
-  int nb_obj = 0, nb_prb = 0, nb_dprb = 0, nb_vec = 0, nb_copy_lin = 0, nb_copy_acc = 0;
-  std::vector<int> obj_b0, prb_b0, dprb_b0, vec_b0;
+  int nb_obj = 0, nb_prb = 0, nb_prb1 = 0, nb_dprb = 0, nb_vec = 0, nb_copy_lin = 0, nb_copy_acc = 0;
+  std::vector<int> obj_b0, prb_b0, prb1_b0, dprb_b0, vec_b0;
   // host copies of the tables (kept alive for the asynchronous uploads)
   std::vector<std::vector<int>> jb_tile;
-  std::vector<int> jb_obj, jb_prb, jb_dprb, jb_vec, jb_copy_lin, jb_copy_acc;
+  std::vector<int> jb_obj, jb_prb, jb_prb1, jb_dprb, jb_vec, jb_copy_lin, jb_copy_acc;
   std::vector<std::vector<TileJob>> tile_jobs;  // [class * TK_N + kind]
   std::vector<RedJob> red_obj[RK_N], red_prb[RK_N], red_sum;
   std::vector<LMJob> lm_jobs;
@@ -132,7 +132,8 @@ struct BatchOps {
   ptlm_status reduce(int kind) {
     B_HIP(launch_obj_reduce_batch(b->dev<RedJob>(b->L.red_obj[kind]), b->dev<int>(b->L.jb_obj), b->nb_obj, s),
           "batch object reduce");
-    B_HIP(launch_probe_reduce_batch(b->dev<RedJob>(b->L.red_prb[kind]), b->dev<int>(b->L.jb_prb), b->nb_prb, s),
+    B_HIP(launch_probe_reduce_batch(b->dev<RedJob>(b->L.red_prb[kind]), b->dev<int>(b->L.jb_prb1), b->nb_prb1,
+                                    b->dev<int>(b->L.jb_prb), b->nb_prb, s),
           "batch probe reduce");
     return PTLM_OK;
   }
@@ -251,14 +252,15 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
       C.block0.push_back(append_run(b.jb_tile[c], (int)m, plans[C.probs[m]].grid, 8));
     C.nblocks = (int)b.jb_tile[c].size();
   }
-  b.jb_obj.clear(); b.jb_prb.clear(); b.jb_dprb.clear(); b.jb_vec.clear(); b.jb_copy_lin.clear();
+  b.jb_obj.clear(); b.jb_prb.clear(); b.jb_prb1.clear(); b.jb_dprb.clear(); b.jb_vec.clear(); b.jb_copy_lin.clear();
   b.jb_copy_acc.clear();
-  b.obj_b0.assign(n, 0); b.prb_b0.assign(n, 0); b.dprb_b0.assign(n, 0); b.vec_b0.assign(n, 0);
+  b.obj_b0.assign(n, 0); b.prb_b0.assign(n, 0); b.prb1_b0.assign(n, 0); b.dprb_b0.assign(n, 0); b.vec_b0.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     const Plan& p = plans[i];
     const int M = p.d.my * p.d.mx;
     b.obj_b0[i] = append_run(b.jb_obj, i, p.otx * p.oty, 1);
     b.prb_b0[i] = append_run(b.jb_prb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);
+    b.prb1_b0[i] = append_run(b.jb_prb1, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 * prb_chunk_count(p.nseg) : 0, 1);
     b.dprb_b0[i] = append_run(b.jb_dprb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);  // 64 pixels a block
     b.vec_b0[i] = append_run(b.jb_vec, i, lm_vec_blocks(p.nvec), 1);
   }
@@ -280,6 +282,7 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
   }
   b.nb_obj = (int)b.jb_obj.size();
   b.nb_prb = (int)b.jb_prb.size();
+  b.nb_prb1 = (int)b.jb_prb1.size();
   b.nb_dprb = (int)b.jb_dprb.size();
   b.nb_vec = (int)b.jb_vec.size();
   b.nb_copy_lin = (int)b.jb_copy_lin.size();
@@ -298,6 +301,7 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
   }
   L.jb_obj = take(b.jb_obj.size() * sizeof(int));
   L.jb_prb = take(b.jb_prb.size() * sizeof(int));
+  L.jb_prb1 = take(b.jb_prb1.size() * sizeof(int));
   L.jb_dprb = take(b.jb_dprb.size() * sizeof(int));
   L.jb_vec = take(b.jb_vec.size() * sizeof(int));
   L.jb_copy_lin = take(b.jb_copy_lin.size() * sizeof(int));
@@ -375,6 +379,7 @@ ptlm_status ptlm_batch_create(int32_t n, const ptlm_desc* descs, const int32_t* 
     e = up(b->L.jb_tile_off[c], b->jb_tile[c].data(), b->jb_tile[c].size() * sizeof(int));
   if (e == hipSuccess) e = up(b->L.jb_obj, b->jb_obj.data(), b->jb_obj.size() * sizeof(int));
   if (e == hipSuccess) e = up(b->L.jb_prb, b->jb_prb.data(), b->jb_prb.size() * sizeof(int));
+  if (e == hipSuccess) e = up(b->L.jb_prb1, b->jb_prb1.data(), b->jb_prb1.size() * sizeof(int));
   if (e == hipSuccess) e = up(b->L.jb_dprb, b->jb_dprb.data(), b->jb_dprb.size() * sizeof(int));
   if (e == hipSuccess) e = up(b->L.jb_vec, b->jb_vec.data(), b->jb_vec.size() * sizeof(int));
   if (e == hipSuccess) e = up(b->L.jb_copy_lin, b->jb_copy_lin.data(), b->jb_copy_lin.size() * sizeof(int));
@@ -500,6 +505,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
       ro.block0 = b->obj_b0[i];
       ro.nblk = g.otiles_x * g.otiles_y;
       rp.block0 = k == RK_DIAG ? b->dprb_b0[i] : b->prb_b0[i];
+      rp.block1 = b->prb1_b0[i];
       rp.nblk = g.joint ? (int)((M + 63) / 64) : 0;  // 64 probe pixels per block (reduction and diagonal)
       b->red_obj[k][i] = ro;
       b->red_prb[k][i] = rp;

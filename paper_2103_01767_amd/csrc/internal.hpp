@@ -93,6 +93,7 @@ struct RedJob {
   double* sums;           // partial-sum output (sum kernels)
   int block0;
   int nblk;
+  int block1;  // first block of the job in a second launch (probe reduction pass one)
 };
 
 struct CopyJob {
@@ -143,7 +144,10 @@ int tile3_per_wg(int L);
 // lam_dev (nullable) overrides lam with a device scalar.
 hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const double* lam_dev, const float* dO,
                              const float2* vO, const int* predicate, hipStream_t s);
-// out_P = sum of probe partials [+ lam * dP .* vP]
+// out_P = sum of probe partials [+ lam * dP .* vP]; with more than PRB_CHUNK segments in two
+// passes, the first summing chunks of PRB_CHUNK partials in place (the partials are consumed)
+constexpr int PRB_CHUNK = 32;
+__host__ __device__ inline int prb_chunk_count(int nseg) { return nseg > PRB_CHUNK ? (nseg + PRB_CHUNK - 1) / PRB_CHUNK : 0; }
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* predicate, hipStream_t s);
 // out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)
@@ -158,7 +162,10 @@ hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, in
 int copy_blocks(size_t n);
 // batched forms (job tables in device memory)
 hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
-hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
+// pass one over jb1 (nb1 blocks: jobs with more than PRB_CHUNK segments, block1 their first),
+// then the final pass over jb (nb blocks)
+hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb1, int nb1, const int* jb, int nb,
+                                     hipStream_t s);
 hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hipStream_t s);
 hipError_t launch_diag_paper_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
                                    const int* prbjb, int nbp, hipStream_t s);

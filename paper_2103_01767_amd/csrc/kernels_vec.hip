@@ -80,8 +80,43 @@ __global__ __launch_bounds__(256) void obj_reduce_batch_kernel(const RedJob* __r
   obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
 }
 
-// out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v]; 64 pixels per block, the segment
-// sum split four ways and combined in LDS in a fixed order.
+// Probe-sized sums of the per-segment probe partials, 64 pixels per block.  With at most
+// PRB_CHUNK segments one pass: out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v].  With more,
+// two passes in place: pass one (one block per 64 pixels and chunk) replaces row c * PRB_CHUNK
+// of probe_part by the sum of its chunk's rows, pass two sums the chunk rows.  Every sum is split
+// four ways over its rows and the four parts are added in a fixed order, so the result depends
+// only on the segment count.  The partials are scratch of one product (every per-position
+// kernel rewrites them), so overwriting them loses nothing.
+__device__ __forceinline__ float2 rows_sum4(const float2* p, int count, size_t stride, bool valid, int grp, int lane,
+                                            float2 (*sh)[64]) {
+  float2 acc = make_float2(0.f, 0.f);
+  if (valid) {
+#pragma unroll 8
+    for (int i = grp; i < count; i += 4) {
+      const float2 val = p[(size_t)i * stride];
+      acc.x += val.x;
+      acc.y += val.y;
+    }
+  }
+  sh[grp][lane] = acc;
+  __syncthreads();
+  return cadd(cadd(sh[0][lane], sh[1][lane]), cadd(sh[2][lane], sh[3][lane]));
+}
+
+// pass one of a scan with more than PRB_CHUNK segments: block (bx, chunk c)
+__device__ __forceinline__ void probe_chunk_body(const Geometry& g, const int* pred, int bx, int c) {
+  if (pred && *pred == 0) return;
+  __shared__ float2 sh[4][64];
+  const int M = g.my * g.mx;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int m = bx * 64 + lane;
+  const int s0 = c * PRB_CHUNK, cnt = min(PRB_CHUNK, g.nseg - s0);
+  float2* row = g.probe_part + (size_t)s0 * M + m;
+  // every read of the chunk's rows is done before the barrier inside, the one write after it
+  const float2 acc = rows_sum4(row, cnt, M, m < M, grp, lane, sh);
+  if (grp == 0 && m < M) *row = acc;
+}
+
 __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out, float lam_h, const double* lam_dev,
                                                   const float* d, const float2* v, const int* pred, int bx) {
   if (pred && *pred == 0) return;
@@ -90,20 +125,10 @@ __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out
   const int M = g.my * g.mx;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int m = bx * 64 + lane;
-  float2 acc = make_float2(0.f, 0.f);
-  if (m < M) {
-    const float2* p = g.probe_part + m;
-#pragma unroll 8
-    for (int s = grp; s < g.nseg; s += 4) {
-      const float2 val = p[(size_t)s * M];
-      acc.x += val.x;
-      acc.y += val.y;
-    }
-  }
-  sh[grp][lane] = acc;
-  __syncthreads();
+  const bool two = g.nseg > PRB_CHUNK;
+  float2 acc = rows_sum4(g.probe_part + m, two ? prb_chunk_count(g.nseg) : g.nseg,
+                         two ? (size_t)PRB_CHUNK * M : (size_t)M, m < M, grp, lane, sh);
   if (grp != 0 || m >= M) return;
-  acc = cadd(cadd(sh[0][lane], sh[1][lane]), cadd(sh[2][lane], sh[3][lane]));
   if (lam != 0.f && v) {
     const float2 vv = v[m];
     if (d) {
@@ -117,9 +142,21 @@ __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out
   out[m] = acc;
 }
 
+__global__ __launch_bounds__(256) void probe_chunk_kernel(Geometry g, const int* pred) {
+  probe_chunk_body(g, pred, blockIdx.x, blockIdx.y);
+}
+
 __global__ __launch_bounds__(256) void probe_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
                                                            const float* d, const float2* v, const int* pred) {
   probe_reduce_body(g, out, lam_h, lam_dev, d, v, pred, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void probe_chunk_batch_kernel(const RedJob* __restrict__ jobs,
+                                                                const int* __restrict__ job_of_block) {
+  const RedJob& J = jobs[job_of_block[blockIdx.x]];
+  const int l = (int)blockIdx.x - J.block1;
+  const int pb = (J.g.my * J.g.mx + 63) / 64;
+  probe_chunk_body(J.g, J.pred, l % pb, l / pb);
 }
 
 __global__ __launch_bounds__(256) void probe_reduce_batch_kernel(const RedJob* __restrict__ jobs,
@@ -296,7 +333,13 @@ hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* jb, int nb, hi
   hipLaunchKernelGGL(obj_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
   return hipGetLastError();
 }
-hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb, int nb, hipStream_t s) {
+hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb1, int nb1, const int* jb, int nb,
+                                     hipStream_t s) {
+  if (nb1 > 0) {
+    hipLaunchKernelGGL(probe_chunk_batch_kernel, dim3(nb1), dim3(256), 0, s, jobs, jb1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(probe_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
   return hipGetLastError();
@@ -330,6 +373,11 @@ hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const 
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* pred, hipStream_t s) {
   const int M = g.my * g.mx;
+  if (g.nseg > PRB_CHUNK) {
+    hipLaunchKernelGGL(probe_chunk_kernel, dim3((M + 63) / 64, prb_chunk_count(g.nseg)), dim3(256), 0, s, g, pred);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(probe_reduce_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, outP, (float)lam, lam_dev, dP,
                      vP, pred);
   return hipGetLastError();
