@@ -170,7 +170,7 @@ def main():
 
     # ---------------- dominant kernel alone: per-position GGN-vector kernel (HIP events)
     prob.linearize(O, P, y)
-    tune_scale, tune_ms = prob.autotune(reps=5) if not args.no_autotune else (1.0, None)
+    tune_scale, tune_ms, tune_xf = prob.autotune(reps=5) if not args.no_autotune else (1.0, None, "fft")
     iso = ggnv_isolated(prob, dev, args.calls, stream)
     kern_ms, call_ms, red_ms = iso["kernel_ms"], iso["call_ms"], iso["reduce_ms"]
     kern_bytes, achieved_gbs, fft_tflops = iso["bytes_per_launch"], iso["achieved_gbs"], iso["fft_tflops"]
@@ -208,7 +208,8 @@ def main():
         "ggnv_positions_per_s_isolated": round(K / (call_ms * 1e-3), 1),
         "ggnv_kernel_ms": round(kern_ms, 4),
         "ggnv_reduce_ms": round(red_ms, 4),
-        "autotune": {"grid_scale": tune_scale, "ms_at_scales_0.5_1_2": tune_ms},
+        "autotune": {"grid_scale": tune_scale, "transform": tune_xf,
+                     "ms_at_scales_0.5_1_2": tune_ms[:3] if tune_ms else None},
         "fft_tflops": round(fft_tflops, 2),
         "fft_frac_fp32_peak": round(fft_tflops / FP32_PEAK_TFLOPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -263,8 +264,8 @@ def ggnv_isolated(prob, dev, calls, stream):
 
 
 def mfma_trial(dev, calls):
-    """The DFT-as-MFMA GGN-vector product (ptlm_ggn_vp_mfma) against the FFT tile kernel's
-    (ptlm_ggn_vp) on two small-probe scans, joint, object 512x512, raster step 4: probe 16x16
+    """The GGN-vector product with the DFT as matrix products on the matrix cores against the
+    FFT tile kernel's (ptlm_set_transform "mfma" / "fft") on two small-probe scans, joint, object 512x512, raster step 4: probe 16x16
     with a 120x120 raster (14 400 positions) and probe 32x32 with a 116x116 raster (13 456
     positions), each linearised at a seeded random point with seeded stand-in counts (the
     product's cost does not depend on the data).  Whole calls (per-position kernel plus the same
@@ -290,7 +291,9 @@ def mfma_trial(dev, calls):
         out = (torch.empty_like(vO), torch.empty_like(vP))
         res = {"workload": "joint, object 512x512, probe %dx%d, %dx%d raster step 4 (%d positions)"
                % (L, L, n, n, n * n)}
-        for name, fn in (("fft", prob.ggn_vp), ("mfma", prob.ggn_vp_mfma)):
+        for name in ("fft", "mfma"):
+            prob.set_transform(name)
+            fn = prob.ggn_vp
             for _ in range(3):
                 fn(vO, vP, out=out)
             torch.cuda.synchronize()
@@ -301,8 +304,10 @@ def mfma_trial(dev, calls):
                 b.record(stream)
             torch.cuda.synchronize()
             res[name + "_call_ms"] = round(float(np.median([a.elapsed_time(b) for a, b in ev])), 4)
+        prob.set_transform("fft")
         f_out = prob.ggn_vp(vO, vP)
-        m_out = prob.ggn_vp_mfma(vO, vP)
+        prob.set_transform("mfma")
+        m_out = prob.ggn_vp(vO, vP)
         res["rel_diff"] = float(max(torch.linalg.norm(f_out[i] - m_out[i]) / torch.linalg.norm(f_out[i])
                                     for i in (0, 1)))
         res["mfma_over_fft"] = round(res["mfma_call_ms"] / res["fft_call_ms"], 3)

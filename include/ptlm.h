@@ -56,6 +56,8 @@ typedef enum {
 typedef enum { PTLM_GAUSS = 0, PTLM_POISSON = 1 } ptlm_metric; /* eq:ell_magnitude */
 typedef enum { PTLM_OBJECT = 0, PTLM_JOINT = 1 } ptlm_mode;    /* SPR eq:cdp / BPR eq:bp */
 typedef enum { PTLM_GGN_MAGNITUDE = 0, PTLM_GGN_INTENSITY = 1 } ptlm_ggn;
+/* How the GGN-vector product applies F (a project choice, ptlm_set_transform). */
+typedef enum { PTLM_TRANSFORM_FFT = 0, PTLM_TRANSFORM_MFMA = 1 } ptlm_transform;
 
 /* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128, or both 48, 96 or 256. */
 typedef struct {
@@ -214,14 +216,16 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
                         const float* d_dO, const float* d_dP, float* d_outO, float* d_outP,
                         void* stream);
 
-/* The same product for 16 x 16 and 32 x 32 probes with the 2D transform done as two complex
- * L x L matrix products (the DFT matrix of eq:expected_count) on the FP32 matrix cores
- * (v_mfma_f32_16x16x4_f32, v_mfma_f32_32x32x2_f32) instead of the FFT: the DFT-as-MFMA
- * variant, for the side-by-side measurement against the FFT kernels that serve ptlm_ggn_vp.
- * Same arguments, layout and results (to rounding) as ptlm_ggn_vp; PTLM_EINVAL for other
- * probe shapes. */
-ptlm_status ptlm_ggn_vp_mfma(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda,
-                             const float* d_dO, const float* d_dP, float* d_outO, float* d_outP, void* stream);
+/* Choose how the GGN-vector product (ptlm_ggn_vp and the products inside ptlm_lm_step /
+ * ptlm_lm_solve) applies the 2D DFT F of eq:expected_count: PTLM_TRANSFORM_FFT, the tile
+ * kernels' radix-16 FFT; PTLM_TRANSFORM_MFMA, F X F as two complex L x L matrix products on the
+ * FP32 matrix cores (v_mfma_f32_16x16x4_f32 / v_mfma_f32_32x32x2_f32), for 16 x 16 and 32 x 32
+ * probes only.  Both give the product to FP32 rounding; the results differ in the last bits.
+ * A handle starts with PTLM_TRANSFORM_MFMA for 16 x 16 probes and PTLM_TRANSFORM_FFT
+ * otherwise; ptlm_autotune may change it, and batches use the starting choice.  Takes effect
+ * from the next call; enqueues nothing.  PTLM_EINVAL for an unknown value or MFMA on another
+ * probe shape. */
+ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform);
 
 /* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
  * stage = 1: per-position kernel only (accumulates into workspace strips);
@@ -252,12 +256,16 @@ ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed,
 
 /* Autotuner of the tile-kernel launch (a project addition).  Times the GGN-vector product
  * (reps calls after one warm-up) with the positions cut into 0.5x, 1x and 2x as many
- * segments (workgroups) as the GPU keeps resident, and keeps the fastest.  Results do not
- * depend on the choice beyond FP32 summation order.  Synchronises the stream.  h_ms (3 host
- * doubles, nullable) receives the times per call, h_scale (nullable) the chosen scale.  The
- * workspace of ptlm_workspace_bytes covers every candidate.  Overwrites the output buffers
- * of the LM (call it before ptlm_lm_init or between LM runs), not the linearisation. */
-ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, void* stream);
+ * segments (workgroups) as the GPU keeps resident, for each transform the probe shape has
+ * (PTLM_TRANSFORM_FFT always, PTLM_TRANSFORM_MFMA at 16 x 16 and 32 x 32), and keeps the
+ * fastest pair.  Results do not depend on the choice beyond FP32 rounding.  Synchronises the
+ * stream.  h_ms (6 host doubles, nullable) receives the time per call at [transform * 3 +
+ * scale index], -1 where the transform does not apply; h_scale (nullable) the chosen scale,
+ * h_transform (nullable) the chosen transform.  The workspace of ptlm_workspace_bytes covers
+ * every candidate.  Overwrites the output buffers of the LM (call it before ptlm_lm_init or
+ * between LM runs), not the linearisation. */
+ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, int32_t* h_transform,
+                          void* stream);
 
 /* Truncated LM (alg:lm_inexact).  ptlm_lm_init resets d_state (mu = mu0, t = 0) on the
  * stream.  ptlm_lm_step runs one outer iteration in place on d_O (and d_P in PTLM_JOINT

@@ -87,7 +87,7 @@ _sig = {
     "ptlm_ggn_vp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
     "ptlm_ggn_vp_stage": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                          _vp]),
-    "ptlm_ggn_vp_mfma": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "ptlm_set_transform": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ptlm_diag": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
     "ptlm_diag_stochastic": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp]),
     "ptlm_lm_init": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_lm_params), _vp, _vp]),
@@ -105,7 +105,7 @@ _sig = {
     "ptlm_learned_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ptlm_lm_set_cnn": (ctypes.c_int, [_vp, ctypes.POINTER(ptlm_cnn_desc), _vp, _vp, ctypes.c_size_t]),
     "ptlm_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double), _vp]),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _vp]),
     "ptlm_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp,
                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "ptlm_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ptlm_desc), _vp, _vp, ctypes.c_size_t, _vp,
@@ -295,18 +295,10 @@ class Problem:
                                 self._p(oP, "outP") if self.joint else None, _stream()))
         return oO, oP
 
-    def ggn_vp_mfma(self, vO, vP=None, lam=0.0, out=None):
-        """ptlm_ggn_vp_mfma: the product with the transform on the matrix cores (16 x 16 and 32 x 32
-        probes)."""
-        if out is None:
-            oO = torch.empty(self.obj_shape, dtype=torch.complex64, device=self.device)
-            oP = torch.empty(self.probe_shape, dtype=torch.complex64, device=self.device) if self.joint else None
-        else:
-            oO, oP = out
-        _check(_lib.ptlm_ggn_vp_mfma(self.handle, self._o(vO, "vO"), self._p(vP, "vP") if self.joint else None,
-                                     float(lam), None, None, self._o(oO, "outO"),
-                                     self._p(oP, "outP") if self.joint else None, _stream()))
-        return oO, oP
+    def set_transform(self, name):
+        """ptlm_set_transform: "fft" (radix-16 FFT tile kernels) or "mfma" (DFT as matrix products
+        on the matrix cores, 16 x 16 and 32 x 32 probes) for the GGN-vector product."""
+        _check(_lib.ptlm_set_transform(self.handle, {"fft": 0, "mfma": 1}[name]))
 
     def ggn_vp_stage(self, stage, vO, vP=None, out=None):
         """Run one stage of the GGN-vector product (1: per-position kernel, 2: reductions)."""
@@ -332,11 +324,13 @@ class Problem:
         return dO, dP
 
     def autotune(self, reps=5):
-        """Pick the segment count of the tile kernels by timing GGN-vector products."""
-        ms = (ctypes.c_double * 3)()
+        """Pick the segment count and the transform of the GGN-vector product by timing it.
+        Returns (scale, ms, transform): ms[transform * 3 + i] at scale 0.5, 1, 2 (-1: n/a)."""
+        ms = (ctypes.c_double * 6)()
         sc = ctypes.c_double(0)
-        _check(_lib.ptlm_autotune(self.handle, int(reps), ms, ctypes.byref(sc), _stream()))
-        return float(sc.value), [float(v) for v in ms]
+        xf = ctypes.c_int32(0)
+        _check(_lib.ptlm_autotune(self.handle, int(reps), ms, ctypes.byref(sc), ctypes.byref(xf), _stream()))
+        return float(sc.value), [float(v) for v in ms], ("fft", "mfma")[xf.value]
 
     def new_state(self):
         return torch.zeros(STATE_BYTES, dtype=torch.uint8, device=self.device)

@@ -187,6 +187,7 @@ ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_
   g.probe_part = (float2*)at(p.off.probe_part);
   g.partials = (double*)at(p.off.partials);
   g.scratch = d.my == 256 ? (float2*)at(p.off.scratch) : nullptr;
+  g.xform = default_xform(d.my, d.mx);
   h->lm_g = (float2*)at(p.off.g);
   h->lm_g_alt = (float2*)at(p.off.g2);
   h->afield_alt = (float2*)at(p.off.afield2);
@@ -238,7 +239,8 @@ ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s) {
   return PTLM_OK;
 }
 
-ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, hipStream_t s) {
+ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, int32_t* h_xform,
+                          hipStream_t s) {
   Plan& p = h->plan;
   const size_t N = (size_t)p.d.ny * p.d.nx;
   float2* out = (float2*)(h->ws + p.off.Ap);
@@ -246,30 +248,39 @@ ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scal
   const float2* vP = h->g.joint ? h->g.P_lin : nullptr;
   hipEvent_t e0 = h->tune_ev[0], e1 = h->tune_ev[1];
   double best = 1e300;
-  int bi = 1;
+  int bi = 1, bx = h->g.xform;
   ptlm_status st = PTLM_OK;
   const int nc = (int)(kNumGridScales);
-  for (int i = 0; i < nc && st == PTLM_OK; ++i) {
-    st = resegment(h, kGridScales[i], s);
-    if (st != PTLM_OK) break;
-    st = ggnv_impl(h, vO, vP, 0.0, nullptr, nullptr, nullptr, out, h->g.joint ? out + N : nullptr, nullptr, s);
-    if (st != PTLM_OK) break;
-    hipEventRecord(e0, s);
-    for (int r = 0; r < reps && st == PTLM_OK; ++r)
+  const int nx = ggnv_mfma_supported(h->g.my, h->g.mx) ? 2 : 1;
+  if (h_ms)
+    for (int i = 0; i < 2 * nc; ++i) h_ms[i] = -1.0;
+  for (int x = 0; x < nx && st == PTLM_OK; ++x) {
+    h->g.xform = x;
+    for (int i = 0; i < nc && st == PTLM_OK; ++i) {
+      st = resegment(h, kGridScales[i], s);
+      if (st != PTLM_OK) break;
       st = ggnv_impl(h, vO, vP, 0.0, nullptr, nullptr, nullptr, out, h->g.joint ? out + N : nullptr, nullptr, s);
-    hipEventRecord(e1, s);
-    hipEventSynchronize(e1);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    const double per = (double)ms / std::max(reps, 1);
-    if (h_ms) h_ms[i] = per;
-    if (per < best) {
-      best = per;
-      bi = i;
+      if (st != PTLM_OK) break;
+      hipEventRecord(e0, s);
+      for (int r = 0; r < reps && st == PTLM_OK; ++r)
+        st = ggnv_impl(h, vO, vP, 0.0, nullptr, nullptr, nullptr, out, h->g.joint ? out + N : nullptr, nullptr, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      const double per = (double)ms / std::max(reps, 1);
+      if (h_ms) h_ms[x * nc + i] = per;
+      if (per < best) {
+        best = per;
+        bi = i;
+        bx = x;
+      }
     }
   }
+  h->g.xform = bx;
   if (st != PTLM_OK) return st;
   if (h_scale) *h_scale = kGridScales[bi];
+  if (h_xform) *h_xform = bx;
   return resegment(h, kGridScales[bi], s);
 }
 }  // namespace ptlm
@@ -479,22 +490,14 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
   return ptlm_ggn_vp_stage(h, d_vO, d_vP, lambda, d_dO, d_dP, d_outO, d_outP, 3, stream);
 }
 
-ptlm_status ptlm_ggn_vp_mfma(ptlm_handle* h, const float* d_vO, const float* d_vP, double lambda, const float* d_dO,
-                             const float* d_dP, float* d_outO, float* d_outP, void* stream) {
+ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform) {
   PTLM_CHECK_H(h);
-  if (!d_vO || !d_outO) return fail(PTLM_EINVAL, "null array");
-  if (h->g.joint && (!d_vP || !d_outP)) return fail(PTLM_EINVAL, "joint mode needs d_vP and d_outP");
-  if (!ggnv_mfma_supported(h->g.my, h->g.mx))
-    return fail(PTLM_EINVAL, "ptlm_ggn_vp_mfma: 16 x 16 and 32 x 32 probes only");
-  hipStream_t s = (hipStream_t)stream;
-  TileArgs a{};
-  a.O = h->g.O_lin;
-  a.P = h->g.P_lin;
-  a.vO = (const float2*)d_vO;
-  a.vP = h->g.joint ? (const float2*)d_vP : nullptr;
-  PTLM_HIP(launch_ggnv_mfma(h->g, a, s), "ggn_vp_mfma");
-  return ggnv_impl(h, (const float2*)d_vO, (const float2*)d_vP, lambda, nullptr, d_dO, d_dP, (float2*)d_outO,
-                   (float2*)d_outP, nullptr, s, 2);
+  if (transform != PTLM_TRANSFORM_FFT && transform != PTLM_TRANSFORM_MFMA)
+    return fail(PTLM_EINVAL, "ptlm_set_transform: unknown transform");
+  if (transform == PTLM_TRANSFORM_MFMA && !ggnv_mfma_supported(h->g.my, h->g.mx))
+    return fail(PTLM_EINVAL, "ptlm_set_transform: the matrix-product transform needs 16 x 16 or 32 x 32 probes");
+  h->g.xform = transform;
+  return PTLM_OK;
 }
 
 ptlm_status ptlm_diag(ptlm_handle* h, float* d_dO, float* d_dP, int32_t exact, void* stream) {
@@ -516,10 +519,11 @@ ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed,
                               (hipStream_t)stream);
 }
 
-ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, void* stream) {
+ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, int32_t* h_transform,
+                          void* stream) {
   PTLM_CHECK_H(h);
   if (reps < 1) return fail(PTLM_EINVAL, "reps must be >= 1");
-  return autotune_impl(h, reps, h_ms, h_scale, (hipStream_t)stream);
+  return autotune_impl(h, reps, h_ms, h_scale, h_transform, (hipStream_t)stream);
 }
 
 const char* ptlm_last_error(void) { return g_last_error.c_str(); }

@@ -91,7 +91,8 @@ ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s,
 ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long seed, unsigned long long draw0,
                                  const int* draw_t, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
 ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s);
-ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, hipStream_t s);
+ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, int32_t* h_xform,
+                          hipStream_t s);
 ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s);
 const float* cnn_output(const ptlm_handle* h);
 ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,

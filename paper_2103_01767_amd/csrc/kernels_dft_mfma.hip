@@ -1,5 +1,6 @@
-// DFT-as-MFMA variant of the GGN-vector product for 16 x 16 and 32 x 32 probes (a measured
-// alternative to the register / LDS FFT of the tile kernels; used by ptlm_ggn_vp_mfma).
+// DFT-as-MFMA form of the GGN-vector product for 16 x 16 and 32 x 32 probes: the alternative to
+// the register / LDS FFT of the tile kernels, chosen per handle (the default for 16 x 16, where
+// it is measured faster; ptlm_set_transform, ptlm_autotune).
 //
 // The unnormalised 2D DFT of an L x L tile X is Y = F X F with F[n][k] = exp(-2 pi i n k / L)
 // (symmetric), the transform F of eq:expected_count up to the 1/L of the unitary form, which
@@ -58,16 +59,13 @@ __device__ __forceinline__ float2 wL(int m, int L) {
   return make_float2((float)c, (float)s);
 }
 
+// one wavefront: every position of segment `seg`
 template <int L>
-__global__ __launch_bounds__(64 * WAVES) void ggnv_kernel(Geometry g, TileArgs a) {
+__device__ __forceinline__ void ggnv_body(const Geometry& g, const TileArgs& a, int seg, int lane) {
   using X = Mf<L>;
   constexpr int NS = X::NS, M = L * L;
   typedef typename X::acc acc;
-  if (a.predicate && *a.predicate == 0) return;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lg = lane / L, lc = lane % L;  // lane group, matrix column
-  const int seg = xcd_block(blockIdx.x, gridDim.x) * WAVES + wv;
-  if (seg >= g.nseg) return;
   const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
   const bool joint = g.joint != 0;
 
@@ -174,9 +172,36 @@ __global__ __launch_bounds__(64 * WAVES) void ggnv_kernel(Geometry g, TileArgs a
   }
 }
 
+template <int L>
+__global__ __launch_bounds__(64 * WAVES) void ggnv_kernel(Geometry g, TileArgs a) {
+  if (a.predicate && *a.predicate == 0) return;
+  const int seg = xcd_block(blockIdx.x, gridDim.x) * WAVES + (int)(threadIdx.x >> 6);
+  if (seg >= g.nseg) return;
+  ggnv_body<L>(g, a, seg, threadIdx.x & 63);
+}
+
+// batched 16 x 16 class: block b of a job runs the job's segments 16 b .. 16 b + 15 (those of
+// the tile kernel's block b), one per wavefront
+constexpr int BATCH_WAVES = 16;
+__global__ __launch_bounds__(64 * BATCH_WAVES) void ggnv16_batch_kernel(const TileJob* __restrict__ jobs,
+                                                                       const int* __restrict__ job_of_block) {
+  const TileJob& J = jobs[job_of_block[blockIdx.x]];
+  if (J.a.predicate && *J.a.predicate == 0) return;
+  const int seg = ((int)blockIdx.x - J.block0) * BATCH_WAVES + (int)(threadIdx.x >> 6);
+  if (seg >= J.g.nseg) return;
+  ggnv_body<16>(J.g, J.a, seg, threadIdx.x & 63);
+}
+
 }  // namespace mfmadft
 
 bool ggnv_mfma_supported(int my, int mx) { return my == mx && (my == 16 || my == 32); }
+int default_xform(int my, int mx) { return my == 16 && mx == 16 ? 1 : 0; }
+
+hipError_t launch_ggnv_mfma_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mfmadft::ggnv16_batch_kernel, dim3(nb), dim3(64 * mfmadft::BATCH_WAVES), 0, s, jobs, jb);
+  return hipGetLastError();
+}
 
 hipError_t launch_ggnv_mfma(const Geometry& g, const TileArgs& a, hipStream_t s) {
   const int nblk = (g.nseg + mfmadft::WAVES - 1) / mfmadft::WAVES;

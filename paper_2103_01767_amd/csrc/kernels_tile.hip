@@ -661,6 +661,7 @@ static hipError_t launch_mx(const Geometry& g, int op, const TileArgs& a, hipStr
 }
 
 hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
+  if (op == OP_GGNV && g.xform == 1 && ggnv_mfma_supported(g.my, g.mx)) return launch_ggnv_mfma(g, a, s);
   if (g.my == 256 && g.mx == 256) return launch_tile256(g, op, a, s);
   if (g.my == 128 && g.mx == 128 && tile128_handles(op)) return launch_tile128(g, op, a, s);
   if (g.my == g.mx && (g.my == 48 || g.my == 96)) return launch_tile3(g, op, a, s);
@@ -675,6 +676,8 @@ hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t
 
 hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
+  // a batch runs every problem with the transform its shape starts with
+  if (op == OP_GGNV && default_xform(my, mx) == 1) return launch_ggnv_mfma_batch(jobs, jb, nb, s);
   if (my == 256 && mx == 256) return launch_tile256_batch(op, jobs, jb, nb, s);
   if (my == 128 && mx == 128) return launch_tile128_batch(op, jobs, jb, nb, s);
   if (my == mx && (my == 48 || my == 96)) return launch_tile3_batch(my, op, jobs, jb, nb, s);

@@ -219,16 +219,19 @@ def test_invalid_arguments():
 
 @pytest.mark.parametrize("probe,n,step", [((64, 64), 20, 6), ((32, 32), 30, 4)], ids=["64x64", "32x32"])
 def test_autotuned_segmentation_keeps_products(probe, n, step):
-    """The autotuner only changes how positions are cut into segments: products stay at parity."""
+    """The autotuner only changes how positions are cut into segments and, at 32 x 32, which
+    transform the product uses: products stay at parity."""
     print("case autotune", probe, flush=True)
     case = make_case(probe, n, n, step, joint=True, seed=31)
     prob = problem(case)
     O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
     lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "gauss", True)
     prob.linearize(O, P, y)
-    scale, ms = prob.autotune(reps=3)
-    print("autotune scale", scale, "ms", ms)
-    assert scale in (0.5, 1.0, 2.0) and all(m > 0 for m in ms)
+    scale, ms, xf = prob.autotune(reps=3)
+    print("autotune scale", scale, "transform", xf, "ms", ms)
+    assert scale in (0.5, 1.0, 2.0) and all(m > 0 for m in ms[:3])
+    assert (xf == "mfma") == (min(ms[3:]) > 0 and min(ms[3:]) < min(ms[:3]))
+    assert all(m > 0 for m in ms[3:]) if probe == (32, 32) else all(m == -1 for m in ms[3:])
     rng = np.random.default_rng(4)
     vO = c64(synth.random_complex(rng, case["O"].shape))
     vP = c64(synth.random_complex(rng, case["P"].shape))
@@ -374,9 +377,9 @@ def test_corner_and_repeated_positions(probe):
 @pytest.mark.parametrize("joint", [False, True])
 @pytest.mark.parametrize("L", [16, 32])
 def test_ggn_vp_mfma_matches_oracle(L, joint, metric):
-    """The DFT-as-MFMA product (16 x 16 and 32 x 32 probes, transform on the matrix cores)
-    against the FP64 oracle and against the FFT kernel's product, on a raster with
-    multi-position segments."""
+    """The GGN-vector product with the DFT as matrix products on the matrix cores (16 x 16 and
+    32 x 32 probes) and with the FFT tile kernel, against the FP64 oracle and each other, on a
+    raster with multi-position segments; the damped product too."""
     print("case ggn mfma", L, joint, metric, flush=True)
     case = make_case((L, L), 9, 10, L // 4, metric=metric, joint=joint, seed=91 + L)
     prob = problem(case)
@@ -387,13 +390,32 @@ def test_ggn_vp_mfma_matches_oracle(L, joint, metric):
     vO = c64(synth.random_complex(rng, case["O"].shape))
     vP = c64(synth.random_complex(rng, case["P"].shape)) if joint else None
     GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128) if joint else None)
-    mO, mP = prob.ggn_vp_mfma(to_dev(vO), to_dev(vP) if joint else None)
-    fO, fP = prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None)
+    out = {}
+    for xf in ("mfma", "fft"):
+        prob.set_transform(xf)
+        out[xf] = prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None)
+    (mO, mP), (fO, fP) = out["mfma"], out["fft"]
     assert rel(host(mO), GO) < TOL
     assert rel(host(mO), host(fO)) < TOL
     if joint:
         assert rel(host(mP), GP) < TOL
         assert rel(host(mP), host(fP)) < TOL
+    # damped with a diagonal: lam D v added by the same reductions
+    dO = np.abs(rng.standard_normal(case["O"].shape + (2,))).astype(np.float32) + 0.1
+    dP = np.abs(rng.standard_normal(case["P"].shape + (2,))).astype(np.float32) + 0.1 if joint else None
+    prob.set_transform("mfma")
+    lam = 0.37
+    oO, oP = prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None, lam=lam, dO=to_dev(dO),
+                         dP=to_dev(dP) if joint else None)
+    rO = GO + lam * (dO[..., 0] * vO.real + 1j * dO[..., 1] * vO.imag)
+    assert rel(host(oO), rO) < TOL
+    if joint:
+        rP = GP + lam * (dP[..., 0] * vP.real + 1j * dP[..., 1] * vP.imag)
+        assert rel(host(oP), rP) < TOL
+
+
+def test_transform_choice_rejected_for_other_shapes():
+    prob = problem(make_case((64, 64), 3, 3, 8, seed=92))
     with pytest.raises(pt.PtlmError):
-        other = problem(make_case((24, 24), 3, 3, 8, seed=92))
-        other.ggn_vp_mfma(to_dev(c64(np.zeros(other.obj_shape))), to_dev(c64(np.zeros(other.probe_shape))))
+        prob.set_transform("mfma")
+    prob.set_transform("fft")
