@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--only-large-scan", action="store_true",
                     help="only time the large-scan GGN-vector product (one JSON line; for profiling)")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--batch-seg-len", type=int, default=2,
+                    help="ptlm_desc.seg_len of the batch's problems (0: each cut as if alone on the GPU)")
     ap.add_argument("--large-lm-iters", type=int, default=3,
                     help="timed LM outer iterations on the large scan (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -180,7 +182,7 @@ def main():
 
     lm = None if args.no_lm else lm_comparison(prob, pr, dev, args.lm_iters)
     nxt = None if args.no_next else lm_variants(pr, dev, args.lm_iters, args.poisson_iters)
-    batch = None if args.no_batch else batch_measure(dev, args.batch_iters)
+    batch = None if args.no_batch else batch_measure(dev, args.batch_iters, args.batch_seg_len)
 
     if cpu is not None:
         cpu["lm_small_object_only"].update(gpu_lm_seconds(dev, "small", 20))
@@ -511,7 +513,7 @@ def lm_variants(pr, dev, iters, poisson_iters):
     return out
 
 
-def batch_measure(dev, iters):
+def batch_measure(dev, iters, seg_len=0):
     """64 independent joint problems of uneven sizes (object side 128..384 enlarged to fit the
     raster, probe side 32/48/64/96, n x n raster with n in 10..30, step = probe / 4, Poisson
     data at 1e3..1e5 photons per pattern) solved together: one launch per LM-attempt step for
@@ -529,7 +531,7 @@ def batch_measure(dev, iters):
     probs = [synth.make_c2_problem(p) for p in range(64)]
     c64 = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
     specs = [dict(obj_shape=p.O_true.shape, probe_shape=p.P_true.shape, positions=p.pos, mode="joint",
-                  background=p.background) for p in probs]
+                  background=p.background, seg_len=seg_len) for p in probs]
     batch = pt.Batch(specs, device=dev)
     gen = torch.Generator(device=dev)
     gen.manual_seed(1002)
@@ -568,7 +570,8 @@ def batch_measure(dev, iters):
         return dict(seconds=round(el, 4), attempts=attempts, final_loss=f, ggnv_products=prods,
                     ggnv_positions_per_s=round(pos_prods / el, 1), reached_s=None if hit is None else round(hit, 4))
 
-    out = {"problems": len(probs), "positions": int(K.sum()), "pixel_positions": KM, "outer_iters": iters}
+    out = {"problems": len(probs), "positions": int(K.sum()), "pixel_positions": KM, "outer_iters": iters,
+           "seg_len": seg_len}
     run(1, True, 2)  # warm-up: compile-time attributes, graph capture path
     out["jacobi_graph"] = run(1, True, iters)
     out["jacobi_eager"] = run(1, False, iters)

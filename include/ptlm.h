@@ -71,6 +71,12 @@ typedef struct {
                          choice) or PTLM_GGN_INTENSITY (eq:ggn_intensity, the ablation of App. C:
                          the same f and gradient, the Hessian of the metric taken in the
                          intensity h; its weight is floored at 1e-30 where it vanishes, y = 0) */
+  int32_t seg_len;    /* launch shape (a project choice, no effect on the method): 0 cuts the
+                         positions over the workgroups the GPU keeps resident; n > 0 also cuts
+                         them into at most ceil(K / n) segments, about n positions each, so that
+                         a problem that shares the GPU in a batch keeps fewer, longer segments
+                         (less overlap-add and probe-partial traffic).  Results depend on it
+                         only through FP32 summation order.  Must be >= 0. */
 } ptlm_desc;
 
 /* LM hyper-parameters (alg:lm_inexact; defaults of Sec. 5 via ptlm_lm_default_params). */

@@ -38,7 +38,8 @@ GGN_MAGNITUDE, GGN_INTENSITY = 0, 1
 class ptlm_desc(ctypes.Structure):
     _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("my", ctypes.c_int32),
                 ("mx", ctypes.c_int32), ("K", ctypes.c_int32), ("metric", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("background", ctypes.c_float), ("ggn", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("background", ctypes.c_float), ("ggn", ctypes.c_int32),
+                ("seg_len", ctypes.c_int32)]
 
 
 class ptlm_lm_params(ctypes.Structure):
@@ -173,26 +174,27 @@ def state_from_tensor(buf: torch.Tensor) -> ptlm_lm_state:
     return ptlm_lm_state.from_buffer_copy(raw[:STATE_BYTES])
 
 
-def _desc(obj_shape, probe_shape, K, metric, mode, background, ggn="magnitude"):
+def _desc(obj_shape, probe_shape, K, metric, mode, background, ggn="magnitude", seg_len=0):
     joint = mode in ("joint", JOINT)
     if ggn not in ("magnitude", "intensity", GGN_MAGNITUDE, GGN_INTENSITY):
         raise ValueError("ggn must be 'magnitude' or 'intensity'")
     return ptlm_desc(int(obj_shape[0]), int(obj_shape[1]), int(probe_shape[0]), int(probe_shape[1]), int(K),
                      POISSON if metric in ("poisson", POISSON) else GAUSS, JOINT if joint else OBJECT,
-                     float(background), GGN_INTENSITY if ggn in ("intensity", GGN_INTENSITY) else GGN_MAGNITUDE)
+                     float(background), GGN_INTENSITY if ggn in ("intensity", GGN_INTENSITY) else GGN_MAGNITUDE,
+                     int(seg_len))
 
 
 class Problem:
     """One ptychography problem on one GPU: handle + workspace + positions."""
 
     def __init__(self, obj_shape, probe_shape, positions, metric="gauss", mode="object",
-                 background=1e-8, device="cuda", ggn="magnitude", _handle=None, _owner=None):
+                 background=1e-8, device="cuda", ggn="magnitude", seg_len=0, _handle=None, _owner=None):
         pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
         self.obj_shape = tuple(int(v) for v in obj_shape)
         self.probe_shape = tuple(int(v) for v in probe_shape)
         self.K = int(pos.shape[0])
         self.joint = mode in ("joint", JOINT)
-        self.desc = _desc(obj_shape, probe_shape, self.K, metric, mode, background, ggn)
+        self.desc = _desc(obj_shape, probe_shape, self.K, metric, mode, background, ggn, seg_len)
         self._pos = pos
         self.device = torch.device(device)
         if _handle is not None:  # a problem of a batch: the batch owns handle and workspace
@@ -435,7 +437,7 @@ class Batch:
     of an LM attempt for all problems, optionally replayed from a captured HIP graph.
 
     ``specs``: list of dicts with obj_shape, probe_shape, positions and optional metric, mode,
-    background, ggn.  ``problem(i)`` is a Problem view on the i-th handle (all single-problem calls)."""
+    background, ggn, seg_len.  ``problem(i)`` is a Problem view on the i-th handle (all single-problem calls)."""
 
     def __init__(self, specs, device="cuda"):
         self.device = torch.device(device)
@@ -445,7 +447,8 @@ class Batch:
         self.specs = specs
         descs = (ptlm_desc * self.n)(*[
             _desc(sp["obj_shape"], sp["probe_shape"], len(p), sp.get("metric", "gauss"), sp.get("mode", "joint"),
-                  sp.get("background", 1e-8), sp.get("ggn", "magnitude")) for sp, p in zip(specs, self._pos)])
+                  sp.get("background", 1e-8), sp.get("ggn", "magnitude"), sp.get("seg_len", 0))
+            for sp, p in zip(specs, self._pos)])
         self._descs = descs
         self._pos_ptrs = (_vp * self.n)(*[p.ctypes.data_as(_vp) for p in self._pos])
         nb = ctypes.c_size_t(0)
@@ -462,7 +465,7 @@ class Batch:
             self.problems.append(Problem(sp["obj_shape"], sp["probe_shape"], self._pos[i],
                                          sp.get("metric", "gauss"), sp.get("mode", "joint"),
                                          sp.get("background", 1e-8), device, sp.get("ggn", "magnitude"),
-                                         _handle=ph, _owner=self))
+                                         sp.get("seg_len", 0), _handle=ph, _owner=self))
         self.states = torch.zeros(self.n * STATE_BYTES, dtype=torch.uint8, device=self.device)
         self._bound = None
 

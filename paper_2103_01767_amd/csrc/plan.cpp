@@ -48,10 +48,15 @@ static void build_csr(const Plan& p, Boxes boxes, int count, std::vector<int>& p
 }
 
 // Workgroups of the tile kernels for a grid scale: scale x (resident workgroups of the chip),
-// at most one per tiles-per-workgroup positions.
+// at most one per tiles-per-workgroup positions, and with seg_len > 0 at most one per
+// tiles-per-workgroup segments of seg_len positions.
 int plan_grid(const Plan& p, double scale) {
   const int resident = 256 * wgs_per_cu(p.d.my, p.d.mx);
-  const int gmax = std::max(1, (int)std::llround(resident * scale));
+  int gmax = std::max(1, (int)std::llround(resident * scale));
+  if (p.d.seg_len > 0) {
+    const int nseg = (p.d.K + p.d.seg_len - 1) / p.d.seg_len;
+    gmax = std::min(gmax, (nseg + p.tpw - 1) / p.tpw);
+  }
   return std::max(1, std::min((p.d.K + p.tpw - 1) / p.tpw, gmax));
 }
 
@@ -133,6 +138,7 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   if (d->metric != PTLM_GAUSS && d->metric != PTLM_POISSON) return fail(PTLM_EINVAL, "unknown metric");
   if (d->ggn != PTLM_GGN_MAGNITUDE && d->ggn != PTLM_GGN_INTENSITY) return fail(PTLM_EINVAL, "unknown GGN kind");
   if (d->mode != PTLM_OBJECT && d->mode != PTLM_JOINT) return fail(PTLM_EINVAL, "unknown mode");
+  if (d->seg_len < 0) return fail(PTLM_EINVAL, "seg_len must be >= 0");
   if (!(d->background > 0.0f) || !std::isfinite(d->background))
     return fail(PTLM_EINVAL, "background must be finite and > 0");
   if ((long long)d->ny * d->nx > (1LL << 31)) return fail(PTLM_EINVAL, "object too large");

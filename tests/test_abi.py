@@ -44,7 +44,7 @@ def test_workspace_validation():
         assert _ws(d, p2)[0] == pt.PTLM_EINVAL
         assert b"position 2" in pt.lib().ptlm_last_error()
     for field, val in (("my", 48), ("mx", 24), ("K", 0), ("metric", 7), ("mode", 3), ("background", 0.0),
-                       ("ggn", 2)):
+                       ("ggn", 2), ("seg_len", -1)):
         d2 = pt.ptlm_desc(48, 40, 32, 16, 3, pt.GAUSS, pt.JOINT, 1e-8)
         setattr(d2, field, val)
         assert _ws(d2, pos)[0] == pt.PTLM_EINVAL, field
@@ -57,6 +57,10 @@ def test_workspace_validation():
     many = np.array([[i % 17, i % 25] for i in range(40)], np.int32)
     d3 = pt.ptlm_desc(48, 40, 32, 16, 40, pt.GAUSS, pt.JOINT, 1e-8)
     assert _ws(d3, many)[1] > n
+    # seg_len caps the segment count: fewer probe partials and strips to hold
+    d4 = pt.ptlm_desc(48, 40, 32, 16, 40, pt.GAUSS, pt.JOINT, 1e-8)
+    d4.seg_len = 10
+    assert _ws(d4, many)[0] == pt.PTLM_OK and _ws(d4, many)[1] < _ws(d3, many)[1]
 
 
 def test_large_probe_shapes():

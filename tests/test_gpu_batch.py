@@ -31,6 +31,10 @@ def c64(x):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).to(DEV)
 
 
+# launch shape of some problems: segments of about this many positions (the rest: default cut)
+SEG_LEN = {12: 3, 14: 2, 16: 5}
+
+
 def make_problems():
     out = []
     for side, probe, n, step, seed in SPECS:
@@ -47,12 +51,14 @@ def make_problems():
         y = synth.poisson_counts(rng, ptycho.intensity(O, P, pos, 1e-8)).astype(np.float32)
         O0 = synth.random_object_guess(rng, side)
         P0 = np.abs(P)  # phaseless start with the true intensity
-        out.append(dict(obj_shape=(side, side), probe_shape=probe, positions=pos, mode="joint", y=y, O0=O0, P0=P0))
+        out.append(dict(obj_shape=(side, side), probe_shape=probe, positions=pos, mode="joint", y=y, O0=O0, P0=P0,
+                        seg_len=SEG_LEN.get(seed, 0)))
     return out
 
 
 def run_single(p, params, T):
-    prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+    prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV,
+                      seg_len=p.get("seg_len", 0))
     O, P = c64(p["O0"]), c64(p["P0"])
     y = torch.from_numpy(p["y"]).to(DEV)
     st = prob.new_state()
@@ -121,7 +127,8 @@ def test_batch_problem_handles_serve_single_calls():
     probs = make_problems()[:3]
     batch = pt.Batch(probs, device=DEV)
     for i, p in enumerate(probs):
-        alone = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+        alone = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV,
+                           seg_len=p.get("seg_len", 0))
         O, P = c64(p["O0"]), c64(p["P0"])
         z1 = batch.problem(i).forward(O, P)
         z2 = alone.forward(O, P)
@@ -140,7 +147,8 @@ def test_batch_learned_preconditioner_equals_alone():
     net_params[-2:] = 0.05  # a non-zero output bias: the learned diagonal differs from App. B
     alone = []
     for p in probs:
-        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV)
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV,
+                          seg_len=p.get("seg_len", 0))
         net = learned.lm_net(net_params, p["obj_shape"], DEV)
         pt.lm_set_cnn(prob, net)
         pt.lm_set_cnn_refresh(prob, 0)
@@ -180,7 +188,7 @@ def test_batch_surrogate_equals_alone():
     alone = []
     for p in probs:
         prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], metric="poisson", mode="joint",
-                          device=DEV)
+                          device=DEV, seg_len=p.get("seg_len", 0))
         O, P = c64(p["O0"]), c64(p["P0"])
         y = torch.from_numpy(p["y"]).to(DEV)
         st = prob.new_state()
@@ -236,7 +244,8 @@ def test_batch_mixed_ggn_equals_alone():
     T = 3
     alone = []
     for p in probs:
-        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV, ggn=p["ggn"])
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV, ggn=p["ggn"],
+                          seg_len=p.get("seg_len", 0))
         O, P = c64(p["O0"]), c64(p["P0"])
         y = torch.from_numpy(p["y"]).to(DEV)
         st = prob.new_state()
