@@ -37,7 +37,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
-FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (published)
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (published; counts packed FP32 instructions)
+# FP32 vector peak without packed instructions (the build disables them): 256 CUs x 64 FMA lanes
+# x 2 flops x 2.4 GHz
+FP32_NONPACKED_TFLOPS = 78.6
 METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learned vs plain"
 
 # HBM-side bytes of one launch of the GGN-vector tile kernel on this workload, from the
@@ -46,10 +49,10 @@ METRIC = "GGN·v scan-positions/s + LM wall-time to loss ≤1.01× oracle, learn
 # same counters read for a plain 256 MiB copy).  Valid only for the kernel and plan sources they
 # were taken on (the plan sets the segments and strips): a different hash of those sources
 # reports traffic as null.
-TRAFFIC = {"fetch_kib": 340173.1953125, "write_kib": 439273.52734375, "fetch_factor": 1.9998, "write_factor": 1.0,
+TRAFFIC = {"fetch_kib": 255300.6, "write_kib": 267243.8, "fetch_factor": 1.99981, "write_factor": 1.0,
            "grid_scale": 1.0,
-           "sources": ["kernels_tile.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp", "plan.cpp"],
-           "sha256": "4b487f3cacdb264b557154f81aa3081f2e28d3a1a410b5736b17c87a8518cd5a"}
+           "sources": ["kernels_tile128.hip", "dft.hpp", "internal.hpp", "tile_pixel.hpp", "plan.cpp"],
+           "sha256": "cbef97640a0c085a8fa36ae1e86d634cbea420df31835c1bb8d284e4bb046908"}
 
 
 def measured_traffic():
@@ -214,10 +217,15 @@ def main():
                      "ms_at_scales_0.5_1_2": tune_ms[:3] if tune_ms else None},
         "fft_tflops": round(fft_tflops, 2),
         "fft_frac_fp32_peak": round(fft_tflops / FP32_PEAK_TFLOPS, 4),
+        "fft_frac_fp32_nonpacked_peak": round(fft_tflops / FP32_NONPACKED_TFLOPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if tune_scale == TRAFFIC["grid_scale"] else None,
-                     "kernel": "t128::kernel<GGNV> (128x128 tile kernel)", "bytes_per_launch": kern_bytes},
+                     "kernel": "t128::kernel<GGNV> (128x128 tile kernel)", "bytes_per_launch": kern_bytes,
+                     "alu": {"achieved": round(fft_tflops, 2), "peak": FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(fft_tflops / FP32_NONPACKED_TFLOPS, 4),
+                             "what": "FFT flops (5 M log2 M per transform, 2 per position) / kernel time, "
+                                     "against the FP32 vector peak without packed instructions"}},
         "ggnv_large_scan": large,
         "dft_mfma_trial": mfma,
         "lm_time_to_target": lm,
