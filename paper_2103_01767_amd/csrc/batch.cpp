@@ -260,7 +260,7 @@ ptlm_status plan_batch(int n, const ptlm_desc* descs, const int32_t* const* h_po
     const int M = p.d.my * p.d.mx;
     b.obj_b0[i] = append_run(b.jb_obj, i, p.otx * p.oty, 1);
     b.prb_b0[i] = append_run(b.jb_prb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);
-    b.prb1_b0[i] = append_run(b.jb_prb1, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 * prb_chunk_count(p.nseg) : 0, 1);
+    b.prb1_b0[i] = append_run(b.jb_prb1, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 * prb_chunk_count(M, p.nseg) : 0, 1);
     b.dprb_b0[i] = append_run(b.jb_dprb, i, p.d.mode == PTLM_JOINT ? (M + 63) / 64 : 0, 1);  // 64 pixels a block
     b.vec_b0[i] = append_run(b.jb_vec, i, lm_vec_blocks(p.nvec), 1);
   }

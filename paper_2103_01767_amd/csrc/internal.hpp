@@ -150,10 +150,15 @@ int tile3_per_wg(int L);
 // lam_dev (nullable) overrides lam with a device scalar.
 hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const double* lam_dev, const float* dO,
                              const float2* vO, const int* predicate, hipStream_t s);
-// out_P = sum of probe partials [+ lam * dP .* vP]; with more than PRB_CHUNK segments in two
-// passes, the first summing chunks of PRB_CHUNK partials in place (the partials are consumed)
+// out_P = sum of probe partials [+ lam * dP .* vP]; when a probe of M pixels gives fewer than
+// PRB_WIDE blocks of 64 pixels and there are more than PRB_CHUNK segments, in two passes, the
+// first summing chunks of PRB_CHUNK partials in place (the partials are consumed).
+// prb_chunk_count: the number of chunks of the first pass, 0 for one pass.
 constexpr int PRB_CHUNK = 32;
-__host__ __device__ inline int prb_chunk_count(int nseg) { return nseg > PRB_CHUNK ? (nseg + PRB_CHUNK - 1) / PRB_CHUNK : 0; }
+constexpr int PRB_WIDE = 128;
+__host__ __device__ inline int prb_chunk_count(int M, int nseg) {
+  return (nseg > PRB_CHUNK && (M + 63) / 64 < PRB_WIDE) ? (nseg + PRB_CHUNK - 1) / PRB_CHUNK : 0;
+}
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* predicate, hipStream_t s);
 // out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)

@@ -107,6 +107,12 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
     }
   }
 
+  // per-lane offsets of the pixel pairs (row, 2 lc + 16 n2) in an object window, the probe and
+  // the strip; a position adds a uniform offset
+  const size_t lane_o = (size_t)row * g.nx + 2 * lc;
+  const int lane_p = row * L + 2 * lc;
+  const size_t lane_s = (size_t)row * box.w + 2 * lc;
+
   for (int k = kbeg; k < kend; ++k) {
     const int2 p = g.pos[k];
     const int ry = p.x, rx = p.y;
@@ -115,13 +121,13 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
     if constexpr (FWD) {
       // ---------------- gather the exit wave (or its perturbation) at pixels (row, 2 lc + e + 16 n2)
       {
-        const size_t orow = (size_t)(ry + row) * g.nx + rx + 2 * lc;
+        const size_t orow = (size_t)ry * g.nx + rx + lane_o;
         const c2* Oq = reinterpret_cast<const c2*>(a.O + orow);
-        const c2* Pq = reinterpret_cast<const c2*>(a.P + row * L + 2 * lc);
+        const c2* Pq = reinterpret_cast<const c2*>(a.P + lane_p);
         if constexpr (OP == OP_JVP || OP == OP_GGNV) {
           const c2* Vq = reinterpret_cast<const c2*>(a.vO + orow);
           if (a.vP) {
-            const c2* VPq = reinterpret_cast<const c2*>(a.vP + row * L + 2 * lc);
+            const c2* VPq = reinterpret_cast<const c2*>(a.vP + lane_p);
 #pragma unroll
             for (int nn = 0; nn < 8; nn += NG) {
 #pragma unroll
@@ -248,9 +254,8 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
       dft8<true>(v);
       dft8<true>(v + 8);
       {
-        const int Y = ry + row;
-        c2* sq = reinterpret_cast<c2*>(strip + (size_t)(Y - box.x) * box.w + (rx + 2 * lc - box.y));
-        const c2* Pq = reinterpret_cast<const c2*>(a.P + row * L + 2 * lc);
+        c2* sq = reinterpret_cast<c2*>(strip + (size_t)(ry - box.x) * box.w + (rx - box.y) + lane_s);
+        const c2* Pq = reinterpret_cast<const c2*>(a.P + lane_p);
         if (k == kbeg) {
 #pragma unroll
           for (int n2 = 0; n2 < 8; ++n2) {
@@ -269,7 +274,7 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
           }
         }
         if (joint) {
-          const c2* Oq = reinterpret_cast<const c2*>(a.O + (size_t)Y * g.nx + rx + 2 * lc);
+          const c2* Oq = reinterpret_cast<const c2*>(a.O + (size_t)ry * g.nx + rx + lane_o);
 #pragma unroll
           for (int nn = 0; nn < 8; nn += NO) {
 #pragma unroll

@@ -80,13 +80,14 @@ __global__ __launch_bounds__(256) void obj_reduce_batch_kernel(const RedJob* __r
   obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
 }
 
-// Probe-sized sums of the per-segment probe partials, 64 pixels per block.  With at most
-// PRB_CHUNK segments one pass: out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v].  With more,
-// two passes in place: pass one (one block per 64 pixels and chunk) replaces row c * PRB_CHUNK
-// of probe_part by the sum of its chunk's rows, pass two sums the chunk rows.  Every sum is split
-// four ways over its rows and the four parts are added in a fixed order, so the result depends
-// only on the segment count.  The partials are scratch of one product (every per-position
-// kernel rewrites them), so overwriting them loses nothing.
+// Probe-sized sums of the per-segment probe partials, 64 pixels per block.  One pass,
+// out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v], unless the probe gives few blocks and there
+// are many segments (prb_chunk_count); then two passes in place: pass one (one block per 64
+// pixels and chunk) replaces row c * PRB_CHUNK of probe_part by the sum of its chunk's rows,
+// pass two sums the chunk rows.  Every sum is split four ways over its rows and the four parts
+// are added in a fixed order, so the result depends only on the probe size and the segment
+// count.  The partials are scratch of one product (every per-position kernel rewrites them), so
+// overwriting them loses nothing.
 __device__ __forceinline__ float2 rows_sum4(const float2* p, int count, size_t stride, bool valid, int grp, int lane,
                                             float2 (*sh)[64]) {
   float2 acc = make_float2(0.f, 0.f);
@@ -103,7 +104,7 @@ __device__ __forceinline__ float2 rows_sum4(const float2* p, int count, size_t s
   return cadd(cadd(sh[0][lane], sh[1][lane]), cadd(sh[2][lane], sh[3][lane]));
 }
 
-// pass one of a scan with more than PRB_CHUNK segments: block (bx, chunk c)
+// pass one of a two-pass reduction: block (bx, chunk c)
 __device__ __forceinline__ void probe_chunk_body(const Geometry& g, const int* pred, int bx, int c) {
   if (pred && *pred == 0) return;
   __shared__ float2 sh[4][64];
@@ -125,8 +126,9 @@ __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out
   const int M = g.my * g.mx;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int m = bx * 64 + lane;
-  const bool two = g.nseg > PRB_CHUNK;
-  float2 acc = rows_sum4(g.probe_part + m, two ? prb_chunk_count(g.nseg) : g.nseg,
+  const int nch = prb_chunk_count(M, g.nseg);
+  const bool two = nch > 0;
+  float2 acc = rows_sum4(g.probe_part + m, two ? nch : g.nseg,
                          two ? (size_t)PRB_CHUNK * M : (size_t)M, m < M, grp, lane, sh);
   if (grp != 0 || m >= M) return;
   if (lam != 0.f && v) {
@@ -373,8 +375,9 @@ hipError_t launch_obj_reduce(const Geometry& g, float2* outO, double lam, const 
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* pred, hipStream_t s) {
   const int M = g.my * g.mx;
-  if (g.nseg > PRB_CHUNK) {
-    hipLaunchKernelGGL(probe_chunk_kernel, dim3((M + 63) / 64, prb_chunk_count(g.nseg)), dim3(256), 0, s, g, pred);
+  if (prb_chunk_count(M, g.nseg) > 0) {
+    hipLaunchKernelGGL(probe_chunk_kernel, dim3((M + 63) / 64, prb_chunk_count(M, g.nseg)), dim3(256), 0, s, g,
+                       pred);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
