@@ -530,7 +530,8 @@ def batch_measure(dev, iters, seg_len=0):
     Reports, for `iters` outer iterations of Jacobi PLM (D = Dg(G)): wall time and GGN-vector
     scan-positions/s of the batch, with graph replay and with eager launches, and the same
     problems solved one after another; then time to the plain (unpreconditioned) run's final
-    batch loss for plain, Jacobi and learned preconditioning.  Data: Poisson draws of the
+    batch loss for plain, Jacobi and learned preconditioning (the networks re-run from the
+    current probes every 5 outer iterations, ptlm_batch_cnn_refresh, and run once at bind).  Data: Poisson draws of the
     GPU forward model at the true object and probe (seeded)."""
     import torch
     import synth
@@ -551,7 +552,7 @@ def batch_measure(dev, iters, seg_len=0):
     K = np.array([p.K for p in probs])
     KM = int(np.sum(K * np.array([p.P_true.shape[0] * p.P_true.shape[1] for p in probs])))
 
-    def run(prec, use_graph, T, target=None, nets=None):
+    def run(prec, use_graph, T, target=None, nets=None, refresh_every=0):
         params = pt.default_params(scaling=1, precond=prec, cg_max=10)
         for i in range(len(probs)):
             pt.lm_set_cnn(batch.problem(i), nets[i] if (prec == 2 and nets) else None)
@@ -560,7 +561,7 @@ def batch_measure(dev, iters, seg_len=0):
         batch.bind(Os, Ps, ys, params, T, use_graph=use_graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hit, attempts, done = None, 0, False
+        hit, attempts, done, last, refreshes = None, 0, False, 0, 0
         while not done and attempts < 30 * T:
             st, n = batch.solve(1 if target is not None else 30 * T, check_every=1 if target is not None else 4)
             attempts += n
@@ -569,14 +570,23 @@ def batch_measure(dev, iters, seg_len=0):
             if target is not None and hit is None and sum(s.f for s in sts) <= target:
                 hit = time.perf_counter() - t0
                 break
+            # the networks' inputs follow the probes: re-run them every `refresh_every` outer
+            # iterations of the slowest problem
+            tmin = min(s.t for s in sts)
+            if refresh_every > 0 and tmin >= last + refresh_every:
+                batch.cnn_refresh()
+                last, refreshes = tmin, refreshes + 1
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         sts = batch.all_states()
         f = sum(float(batch.problem(i).loss(Os[i], Ps[i], ys[i]).cpu()[0]) for i in range(len(probs)))
         prods = sum(s.products for s in sts)
         pos_prods = sum(s.products * int(k) for s, k in zip(sts, K))
-        return dict(seconds=round(el, 4), attempts=attempts, final_loss=f, ggnv_products=prods,
-                    ggnv_positions_per_s=round(pos_prods / el, 1), reached_s=None if hit is None else round(hit, 4))
+        out_r = dict(seconds=round(el, 4), attempts=attempts, final_loss=f, ggnv_products=prods,
+                     ggnv_positions_per_s=round(pos_prods / el, 1), reached_s=None if hit is None else round(hit, 4))
+        if prec == 2:
+            out_r["network_refreshes"] = refreshes
+        return out_r
 
     out = {"problems": len(probs), "positions": int(K.sum()), "pixel_positions": KM, "outer_iters": iters,
            "seg_len": seg_len}
@@ -603,7 +613,8 @@ def batch_measure(dev, iters, seg_len=0):
     out["jacobi_to_target"] = run(1, True, iters, target=target)
     net_params = learned.load(dev)
     nets = [learned.lm_net(net_params, p.O_true.shape, dev) for p in probs]
-    out["learned_to_target"] = run(2, True, iters, target=target, nets=nets)
+    out["learned_to_target"] = run(2, True, iters, target=target, nets=nets, refresh_every=5)
+    out["learned_once_to_target"] = run(2, True, iters, target=target, nets=nets)
     for i in range(len(probs)):
         pt.lm_set_cnn(batch.problem(i), None)
     return out

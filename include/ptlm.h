@@ -351,7 +351,8 @@ ptlm_status ptlm_lm_set_cnn(ptlm_handle* h, const ptlm_cnn_desc* d, const float*
 /* How often ptlm_lm_step re-runs the registered network: every `every`-th linearisation
  * (default 1), or only at the first one after registration (every = 0).  Between runs the
  * learned diagonal is rebuilt from the kept network output and the new App. B scale.  A
- * batch (ptlm_batch_bind) runs each network once, from the bound probe. */
+ * batch (ptlm_batch_bind) runs each network from the bound probe, and again at each
+ * ptlm_batch_cnn_refresh. */
 ptlm_status ptlm_lm_set_cnn_refresh(ptlm_handle* h, int32_t every);
 
 /* ---------------------------------------------------------------------------------------
@@ -388,6 +389,14 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
                             void* stream);
 /* Enqueue one LM attempt for every problem still running (no host synchronisation). */
 ptlm_status ptlm_batch_attempt(ptlm_batch* b, void* stream);
+/* Learned preconditioner of a batch (params->precond == 2): re-run every problem's registered
+ * network on its features from its current probe (the bound d_P), on `stream`, between two
+ * attempts.  The next linearisation of each problem builds its learned diagonal from the new
+ * output; the linearisation state itself is not touched.  The network's inputs follow the
+ * probe, which the joint LM updates, so a caller refreshes them every few outer iterations (a
+ * refresh costs one network run per problem).  PTLM_EINVAL if the batch is not bound or a
+ * problem has no network. */
+ptlm_status ptlm_batch_cnn_refresh(ptlm_batch* b, void* stream);
 /* Attempts until every problem has run T outer iterations (or met a non-finite value),
  * reading the states every check_every attempts, at most max_attempts.  Returns PTLM_OK,
  * PTLM_ENUMERIC (some problem failed; the others finished) or PTLM_ENOTACCEPTED (budget

@@ -115,6 +115,7 @@ _sig = {
     "ptlm_batch_bind": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ptlm_lm_params), ctypes.c_int32,
                                        ctypes.c_int32, _vp]),
     "ptlm_batch_attempt": (ctypes.c_int, [_vp, _vp]),
+    "ptlm_batch_cnn_refresh": (ctypes.c_int, [_vp, _vp]),
     "ptlm_batch_solve": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ptlm_batch_destroy": (ctypes.c_int, [_vp]),
     "ptlm_lm_set_cnn_refresh": (ctypes.c_int, [_vp, ctypes.c_int32]),
@@ -484,6 +485,10 @@ class Batch:
 
     def attempt(self):
         _check(_lib.ptlm_batch_attempt(self.handle, _stream()))
+
+    def cnn_refresh(self):
+        """ptlm_batch_cnn_refresh: re-run every problem's network from its current probe."""
+        _check(_lib.ptlm_batch_cnn_refresh(self.handle, _stream()))
 
     def solve(self, max_attempts, check_every=4):
         done = ctypes.c_int32(0)

@@ -93,7 +93,9 @@ ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long
 ptlm_status resegment(ptlm_handle* h, double scale, hipStream_t s);
 ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scale, int32_t* h_xform,
                           hipStream_t s);
-ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s);
+// run the handle's registered network on its features: from the linearisation's probe, or from P
+// (a device probe of the handle's shape) when given
+ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s, const float2* P = nullptr);
 const float* cnn_output(const ptlm_handle* h);
 ptlm_status init_handle(ptlm_handle* h, const ptlm_desc* desc, const int32_t* h_pos, void* d_ws, size_t ws_bytes,
                         hipStream_t s);

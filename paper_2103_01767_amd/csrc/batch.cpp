@@ -79,6 +79,7 @@ struct ptlm_batch {
   int T = 0;
   ptlm_lm_state* d_states = nullptr;
   std::vector<ptlm_lm_state> h_states;
+  std::vector<const float2*> bound_P;  // the bound probes (learned-preconditioner refresh)
   int use_graph = 0;
   bool eager_done = false;
   hipStream_t cap = nullptr;
@@ -419,6 +420,8 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   b->d_states = d_states;
   b->use_graph = use_graph;
   const int n = b->n;
+  b->bound_P.assign(n, nullptr);
+  for (int i = 0; i < n; ++i) b->bound_P[i] = (const float2*)d_P[i];
   // tile jobs
   b->tile_jobs.assign(b->classes.size() * TK_N, {});
   for (size_t c = 0; c < b->classes.size(); ++c) {
@@ -613,6 +616,17 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
   B_HIP(launch_fin_batch(F_INIT, b->dev<LMJob>(b->L.lm_jobs), n, 0, FL_NONE, s), "batch init");
   b->h_states.assign(n, ptlm_lm_state{});
   b->bound = true;
+  return PTLM_OK;
+}
+
+ptlm_status ptlm_batch_cnn_refresh(ptlm_batch* b, void* stream) {
+  if (!b || !b->bound) return fail(PTLM_EINVAL, "batch is not bound");
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < b->n; ++i)
+    if (!b->hs[i]->cnn_params) return fail(PTLM_EINVAL, "problem " + std::to_string(i) + " has no network");
+  // features from each problem's current probe; the linearisation state is not touched, and the
+  // next linearisation of each problem builds its learned diagonal from the new output
+  for (int i = 0; i < b->n; ++i) PTLM_TRY(cnn_refresh(b->hs[i], s, b->bound_P[i]));
   return PTLM_OK;
 }
 

@@ -220,12 +220,14 @@ ptlm_status ptlm_lm_set_cnn_refresh(ptlm_handle* h, int32_t every) {
 
 namespace ptlm {
 // features (from the linearisation probe) -> network -> r, kept in the network workspace
-ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s) {
+ptlm_status cnn_refresh(ptlm_handle* h, hipStream_t s, const float2* P) {
   const CnnLayout L = layout(h->cnn);
   float* feat = (float*)(h->cnn_ws + L.feat);
   float* r = (float*)(h->cnn_ws + L.r);
   double* scal = (double*)(h->ws + h->plan.off.scal) + 8;
-  CNN_HIP(launch_features(h->g, feat, scal, s), "lm features");
+  Geometry gf = h->g;
+  if (P) gf.P_lin = const_cast<float2*>(P);  // the features read the probe only
+  CNN_HIP(launch_features(gf, feat, scal, s), "lm features");
   const ptlm_status st = cnn_forward_impl(h->cnn, h->cnn_params, feat, r, h->cnn_ws, s);
   if (st != PTLM_OK) return st;
   h->cnn_ready = true;

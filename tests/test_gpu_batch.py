@@ -177,6 +177,53 @@ def test_batch_learned_preconditioner_equals_alone():
         assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
 
 
+def test_batch_learned_refresh_equals_alone_every_linearisation():
+    """ptlm_batch_cnn_refresh after every attempt re-runs each network from the probe its next
+    linearisation starts from (the new iterate after an accepted step, the unchanged one after
+    a reject), so the batch equals each problem solved alone with the network re-run at every
+    linearisation, bit for bit."""
+    print("case batch learned refresh", flush=True)
+    from paper_2103_01767_amd import learned
+    probs = make_problems()[:4]
+    params = pt.default_params(scaling=1, precond=2, cg_max=5)
+    T = 3
+    net_params = learned.he_params(5, DEV)
+    net_params[-2:] = -0.05
+    alone = []
+    for p in probs:
+        prob = pt.Problem(p["obj_shape"], p["probe_shape"], p["positions"], mode="joint", device=DEV,
+                          seg_len=p.get("seg_len", 0))
+        pt.lm_set_cnn(prob, learned.lm_net(net_params, p["obj_shape"], DEV))
+        pt.lm_set_cnn_refresh(prob, 1)
+        O, P = c64(p["O0"]), c64(p["P0"])
+        y = torch.from_numpy(p["y"]).to(DEV)
+        st = prob.new_state()
+        prob.lm_init(params, st)
+        for _ in range(T):
+            prob.lm_step(O, P, y, params, st)
+        torch.cuda.synchronize()
+        alone.append((O, P, pt.state_from_tensor(st)))
+    batch = pt.Batch(probs, device=DEV)
+    nets = [learned.lm_net(net_params, p["obj_shape"], DEV) for p in probs]
+    for i in range(len(probs)):
+        pt.lm_set_cnn(batch.problem(i), nets[i])
+    Os = [c64(p["O0"]) for p in probs]
+    Ps = [c64(p["P0"]) for p in probs]
+    ys = [torch.from_numpy(p["y"]).to(DEV) for p in probs]
+    batch.bind(Os, Ps, ys, params, T, use_graph=True)
+    for _ in range(100):
+        status, _ = batch.solve(1, check_every=1)
+        if all(s.t >= T for s in batch.all_states()):
+            break
+        batch.cnn_refresh()
+    torch.cuda.synchronize()
+    for i, (O1, P1, s1) in enumerate(alone):
+        s2 = batch.state(i)
+        print("problem %d: f %.6e / %.6e products %d / %d" % (i, s1.f, s2.f, s1.products, s2.products))
+        assert s2.t == T and s2.f == s1.f and s2.products == s1.products
+        assert torch.equal(Os[i], O1) and torch.equal(Ps[i], P1)
+
+
 def test_batch_surrogate_equals_alone():
     """The surrogate term of App. E is read from each problem's device state by the batched
     kernels: a Poisson batch with the schedule equals its problems solved alone."""
