@@ -68,6 +68,101 @@ __global__ __launch_bounds__(256) void conv_kernel(const float* __restrict__ x, 
   }
 }
 
+// The same convolution for 32 output channels on the FP32 matrix cores: an implicit GEMM
+// y[o, p] = b[o] + sum_q A[o, q] B[q, p] over the 16 x 16 output pixels p of a block, with
+// q = (tap k, input channel c) in the order k * CIN_P + c (CIN_P = cin rounded up to 4, 8, 16
+// or 32; padded channels are zero).  Each wavefront owns 64 pixels (rows 4 w .. 4 w + 3 of the
+// tile) as two 32-pixel column blocks of v_mfma_f32_32x32x2_f32 (32 channels x 32 pixels,
+// 2 values of q per instruction).  Lane l supplies A[l % 32][2 j + l / 32] (a weight, from LDS)
+// and B[2 j + l / 32][l % 32] (an input pixel of channel 2 j + l / 32 at tap k, from the LDS
+// tile with halo), and register r of its result holds channel 8 (r / 4) + 4 (l / 32) + r % 4 of
+// pixel l % 32.  Exact FP32 products and sums, in another order than conv_kernel.
+constexpr int CP = CT + 3;             // LDS row pitch of the input tile
+constexpr int CPL = (CT + 2) * CP;     // LDS plane of one channel
+typedef float v16f_c __attribute__((ext_vector_type(16)));
+
+template <int CIN_P>
+constexpr size_t conv32_lds_bytes() {
+  return (size_t)(CIN_P * CPL + 9 * CIN_P * 32) * sizeof(float);
+}
+
+template <int CIN_P>
+__global__ __launch_bounds__(256, 2) void conv32_mfma_kernel(const float* __restrict__ x, int cin, int h, int w,
+                                                             const float* __restrict__ wt,
+                                                             const float* __restrict__ b, float* __restrict__ y,
+                                                             int relu, const float* __restrict__ mask) {
+  extern __shared__ float smem_c[];
+  float* s_in = smem_c;                  // [CIN_P][CT + 2][CP]
+  float* s_w = smem_c + CIN_P * CPL;     // [9][CIN_P][32]: s_w[(k CIN_P + c) 32 + o] = W[o][c][k]
+  const int n = blockIdx.z;
+  const int X0 = blockIdx.x * CT, Y0 = blockIdx.y * CT;
+  const size_t plane = (size_t)h * w;
+  const float* xn = x + (size_t)n * cin * plane;
+  for (int i = threadIdx.x; i < CIN_P * (CT + 2) * (CT + 2); i += 256) {
+    const int c = i / ((CT + 2) * (CT + 2)), r = i % ((CT + 2) * (CT + 2));
+    const int ry = r / (CT + 2), rx = r % (CT + 2);
+    const int yy = Y0 + ry - 1, xx = X0 + rx - 1;
+    s_in[c * CPL + ry * CP + rx] =
+        (c < cin && yy >= 0 && yy < h && xx >= 0 && xx < w) ? xn[c * plane + (size_t)yy * w + xx] : 0.f;
+  }
+  for (int i = threadIdx.x; i < 9 * CIN_P * 32; i += 256) {
+    const int o = i & 31, c = (i >> 5) % CIN_P, k = (i >> 5) / CIN_P;
+    s_w[i] = c < cin ? wt[(c * 9 + k) * 32 + o] : 0.f;
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gq = lane >> 5, lo = lane & 31;
+  const float* wa = s_w + gq * 32 + lo;
+  const float* xb0 = s_in + gq * CPL + (4 * wv + (lo >> 4)) * CP + (lo & 15);  // rows 4 w, 4 w + 1
+  const float* xb1 = xb0 + 2 * CP;                                            // rows 4 w + 2, 4 w + 3
+  v16f_c acc0 = {}, acc1 = {};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int koff = (k / 3) * CP + (k % 3);
+#pragma unroll
+    for (int j = 0; j < CIN_P / 2; ++j) {
+      const float av = wa[(k * CIN_P + 2 * j) * 32];
+      const float b0 = xb0[2 * j * CPL + koff];
+      const float b1 = xb1[2 * j * CPL + koff];
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc1, 0, 0, 0);
+    }
+  }
+  const int xx = X0 + (lo & 15);
+  float* yn = y + (size_t)n * 32 * plane;
+  const float* mn = mask ? mask + (size_t)n * 32 * plane : nullptr;
+#pragma unroll
+  for (int chk = 0; chk < 2; ++chk) {
+    const int yy = Y0 + 4 * wv + 2 * chk + (lo >> 4);
+    if (yy >= h || xx >= w) continue;
+    const size_t at = (size_t)yy * w + xx;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = 8 * (r >> 2) + 4 * gq + (r & 3);
+      float val = (chk == 0 ? acc0[r] : acc1[r]) + b[o];
+      if (relu) val = fmaxf(val, 0.f);
+      if (mn && !(mn[o * plane + at] > 0.f)) val = 0.f;
+      yn[o * plane + at] = val;
+    }
+  }
+}
+
+template <int CIN_P>
+static hipError_t launch_conv32(const float* x, int n, int cin, int h, int w, const float* wt, const float* b,
+                                float* y, int relu, const float* mask, hipStream_t s) {
+  static bool attr_set = false;
+  constexpr size_t lds = conv32_lds_bytes<CIN_P>();
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)conv32_mfma_kernel<CIN_P>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid((w + CT - 1) / CT, (h + CT - 1) / CT, n);
+  hipLaunchKernelGGL(conv32_mfma_kernel<CIN_P>, grid, dim3(256), lds, s, x, cin, h, w, wt, b, y, relu, mask);
+  return hipGetLastError();
+}
+
 // forward weights W[o][c][k] -> wt[c][k][o4] (o padded to a multiple of 4 with zeros)
 __global__ void wt_forward_kernel(const float* W, int cout, int cin, int cpad, float* wt) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -332,6 +427,13 @@ static int padc(int c) { return (c + 3) / 4 * 4; }
 
 hipError_t launch_conv(const float* x, int n, int cin, int h, int w, const float* wt, const float* b, float* y,
                        int cout, int relu, const float* mask, hipStream_t s) {
+  // 32 output channels: the matrix-core form
+  if (cout == 32 && cin <= 32) {
+    if (cin <= 4) return launch_conv32<4>(x, n, cin, h, w, wt, b, y, relu, mask, s);
+    if (cin <= 8) return launch_conv32<8>(x, n, cin, h, w, wt, b, y, relu, mask, s);
+    if (cin <= 16) return launch_conv32<16>(x, n, cin, h, w, wt, b, y, relu, mask, s);
+    return launch_conv32<32>(x, n, cin, h, w, wt, b, y, relu, mask, s);
+  }
   dim3 grid((w + CT - 1) / CT, (h + CT - 1) / CT, n);
   switch (cout) {
     case 2: hipLaunchKernelGGL(conv_kernel<2>, grid, dim3(256), 0, s, x, cin, h, w, wt, b, y, relu, mask); break;
