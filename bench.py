@@ -401,7 +401,7 @@ def large_scan_lm(prob, pr, dev, iters):
 
 def lm_comparison(prob, pr, dev, iters):
     """LM wall time to f <= 1.01 f_oracle, for plain (unpreconditioned), Jacobi and learned PCG
-    (network re-run at every linearisation, or once from the starting probe).
+    (network re-run at every linearisation, at every third, or once from the starting probe).
 
     Data: the stored Poisson counts of the workload; f_oracle: the FP64 oracle's loss after its
     stored number of outer iterations (D = Dg(G), Jacobi PCG) on the same data.  Each variant
@@ -419,7 +419,7 @@ def lm_comparison(prob, pr, dev, iters):
     out = {"target_loss": target, "oracle_final_loss": ref["f_final"], "oracle_iters": ref["T"],
            "max_iters": iters}
     for name, prec, every in (("plain", 0, 1), ("jacobi", 1, 1), ("jacobi_exact", 3, 1), ("learned", 2, 1),
-                              ("learned_once", 2, 0)):
+                              ("learned_every_3", 2, 3), ("learned_once", 2, 0)):
         pt.lm_set_cnn(prob, net if prec == 2 else None)
         if prec == 2:
             pt.lm_set_cnn_refresh(prob, every)
