@@ -357,9 +357,10 @@ def large_scan(dev, calls, lm_iters=0):
 def large_scan_lm(prob, pr, dev, iters):
     """Outer LM iterations on the large scan (D = Dg(G), at most 10 PCG products per solve),
     with the App. B Jacobi and with the learned preconditioner (network re-run at every
-    linearisation, or run once at the first).  Data: Poisson draws (seeded) of the forward model at the true object and
-    probe, about 1e3 photons per pattern.  One untimed iteration first, then `iters` timed ones;
-    the reported rate is scan positions through GGN-vector products per second."""
+    linearisation, at every third, or run once at the first).  Data: Poisson draws (seeded) of the
+    forward model at the true object and probe, about 1e3 photons per pattern.  One untimed
+    iteration first, then `iters` timed ones; the reported rate is scan positions through
+    GGN-vector products per second."""
     import torch
     import paper_2103_01767_amd as pt
     from paper_2103_01767_amd import learned
@@ -371,7 +372,8 @@ def large_scan_lm(prob, pr, dev, iters):
     del z
     net = learned.lm_net(learned.load(dev), pr.O_true.shape, dev)
     out = {"data": "Poisson draws of the forward model at the true object and probe", "timed_iters": iters}
-    for name, prec, every in (("jacobi", 1, 1), ("learned", 2, 1), ("learned_once", 2, 0)):
+    for name, prec, every in (("jacobi", 1, 1), ("learned", 2, 1), ("learned_every_3", 2, 3),
+                              ("learned_once", 2, 0)):
         pt.lm_set_cnn(prob, net if prec == 2 else None)
         if prec == 2:
             pt.lm_set_cnn_refresh(prob, every)
