@@ -21,7 +21,11 @@ struct Cfg3 {
   static constexpr int NT = L * R;                          // threads per tile (16 values each)
   static constexpr int WG = 576;
   static constexpr int TPW = WG / NT;                       // 4 tiles of 48 x 48, 1 of 96 x 96
-  static constexpr int LDX = L + 1;                         // LDS row pitch (complex)
+  // LDS row pitch (complex), chosen with the LDS bank model of gfx950 (32 banks of 4 bytes, a
+  // 64-bit access served per half wavefront at the cost of its most-hit bank): L + 3 spreads
+  // the x passes' row accesses best among the pitches up to L + 40 (largest bank load 1.6x the
+  // least possible at 96, against 2.5x at L + 1); the y passes stay conflict-free
+  static constexpr int LDX = L + 3;
   static constexpr int TILE = L * LDX;
   static constexpr int GMAX = (16 + R - 1) / R;             // radix-R DFTs per thread in pass 2
   static constexpr int VMAX = GMAX * R > 16 ? GMAX * R : 16;
