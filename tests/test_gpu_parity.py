@@ -373,6 +373,46 @@ def test_corner_and_repeated_positions(probe):
     _check_products(probe, O, P, pos, "poisson", True, seed=probe[0] + 1)
 
 
+@pytest.mark.parametrize("ggn", ["magnitude", "intensity"])
+@pytest.mark.parametrize("probe,photons", [((48, 48), 20.0), ((64, 64), 30.0), ((128, 128), 100.0)],
+                         ids=lambda p: "%dx%d" % p if isinstance(p, tuple) else "%g" % p)
+def test_poisson_low_counts_extreme_weights(probe, photons, ggn):
+    """Poisson data at a few hundredths of a photon per pixel: many counts y >= 1 fall where the
+    model intensity h is far below 1, so the GGN weights 2 + 2y/h (or 4y/h) reach 2e4-3e5 and the
+    FP64 refinement of the linearisation rewrites those pixels.  The linearisation's loss and
+    gradient and the plain and damped GGN-vector products stay within 1e-5 of the FP64 oracle."""
+    print("case poisson low counts", probe, photons, ggn, flush=True)
+    case = make_case(probe, 5, 6, max(probe) // 4, metric="poisson", joint=True, seed=17 + probe[0],
+                     photons=photons)
+    prob = pt.Problem(case["O"].shape, case["P"].shape, case["pos"], metric="poisson", mode="joint",
+                      background=1e-8, device=DEV, ggn=ggn)
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "poisson", True, ggn=ggn)
+    w = lin.l2 if hasattr(lin, "l2") else None
+    if w is not None:
+        print("largest GGN weight %.3e, pixels above 1e4: %d" % (float(np.max(w)), int(np.sum(w > 1e4))))
+        assert np.sum(w > 1e4) > 0
+    f, gO, gP = prob.linearize(O, P, y)
+    f = host(f)
+    assert abs(f[0] - lin.f) <= 1e-5 * abs(lin.f)
+    rgO, rgP = ptycho.gradient(lin)
+    assert rel(host(gO), rgO) < TOL and rel(host(gP), rgP) < TOL
+    rng = np.random.default_rng(29)
+    vO = c64(synth.random_complex(rng, case["O"].shape))
+    vP = c64(synth.random_complex(rng, case["P"].shape))
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128))
+    oO, oP = prob.ggn_vp(to_dev(vO), to_dev(vP))
+    print("ggn rel", rel(host(oO), GO), rel(host(oP), GP))
+    assert rel(host(oO), GO) < TOL and rel(host(oP), GP) < TOL
+    dO = np.abs(rng.standard_normal(case["O"].shape + (2,))).astype(np.float32) + 0.1
+    dP = np.abs(rng.standard_normal(case["P"].shape + (2,))).astype(np.float32) + 0.1
+    lam = 0.21
+    oO, oP = prob.ggn_vp(to_dev(vO), to_dev(vP), lam=lam, dO=to_dev(dO), dP=to_dev(dP))
+    rO = GO + lam * (dO[..., 0] * vO.real + 1j * dO[..., 1] * vO.imag)
+    rP = GP + lam * (dP[..., 0] * vP.real + 1j * dP[..., 1] * vP.imag)
+    assert rel(host(oO), rO) < TOL and rel(host(oP), rP) < TOL
+
+
 @pytest.mark.parametrize("metric", ["gauss", "poisson"])
 @pytest.mark.parametrize("joint", [False, True])
 @pytest.mark.parametrize("L", [16, 32])
