@@ -3,17 +3,18 @@
 The network predicts the shape of the GGN diagonal's object block from the illumination
 geometry; the learned preconditioner is s * exp(r) with s the largest App. B object entry.
 Everything runs through the library's HIP kernels:
-* samples come from LM runs on seeded problems of two recipes: the small object-only recipe
-  with a random quadratic probe phase (``synth.make_c3``: 64x64 object, 16x16 probe, 8x8
-  raster, noise-free; plain LM, D = I) and proxies of the joint 512x512 / 128x128 workload
-  (same probe recipe and scan step, 256x256 object, 8x8 raster, Poisson data; D = Dg(G),
-  Jacobi PCG).  At every iterate the input maps are ``ptlm_cnn_features`` and the target is
+* samples come from LM runs on seeded problems of the small object-only recipe with a random
+  quadratic probe phase (``synth.make_c3``: 64x64 object, 16x16 probe, 8x8 raster, noise-free;
+  plain LM, D = I) and of the joint 512x512 / 128x128 workload's recipe with other seeds
+  (``c1like``: 40x40 raster, Poisson data at 1e4 photons; D = Dg(G), Jacobi PCG) and of the
+  uneven batch's recipe (``c2like``: probe sides 32-96, cropped to 128x128 samples), optionally
+  also of smaller proxies of the joint workload (256x256 object, 8x8 raster).  At every iterate the input maps are ``ptlm_cnn_features`` and the target is
   t = log(d_exact / s) on illuminated object pixels: the exact diagonal of G (``ptlm_diag``
   exact, floored at 1e-6 of its maximum) relative to the largest App. B object entry s;
 * training is Adam on the masked squared error with ``ptlm_cnn_loss_grad`` / ``ptlm_cnn_adam``
   over minibatches drawn from one recipe at a time.
 
-    python -m paper_2103_01767_amd.learned train [--small 200 --proxies 40 --steps 3000]
+    python -m paper_2103_01767_amd.learned train [--small 200 --c1like 200 --c2like 200 --steps 3000]
 """
 from __future__ import annotations
 
@@ -43,6 +44,34 @@ def proxy(seed: int):
 def small(seed: int):
     import synth
     return synth.make_c3(seed)
+
+
+def c1like(seed: int):
+    """A problem of the joint 512x512 / 128x128 workload's recipe with seed 60000 + seed."""
+    import synth
+    return synth.make_c1(60000 + seed)
+
+
+def c2like(seed: int):
+    """A problem of the uneven batch's recipe (probe side 32, 48, 64 or 96, object side 179 and
+    up, 1e3-1e5 photons) drawn with index 1000 + seed, outside the 64 problems of the batch."""
+    import synth
+    return synth.make_c2_problem(1000 + seed)
+
+
+def crop_samples(samples, side, seed):
+    """One seeded side x side crop of every sample (the network is fully convolutional with a
+    9 x 9 receptive field), so that samples of different object sizes share one minibatch shape."""
+    g = torch.Generator()
+    g.manual_seed(seed)
+    out = []
+    for x, t, m in samples:
+        h, w = x.shape[1:]
+        r = int(torch.randint(0, h - side + 1, (1,), generator=g))
+        c = int(torch.randint(0, w - side + 1, (1,), generator=g))
+        cut = lambda a: a[:, r:r + side, c:c + side].contiguous()
+        out.append((cut(x), cut(t), cut(m)))
+    return out
 
 
 def _c64(a, dev):
@@ -222,7 +251,12 @@ def main():
     ap.add_argument("cmd", choices=["train"])
     ap.add_argument("--small", type=int, default=200, help="training problems of the small recipe")
     ap.add_argument("--small-iters", type=int, default=20)
-    ap.add_argument("--proxies", type=int, default=40, help="training proxies of the joint workload")
+    ap.add_argument("--c1like", type=int, default=200, help="training runs of the joint 512/128 recipe")
+    ap.add_argument("--c1like-iters", type=int, default=5)
+    ap.add_argument("--c2like", type=int, default=200, help="training runs of the uneven batch's recipe")
+    ap.add_argument("--c2like-iters", type=int, default=5)
+    ap.add_argument("--crop", type=int, default=128, help="crop side of the batch-recipe samples")
+    ap.add_argument("--proxies", type=int, default=0, help="training proxies (256x256) of the joint workload")
     ap.add_argument("--proxy-iters", type=int, default=5)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8)
@@ -232,24 +266,32 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     train_small = build_samples(range(2000, 2000 + a.small), small, a.small_iters, dev)
+    train_c1 = build_samples(range(a.c1like), c1like, a.c1like_iters, dev)
+    train_c2 = crop_samples(build_samples(range(a.c2like), c2like, a.c2like_iters, dev), a.crop, 1)
     train_proxy = build_samples(range(a.proxies), proxy, a.proxy_iters, dev)
     held_small = build_samples(range(3000, 3020), small, a.small_iters, dev)
-    held_proxy = build_samples(range(1000, 1004), proxy, a.proxy_iters, dev)
+    held_c1 = build_samples(range(1000, 1004), c1like, a.c1like_iters, dev)
+    held_c2 = crop_samples(build_samples(range(500, 520), c2like, a.c2like_iters, dev), a.crop, 2)
     t1 = time.time()
-    print("samples %d + %d (+%d + %d held out) in %.1fs" % (len(train_small), len(train_proxy), len(held_small),
-                                                           len(held_proxy), t1 - t0), flush=True)
+    print("samples %d + %d + %d + %d (+%d + %d + %d held out) in %.1fs"
+          % (len(train_small), len(train_c1), len(train_c2), len(train_proxy), len(held_small), len(held_c1),
+             len(held_c2), t1 - t0), flush=True)
     base = he_params(0, dev)
-    params, hist = train_cnn([train_small, train_proxy], a.steps, a.batch, a.lr, dev=dev,
+    params, hist = train_cnn([train_small, train_c1, train_c2, train_proxy], a.steps, a.batch, a.lr, dev=dev,
                              log=lambda s: print(s, flush=True))
     torch.cuda.synchronize()
     t2 = time.time()
-    meta = {"arch": ARCH, "small": a.small, "small_iters": a.small_iters, "proxies": a.proxies,
-            "proxy_iters": a.proxy_iters, "steps": a.steps, "batch": a.batch, "lr": a.lr,
+    meta = {"arch": ARCH, "small": a.small, "small_iters": a.small_iters, "c1like": a.c1like,
+            "c1like_iters": a.c1like_iters, "c2like": a.c2like, "c2like_iters": a.c2like_iters, "crop": a.crop,
+            "proxies": a.proxies, "proxy_iters": a.proxy_iters,
+            "steps": a.steps, "batch": a.batch, "lr": a.lr,
             "train_seconds": round(t2 - t1, 2), "sample_seconds": round(t1 - t0, 2),
             "heldout_small_loss_untrained": mean_loss(base, held_small, dev),
             "heldout_small_loss": mean_loss(params, held_small, dev),
-            "heldout_proxy_loss_untrained": mean_loss(base, held_proxy, dev),
-            "heldout_proxy_loss": mean_loss(params, held_proxy, dev),
+            "heldout_c1like_loss_untrained": mean_loss(base, held_c1, dev),
+            "heldout_c1like_loss": mean_loss(params, held_c1, dev),
+            "heldout_c2like_loss_untrained": mean_loss(base, held_c2, dev),
+            "heldout_c2like_loss": mean_loss(params, held_c2, dev),
             "history": hist}
     if a.out:
         global PARAMS_PATH, META_PATH
