@@ -3,14 +3,15 @@
 The network predicts the shape of the GGN diagonal's object block from the illumination
 geometry; the learned preconditioner is s * exp(r) with s the largest App. B object entry.
 Everything runs through the library's HIP kernels:
-* samples come from LM runs on seeded problems of the small object-only recipe with a random
-  quadratic probe phase (``synth.make_c3``: 64x64 object, 16x16 probe, 8x8 raster, noise-free;
-  plain LM, D = I) and of the joint 512x512 / 128x128 workload's recipe with other seeds
-  (``c1like``: 40x40 raster, Poisson data at 1e4 photons; D = Dg(G), Jacobi PCG) and of the
-  uneven batch's recipe (``c2like``: probe sides 32-96, cropped to 128x128 samples), optionally
-  also of smaller proxies of the joint workload (256x256 object, 8x8 raster).  At every iterate the input maps are ``ptlm_cnn_features`` and the target is
-  t = log(d_exact / s) on illuminated object pixels: the exact diagonal of G (``ptlm_diag``
-  exact, floored at 1e-6 of its maximum) relative to the largest App. B object entry s;
+* samples come from LM runs on seeded problems of three recipes: the small object-only recipe
+  with a random quadratic probe phase (``synth.make_c3``: 64x64 object, 16x16 probe, 8x8 raster,
+  noise-free; plain LM, D = I), the joint 512x512 / 128x128 workload's recipe with other seeds
+  (``c1like``: 40x40 raster, Poisson data at 1e4 photons; D = Dg(G), Jacobi PCG) and the uneven
+  batch's recipe (``c2like``: probe sides 32-96, cropped to 128x128 samples); smaller proxies of
+  the joint workload (256x256 object, 8x8 raster) are optional.  At every iterate the input maps
+  are ``ptlm_cnn_features`` and the target is t = log(d_exact / s) on illuminated object pixels:
+  the exact diagonal of G (``ptlm_diag`` exact, floored at 1e-6 of its maximum) relative to the
+  largest App. B object entry s;
 * training is Adam on the masked squared error with ``ptlm_cnn_loss_grad`` / ``ptlm_cnn_adam``
   over minibatches drawn from one recipe at a time.
 
