@@ -229,8 +229,8 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
  * probes only.  Both give the product to FP32 rounding; the results differ in the last bits.
  * A handle starts with PTLM_TRANSFORM_MFMA for 16 x 16 probes and PTLM_TRANSFORM_FFT
  * otherwise; ptlm_autotune may change it, and batches use the starting choice.  Takes effect
- * from the next call; enqueues nothing.  PTLM_EINVAL for an unknown value or MFMA on another
- * probe shape. */
+ * from the next call; enqueues nothing.  PTLM_EINVAL for an unknown value, MFMA on another
+ * probe shape, or the handle of a batch's problem (ptlm_batch_problem). */
 ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform);
 
 /* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
@@ -269,7 +269,8 @@ ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed,
  * scale index], -1 where the transform does not apply; h_scale (nullable) the chosen scale,
  * h_transform (nullable) the chosen transform.  The workspace of ptlm_workspace_bytes covers
  * every candidate.  Overwrites the output buffers of the LM (call it before ptlm_lm_init or
- * between LM runs), not the linearisation. */
+ * between LM runs), not the linearisation.  PTLM_EINVAL for the handle of a batch's problem,
+ * whose launch shape the batch fixes. */
 ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_scale, int32_t* h_transform,
                           void* stream);
 

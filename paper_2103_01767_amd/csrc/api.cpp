@@ -492,6 +492,7 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
 
 ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform) {
   PTLM_CHECK_H(h);
+  if (h->in_batch) return fail(PTLM_EINVAL, "ptlm_set_transform: the handle belongs to a batch");
   if (transform != PTLM_TRANSFORM_FFT && transform != PTLM_TRANSFORM_MFMA)
     return fail(PTLM_EINVAL, "ptlm_set_transform: unknown transform");
   if (transform == PTLM_TRANSFORM_MFMA && !ggnv_mfma_supported(h->g.my, h->g.mx))
@@ -523,6 +524,7 @@ ptlm_status ptlm_autotune(ptlm_handle* h, int32_t reps, double* h_ms, double* h_
                           void* stream) {
   PTLM_CHECK_H(h);
   if (reps < 1) return fail(PTLM_EINVAL, "reps must be >= 1");
+  if (h->in_batch) return fail(PTLM_EINVAL, "ptlm_autotune: the handle belongs to a batch (its launch shape is fixed)");
   return autotune_impl(h, reps, h_ms, h_scale, h_transform, (hipStream_t)stream);
 }
 

@@ -40,6 +40,7 @@ struct ptlm_handle {
   ptlm::Plan plan;
   ptlm::Geometry g{};
   char* ws = nullptr;
+  bool in_batch = false;    // a problem of a batch: its launch shape is fixed by the batch's tables
   ptlm_cnn_desc cnn{};      // registered preconditioner network (ptlm_lm_set_cnn)
   const float* cnn_params = nullptr;
   char* cnn_ws = nullptr;

@@ -363,6 +363,7 @@ ptlm_status ptlm_batch_create(int32_t n, const ptlm_desc* descs, const int32_t* 
   hipStream_t s = (hipStream_t)stream;
   for (int i = 0; i < n; ++i) {
     ptlm_handle* h = new ptlm_handle();
+    h->in_batch = true;
     st = init_handle(h, &descs[i], h_pos[i], b->ws + b->ws_off[i], plans[i].ws_bytes, s);
     if (st != PTLM_OK) {
       delete h;

@@ -133,6 +133,11 @@ def test_batch_problem_handles_serve_single_calls():
         z1 = batch.problem(i).forward(O, P)
         z2 = alone.forward(O, P)
         assert torch.equal(z1, z2)
+    # the batch's tables fix each problem's launch shape: no re-segmentation or transform change
+    with pytest.raises(pt.PtlmError, match="batch"):
+        batch.problem(0).autotune(reps=1)
+    with pytest.raises(pt.PtlmError, match="batch"):
+        batch.problem(0).set_transform("fft")
 
 
 def test_batch_learned_preconditioner_equals_alone():
