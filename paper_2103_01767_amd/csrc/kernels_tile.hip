@@ -299,9 +299,17 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
         }
       }
       if constexpr (OP == OP_LINEARIZE) {
-        // per-position trace of the metric Hessian (App. B), reduced over the tile
-        tr = tile_sum<C>(tr, red, 0, slot);
-        if (act && t == 0) g.trace[k] = tr;
+        // per-position trace of the metric Hessian (App. B), reduced over the tile; a tile of
+        // several wavefronts leaves their sums in LDS, added after the inverse transform's
+        // next workgroup barrier
+        if constexpr (C::NT > 64) {
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+          if ((threadIdx.x & 63) == 0) red[(threadIdx.x / 64) * 2] = tr;
+        } else {
+          tr = tile_sum<C>(tr, red, 0, slot);
+          if (act && t == 0) g.trace[k] = tr;
+        }
       }
     }
 
@@ -409,6 +417,15 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
         for (int u = 0; u < V; ++u) dft16<true>(v[u]);
       }
       __syncthreads();
+      if constexpr (OP == OP_LINEARIZE && C::NT > 64) {
+        // the trace's wavefront sums in order (the next position writes them after the
+        // barrier below)
+        if (act && t == 0) {
+          double x = 0.0;
+          for (int w = 0; w < C::NT / 64; ++w) x += red[(slot * (C::NT / 64) + w) * 2];
+          g.trace[k] = x;
+        }
+      }
       if (act) {
 #pragma unroll
         for (int u = 0; u < V; ++u) {

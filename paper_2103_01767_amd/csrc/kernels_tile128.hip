@@ -202,18 +202,13 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
         pixel_op<OP, MET>(g, a, base + (size_t)ky * L + col, isq, bgv, v[r], s0, s1, tr);
       }
       if constexpr (OP == OP_LINEARIZE) {
-        // per-position trace of the metric Hessian (App. B); slots alternate by position parity,
-        // so the next position's writes cannot meet this position's read
+        // per-position trace of the metric Hessian (App. B): each wavefront leaves its part in
+        // the slot of this position's parity; thread 0 sums the slot after the y -> x transpose
+        // barrier below, before it reaches the next position's first barrier, while the next
+        // position's parts go to the other slot
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
-        double* slot = red_tr + (k & 1) * NW;
-        if (lane == 0) slot[wv] = tr;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          double t = 0.0;
-          for (int q = 0; q < NW; ++q) t += slot[q];
-          g.trace[k] = t;
-        }
+        if (lane == 0) red_tr[(k & 1) * NW + wv] = tr;
       }
     }
 
@@ -237,6 +232,14 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
 #pragma unroll
       for (int j = 0; j < 16; ++j) lds[at(lr + 8 * j, col)] = v[j];
       __syncthreads();
+      if constexpr (OP == OP_LINEARIZE) {
+        if (threadIdx.x == 0) {
+          const double* slot = red_tr + (k & 1) * NW;
+          double t = 0.0;
+          for (int q = 0; q < NW; ++q) t += slot[q];
+          g.trace[k] = t;
+        }
+      }
       // ---------------- inverse x pass B: DFT16 over k1 -> n1 for k2 = lc, conjugate twiddle
 #pragma unroll
       for (int k1 = 0; k1 < 16; ++k1) v[k1] = lds[at(row, lc + 8 * k1)];

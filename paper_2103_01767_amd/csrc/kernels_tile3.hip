@@ -32,6 +32,7 @@ struct Cfg3 {
   static constexpr int NWAVE = WG / 64;
   static constexpr int TW_OFF = L == 48 ? 480 : 528;        // W_L^(n k), n < R, k < 16
   static_assert(TPW * NT == WG, "tiles must fill the workgroup");
+  static_assert(NT % 16 == 0, "the trace sums take 16 strided parts");
 };
 
 namespace {
@@ -54,7 +55,8 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
   extern __shared__ float2 smem[];
   double* red = reinterpret_cast<double*>(smem + C::TPW * C::TILE);  // [NWAVE][2]
   double* tsum = red + 2 * C::NWAVE;                                 // [WG] per-thread values
-  float2* tw = reinterpret_cast<float2*>(tsum + C::WG);              // [R][16]
+  double* tpart = tsum + C::WG;                                      // [TPW][16] partial sums
+  float2* tw = reinterpret_cast<float2*>(tpart + C::TPW * 16);       // [R][16]
   for (int i = threadIdx.x; i < R * 16; i += C::WG) tw[i] = g.tw[C::TW_OFF + i];
   __syncthreads();
 
@@ -217,9 +219,15 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
           }
         }
       }
-      if constexpr (OP == OP_LINEARIZE || OP == OP_DIAG_EXACT) {
-        // per-tile sum (trace of ell'' / sum |a|^2) through LDS, fixed order
-        tsum[threadIdx.x] = OP == OP_LINEARIZE ? tr : asum;
+      if constexpr (OP == OP_LINEARIZE) {
+        // per-tile trace of ell'' (App. B): each thread leaves its part in LDS; the sum runs in
+        // a fixed order after the next two barriers of the inverse transform (16 strided
+        // partial sums per tile, then their sum), and the next position's parts are written
+        // only after the position's last barrier
+        tsum[threadIdx.x] = tr;
+      } else if constexpr (OP == OP_DIAG_EXACT) {
+        // per-tile sum of |a|^2 through LDS, fixed order, returned to every thread of the tile
+        tsum[threadIdx.x] = asum;
         __syncthreads();
         if (t == 0) {
           double s = 0.0;
@@ -227,11 +235,7 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
           tsum[slot * NT] = s;
         }
         __syncthreads();
-        if constexpr (OP == OP_LINEARIZE) {
-          if (act && t == 0) g.trace[k] = tsum[slot * NT];
-        } else {
-          asum = tsum[slot * NT];
-        }
+        asum = tsum[slot * NT];
         __syncthreads();
       }
     }
@@ -290,6 +294,15 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
         }
       }
       __syncthreads();
+      if constexpr (OP == OP_LINEARIZE) {
+        // trace, first level: partial sum j of tile ts over its parts j, j + 16, j + 32, ...
+        if (threadIdx.x < C::TPW * 16) {
+          const int ts = threadIdx.x / 16, j = threadIdx.x % 16;
+          double s = 0.0;
+          for (int i = 0; i < NT / 16; ++i) s += tsum[ts * NT + j + 16 * i];
+          tpart[threadIdx.x] = s;
+        }
+      }
       if (act) {
 #pragma unroll
         for (int gg = 0; gg < GMAX; ++gg) {
@@ -301,6 +314,15 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
         }
       }
       __syncthreads();
+      if constexpr (OP == OP_LINEARIZE) {
+        // trace, second level: the tile's 16 partial sums in order
+        if (act && t == 0) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) s += tpart[slot * 16 + j];
+          g.trace[k] = s;
+        }
+      }
       // ---------------- inverse y pass 1 (DFT16 over k1 -> n2): rows ys + R n2
       if (act) {
 #pragma unroll
@@ -416,7 +438,7 @@ __global__ __launch_bounds__(576) void tile3_batch_kernel(const TileJob* __restr
 template <int L>
 size_t tile3_lds() {
   using C = Cfg3<L>;
-  return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)(2 * C::NWAVE + C::WG) * sizeof(double) +
+  return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)(2 * C::NWAVE + C::WG + C::TPW * 16) * sizeof(double) +
          (size_t)C::R * 16 * sizeof(float2);
 }
 
