@@ -275,7 +275,8 @@ def ggnv_isolated(prob, dev, calls, stream):
 
 def mfma_trial(dev, calls):
     """The GGN-vector product with the DFT as matrix products on the matrix cores against the
-    FFT tile kernel's (ptlm_set_transform "mfma" / "fft") on two small-probe scans, joint, object 512x512, raster step 4: probe 16x16
+    FFT tile kernel's, in its standard and its wide tile grouping (ptlm_set_transform "mfma" /
+    "fft" / "fft_wide"), on two small-probe scans, joint, object 512x512, raster step 4: probe 16x16
     with a 120x120 raster (14 400 positions) and probe 32x32 with a 116x116 raster (13 456
     positions), each linearised at a seeded random point with seeded stand-in counts (the
     product's cost does not depend on the data).  Whole calls (per-position kernel plus the same
@@ -301,7 +302,7 @@ def mfma_trial(dev, calls):
         out = (torch.empty_like(vO), torch.empty_like(vP))
         res = {"workload": "joint, object 512x512, probe %dx%d, %dx%d raster step 4 (%d positions)"
                % (L, L, n, n, n * n)}
-        for name in ("fft", "mfma"):
+        for name in ("fft", "mfma", "fft_wide"):
             prob.set_transform(name)
             fn = prob.ggn_vp
             for _ in range(3):
@@ -321,6 +322,7 @@ def mfma_trial(dev, calls):
         res["rel_diff"] = float(max(torch.linalg.norm(f_out[i] - m_out[i]) / torch.linalg.norm(f_out[i])
                                     for i in (0, 1)))
         res["mfma_over_fft"] = round(res["mfma_call_ms"] / res["fft_call_ms"], 3)
+        res["fft_wide_over_fft"] = round(res["fft_wide_call_ms"] / res["fft_call_ms"], 3)
         out_all["%dx%d" % (L, L)] = res
         del prob
     return out_all

@@ -56,8 +56,9 @@ typedef enum {
 typedef enum { PTLM_GAUSS = 0, PTLM_POISSON = 1 } ptlm_metric; /* eq:ell_magnitude */
 typedef enum { PTLM_OBJECT = 0, PTLM_JOINT = 1 } ptlm_mode;    /* SPR eq:cdp / BPR eq:bp */
 typedef enum { PTLM_GGN_MAGNITUDE = 0, PTLM_GGN_INTENSITY = 1 } ptlm_ggn;
-/* How the GGN-vector product applies F (a project choice, ptlm_set_transform). */
-typedef enum { PTLM_TRANSFORM_FFT = 0, PTLM_TRANSFORM_MFMA = 1 } ptlm_transform;
+/* How the GGN-vector product applies F and groups its tiles (a project choice,
+ * ptlm_set_transform). */
+typedef enum { PTLM_TRANSFORM_FFT = 0, PTLM_TRANSFORM_MFMA = 1, PTLM_TRANSFORM_FFT_WIDE = 2 } ptlm_transform;
 
 /* Problem description.  Probe sides my, mx must each be 16, 32, 64 or 128, or both 48, 96 or 256. */
 typedef struct {
@@ -226,11 +227,14 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
  * ptlm_lm_solve) applies the 2D DFT F of eq:expected_count: PTLM_TRANSFORM_FFT, the tile
  * kernels' radix-16 FFT; PTLM_TRANSFORM_MFMA, F X F as two complex L x L matrix products on the
  * FP32 matrix cores (v_mfma_f32_16x16x4_f32 / v_mfma_f32_32x32x2_f32), for 16 x 16 and 32 x 32
- * probes only.  Both give the product to FP32 rounding; the results differ in the last bits.
- * A handle starts with PTLM_TRANSFORM_MFMA for 16 x 16 probes and PTLM_TRANSFORM_FFT
- * otherwise; ptlm_autotune may change it, and batches use the starting choice.  Takes effect
- * from the next call; enqueues nothing.  PTLM_EINVAL for an unknown value, MFMA on another
- * probe shape, or the handle of a batch's problem (ptlm_batch_problem). */
+ * probes only; PTLM_TRANSFORM_FFT_WIDE, the radix-16 FFT with workgroups of twice the tiles
+ * (512 threads) over the same segments, for probe sides of 16 to 128 with at most 4096 pixels.
+ * All give the product to FP32 rounding; MFMA differs from the FFT in the last bits, the wide
+ * grouping gives the FFT's bits.  A handle starts with PTLM_TRANSFORM_MFMA for 16 x 16 probes,
+ * PTLM_TRANSFORM_FFT_WIDE for 32 x 32 and PTLM_TRANSFORM_FFT otherwise; ptlm_autotune may
+ * change it, and batches use the starting choice.  Takes effect from the next call; enqueues
+ * nothing.  PTLM_EINVAL for an unknown value, a value the probe shape does not have, or the
+ * handle of a batch's problem (ptlm_batch_problem). */
 ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform);
 
 /* The two stages of ptlm_ggn_vp, for timing the per-position kernel on its own.
@@ -263,10 +267,11 @@ ptlm_status ptlm_diag_stochastic(ptlm_handle* h, int32_t samples, uint64_t seed,
 /* Autotuner of the tile-kernel launch (a project addition).  Times the GGN-vector product
  * (reps calls after one warm-up) with the positions cut into 0.5x, 1x and 2x as many
  * segments (workgroups) as the GPU keeps resident, for each transform the probe shape has
- * (PTLM_TRANSFORM_FFT always, PTLM_TRANSFORM_MFMA at 16 x 16 and 32 x 32), and keeps the
- * fastest pair.  Results do not depend on the choice beyond FP32 rounding.  Synchronises the
- * stream.  h_ms (6 host doubles, nullable) receives the time per call at [transform * 3 +
- * scale index], -1 where the transform does not apply; h_scale (nullable) the chosen scale,
+ * (PTLM_TRANSFORM_FFT always, PTLM_TRANSFORM_MFMA at 16 x 16 and 32 x 32,
+ * PTLM_TRANSFORM_FFT_WIDE up to 4096 pixels), and keeps the fastest pair.  Results do not
+ * depend on the choice beyond FP32 rounding.  Synchronises the stream.  h_ms (9 host doubles,
+ * nullable) receives the time per call at [transform * 3 + scale index], -1 where the
+ * transform does not apply; h_scale (nullable) the chosen scale,
  * h_transform (nullable) the chosen transform.  The workspace of ptlm_workspace_bytes covers
  * every candidate.  Overwrites the output buffers of the LM (call it before ptlm_lm_init or
  * between LM runs), not the linearisation.  PTLM_EINVAL for the handle of a batch's problem,

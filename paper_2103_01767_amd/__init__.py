@@ -33,6 +33,8 @@ PTLM_ENUMERIC = -4
 GAUSS, POISSON = 0, 1
 OBJECT, JOINT = 0, 1
 GGN_MAGNITUDE, GGN_INTENSITY = 0, 1
+# ptlm_transform values by name (PTLM_TRANSFORM_FFT, _MFMA, _FFT_WIDE)
+TRANSFORMS = ("fft", "mfma", "fft_wide")
 
 
 class ptlm_desc(ctypes.Structure):
@@ -299,9 +301,10 @@ class Problem:
         return oO, oP
 
     def set_transform(self, name):
-        """ptlm_set_transform: "fft" (radix-16 FFT tile kernels) or "mfma" (DFT as matrix products
-        on the matrix cores, 16 x 16 and 32 x 32 probes) for the GGN-vector product."""
-        _check(_lib.ptlm_set_transform(self.handle, {"fft": 0, "mfma": 1}[name]))
+        """ptlm_set_transform: "fft" (radix-16 FFT tile kernels), "mfma" (DFT as matrix products
+        on the matrix cores, 16 x 16 and 32 x 32 probes) or "fft_wide" (the FFT with twice the
+        tiles per workgroup, probes of at most 4096 pixels) for the GGN-vector product."""
+        _check(_lib.ptlm_set_transform(self.handle, TRANSFORMS.index(name)))
 
     def ggn_vp_stage(self, stage, vO, vP=None, out=None):
         """Run one stage of the GGN-vector product (1: per-position kernel, 2: reductions)."""
@@ -329,11 +332,11 @@ class Problem:
     def autotune(self, reps=5):
         """Pick the segment count and the transform of the GGN-vector product by timing it.
         Returns (scale, ms, transform): ms[transform * 3 + i] at scale 0.5, 1, 2 (-1: n/a)."""
-        ms = (ctypes.c_double * 6)()
+        ms = (ctypes.c_double * (3 * len(TRANSFORMS)))()
         sc = ctypes.c_double(0)
         xf = ctypes.c_int32(0)
         _check(_lib.ptlm_autotune(self.handle, int(reps), ms, ctypes.byref(sc), ctypes.byref(xf), _stream()))
-        return float(sc.value), [float(v) for v in ms], ("fft", "mfma")[xf.value]
+        return float(sc.value), [float(v) for v in ms], TRANSFORMS[xf.value]
 
     def new_state(self):
         return torch.zeros(STATE_BYTES, dtype=torch.uint8, device=self.device)

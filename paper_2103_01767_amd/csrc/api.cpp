@@ -251,10 +251,12 @@ ptlm_status autotune_impl(ptlm_handle* h, int reps, double* h_ms, double* h_scal
   int bi = 1, bx = h->g.xform;
   ptlm_status st = PTLM_OK;
   const int nc = (int)(kNumGridScales);
-  const int nx = ggnv_mfma_supported(h->g.my, h->g.mx) ? 2 : 1;
   if (h_ms)
-    for (int i = 0; i < 2 * nc; ++i) h_ms[i] = -1.0;
-  for (int x = 0; x < nx && st == PTLM_OK; ++x) {
+    for (int i = 0; i < kNumTransforms * nc; ++i) h_ms[i] = -1.0;
+  for (int x = 0; x < kNumTransforms && st == PTLM_OK; ++x) {
+    if ((x == PTLM_TRANSFORM_MFMA && !ggnv_mfma_supported(h->g.my, h->g.mx)) ||
+        (x == PTLM_TRANSFORM_FFT_WIDE && !ggnv_wide_supported(h->g.my, h->g.mx)))
+      continue;
     h->g.xform = x;
     for (int i = 0; i < nc && st == PTLM_OK; ++i) {
       st = resegment(h, kGridScales[i], s);
@@ -493,10 +495,12 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
 ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform) {
   PTLM_CHECK_H(h);
   if (h->in_batch) return fail(PTLM_EINVAL, "ptlm_set_transform: the handle belongs to a batch");
-  if (transform != PTLM_TRANSFORM_FFT && transform != PTLM_TRANSFORM_MFMA)
+  if (transform != PTLM_TRANSFORM_FFT && transform != PTLM_TRANSFORM_MFMA && transform != PTLM_TRANSFORM_FFT_WIDE)
     return fail(PTLM_EINVAL, "ptlm_set_transform: unknown transform");
   if (transform == PTLM_TRANSFORM_MFMA && !ggnv_mfma_supported(h->g.my, h->g.mx))
     return fail(PTLM_EINVAL, "ptlm_set_transform: the matrix-product transform needs 16 x 16 or 32 x 32 probes");
+  if (transform == PTLM_TRANSFORM_FFT_WIDE && !ggnv_wide_supported(h->g.my, h->g.mx))
+    return fail(PTLM_EINVAL, "ptlm_set_transform: the wide grouping needs probe sides of 16-128 with at most 4096 pixels");
   h->g.xform = transform;
   return PTLM_OK;
 }

@@ -79,6 +79,7 @@ ptlm_status hip_fail(hipError_t e, const char* where);
 ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double grid_scale = 1.0);
 // segment count scales the autotuner tries (the workspace holds the largest segment tables)
 constexpr int kNumGridScales = 3;
+constexpr int kNumTransforms = 3;  // ptlm_transform values
 extern const double kGridScales[kNumGridScales];
 // workgroups of the tile kernels at a grid scale; cut the positions into segments for them
 int plan_grid(const Plan& p, double scale);

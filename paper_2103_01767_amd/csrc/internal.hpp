@@ -27,7 +27,8 @@ struct Geometry {
   float background;
   int nseg;    // number of position segments (= grid * tiles per workgroup)
   int grid;    // workgroups of the tile kernels
-  int xform;   // transform of the GGN-vector product: 0 FFT tile kernel, 1 DFT as matrix products
+  int xform;   // transform of the GGN-vector product: 0 FFT tile kernel, 1 DFT as matrix products,
+               // 2 FFT tile kernel with the wide grouping (twice the tiles per workgroup)
   // constant tables in the workspace
   const float2* tw;       // twiddles W_L^(n k), n < L/16, k < 16: L = 32, 64, 128, 256, 48, 96
                           // (offsets 0, 32, 96, 224, 480, 528)
@@ -133,9 +134,13 @@ hipError_t launch_refine(const Geometry& g, const TileArgs& a, hipStream_t s);
 // DFT-as-MFMA GGN-vector kernel for 16 x 16 and 32 x 32 probes (kernels_dft_mfma.hip), same
 // scratch as the tile kernels
 bool ggnv_mfma_supported(int my, int mx);
-// the transform a new handle starts with: the matrix products for 16 x 16 probes (measured
-// faster there), the FFT tile kernels otherwise
+// the transform a new handle starts with: the matrix products for 16 x 16 probes and the wide
+// grouping for 32 x 32 (each measured fastest there), the FFT tile kernels otherwise
 int default_xform(int my, int mx);
+// the wide grouping of the generic FFT tile kernel's GGN-vector product (kernels_tile.hip): for
+// probes of at most 4096 pixels on that kernel, workgroups of twice the tiles over the same
+// segments, ceil(grid / 2) of them; the batched form takes the standard block table
+bool ggnv_wide_supported(int my, int mx);
 hipError_t launch_ggnv_mfma(const Geometry& g, const TileArgs& a, hipStream_t s);
 // batched form over the tile kernels' block table of a 16 x 16 class (16 segments per block)
 hipError_t launch_ggnv_mfma_batch(const TileJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);

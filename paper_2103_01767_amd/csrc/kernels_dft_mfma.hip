@@ -195,7 +195,11 @@ __global__ __launch_bounds__(64 * BATCH_WAVES) void ggnv16_batch_kernel(const Ti
 }  // namespace mfmadft
 
 bool ggnv_mfma_supported(int my, int mx) { return my == mx && (my == 16 || my == 32); }
-int default_xform(int my, int mx) { return my == 16 && mx == 16 ? 1 : 0; }
+int default_xform(int my, int mx) {
+  if (my == 16 && mx == 16) return 1;
+  if (my == 32 && mx == 32) return 2;
+  return 0;
+}
 
 hipError_t launch_ggnv_mfma_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;

@@ -21,13 +21,15 @@
 
 namespace ptlm {
 
-template <int MY_, int MX_>
+// W: workgroup width, 1 for tiles filling 256 threads, 2 for the wide grouping of the
+// GGN-vector product (PTLM_TRANSFORM_FFT_WIDE: twice the tiles, the same segments)
+template <int MY_, int MX_, int W_ = 1>
 struct Cfg {
   static constexpr int MY = MY_, MX = MX_, M = MY * MX;
   static constexpr int NV = M / 16;                       // virtual threads per tile (16 values each)
   static constexpr int V = 1;                             // virtual threads per real thread
   static constexpr int NT = NV / V;                       // real threads per tile
-  static constexpr int TPW = NT >= 256 ? 1 : 256 / NT;    // tiles per workgroup
+  static constexpr int TPW = (NT >= 256 ? 1 : 256 / NT) * W_;  // tiles per workgroup
   static constexpr int WG = NT * TPW;
   static constexpr int RX = MX / 16, RY = MY / 16;        // second-pass radices
   static constexpr int GX = 16 / RX, GY = 16 / RY;        // second-pass groups per virtual thread
@@ -65,9 +67,9 @@ __device__ __forceinline__ double tile_sum(double x, double* red, int col, int s
 
 // MET: the metric / GGN-weight code of the per-pixel op (tile_pixel.hpp); -1 reads it from g
 // per pixel (batched launches mix problems)
-template <int MY, int MX, int OP, int MET>
+template <int MY, int MX, int OP, int MET, int W = 1>
 __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, int bid, int nblk) {
-  using C = Cfg<MY, MX>;
+  using C = Cfg<MY, MX, W>;
   constexpr int RX = C::RX, RY = C::RY, GX = C::GX, GY = C::GY, LDX = C::LDX, XA = C::XA, V = C::V, NT = C::NT;
   constexpr bool FWD_FFT = OP != OP_VJP && OP != OP_VJP_RAND;
   constexpr bool INV_FFT = OP == OP_LINEARIZE || OP == OP_VJP || OP == OP_GGNV || OP == OP_VJP_RAND;
@@ -86,12 +88,14 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   float2* lds = smem + slot * C::TILE;
   const int blk = xcd_block(bid, nblk);
   const int seg = blk * C::TPW + slot;
-  const int kbeg = g.seg_start[seg], kend = g.seg_start[seg + 1];
+  // a wide launch over an odd number of standard workgroups has slots past the last segment
+  const bool real = seg < g.nseg;
+  const int kbeg = real ? g.seg_start[seg] : 0, kend = real ? g.seg_start[seg + 1] : 0;
   int maxlen = 0;
 #pragma unroll
   for (int s = 0; s < C::TPW; ++s) {
     const int q = blk * C::TPW + s;
-    maxlen = max(maxlen, g.seg_start[q + 1] - g.seg_start[q]);
+    if (q < g.nseg) maxlen = max(maxlen, g.seg_start[q + 1] - g.seg_start[q]);
   }
   const float2* twx = tw_table(s_tw, MX);
   const float2* twy = tw_table(s_tw, MY);
@@ -106,7 +110,7 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   for (int u = 0; u < VA; ++u)
 #pragma unroll
     for (int j = 0; j < JA; ++j) accP[u][j] = make_float2(0.f, 0.f);
-  float2* pslot = g.probe_part + (size_t)seg * C::M;  // this segment's probe partial
+  float2* pslot = g.probe_part + (size_t)(real ? seg : 0) * C::M;  // this segment's probe partial
   double s0 = 0.0, s1 = 0.0;
 
   // The segment's first position stores its contribution into the strip (and the global
@@ -115,8 +119,10 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   float2* strip = nullptr;
   int4 box = make_int4(0, 0, 0, 0);
   if constexpr (SCATTER) {
-    strip = g.strips + g.seg_off[seg];
-    box = g.seg_box[seg];
+    if (real) {
+      strip = g.strips + g.seg_off[seg];
+      box = g.seg_box[seg];
+    }
     if (kend > kbeg) {
       const int2 p0 = g.pos[kbeg];
       const int area = box.z * box.w;
@@ -125,7 +131,7 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
         if ((unsigned)(Y - p0.x) >= (unsigned)MY || (unsigned)(X - p0.y) >= (unsigned)MX)
           strip[i] = make_float2(0.f, 0.f);
       }
-    } else if (!C::PROBE_REGS && joint) {
+    } else if (!C::PROBE_REGS && joint && real) {
       for (int i = t; i < C::M; i += NT) pslot[i] = make_float2(0.f, 0.f);
     }
   }
@@ -528,7 +534,7 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   }
 
   if constexpr (SCATTER && C::PROBE_REGS) {
-    if (joint) {
+    if (joint && real) {
 #pragma unroll
       for (int u = 0; u < V; ++u) {
         const int tv = t + u * NT, xy = tv / RX, xn1 = tv % RX;
@@ -566,27 +572,29 @@ __device__ __forceinline__ void tile_body(const Geometry g, const TileArgs a, in
   }
 }
 
-template <int MY, int MX, int OP, int MET>
-__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_kernel(Geometry g, TileArgs a) {
-  tile_body<MY, MX, OP, MET>(g, a, blockIdx.x, gridDim.x);
+template <int MY, int MX, int OP, int MET, int W = 1>
+__global__ __launch_bounds__((Cfg<MY, MX, W>::WG)) void tile_kernel(Geometry g, TileArgs a) {
+  tile_body<MY, MX, OP, MET, W>(g, a, blockIdx.x, gridDim.x);
 }
 
 // batched: block b belongs to job job_of_block[b]; trailing blocks of a job's run exit
-template <int MY, int MX, int OP>
-__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_batch_kernel(const TileJob* __restrict__ jobs,
-                                                                       const int* __restrict__ job_of_block) {
+// (the wide grouping runs the segments of standard blocks 2b and 2b + 1 in block b)
+template <int MY, int MX, int OP, int W = 1>
+__global__ __launch_bounds__((Cfg<MY, MX, W>::WG)) void tile_batch_kernel(const TileJob* __restrict__ jobs,
+                                                                          const int* __restrict__ job_of_block) {
   const TileJob& J = jobs[job_of_block[blockIdx.x]];
   const int b = (int)blockIdx.x - J.block0;
-  if (b >= J.g.grid) return;
-  tile_body<MY, MX, OP, -1>(J.g, J.a, b, J.g.grid);
+  const int nb = (J.g.grid + W - 1) / W;
+  if (b >= nb) return;
+  tile_body<MY, MX, OP, -1, W>(J.g, J.a, b, nb);
 }
 
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <int MY, int MX>
+template <int MY, int MX, int W = 1>
 static size_t lds_bytes() {
-  using C = Cfg<MY, MX>;
+  using C = Cfg<MY, MX, W>;
   return (size_t)C::TPW * C::TILE * sizeof(float2) + (size_t)C::NWAVE * 2 * sizeof(double) + 224 * sizeof(float2);
 }
 
@@ -677,8 +685,64 @@ static hipError_t launch_mx(const Geometry& g, int op, const TileArgs& a, hipStr
   }
 }
 
+// GGN-vector product with the wide grouping: ceil(grid / 2) workgroups of twice the tiles
+template <int MY, int MX>
+static hipError_t launch_wide(const Geometry& g, const TileArgs& a, hipStream_t s) {
+  using C = Cfg<MY, MX, 2>;
+  const size_t lds = lds_bytes<MY, MX, 2>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<MY, MX, OP_GGNV, 0, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile_kernel<MY, MX, OP_GGNV, 0, 2>), dim3((g.grid + 1) / 2), dim3(C::WG), lds, s, g, a);
+  return hipGetLastError();
+}
+
+template <int MY, int MX>
+static hipError_t launch_wide_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+  using C = Cfg<MY, MX, 2>;
+  const size_t lds = lds_bytes<MY, MX, 2>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)tile_batch_kernel<MY, MX, OP_GGNV, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((tile_batch_kernel<MY, MX, OP_GGNV, 2>), dim3(nb), dim3(C::WG), lds, s, jobs, jb);
+  return hipGetLastError();
+}
+
+// probe shapes of the generic kernel with at most 256 threads a tile (M <= 4096)
+bool ggnv_wide_supported(int my, int mx) {
+  const bool side = (my == 16 || my == 32 || my == 64 || my == 128) && (mx == 16 || mx == 32 || mx == 64 || mx == 128);
+  return side && my * mx <= 4096;
+}
+
+#define PTLM_WIDE_SHAPES(X) \
+  X(16, 16) X(16, 32) X(16, 64) X(16, 128) X(32, 16) X(32, 32) X(32, 64) X(32, 128) X(64, 16) X(64, 32) X(64, 64) \
+  X(128, 16) X(128, 32)
+
+static hipError_t launch_ggnv_wide(const Geometry& g, const TileArgs& a, hipStream_t s) {
+#define PTLM_W(A, B) if (g.my == A && g.mx == B) return launch_wide<A, B>(g, a, s);
+  PTLM_WIDE_SHAPES(PTLM_W)
+#undef PTLM_W
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_ggnv_wide_batch(int my, int mx, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
+#define PTLM_W(A, B) if (my == A && mx == B) return launch_wide_batch<A, B>(jobs, jb, nb, s);
+  PTLM_WIDE_SHAPES(PTLM_W)
+#undef PTLM_W
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t s) {
   if (op == OP_GGNV && g.xform == 1 && ggnv_mfma_supported(g.my, g.mx)) return launch_ggnv_mfma(g, a, s);
+  if (op == OP_GGNV && g.xform == 2 && ggnv_wide_supported(g.my, g.mx)) return launch_ggnv_wide(g, a, s);
   if (g.my == 256 && g.mx == 256) return launch_tile256(g, op, a, s);
   if (g.my == 128 && g.mx == 128 && tile128_handles(op)) return launch_tile128(g, op, a, s);
   if (g.my == g.mx && (g.my == 48 || g.my == 96)) return launch_tile3(g, op, a, s);
@@ -695,6 +759,7 @@ hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const 
   if (nb <= 0) return hipSuccess;
   // a batch runs every problem with the transform its shape starts with
   if (op == OP_GGNV && default_xform(my, mx) == 1) return launch_ggnv_mfma_batch(jobs, jb, nb, s);
+  if (op == OP_GGNV && default_xform(my, mx) == 2) return launch_ggnv_wide_batch(my, mx, jobs, jb, nb, s);
   if (my == 256 && mx == 256) return launch_tile256_batch(op, jobs, jb, nb, s);
   if (my == 128 && mx == 128) return launch_tile128_batch(op, jobs, jb, nb, s);
   if (my == mx && (my == 48 || my == 96)) return launch_tile3_batch(my, op, jobs, jb, nb, s);

@@ -219,8 +219,8 @@ def test_invalid_arguments():
 
 @pytest.mark.parametrize("probe,n,step", [((64, 64), 20, 6), ((32, 32), 30, 4)], ids=["64x64", "32x32"])
 def test_autotuned_segmentation_keeps_products(probe, n, step):
-    """The autotuner only changes how positions are cut into segments and, at 32 x 32, which
-    transform the product uses: products stay at parity."""
+    """The autotuner only changes how positions are cut into segments and which transform and
+    tile grouping the product uses: products stay at parity."""
     print("case autotune", probe, flush=True)
     case = make_case(probe, n, n, step, joint=True, seed=31)
     prob = problem(case)
@@ -229,9 +229,12 @@ def test_autotuned_segmentation_keeps_products(probe, n, step):
     prob.linearize(O, P, y)
     scale, ms, xf = prob.autotune(reps=3)
     print("autotune scale", scale, "transform", xf, "ms", ms)
-    assert scale in (0.5, 1.0, 2.0) and all(m > 0 for m in ms[:3])
-    assert (xf == "mfma") == (min(ms[3:]) > 0 and min(ms[3:]) < min(ms[:3]))
-    assert all(m > 0 for m in ms[3:]) if probe == (32, 32) else all(m == -1 for m in ms[3:])
+    assert scale in (0.5, 1.0, 2.0) and len(ms) == 9
+    fft, mfma, wide = ms[0:3], ms[3:6], ms[6:9]
+    assert all(m > 0 for m in fft) and all(m > 0 for m in wide)  # both shapes have the wide grouping
+    assert all(m > 0 for m in mfma) if probe == (32, 32) else all(m == -1 for m in mfma)
+    best = min((m, name) for name, row in zip(pt.TRANSFORMS, (fft, mfma, wide)) for m in row if m > 0)
+    assert xf == best[1] and min(ms[3 * pt.TRANSFORMS.index(xf):][:3]) == best[0]
     rng = np.random.default_rng(4)
     vO = c64(synth.random_complex(rng, case["O"].shape))
     vP = c64(synth.random_complex(rng, case["P"].shape))
@@ -459,3 +462,37 @@ def test_transform_choice_rejected_for_other_shapes():
     with pytest.raises(pt.PtlmError):
         prob.set_transform("mfma")
     prob.set_transform("fft")
+    prob.set_transform("fft_wide")
+    for shape in ((128, 128), (64, 128), (96, 96)):  # more than 4096 pixels or not the generic kernel
+        big = problem(make_case(shape, 2, 2, 8, seed=93))
+        with pytest.raises(pt.PtlmError):
+            big.set_transform("fft_wide")
+        big.set_transform("fft")
+
+
+@pytest.mark.parametrize("joint", [False, True], ids=["object", "joint"])
+@pytest.mark.parametrize("probe", [(16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (128, 32)],
+                         ids=lambda p: "%dx%d" % p)
+def test_ggn_vp_wide_grouping_equals_fft(probe, joint):
+    """The wide grouping (twice the tiles per workgroup over the same segments) runs the FFT tile
+    kernel's arithmetic unchanged: its GGN-vector product equals the standard grouping's bit for
+    bit and the FP64 oracle to the bar.  A 9 x 9 raster gives an odd standard grid for every
+    shape here but 16 x 16, so the last wide workgroup has slots past the last segment."""
+    print("case ggn wide", probe, joint, flush=True)
+    case = make_case(probe, 9, 9, 6, joint=joint, seed=95 + probe[0] + probe[1])
+    prob = problem(case)
+    O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
+    lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "gauss", joint)
+    prob.linearize(O, P, y)
+    rng = np.random.default_rng(13)
+    vO = c64(synth.random_complex(rng, case["O"].shape))
+    vP = c64(synth.random_complex(rng, case["P"].shape)) if joint else None
+    GO, GP = ptycho.ggn_vp(lin, vO.astype(np.complex128), vP.astype(np.complex128) if joint else None)
+    out = {}
+    for xf in ("fft", "fft_wide", "fft"):
+        prob.set_transform(xf)
+        out[xf] = [host(t) for t in prob.ggn_vp(to_dev(vO), to_dev(vP) if joint else None) if t is not None]
+    assert all(np.array_equal(a, b) for a, b in zip(out["fft_wide"], out["fft"]))
+    assert rel(out["fft_wide"][0], GO) < TOL
+    if joint:
+        assert rel(out["fft_wide"][1], GP) < TOL
