@@ -232,7 +232,8 @@ ptlm_status ptlm_ggn_vp(ptlm_handle* h, const float* d_vO, const float* d_vP, do
  * All give the product to FP32 rounding; MFMA differs from the FFT in the last bits, the wide
  * grouping gives the FFT's bits.  A handle starts with PTLM_TRANSFORM_MFMA for 16 x 16 probes,
  * PTLM_TRANSFORM_FFT_WIDE for 32 x 32 and PTLM_TRANSFORM_FFT otherwise; ptlm_autotune may
- * change it, and batches use the starting choice.  Takes effect from the next call; enqueues
+ * change it.  Batches run each shape's starting choice, but the standard grouping in place of
+ * the wide one (same bits).  Takes effect from the next call; enqueues
  * nothing.  PTLM_EINVAL for an unknown value, a value the probe shape does not have, or the
  * handle of a batch's problem (ptlm_batch_problem). */
 ptlm_status ptlm_set_transform(ptlm_handle* h, int32_t transform);

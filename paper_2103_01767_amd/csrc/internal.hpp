@@ -139,7 +139,8 @@ bool ggnv_mfma_supported(int my, int mx);
 int default_xform(int my, int mx);
 // the wide grouping of the generic FFT tile kernel's GGN-vector product (kernels_tile.hip): for
 // probes of at most 4096 pixels on that kernel, workgroups of twice the tiles over the same
-// segments, ceil(grid / 2) of them; the batched form takes the standard block table
+// segments, ceil(grid / 2) of them (single problems only: batches keep the standard grouping,
+// which gives the same bits)
 bool ggnv_wide_supported(int my, int mx);
 hipError_t launch_ggnv_mfma(const Geometry& g, const TileArgs& a, hipStream_t s);
 // batched form over the tile kernels' block table of a 16 x 16 class (16 segments per block)

@@ -578,15 +578,13 @@ __global__ __launch_bounds__((Cfg<MY, MX, W>::WG)) void tile_kernel(Geometry g, 
 }
 
 // batched: block b belongs to job job_of_block[b]; trailing blocks of a job's run exit
-// (the wide grouping runs the segments of standard blocks 2b and 2b + 1 in block b)
-template <int MY, int MX, int OP, int W = 1>
-__global__ __launch_bounds__((Cfg<MY, MX, W>::WG)) void tile_batch_kernel(const TileJob* __restrict__ jobs,
-                                                                          const int* __restrict__ job_of_block) {
+template <int MY, int MX, int OP>
+__global__ __launch_bounds__((Cfg<MY, MX>::WG)) void tile_batch_kernel(const TileJob* __restrict__ jobs,
+                                                                       const int* __restrict__ job_of_block) {
   const TileJob& J = jobs[job_of_block[blockIdx.x]];
   const int b = (int)blockIdx.x - J.block0;
-  const int nb = (J.g.grid + W - 1) / W;
-  if (b >= nb) return;
-  tile_body<MY, MX, OP, -1, W>(J.g, J.a, b, nb);
+  if (b >= J.g.grid) return;
+  tile_body<MY, MX, OP, -1>(J.g, J.a, b, J.g.grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,21 +699,6 @@ static hipError_t launch_wide(const Geometry& g, const TileArgs& a, hipStream_t 
   return hipGetLastError();
 }
 
-template <int MY, int MX>
-static hipError_t launch_wide_batch(const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
-  using C = Cfg<MY, MX, 2>;
-  const size_t lds = lds_bytes<MY, MX, 2>();
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)tile_batch_kernel<MY, MX, OP_GGNV, 2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((tile_batch_kernel<MY, MX, OP_GGNV, 2>), dim3(nb), dim3(C::WG), lds, s, jobs, jb);
-  return hipGetLastError();
-}
-
 // probe shapes of the generic kernel with at most 256 threads a tile (M <= 4096)
 bool ggnv_wide_supported(int my, int mx) {
   const bool side = (my == 16 || my == 32 || my == 64 || my == 128) && (mx == 16 || mx == 32 || mx == 64 || mx == 128);
@@ -728,13 +711,6 @@ bool ggnv_wide_supported(int my, int mx) {
 
 static hipError_t launch_ggnv_wide(const Geometry& g, const TileArgs& a, hipStream_t s) {
 #define PTLM_W(A, B) if (g.my == A && g.mx == B) return launch_wide<A, B>(g, a, s);
-  PTLM_WIDE_SHAPES(PTLM_W)
-#undef PTLM_W
-  return hipErrorInvalidValue;
-}
-
-static hipError_t launch_ggnv_wide_batch(int my, int mx, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
-#define PTLM_W(A, B) if (my == A && mx == B) return launch_wide_batch<A, B>(jobs, jb, nb, s);
   PTLM_WIDE_SHAPES(PTLM_W)
 #undef PTLM_W
   return hipErrorInvalidValue;
@@ -758,8 +734,10 @@ hipError_t launch_tile(const Geometry& g, int op, const TileArgs& a, hipStream_t
 hipError_t launch_tile_batch(int my, int mx, int op, const TileJob* jobs, const int* jb, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   // a batch runs every problem with the transform its shape starts with
+  // the matrix products where a shape starts with them; the wide grouping, which gives the
+  // standard grouping's bits, is not used in batches (measured slower on the batch's short
+  // segments of small problems)
   if (op == OP_GGNV && default_xform(my, mx) == 1) return launch_ggnv_mfma_batch(jobs, jb, nb, s);
-  if (op == OP_GGNV && default_xform(my, mx) == 2) return launch_ggnv_wide_batch(my, mx, jobs, jb, nb, s);
   if (my == 256 && mx == 256) return launch_tile256_batch(op, jobs, jb, nb, s);
   if (my == 128 && mx == 128) return launch_tile128_batch(op, jobs, jb, nb, s);
   if (my == mx && (my == 48 || my == 96)) return launch_tile3_batch(my, op, jobs, jb, nb, s);
