@@ -63,12 +63,8 @@ ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s,
   a.predicate = pred;
   hipError_t e = launch_tile(h->g, OP_DIAG_EXACT, a, s);
   if (e != hipSuccess) return hip_fail(e, "diag exact");
-  e = launch_obj_reduce(h->g, (float2*)dO, 0.0, nullptr, nullptr, nullptr, pred, s);
-  if (e != hipSuccess) return hip_fail(e, "diag exact O");
-  if (dP) {
-    e = launch_probe_reduce(h->g, (float2*)dP, 0.0, nullptr, nullptr, nullptr, pred, s);
-    if (e != hipSuccess) return hip_fail(e, "diag exact P");
-  }
+  e = launch_reduce_pair(h->g, (float2*)dO, (float2*)dP, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr, pred, s);
+  if (e != hipSuccess) return hip_fail(e, "diag exact reduce");
   return PTLM_OK;
 }
 
@@ -118,8 +114,9 @@ ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, con
   PTLM_HIP(launch_tile(g, OP_LINEARIZE, a, s), "linearize");
   PTLM_HIP(launch_refine(g, a, s), "linearize refine");
   PTLM_HIP(launch_sum_partials(g.partials, g.grid, d_f, 2, s), "linearize sum");
-  PTLM_HIP(launch_obj_reduce(g, gO, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gO");
-  if (g.joint && gP) PTLM_HIP(launch_probe_reduce(g, gP, 0.0, nullptr, nullptr, nullptr, nullptr, s), "linearize gP");
+  PTLM_HIP(launch_reduce_pair(g, gO, g.joint ? gP : nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              s),
+           "linearize gradient");
   return PTLM_OK;
 }
 
@@ -136,8 +133,8 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
     PTLM_HIP(launch_tile(h->g, OP_GGNV, a, s), "ggn_vp");
   }
   if (stage & 2) {
-    PTLM_HIP(launch_obj_reduce(h->g, outO, lam, lam_dev, dO, vO, pred, s), "ggn_vp O");
-    if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, outP, lam, lam_dev, dP, vP, pred, s), "ggn_vp P");
+    PTLM_HIP(launch_reduce_pair(h->g, outO, h->g.joint ? outP : nullptr, lam, lam_dev, dO, dP, vO, vP, pred, s),
+             "ggn_vp reduce");
   }
   return PTLM_OK;
 }
@@ -470,8 +467,9 @@ ptlm_status ptlm_vjp(ptlm_handle* h, const float* d_w, float* d_outO, float* d_o
   a.P = h->g.P_lin;
   a.win = d_w;
   PTLM_HIP(launch_tile(h->g, OP_VJP, a, s), "vjp");
-  PTLM_HIP(launch_obj_reduce(h->g, (float2*)d_outO, 0.0, nullptr, nullptr, nullptr, nullptr, s), "vjp O");
-  if (h->g.joint) PTLM_HIP(launch_probe_reduce(h->g, (float2*)d_outP, 0.0, nullptr, nullptr, nullptr, nullptr, s), "vjp P");
+  PTLM_HIP(launch_reduce_pair(h->g, (float2*)d_outO, h->g.joint ? (float2*)d_outP : nullptr, 0.0, nullptr, nullptr,
+                              nullptr, nullptr, nullptr, nullptr, s),
+           "vjp reduce");
   return PTLM_OK;
 }
 

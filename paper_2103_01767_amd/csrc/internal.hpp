@@ -167,6 +167,11 @@ __host__ __device__ inline int prb_chunk_count(int M, int nseg) {
 }
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* predicate, hipStream_t s);
+// both of the above in one launch (after the probe's first pass when it takes two); outP null:
+// the object sum alone
+hipError_t launch_reduce_pair(const Geometry& g, float2* outO, float2* outP, double lam, const double* lam_dev,
+                              const float* dO, const float* dP, const float2* vO, const float2* vP,
+                              const int* predicate, hipStream_t s);
 // out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)
 hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s,
                                const int* pred = nullptr);

@@ -144,6 +144,22 @@ __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out
   out[m] = acc;
 }
 
+// The object and probe sums of one product or gradient in one launch: blocks 0 .. nprb - 1 run
+// the probe sum (started first: each adds every segment's partial), the rest the object
+// tiles, with the bodies of the two separate kernels (same results).
+__global__ __launch_bounds__(256) void pair_reduce_kernel(Geometry g, float2* outO, float2* outP, float lam_h,
+                                                          const double* lam_dev, const float* dO, const float* dP,
+                                                          const float2* vO, const float2* vP, const int* pred,
+                                                          int nprb) {
+  const int b = blockIdx.x;
+  if (b < nprb) {
+    probe_reduce_body(g, outP, lam_h, lam_dev, dP, vP, pred, b);
+  } else {
+    const int l = b - nprb;
+    obj_reduce_body(g, outO, lam_h, lam_dev, dO, vO, pred, l % g.otiles_x, l / g.otiles_x);
+  }
+}
+
 __global__ __launch_bounds__(256) void probe_chunk_kernel(Geometry g, const int* pred) {
   probe_chunk_body(g, pred, blockIdx.x, blockIdx.y);
 }
@@ -383,6 +399,22 @@ hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, cons
   }
   hipLaunchKernelGGL(probe_reduce_kernel, dim3((M + 63) / 64), dim3(256), 0, s, g, outP, (float)lam, lam_dev, dP,
                      vP, pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_pair(const Geometry& g, float2* outO, float2* outP, double lam, const double* lam_dev,
+                              const float* dO, const float* dP, const float2* vO, const float2* vP, const int* pred,
+                              hipStream_t s) {
+  const int M = g.my * g.mx;
+  const int nprb = outP ? (M + 63) / 64 : 0;
+  if (outP && prb_chunk_count(M, g.nseg) > 0) {
+    hipLaunchKernelGGL(probe_chunk_kernel, dim3((M + 63) / 64, prb_chunk_count(M, g.nseg)), dim3(256), 0, s, g,
+                       pred);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3(nprb + g.otiles_x * g.otiles_y), dim3(256), 0, s, g, outO, outP,
+                     (float)lam, lam_dev, dO, dP, vO, vP, pred, nprb);
   return hipGetLastError();
 }
 

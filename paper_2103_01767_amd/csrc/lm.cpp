@@ -113,9 +113,9 @@ struct SingleOps {
     LM_HIP(launch_tile(g, OP_LINEARIZE, ta, s), "lm linearize");
     LM_HIP(launch_refine(g, ta, s), "lm linearize refine");
     LM_HIP(launch_sum_partials(g.partials, g.grid, a.scal + SC_F, 2, s, flag(FL_TILE)), "lm linearize sum");
-    LM_HIP(launch_obj_reduce(g, a.g, 0.0, nullptr, nullptr, nullptr, flag(FL_TILE), s), "lm gradient O");
-    if (g.joint)
-      LM_HIP(launch_probe_reduce(g, a.g + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_TILE), s), "lm gradient P");
+    LM_HIP(launch_reduce_pair(g, a.g, g.joint ? a.g + a.nobj : nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              flag(FL_TILE), s),
+           "lm gradient");
     return PTLM_OK;
   }
   // geometry whose linearisation buffers are the spares (the trial's linearisation)
@@ -190,10 +190,9 @@ struct SingleOps {
     if (!spec) return PTLM_OK;
     const Geometry gs = spare_geometry();
     LM_HIP(launch_sum_partials(gs.partials, gs.grid, a.scal + SC_F, 2, s, flag(FL_ACCEPTED)), "lm trial sums");
-    LM_HIP(launch_obj_reduce(gs, h->lm_g_alt, 0.0, nullptr, nullptr, nullptr, flag(FL_ACCEPTED), s), "lm trial grad O");
-    if (gs.joint)
-      LM_HIP(launch_probe_reduce(gs, h->lm_g_alt + a.nobj, 0.0, nullptr, nullptr, nullptr, flag(FL_ACCEPTED), s),
-             "lm trial grad P");
+    LM_HIP(launch_reduce_pair(gs, h->lm_g_alt, gs.joint ? h->lm_g_alt + a.nobj : nullptr, 0.0, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, flag(FL_ACCEPTED), s),
+           "lm trial gradient");
     return PTLM_OK;
   }
   // PCG look-ahead: iteration i is enqueued once the decision on iteration i - 1 is known
