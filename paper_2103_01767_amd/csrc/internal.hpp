@@ -98,6 +98,15 @@ struct RedJob {
   int block1;  // first block of the job in a second launch (probe reduction pass one)
 };
 
+// one copy of a multi-copy launch (launch_copies): dst[i] = src[i], i < n, unless *pred == 0
+struct CopyItem {
+  const float2* src;
+  float2* dst;
+  size_t n;
+  const int* pred;
+};
+constexpr int MAX_COPIES = 4;
+
 struct CopyJob {
   const float2* src;
   float2* dst;
@@ -179,6 +188,8 @@ hipError_t launch_sum_partials(const double* partials, int count, double* out, i
 hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
 // dst[i] = src[i], i < n, unless *pred == 0 (copy_blocks(n) blocks)
 hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s);
+// up to MAX_COPIES independent copies in one launch (copy_blocks(n) blocks each)
+hipError_t launch_copies(const CopyItem* items, int count, hipStream_t s);
 hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, int first, const int* pred,
                            hipStream_t s);
 int copy_blocks(size_t n);

@@ -322,11 +322,43 @@ __global__ __launch_bounds__(1024) void diag_paper_probe_kernel(Geometry g, floa
   diag_paper_probe_body(g, dP, blockIdx.x);
 }
 
+// both parts of the App. B diagonal in one launch: blocks 0 .. nprb - 1 the probe part (started
+// first: each block walks every position), the rest the object tiles
+__global__ __launch_bounds__(1024) void diag_paper_pair_kernel(Geometry g, float* dO, float* dP, const int* pred,
+                                                               int nprb) {
+  if (pred && *pred == 0) return;
+  const int b = blockIdx.x;
+  if (b < nprb) {
+    diag_paper_probe_body(g, dP, b);
+  } else {
+    const int l = b - nprb;
+    diag_paper_obj_body(g, dO, l % g.otiles_x, l / g.otiles_x);
+  }
+}
+
 __global__ __launch_bounds__(256) void copy_kernel(const float2* __restrict__ src, float2* __restrict__ dst, size_t n,
                                                    const int* pred) {
   if (pred && *pred == 0) return;
   const size_t stride = (size_t)gridDim.x * 256;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// up to MAX_COPIES independent copies in one launch; copy c owns blocks first[c] .. first[c+1]-1
+struct CopySet {
+  CopyItem item[MAX_COPIES];
+  int first[MAX_COPIES + 1];
+  int count;
+};
+
+__global__ __launch_bounds__(256) void copies_kernel(CopySet cs) {
+  int c = 0;
+  while (c + 1 < cs.count && (int)blockIdx.x >= cs.first[c + 1]) ++c;
+  const CopyItem it = cs.item[c];
+  if (it.pred && *it.pred == 0) return;
+  const int nb = cs.first[c + 1] - cs.first[c];
+  const size_t stride = (size_t)nb * 256;
+  for (size_t i = (size_t)((int)blockIdx.x - cs.first[c]) * 256 + threadIdx.x; i < it.n; i += stride)
+    it.dst[i] = it.src[i];
 }
 
 __global__ __launch_bounds__(1024) void diag_paper_probe_batch_kernel(const RedJob* __restrict__ jobs,
@@ -425,12 +457,11 @@ hipError_t launch_sum_partials(const double* partials, int count, double* out, i
 }
 
 hipError_t launch_diag_paper(const Geometry& g, float* dO, float* dP, hipStream_t s, const int* pred) {
-  hipLaunchKernelGGL(diag_paper_obj_kernel, dim3(g.otiles_x, g.otiles_y), dim3(DIAG_OBJ_THREADS), 0, s, g, dO, pred);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !dP) return e;
+  static_assert(DIAG_PRB_THREADS == DIAG_OBJ_THREADS, "one launch runs both diagonal parts");
   const int M = g.my * g.mx;
-  hipLaunchKernelGGL(diag_paper_probe_kernel, dim3((M + DIAG_PRB_PIX - 1) / DIAG_PRB_PIX), dim3(DIAG_PRB_THREADS), 0,
-                     s, g, dP, pred);
+  const int nprb = dP ? (M + DIAG_PRB_PIX - 1) / DIAG_PRB_PIX : 0;
+  hipLaunchKernelGGL(diag_paper_pair_kernel, dim3(nprb + g.otiles_x * g.otiles_y), dim3(DIAG_OBJ_THREADS), 0, s, g,
+                     dO, dP, pred, nprb);
   return hipGetLastError();
 }
 
@@ -465,6 +496,20 @@ hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, in
 
 hipError_t launch_copy(const float2* src, float2* dst, size_t n, const int* pred, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(copy_blocks(n)), dim3(256), 0, s, src, dst, n, pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_copies(const CopyItem* items, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > MAX_COPIES) return hipErrorInvalidValue;
+  CopySet cs{};
+  cs.count = count;
+  cs.first[0] = 0;
+  for (int c = 0; c < count; ++c) {
+    cs.item[c] = items[c];
+    cs.first[c + 1] = cs.first[c] + copy_blocks(items[c].n);
+  }
+  hipLaunchKernelGGL(copies_kernel, dim3(cs.first[count]), dim3(256), 0, s, cs);
   return hipGetLastError();
 }
 

@@ -98,8 +98,9 @@ struct SingleOps {
       LM_HIP(launch_vec(V_SAME, a, FL_LIN, s), "lm same point");
       LM_HIP(launch_fin(F_ADOPT, a, a.vec_blocks, FL_LIN, s), "lm adopt");
     }
-    LM_HIP(launch_copy(O, g.O_lin, (size_t)g.ny * g.nx, flag(FL_LIN), s), "lm copy O");
-    LM_HIP(launch_copy(P, g.P_lin, (size_t)g.my * g.mx, flag(FL_LIN), s), "lm copy P");
+    const CopyItem c[2] = {{O, g.O_lin, (size_t)g.ny * g.nx, flag(FL_LIN)},
+                           {P, g.P_lin, (size_t)g.my * g.mx, flag(FL_LIN)}};
+    LM_HIP(launch_copies(c, 2, s), "lm copy O, P");
     return PTLM_OK;
   }
   ptlm_status linearize() {
@@ -224,12 +225,11 @@ struct SingleOps {
   ptlm_status copy_plugin() {
     Geometry& g = h->g;
     const size_t M = (size_t)g.my * g.mx;
-    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_LS_TAKE), s), "lm plug-in O");
-    LM_HIP(launch_copy(g.O_lin, O, a.nobj, flag(FL_LS_KEEP), s), "lm plug-in keep O");
-    if (g.joint) {
-      LM_HIP(launch_copy(a.ztrial + a.nobj, P, M, flag(FL_LS_TAKE), s), "lm plug-in P");
-      LM_HIP(launch_copy(g.P_lin, P, M, flag(FL_LS_KEEP), s), "lm plug-in keep P");
-    }
+    const CopyItem c[4] = {{a.ztrial, O, a.nobj, flag(FL_LS_TAKE)},
+                           {g.O_lin, O, a.nobj, flag(FL_LS_KEEP)},
+                           {a.ztrial + a.nobj, P, M, flag(FL_LS_TAKE)},
+                           {g.P_lin, P, M, flag(FL_LS_KEEP)}};
+    LM_HIP(launch_copies(c, g.joint ? 4 : 2, s), "lm plug-in copies");
     return PTLM_OK;
   }
   // line-search look-ahead: step size i is enqueued once the test of size i - 2 is known (the
@@ -251,12 +251,11 @@ struct SingleOps {
     // the accepted step's blocks (both, or the active one of the alternating update)
     Geometry& g = h->g;
     const size_t M = (size_t)g.my * g.mx;
-    LM_HIP(launch_copy(a.ztrial, O, a.nobj, flag(FL_ACC_O), s), "lm accept O");
-    LM_HIP(launch_copy(a.dx, a.prev, a.nobj, flag(FL_ACC_O), s), "lm keep step O");
-    if (g.joint) {
-      LM_HIP(launch_copy(a.ztrial + a.nobj, P, M, flag(FL_ACC_P), s), "lm accept P");
-      LM_HIP(launch_copy(a.dx + a.nobj, a.prev + a.nobj, M, flag(FL_ACC_P), s), "lm keep step P");
-    }
+    const CopyItem c[4] = {{a.ztrial, O, a.nobj, flag(FL_ACC_O)},
+                           {a.dx, a.prev, a.nobj, flag(FL_ACC_O)},
+                           {a.ztrial + a.nobj, P, M, flag(FL_ACC_P)},
+                           {a.dx + a.nobj, a.prev + a.nobj, M, flag(FL_ACC_P)}};
+    LM_HIP(launch_copies(c, g.joint ? 4 : 2, s), "lm accept copies");
     return PTLM_OK;
   }
 };
