@@ -131,11 +131,10 @@ struct BatchOps {
     return PTLM_OK;
   }
   ptlm_status reduce(int kind) {
-    B_HIP(launch_obj_reduce_batch(b->dev<RedJob>(b->L.red_obj[kind]), b->dev<int>(b->L.jb_obj), b->nb_obj, s),
-          "batch object reduce");
-    B_HIP(launch_probe_reduce_batch(b->dev<RedJob>(b->L.red_prb[kind]), b->dev<int>(b->L.jb_prb1), b->nb_prb1,
-                                    b->dev<int>(b->L.jb_prb), b->nb_prb, s),
-          "batch probe reduce");
+    B_HIP(launch_reduce_pair_batch(b->dev<RedJob>(b->L.red_obj[kind]), b->dev<int>(b->L.jb_obj), b->nb_obj,
+                                   b->dev<RedJob>(b->L.red_prb[kind]), b->dev<int>(b->L.jb_prb1), b->nb_prb1,
+                                   b->dev<int>(b->L.jb_prb), b->nb_prb, s),
+          "batch reduce");
     return PTLM_OK;
   }
   ptlm_status copy_lin() {

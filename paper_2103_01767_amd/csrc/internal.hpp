@@ -194,11 +194,10 @@ hipError_t launch_sq_accum(const float2* u, float2* d, size_t n, float scale, in
                            hipStream_t s);
 int copy_blocks(size_t n);
 // batched forms (job tables in device memory)
-hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* job_of_block, int nblocks, hipStream_t s);
-// pass one over jb1 (nb1 blocks: jobs with more than PRB_CHUNK segments, block1 their first),
-// then the final pass over jb (nb blocks)
-hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb1, int nb1, const int* jb, int nb,
-                                     hipStream_t s);
+// the object and probe sums of a batch in one launch (the probe part after a first pass over
+// jb1, nb1 blocks: jobs with more than PRB_CHUNK segments, block1 their first, when nb1 > 0)
+hipError_t launch_reduce_pair_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
+                                    const int* jb1, int nb1, const int* prbjb, int nbp, hipStream_t s);
 hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hipStream_t s);
 hipError_t launch_diag_paper_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
                                    const int* prbjb, int nbp, hipStream_t s);

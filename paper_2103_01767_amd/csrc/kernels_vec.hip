@@ -73,13 +73,6 @@ __global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out
   obj_reduce_body(g, out, lam_h, lam_dev, d, v, pred, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void obj_reduce_batch_kernel(const RedJob* __restrict__ jobs,
-                                                               const int* __restrict__ job_of_block) {
-  const RedJob& J = jobs[job_of_block[blockIdx.x]];
-  const int l = (int)blockIdx.x - J.block0;
-  obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
-}
-
 // Probe-sized sums of the per-segment probe partials, 64 pixels per block.  One pass,
 // out_P[m] = sum_s probe_part[s][m] [+ lam * D .* v], unless the probe gives few blocks and there
 // are many segments (prb_chunk_count); then two passes in place: pass one (one block per 64
@@ -177,10 +170,21 @@ __global__ __launch_bounds__(256) void probe_chunk_batch_kernel(const RedJob* __
   probe_chunk_body(J.g, J.pred, l % pb, l / pb);
 }
 
-__global__ __launch_bounds__(256) void probe_reduce_batch_kernel(const RedJob* __restrict__ jobs,
-                                                                 const int* __restrict__ job_of_block) {
-  const RedJob& J = jobs[job_of_block[blockIdx.x]];
-  probe_reduce_body(J.g, J.outP, 0.f, J.lam_dev, J.dP, J.vP, J.pred, (int)blockIdx.x - J.block0);
+// batched form of pair_reduce_kernel: blocks 0 .. nbp - 1 over the probe job table, the rest
+// over the object job table
+__global__ __launch_bounds__(256) void pair_reduce_batch_kernel(const RedJob* __restrict__ objjobs,
+                                                                const int* __restrict__ objjb,
+                                                                const RedJob* __restrict__ prbjobs,
+                                                                const int* __restrict__ prbjb, int nbp) {
+  const int b = blockIdx.x;
+  if (b < nbp) {
+    const RedJob& J = prbjobs[prbjb[b]];
+    probe_reduce_body(J.g, J.outP, 0.f, J.lam_dev, J.dP, J.vP, J.pred, b - J.block0);
+  } else {
+    const RedJob& J = objjobs[objjb[b - nbp]];
+    const int l = b - nbp - J.block0;
+    obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
+  }
 }
 
 // out[j] = sum_i partials[i*4 + j], j < nout, fixed-order tree
@@ -378,20 +382,15 @@ __global__ __launch_bounds__(256) void copy_batch_kernel(const CopyJob* __restri
     J.dst[i] = J.src[i];
 }
 
-hipError_t launch_obj_reduce_batch(const RedJob* jobs, const int* jb, int nb, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(obj_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
-  return hipGetLastError();
-}
-hipError_t launch_probe_reduce_batch(const RedJob* jobs, const int* jb1, int nb1, const int* jb, int nb,
-                                     hipStream_t s) {
+hipError_t launch_reduce_pair_batch(const RedJob* objjobs, const int* objjb, int nbo, const RedJob* prbjobs,
+                                    const int* jb1, int nb1, const int* prbjb, int nbp, hipStream_t s) {
   if (nb1 > 0) {
-    hipLaunchKernelGGL(probe_chunk_batch_kernel, dim3(nb1), dim3(256), 0, s, jobs, jb1);
+    hipLaunchKernelGGL(probe_chunk_batch_kernel, dim3(nb1), dim3(256), 0, s, prbjobs, jb1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_reduce_batch_kernel, dim3(nb), dim3(256), 0, s, jobs, jb);
+  if (nbo + nbp <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_reduce_batch_kernel, dim3(nbo + nbp), dim3(256), 0, s, objjobs, objjb, prbjobs, prbjb, nbp);
   return hipGetLastError();
 }
 hipError_t launch_sum_partials_batch(const RedJob* jobs, int njobs, int nout, hipStream_t s) {
