@@ -18,10 +18,14 @@ __device__ __forceinline__ double rdot(float2 a, float2 b) {
   return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
 }
 
-// z = M^{-1} r for the PCG preconditioner of this attempt (per real coordinate)
-__device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r, double lam) {
+// z = M^{-1} r for the PCG preconditioner of this attempt (per real coordinate), from the entry's
+// App. B diagonal d (read when the preconditioner or the damping uses it) and its learned,
+// exact or estimated diagonal l (preconditioner codes 2 and up)
+__device__ __forceinline__ bool minv_reads_diag(const LMArgs& a) {
+  return a.prm.precond == 1 || (a.prm.precond >= 2 && a.prm.scaling);
+}
+__device__ __forceinline__ float2 minv_of(const LMArgs& a, float2 r, double lam, float2 d, float2 l) {
   if (a.prm.precond == 1) {
-    const float2 d = a.diag[i];
     if (a.prm.scaling) {
       const float s = (float)(1.0 + lam);
       return make_float2(r.x / (s * d.x), r.y / (s * d.y));
@@ -29,11 +33,15 @@ __device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r
     return make_float2(r.x / (d.x + (float)lam), r.y / (d.y + (float)lam));
   }
   if (a.prm.precond >= 2) {  // learned, exact or estimated Dg(G), plus lambda D
-    const float2 d = a.learned[i];
-    const float2 D = a.prm.scaling ? a.diag[i] : make_float2(1.f, 1.f);
-    return make_float2(r.x / fmaf((float)lam, D.x, d.x), r.y / fmaf((float)lam, D.y, d.y));
+    const float2 D = a.prm.scaling ? d : make_float2(1.f, 1.f);
+    return make_float2(r.x / fmaf((float)lam, D.x, l.x), r.y / fmaf((float)lam, D.y, l.y));
   }
   return r;
+}
+__device__ __forceinline__ float2 apply_minv(const LMArgs& a, size_t i, float2 r, double lam) {
+  const float2 d = minv_reads_diag(a) ? a.diag[i] : make_float2(1.f, 1.f);
+  const float2 l = a.prm.precond >= 2 ? a.learned[i] : make_float2(0.f, 0.f);
+  return minv_of(a, r, lam, d, l);
 }
 
 // eq:projection for the sets of eq:constraints: clamp the magnitude of an object entry to
@@ -138,7 +146,56 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
   const Range act = active_range(a);
   const size_t lo = BLOCK ? act.lo : 0, hi = BLOCK ? act.hi : a.n;
   const size_t stride = (size_t)nblk * blockDim.x;
-  for (size_t i = lo + (size_t)bid * blockDim.x + threadIdx.x; i < hi; i += stride) {
+  constexpr bool PCG = OP == V_PAP || OP == V_CG_STEP || OP == V_P_STEP;
+  if constexpr (PCG) {
+    // the PCG recurrence: a thread's entries i, i + stride, ... in groups of four, every load of a
+    // group issued before its arithmetic (the same entries and the same order of the sums)
+    constexpr int U = 4;
+    const bool rd = minv_reads_diag(a), rl = a.prm.precond >= 2;
+    for (size_t i0 = lo + (size_t)bid * blockDim.x + threadIdx.x; i0 < hi; i0 += U * stride) {
+      float2 p[U], q[U], x[U], r[U], d[U], l[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t i = i0 + u * stride;
+        if (i >= hi) continue;
+        p[u] = a.p[i];
+        if constexpr (OP == V_P_STEP) {
+          q[u] = a.z[i];
+        } else {
+          q[u] = a.Ap[i];
+        }
+        if constexpr (OP == V_CG_STEP) {
+          x[u] = a.dx[i];
+          r[u] = a.r[i];
+          d[u] = rd ? a.diag[i] : make_float2(1.f, 1.f);
+          l[u] = rl ? a.learned[i] : make_float2(0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t i = i0 + u * stride;
+        if (i >= hi) continue;
+        if constexpr (OP == V_PAP) {
+          acc0 += rdot(p[u], q[u]);
+        } else if constexpr (OP == V_CG_STEP) {
+          float2 xx = x[u], rr = r[u];
+          xx.x = fmaf(alpha, p[u].x, xx.x);
+          xx.y = fmaf(alpha, p[u].y, xx.y);
+          rr.x = fmaf(-alpha, q[u].x, rr.x);
+          rr.y = fmaf(-alpha, q[u].y, rr.y);
+          const float2 z = minv_of(a, rr, lam, d[u], l[u]);
+          a.dx[i] = xx;
+          a.r[i] = rr;
+          a.z[i] = z;
+          acc0 += rdot(rr, z);
+          acc1 += rdot(rr, rr);
+        } else {
+          a.p[i] = make_float2(fmaf(beta, p[u].x, q[u].x), fmaf(beta, p[u].y, q[u].y));
+        }
+      }
+    }
+  }
+  for (size_t i = lo + (size_t)bid * blockDim.x + threadIdx.x; !PCG && i < hi; i += stride) {
     if constexpr (OP == V_GNORM) {  // ||g_O||^2, ||g_P||^2
       const float2 g = a.g[i];
       if (i < a.nobj) acc0 += rdot(g, g);
@@ -229,24 +286,6 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       a.p[i] = z;
       acc0 += rdot(r, z);
       acc1 += rdot(r, r);
-    } else if constexpr (OP == V_PAP) {
-      acc0 += rdot(a.p[i], a.Ap[i]);
-    } else if constexpr (OP == V_CG_STEP) {
-      const float2 p = a.p[i], ap = a.Ap[i];
-      float2 x = a.dx[i], r = a.r[i];
-      x.x = fmaf(alpha, p.x, x.x);
-      x.y = fmaf(alpha, p.y, x.y);
-      r.x = fmaf(-alpha, ap.x, r.x);
-      r.y = fmaf(-alpha, ap.y, r.y);
-      const float2 z = apply_minv(a, i, r, lam);
-      a.dx[i] = x;
-      a.r[i] = r;
-      a.z[i] = z;
-      acc0 += rdot(r, z);
-      acc1 += rdot(r, r);
-    } else if constexpr (OP == V_P_STEP) {
-      const float2 z = a.z[i], p = a.p[i];
-      a.p[i] = make_float2(fmaf(beta, p.x, z.x), fmaf(beta, p.y, z.y));
     } else if constexpr (OP == V_TRIAL) {
       const float2 x = a.dx[i];
       const float2 base = i < a.nobj ? a.O[i] : a.P[i - a.nobj];
