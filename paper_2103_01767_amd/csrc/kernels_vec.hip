@@ -263,11 +263,6 @@ __device__ __forceinline__ void diag_paper_obj_body(const Geometry& g, float* dO
   dO[2 * n + 1] = val;
 }
 
-__global__ __launch_bounds__(1024) void diag_paper_obj_kernel(Geometry g, float* dO, const int* pred) {
-  if (pred && *pred == 0) return;
-  diag_paper_obj_body(g, dO, blockIdx.x, blockIdx.y);
-}
-
 __global__ __launch_bounds__(1024) void diag_paper_obj_batch_kernel(const RedJob* __restrict__ jobs,
                                                                    const int* __restrict__ job_of_block) {
   const RedJob& J = jobs[job_of_block[blockIdx.x]];
@@ -319,11 +314,6 @@ __device__ __forceinline__ void diag_paper_probe_body(const Geometry& g, float* 
   const float val = (float)(sum / (2.0 * M));
   dP[2 * m] = val;
   dP[2 * m + 1] = val;
-}
-
-__global__ __launch_bounds__(1024) void diag_paper_probe_kernel(Geometry g, float* dP, const int* pred) {
-  if (pred && *pred == 0) return;
-  diag_paper_probe_body(g, dP, blockIdx.x);
 }
 
 // both parts of the App. B diagonal in one launch: blocks 0 .. nprb - 1 the probe part (started
