@@ -27,6 +27,31 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert set(names) == set(pt.EXPORTS)
 
 
+def header_enum_values():
+    """name -> value of every enumerator the header defines"""
+    text = open(HEADER).read()
+    out = {}
+    for body in re.findall(r"typedef enum\s*\{([^}]*)\}", text):
+        for name, val in re.findall(r"(PTLM_\w+)\s*=\s*(-?\d+)", body):
+            out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_the_header():
+    """The binding's status codes, metric / mode / GGN codes and transform names carry the
+    header's values."""
+    e = header_enum_values()
+    for name in ("PTLM_OK", "PTLM_ENOTACCEPTED", "PTLM_EINVAL", "PTLM_EWORKSPACE", "PTLM_EHIP", "PTLM_ENUMERIC"):
+        assert getattr(pt, name) == e[name], name
+    assert (pt.GAUSS, pt.POISSON) == (e["PTLM_GAUSS"], e["PTLM_POISSON"])
+    assert (pt.OBJECT, pt.JOINT) == (e["PTLM_OBJECT"], e["PTLM_JOINT"])
+    assert (pt.GGN_MAGNITUDE, pt.GGN_INTENSITY) == (e["PTLM_GGN_MAGNITUDE"], e["PTLM_GGN_INTENSITY"])
+    transforms = {k: v for k, v in e.items() if k.startswith("PTLM_TRANSFORM_")}
+    assert len(pt.TRANSFORMS) == len(transforms)
+    for name, value in transforms.items():
+        assert pt.TRANSFORMS[value] == name[len("PTLM_TRANSFORM_"):].lower(), name
+
+
 def _ws(desc, pos):
     n = ctypes.c_size_t(0)
     st = pt.lib().ptlm_workspace_bytes(ctypes.byref(desc), pos.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n))
