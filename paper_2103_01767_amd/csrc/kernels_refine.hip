@@ -32,6 +32,23 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// v / n and v mod n for 0 <= v < 2^24, 1 <= n <= 256, inv_n = 1.0f / n: the float quotient is
+// within one of the true one (v and n exact, inv_n and the product each within half an ulp), so
+// one correction step each way gives the exact result without an integer division
+__device__ __forceinline__ int fdiv_small(int v, int n, float inv_n) {
+  int q = (int)((float)v * inv_n);
+  const int r = v - q * n;
+  if (r < 0) --q;
+  else if (r >= n) ++q;
+  return q;
+}
+__device__ __forceinline__ int fmod_small(int v, int n, float inv_n) {
+  int r = v - (int)((float)v * inv_n) * n;
+  if (r < 0) r += n;
+  else if (r >= n) r -= n;
+  return r;
+}
+
 __global__ __launch_bounds__(NT) void refine_kernel(Geometry g, TileArgs a) {
   if (a.predicate && *a.predicate == 0) return;
   const int k = blockIdx.x;
@@ -39,34 +56,45 @@ __global__ __launch_bounds__(NT) void refine_kernel(Geometry g, TileArgs a) {
   const size_t base = (size_t)k * M;
   __shared__ double2 twy[256], twx[256];  // exp(-2 pi i j / my), exp(-2 pi i j / mx)
   __shared__ int list[CAP];
-  __shared__ int wave_cnt[NT / 64];
+  __shared__ unsigned long long ballots[256][NT / 64];  // per round of NT pixels (M <= 65536)
+  __shared__ int round_base[256];
   __shared__ int count;
   __shared__ double2 part[NT / 64][NB];
   __shared__ double dtrace;
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float wmin = (float)sqrt(W_REFINE);
-  // ---- list the flagged pixels in pixel order
-  if (t == 0) count = 0;
-  __syncthreads();
-  for (int m0 = 0; m0 < M; m0 += NT) {
-    const int m = m0 + t;
+  // ---- list the flagged pixels in pixel order.  Pixel m = t + NT j is read by thread t in round
+  // j (coalesced) and each wavefront keeps its ballot of the round in LDS, so one barrier
+  // separates the reads from the listing.  Pixel order is round-major: a flagged pixel's rank
+  // is the flag count of every earlier round, plus the earlier wavefronts' count of its round,
+  // plus the lower lanes' count in its own wavefront.
+  const int rounds = (M + NT - 1) / NT;
+  for (int j = 0; j < rounds; ++j) {
+    const int m = t + NT * j;
     const bool fl = m < M && g.w2[base + m] > wmin;
     const unsigned long long bal = __ballot(fl);
-    if (lane == 0) wave_cnt[wv] = __popcll(bal);
-    __syncthreads();
-    int off = count;
-    for (int w = 0; w < wv; ++w) off += wave_cnt[w];
-    const int rank = off + __popcll(bal & ((1ull << lane) - 1ull));
-    if (fl && rank < CAP) list[rank] = m;
-    __syncthreads();
-    if (t == 0) {
-      int c = count;
-      for (int w = 0; w < NT / 64; ++w) c += wave_cnt[w];
-      count = c < CAP ? c : CAP;
-    }
-    __syncthreads();
+    if (lane == 0) ballots[j][wv] = bal;
   }
+  __syncthreads();
+  if (t == 0) {
+    int c = 0;
+    for (int j = 0; j < rounds; ++j) {
+      round_base[j] = c;
+      for (int w = 0; w < NT / 64; ++w) c += __popcll(ballots[j][w]);
+    }
+    count = c < CAP ? c : CAP;
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int j = 0; j < rounds; ++j) {
+    const unsigned long long bal = ballots[j][wv];
+    if (!((bal >> lane) & 1ull)) continue;
+    int rank = round_base[j] + __popcll(bal & below);
+    for (int w = 0; w < wv; ++w) rank += __popcll(ballots[j][w]);
+    if (rank < CAP) list[rank] = t + NT * j;
+  }
+  __syncthreads();
   const int n = count;
   if (n == 0) return;
 
@@ -87,6 +115,9 @@ __global__ __launch_bounds__(NT) void refine_kernel(Geometry g, TileArgs a) {
   const double bg = a.bg_add ? (double)g.background + *a.bg_add : (double)g.background;
   const bool poisson = g.metric != 0, intensity = g.ggn != 0;
   const double isq = 1.0 / sqrt((double)M);
+  const float inv_my = 1.0f / (float)my, inv_mx = 1.0f / (float)mx;
+  const bool xfix = NT % mx == 0;
+  const int xcol = t % mx, ystep = NT / mx;
   for (int b0 = 0; b0 < n; b0 += NB) {
     const int nb = n - b0 < NB ? n - b0 : NB;
     int ky[NB], kx[NB];
@@ -99,18 +130,49 @@ __global__ __launch_bounds__(NT) void refine_kernel(Geometry g, TileArgs a) {
     double2 acc[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) acc[i] = make_double2(0.0, 0.0);
-    // direct DFT at the nb frequencies: sum over the window pixels (y, x) of psi exp(...)
-    for (int q = t; q < M; q += NT) {
-      const int y = q / mx, x = q % mx;
-      const float2 P = a.P[q];
-      const float2 O = a.O[(size_t)(pk.x + y) * g.nx + pk.y + x];
-      const double2 psi = zmul(make_double2(P.x, P.y), make_double2(O.x, O.y));
+    // direct DFT at the nb frequencies: sum over the window pixels (y, x) of psi exp(...), each
+    // thread over its pixels q = t, t + NT, ... in that order.  When NT is a multiple of the
+    // window width a thread keeps one column x, so its x twiddles are read once per pass and
+    // its row advances by NT / mx; otherwise the pixel's row, column and twiddle indices come
+    // from the float-reciprocal quotient (all operands below 2^24, exact after the correction)
+    if (xfix) {
+      // the thread's column is fixed: sum psi exp(-2 pi i ky y / my) over its rows, then apply
+      // the column's twiddle once; the row twiddle's index advances by ky * ystep mod my
+      int y = t / mx;
+      int iy[NB], dy[NB];
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const double2 w = zmul(twy[(ky[i] * y) % my], twx[(kx[i] * x) % mx]);
-        const double2 v = zmul(psi, w);
-        acc[i].x += v.x;
-        acc[i].y += v.y;
+        iy[i] = fmod_small(ky[i] * y, my, inv_my);
+        dy[i] = fmod_small(ky[i] * ystep, my, inv_my);
+      }
+      for (int q = t; q < M; q += NT, y += ystep) {
+        const float2 P = a.P[q];
+        const float2 O = a.O[(size_t)(pk.x + y) * g.nx + pk.y + xcol];
+        const double2 psi = zmul(make_double2(P.x, P.y), make_double2(O.x, O.y));
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const double2 v = zmul(psi, twy[iy[i]]);
+          acc[i].x += v.x;
+          acc[i].y += v.y;
+          iy[i] += dy[i];
+          if (iy[i] >= my) iy[i] -= my;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) acc[i] = zmul(acc[i], twx[fmod_small(kx[i] * xcol, mx, inv_mx)]);
+    } else {
+      for (int q = t; q < M; q += NT) {
+        const int y = fdiv_small(q, mx, inv_mx), x = q - y * mx;
+        const float2 P = a.P[q];
+        const float2 O = a.O[(size_t)(pk.x + y) * g.nx + pk.y + x];
+        const double2 psi = zmul(make_double2(P.x, P.y), make_double2(O.x, O.y));
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const double2 w = zmul(twy[fmod_small(ky[i] * y, my, inv_my)], twx[fmod_small(kx[i] * x, mx, inv_mx)]);
+          const double2 v = zmul(psi, w);
+          acc[i].x += v.x;
+          acc[i].y += v.y;
+        }
       }
     }
 #pragma unroll
