@@ -471,15 +471,17 @@ def test_transform_choice_rejected_for_other_shapes():
 
 
 @pytest.mark.parametrize("joint", [False, True], ids=["object", "joint"])
-@pytest.mark.parametrize("probe", [(16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (128, 32)],
-                         ids=lambda p: "%dx%d" % p)
-def test_ggn_vp_wide_grouping_equals_fft(probe, joint):
+@pytest.mark.parametrize("probe,ny,nx", [((16, 16), 9, 9), ((16, 32), 9, 9), ((32, 32), 9, 9), ((32, 64), 9, 9),
+                                         ((64, 64), 9, 9), ((128, 32), 9, 9), ((32, 32), 1, 1), ((64, 64), 1, 2)],
+                         ids=lambda p: "%dx%d" % p if isinstance(p, tuple) else str(p))
+def test_ggn_vp_wide_grouping_equals_fft(probe, ny, nx, joint):
     """The wide grouping (twice the tiles per workgroup over the same segments) runs the FFT tile
     kernel's arithmetic unchanged: its GGN-vector product equals the standard grouping's bit for
     bit and the FP64 oracle to the bar.  A 9 x 9 raster gives an odd standard grid for every
-    shape here but 16 x 16, so the last wide workgroup has slots past the last segment."""
-    print("case ggn wide", probe, joint, flush=True)
-    case = make_case(probe, 9, 9, 6, joint=joint, seed=95 + probe[0] + probe[1])
+    shape here but 16 x 16, so the last wide workgroup has slots past the last segment; one and
+    two positions leave a single wide workgroup with one or two real slots."""
+    print("case ggn wide", probe, ny, nx, joint, flush=True)
+    case = make_case(probe, ny, nx, 6, joint=joint, seed=95 + probe[0] + probe[1])
     prob = problem(case)
     O, P, y = to_dev(case["O"]), to_dev(case["P"]), to_dev(case["y"])
     lin = ptycho.linearize(case["O64"], case["P64"], case["pos"], case["y64"], 1e-8, "gauss", joint)
