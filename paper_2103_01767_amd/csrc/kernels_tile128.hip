@@ -21,7 +21,8 @@
 //   access is served per half wavefront, at the cost of the most-hit bank).  The twiddle table
 //   is padded to 17 entries a row for the same reason.
 // * The probe part of the overlap-add is summed in registers across the segment, so only the
-//   object strip is read-modify-written per position.
+//   object strip is read-modify-written per position (except in the linearisation, which has no
+//   registers to spare and read-modify-writes the segment's probe slot as well).
 #include "dft.hpp"
 #include "internal.hpp"
 #include "tile_pixel.hpp"
@@ -83,7 +84,11 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
   const bool joint = g.joint != 0;
   const float bgv = a.bg_add ? (float)((double)g.background + *a.bg_add) : g.background;
 
-  // probe partial of the overlap-add: accP[e * 8 + n2] <-> probe pixel (row, 2 lc + e + 16 n2)
+  // probe partial of the overlap-add: accP[e * 8 + n2] <-> probe pixel (row, 2 lc + e + 16 n2).
+  // The linearisation, which also keeps the loss sums and streams the counts and the phasor
+  // field, has no registers left for it: there the partial is read-modify-written in the
+  // segment's probe slot instead (the first position stores), in the same order of the sums.
+  constexpr bool PREG = OP != OP_LINEARIZE;
   float2 accP[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) accP[j] = make_float2(0.f, 0.f);
@@ -278,15 +283,36 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
         }
         if (joint) {
           const c2* Oq = reinterpret_cast<const c2*>(a.O + (size_t)ry * g.nx + rx + lane_o);
+          if constexpr (PREG) {
 #pragma unroll
-          for (int nn = 0; nn < 8; nn += NO) {
+            for (int nn = 0; nn < 8; nn += NO) {
 #pragma unroll
-            for (int n2 = nn; n2 < nn + NO; ++n2) {
-              const c2 oo = Oq[8 * n2];
-              accP[n2] = cadd(accP[n2], cmulc(v[n2], oo.a));
-              accP[8 + n2] = cadd(accP[8 + n2], cmulc(v[8 + n2], oo.b));
+              for (int n2 = nn; n2 < nn + NO; ++n2) {
+                const c2 oo = Oq[8 * n2];
+                accP[n2] = cadd(accP[n2], cmulc(v[n2], oo.a));
+                accP[8 + n2] = cadd(accP[8 + n2], cmulc(v[8 + n2], oo.b));
+              }
+              __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+          } else {
+            c2* pq = reinterpret_cast<c2*>(g.probe_part + (size_t)seg * M + lane_p);
+            if (k == kbeg) {
+#pragma unroll
+              for (int n2 = 0; n2 < 8; ++n2) {
+                const c2 oo = Oq[8 * n2];
+                pq[8 * n2] = c2{cmulc(v[n2], oo.a), cmulc(v[8 + n2], oo.b)};
+              }
+            } else {
+#pragma unroll
+              for (int nn = 0; nn < 8; nn += NO) {
+#pragma unroll
+                for (int n2 = nn; n2 < nn + NO; ++n2) {
+                  const c2 oo = Oq[8 * n2], cur = pq[8 * n2];
+                  pq[8 * n2] = c2{cadd(cur.a, cmulc(v[n2], oo.a)), cadd(cur.b, cmulc(v[8 + n2], oo.b))};
+                }
+                __builtin_amdgcn_sched_barrier(0);
+              }
+            }
           }
         }
       }
@@ -294,7 +320,8 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
   }
 
   if constexpr (INV) {
-    if (joint) {
+    // (an empty segment leaves a zero slot in either form)
+    if (joint && (PREG || kend == kbeg)) {
       c2* pp = reinterpret_cast<c2*>(g.probe_part + (size_t)seg * M + row * L + 2 * lc);
 #pragma unroll
       for (int n2 = 0; n2 < 8; ++n2) pp[8 * n2] = c2{accP[n2], accP[8 + n2]};

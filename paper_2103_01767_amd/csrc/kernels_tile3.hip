@@ -77,6 +77,9 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
   const float isq = 1.0f / (float)L;
   const bool joint = g.joint != 0;
   const float bgv = a.bg_add ? (float)((double)g.background + *a.bg_add) : g.background;
+  // probe partial of the overlap-add, in registers across the segment; the linearisation has
+  // none to spare and read-modify-writes it in the segment's probe slot (same order of the sums)
+  constexpr bool PREG = OP != OP_LINEARIZE;
   float2 accP[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) accP[j] = make_float2(0.f, 0.f);
@@ -378,8 +381,19 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
         }
         if (joint) {
           const float2* Orow = a.O + (size_t)Y * g.nx + rx + xc;
+          if constexpr (PREG) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j) accP[j] = cadd(accP[j], cmulc(v[j], Orow[R * j]));
+            for (int j = 0; j < 16; ++j) accP[j] = cadd(accP[j], cmulc(v[j], Orow[R * j]));
+          } else {
+            float2* pp = g.probe_part + (size_t)seg * C::M + xy * L + xc;
+            if (it == 0) {
+#pragma unroll
+              for (int j = 0; j < 16; ++j) pp[R * j] = cmulc(v[j], Orow[R * j]);
+            } else {
+#pragma unroll
+              for (int j = 0; j < 16; ++j) pp[R * j] = cadd(pp[R * j], cmulc(v[j], Orow[R * j]));
+            }
+          }
         }
       }
       // the next position's x pass 1 writes rows other threads may still read here
@@ -388,7 +402,8 @@ __device__ __forceinline__ void tile3_body(const Geometry g, const TileArgs a, i
   }
 
   if constexpr (SCATTER) {
-    if (joint) {
+    // (an empty segment leaves a zero slot in either form)
+    if (joint && (PREG || kend == kbeg)) {
       float2* pp = g.probe_part + (size_t)seg * C::M + xy * L + xc;
 #pragma unroll
       for (int j = 0; j < 16; ++j) pp[R * j] = accP[j];
