@@ -122,7 +122,7 @@ ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, con
 
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
                       const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
-                      int stage) {
+                      int stage, double* pap, const int* pap_block) {
   if (stage & 1) {
     TileArgs a{};
     a.O = h->g.O_lin;
@@ -133,7 +133,8 @@ ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double
     PTLM_HIP(launch_tile(h->g, OP_GGNV, a, s), "ggn_vp");
   }
   if (stage & 2) {
-    PTLM_HIP(launch_reduce_pair(h->g, outO, h->g.joint ? outP : nullptr, lam, lam_dev, dO, dP, vO, vP, pred, s),
+    PTLM_HIP(launch_reduce_pair(h->g, outO, h->g.joint ? outP : nullptr, lam, lam_dev, dO, dP, vO, vP, pred, s, pap,
+                                pap_block),
              "ggn_vp reduce");
   }
   return PTLM_OK;

@@ -88,7 +88,7 @@ ptlm_status linearize_impl(ptlm_handle* h, const float2* O, const float2* P, con
                            float2* gO, float2* gP, hipStream_t s);
 ptlm_status ggnv_impl(ptlm_handle* h, const float2* vO, const float2* vP, double lam, const double* lam_dev,
                       const float* dO, const float* dP, float2* outO, float2* outP, const int* pred, hipStream_t s,
-                      int stage = 3);
+                      int stage = 3, double* pap = nullptr, const int* pap_block = nullptr);
 ptlm_status diag_exact_impl(ptlm_handle* h, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);
 ptlm_status diag_stochastic_impl(ptlm_handle* h, int samples, unsigned long long seed, unsigned long long draw0,
                                  const int* draw_t, float* dO, float* dP, hipStream_t s, const int* pred = nullptr);

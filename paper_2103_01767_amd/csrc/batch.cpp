@@ -503,6 +503,10 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
         }
         r.lam_dev = &d_states[i].lambda;
         r.pred = flags + (k == RK_WARM ? FL_WARM : FL_CG);
+        if (k == RK_P) {  // a PCG product: the parts of p.Ap, laid out as the single-problem launch's
+          r.pap = a.partials;
+          r.pap_block = params->alternate ? &d_states[i].block : nullptr;
+        }
       }
       RedJob ro = r, rp = r;
       ro.block0 = b->obj_b0[i];
@@ -510,6 +514,7 @@ ptlm_status ptlm_batch_bind(ptlm_batch* b, float* const* d_O, float* const* d_P,
       rp.block0 = k == RK_DIAG ? b->dprb_b0[i] : b->prb_b0[i];
       rp.block1 = b->prb1_b0[i];
       rp.nblk = g.joint ? (int)((M + 63) / 64) : 0;  // 64 probe pixels per block (reduction and diagonal)
+      ro.pap_base = rp.nblk;
       b->red_obj[k][i] = ro;
       b->red_prb[k][i] = rp;
     }

@@ -93,6 +93,9 @@ struct RedJob {
   const double* lam_dev;  // damping read from the device (null: none)
   const int* pred;        // skip when *pred == 0
   double* sums;           // partial-sum output (sum kernels)
+  double* pap;            // nullable: per-block parts of p.Ap, p = v (pair reduction of a PCG product)
+  const int* pap_block;   // nullable: the alternating update's active block (0 object, 1 probe)
+  int pap_base;           // index of the job's first object block among its p.Ap parts
   int block0;
   int nblk;
   int block1;  // first block of the job in a second launch (probe reduction pass one)
@@ -177,10 +180,17 @@ __host__ __device__ inline int prb_chunk_count(int M, int nseg) {
 hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, const double* lam_dev, const float* dP,
                                const float2* vP, const int* predicate, hipStream_t s);
 // both of the above in one launch (after the probe's first pass when it takes two); outP null:
-// the object sum alone
+// the object sum alone.  With pap, the launch's block b (probe blocks first, then the object
+// tiles) also stores its part of the real inner product v.out at pap[4 b]; with pap_block,
+// only the block *pap_block selects (0 object, 1 probe) contributes.
 hipError_t launch_reduce_pair(const Geometry& g, float2* outO, float2* outP, double lam, const double* lam_dev,
                               const float* dO, const float* dP, const float2* vO, const float2* vP,
-                              const int* predicate, hipStream_t s);
+                              const int* predicate, hipStream_t s, double* pap = nullptr,
+                              const int* pap_block = nullptr);
+// number of blocks of launch_reduce_pair (the p.Ap parts it leaves)
+inline int reduce_pair_blocks(const Geometry& g, bool probe) {
+  return (probe ? (g.my * g.mx + 63) / 64 : 0) + g.otiles_x * g.otiles_y;
+}
 // out[j] = sum of the j-th entries of `count` double4 partials, j < nout (<= 4)
 hipError_t launch_sum_partials(const double* partials, int count, double* out, int nout, hipStream_t s,
                                const int* pred = nullptr);

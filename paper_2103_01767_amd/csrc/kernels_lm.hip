@@ -103,11 +103,12 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
   if (flag_clear(a, flag)) return;
   const double lam = a.st->lambda;
   const bool warm = a.st->use_warm != 0;
-  // V_CG_STEP: alpha = r.z / p^T A p from V_PAP's partials (what a finalize kernel would do)
+  // V_CG_STEP: alpha = r.z / p^T A p from the parts the product's sums left (what a finalize
+  //            kernel would do)
   // V_P_STEP:  beta = r'.z' / r.z from V_CG_STEP's partials, and the PCG stopping test
   float alpha = 0.f, beta = 0.f;
   if constexpr (OP == V_CG_STEP) {
-    const double pap = block_sum_partials(a.partials, a.vec_blocks, 0);
+    const double pap = block_sum_partials(a.partials, a.pap_count, 0);
     const bool curv = pap > 0.0 && isfinite(pap);
     const double al = curv ? a.scal[SC_RZ + (iter & 1)] / pap : 0.0;
     if (bid == 0 && threadIdx.x == 0) {
@@ -141,12 +142,12 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
   double acc0 = 0.0, acc1 = 0.0;
   // steps of the PCG recurrence and of the projected plug-in touch the active block only;
   // V_CG_INIT and V_WARM_P clear the rest of their vectors, V_TRIAL keeps it at the iterate
-  constexpr bool BLOCK = OP == V_PAP || OP == V_CG_STEP || OP == V_P_STEP || OP == V_PROJ || OP == V_LS_DIR ||
+  constexpr bool BLOCK = OP == V_CG_STEP || OP == V_P_STEP || OP == V_PROJ || OP == V_LS_DIR ||
                          OP == V_LS_NEG;
   const Range act = active_range(a);
   const size_t lo = BLOCK ? act.lo : 0, hi = BLOCK ? act.hi : a.n;
   const size_t stride = (size_t)nblk * blockDim.x;
-  constexpr bool PCG = OP == V_PAP || OP == V_CG_STEP || OP == V_P_STEP;
+  constexpr bool PCG = OP == V_CG_STEP || OP == V_P_STEP;
   if constexpr (PCG) {
     // the PCG recurrence: a thread's entries i, i + stride, ... in groups of four, every load of a
     // group issued before its arithmetic (the same entries and the same order of the sums)
@@ -175,9 +176,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       for (int u = 0; u < U; ++u) {
         const size_t i = i0 + u * stride;
         if (i >= hi) continue;
-        if constexpr (OP == V_PAP) {
-          acc0 += rdot(p[u], q[u]);
-        } else if constexpr (OP == V_CG_STEP) {
+        if constexpr (OP == V_CG_STEP) {
           float2 xx = x[u], rr = r[u];
           xx.x = fmaf(alpha, p[u].x, xx.x);
           xx.y = fmaf(alpha, p[u].y, xx.y);
@@ -306,7 +305,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
     }
   }
   constexpr bool MAXR = OP == V_DIAGMAX || OP == V_XMAX;
-  constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_PAP || OP == V_CG_STEP ||
+  constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_CG_STEP ||
                         OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG || OP == V_SAME;
   if constexpr (SUMS) {
     __shared__ double sh[256][2];
@@ -326,7 +325,8 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      // V_CG_STEP leaves its sums in columns 2, 3: every block still reads V_PAP's in column 0
+      // V_CG_STEP leaves its sums in columns 2, 3: every block still reads the p.Ap parts in
+      // column 0
       constexpr int c = OP == V_CG_STEP ? 2 : 0;
       a.partials[bid * 4 + c] = sh[0][0];
       a.partials[bid * 4 + c + 1] = sh[0][1];
@@ -623,7 +623,7 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 }
 
 #define PTLM_VEC_CASES(X)                                                                                 \
-  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_PAP) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
+  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
   X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME) X(V_LEARNED)
 #define PTLM_FIN_CASES(X)                                                                                 \
   X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \

@@ -11,8 +11,22 @@ namespace ptlm {
 // One block per 16x16 object tile: the tile's segment list (boxes, offsets) is staged in
 // LDS, then every thread sums its pixel over the list with independent loads.
 constexpr int OBJ_LIST = 256;
+// p.Ap of a PCG iteration, folded into the sums that finish its product: each block of the
+// object and probe sums adds rdot(v, out) over its pixels (FP64; the pixels of the block the
+// alternating update leaves inactive count zero) and stores it at pap[4 * pidx] for the next
+// vector step to sum in a fixed order.
+__device__ __forceinline__ double pdot(float2 a, float2 b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 __device__ __forceinline__ void obj_reduce_body(const Geometry& g, float2* out, float lam_h, const double* lam_dev,
-                                                const float* d, const float2* v, const int* pred, int bx, int by) {
+                                                const float* d, const float2* v, const int* pred, int bx, int by,
+                                                double* pap = nullptr, const int* pap_block = nullptr, int pidx = 0) {
   if (pred && *pred == 0) return;
   __shared__ int4 s_box[OBJ_LIST];
   __shared__ long long s_off[OBJ_LIST];
@@ -53,19 +67,31 @@ __device__ __forceinline__ void obj_reduce_body(const Geometry& g, float2* out, 
       }
     }
   }
-  if (!in) return;
-  const size_t n = (size_t)Y * g.nx + X;
-  if (lam != 0.f && v) {
-    const float2 vv = v[n];
-    if (d) {
-      acc.x = fmaf(lam * d[2 * n], vv.x, acc.x);
-      acc.y = fmaf(lam * d[2 * n + 1], vv.y, acc.y);
-    } else {
-      acc.x = fmaf(lam, vv.x, acc.x);
-      acc.y = fmaf(lam, vv.y, acc.y);
+  const bool dot = pap && v && (!pap_block || *pap_block == 0);
+  double pd = 0.0;
+  if (in) {
+    const size_t n = (size_t)Y * g.nx + X;
+    const float2 vv = v && (lam != 0.f || dot) ? v[n] : make_float2(0.f, 0.f);
+    if (lam != 0.f && v) {
+      if (d) {
+        acc.x = fmaf(lam * d[2 * n], vv.x, acc.x);
+        acc.y = fmaf(lam * d[2 * n + 1], vv.y, acc.y);
+      } else {
+        acc.x = fmaf(lam, vv.x, acc.x);
+        acc.y = fmaf(lam, vv.y, acc.y);
+      }
     }
+    out[n] = acc;
+    if (dot) pd = pdot(vv, acc);
   }
-  out[n] = acc;
+  if (pap) {
+    // every thread of the block reaches this barrier (none has returned)
+    __shared__ double wsum[4];
+    pd = wave_sum(pd);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = pd;
+    __syncthreads();
+    if (threadIdx.x == 0) pap[(size_t)pidx * 4] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+  }
 }
 
 __global__ __launch_bounds__(256) void obj_reduce_kernel(Geometry g, float2* out, float lam_h, const double* lam_dev,
@@ -112,7 +138,9 @@ __device__ __forceinline__ void probe_chunk_body(const Geometry& g, const int* p
 }
 
 __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out, float lam_h, const double* lam_dev,
-                                                  const float* d, const float2* v, const int* pred, int bx) {
+                                                  const float* d, const float2* v, const int* pred, int bx,
+                                                  double* pap = nullptr, const int* pap_block = nullptr,
+                                                  int pidx = 0) {
   if (pred && *pred == 0) return;
   __shared__ float2 sh[4][64];
   const float lam = lam_dev ? (float)*lam_dev : lam_h;
@@ -123,33 +151,43 @@ __device__ __forceinline__ void probe_reduce_body(const Geometry& g, float2* out
   const bool two = nch > 0;
   float2 acc = rows_sum4(g.probe_part + m, two ? nch : g.nseg,
                          two ? (size_t)PRB_CHUNK * M : (size_t)M, m < M, grp, lane, sh);
-  if (grp != 0 || m >= M) return;
-  if (lam != 0.f && v) {
-    const float2 vv = v[m];
-    if (d) {
-      acc.x = fmaf(lam * d[2 * m], vv.x, acc.x);
-      acc.y = fmaf(lam * d[2 * m + 1], vv.y, acc.y);
-    } else {
-      acc.x = fmaf(lam, vv.x, acc.x);
-      acc.y = fmaf(lam, vv.y, acc.y);
+  if (grp != 0) return;  // the first wavefront holds the sums
+  const bool dot = pap && v && (!pap_block || *pap_block != 0);
+  double pd = 0.0;
+  if (m < M) {
+    const float2 vv = v && (lam != 0.f || dot) ? v[m] : make_float2(0.f, 0.f);
+    if (lam != 0.f && v) {
+      if (d) {
+        acc.x = fmaf(lam * d[2 * m], vv.x, acc.x);
+        acc.y = fmaf(lam * d[2 * m + 1], vv.y, acc.y);
+      } else {
+        acc.x = fmaf(lam, vv.x, acc.x);
+        acc.y = fmaf(lam, vv.y, acc.y);
+      }
     }
+    out[m] = acc;
+    if (dot) pd = pdot(vv, acc);
   }
-  out[m] = acc;
+  if (pap) {
+    pd = wave_sum(pd);
+    if (lane == 0) pap[(size_t)pidx * 4] = pd;
+  }
 }
 
 // The object and probe sums of one product or gradient in one launch: blocks 0 .. nprb - 1 run
 // the probe sum (started first: each adds every segment's partial), the rest the object
 // tiles, with the bodies of the two separate kernels (same results).
+// With pap, block b also leaves its part of p.Ap (p = v) at pap[4 b].
 __global__ __launch_bounds__(256) void pair_reduce_kernel(Geometry g, float2* outO, float2* outP, float lam_h,
                                                           const double* lam_dev, const float* dO, const float* dP,
                                                           const float2* vO, const float2* vP, const int* pred,
-                                                          int nprb) {
+                                                          int nprb, double* pap, const int* pap_block) {
   const int b = blockIdx.x;
   if (b < nprb) {
-    probe_reduce_body(g, outP, lam_h, lam_dev, dP, vP, pred, b);
+    probe_reduce_body(g, outP, lam_h, lam_dev, dP, vP, pred, b, pap, pap_block, b);
   } else {
     const int l = b - nprb;
-    obj_reduce_body(g, outO, lam_h, lam_dev, dO, vO, pred, l % g.otiles_x, l / g.otiles_x);
+    obj_reduce_body(g, outO, lam_h, lam_dev, dO, vO, pred, l % g.otiles_x, l / g.otiles_x, pap, pap_block, b);
   }
 }
 
@@ -179,11 +217,13 @@ __global__ __launch_bounds__(256) void pair_reduce_batch_kernel(const RedJob* __
   const int b = blockIdx.x;
   if (b < nbp) {
     const RedJob& J = prbjobs[prbjb[b]];
-    probe_reduce_body(J.g, J.outP, 0.f, J.lam_dev, J.dP, J.vP, J.pred, b - J.block0);
+    const int l = b - J.block0;
+    probe_reduce_body(J.g, J.outP, 0.f, J.lam_dev, J.dP, J.vP, J.pred, l, J.pap, J.pap_block, l);
   } else {
     const RedJob& J = objjobs[objjb[b - nbp]];
     const int l = b - nbp - J.block0;
-    obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x);
+    obj_reduce_body(J.g, J.outO, 0.f, J.lam_dev, J.dO, J.vO, J.pred, l % J.g.otiles_x, l / J.g.otiles_x, J.pap,
+                    J.pap_block, J.pap_base + l);
   }
 }
 
@@ -425,7 +465,7 @@ hipError_t launch_probe_reduce(const Geometry& g, float2* outP, double lam, cons
 
 hipError_t launch_reduce_pair(const Geometry& g, float2* outO, float2* outP, double lam, const double* lam_dev,
                               const float* dO, const float* dP, const float2* vO, const float2* vP, const int* pred,
-                              hipStream_t s) {
+                              hipStream_t s, double* pap, const int* pap_block) {
   const int M = g.my * g.mx;
   const int nprb = outP ? (M + 63) / 64 : 0;
   if (outP && prb_chunk_count(M, g.nseg) > 0) {
@@ -435,7 +475,7 @@ hipError_t launch_reduce_pair(const Geometry& g, float2* outO, float2* outP, dou
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(pair_reduce_kernel, dim3(nprb + g.otiles_x * g.otiles_y), dim3(256), 0, s, g, outO, outP,
-                     (float)lam, lam_dev, dO, dP, vO, vP, pred, nprb);
+                     (float)lam, lam_dev, dO, dP, vO, vP, pred, nprb, pap, pap_block);
   return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ LMArgs make_lm_args(ptlm_handle* h, const ptlm_lm_params* prm, ptlm_lm_state* st
   a.partials = h->g.partials;
   a.scal = (double*)(h->ws + p.off.scal);
   a.vec_blocks = lm_vec_blocks(a.n);
+  a.pap_count = reduce_pair_blocks(h->g, h->g.joint);
   a.tile_grid = h->g.grid;
   a.t_max = INT_MAX;
   return a;
@@ -164,8 +165,11 @@ struct SingleOps {
     const size_t N = a.nobj;
     const float* dO = a.prm.scaling ? (const float*)a.diag : nullptr;
     const float* dP = a.prm.scaling ? (const float*)(a.diag + N) : nullptr;
+    // a PCG product leaves the parts of p.Ap for the step that follows it
+    const bool pcg = which == GG_P;
     return ggnv_impl(h, v, h->g.joint ? v + N : nullptr, 0.0, &a.st->lambda, dO, dP, a.Ap,
-                     h->g.joint ? a.Ap + N : nullptr, pred, s);
+                     h->g.joint ? a.Ap + N : nullptr, pred, s, 3, pcg ? a.partials : nullptr,
+                     pcg && a.prm.alternate ? &a.st->block : nullptr);
   }
   ptlm_status trial_loss() {
     Geometry& g = h->g;

@@ -64,8 +64,7 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
     bool go = true;
     PTLM_TRY(o.cg_gate(i, &go));
     if (!go) break;
-    PTLM_TRY(o.ggnv(GG_P));
-    PTLM_TRY(o.vec(V_PAP, FL_CG, i));      // p^T A p partials
+    PTLM_TRY(o.ggnv(GG_P));                // A p, and the parts of p^T A p
     PTLM_TRY(o.vec(V_CG_STEP, FL_CG, i));  // alpha; Delta, r, z and the r.z, r.r partials
     PTLM_TRY(o.vec(V_P_STEP, FL_CG, i));   // beta, stopping test; p = z + beta p
     PTLM_TRY(o.cg_mark(i + 1));

@@ -18,7 +18,7 @@ inline int lm_vec_blocks(size_t n) {
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_XMAX_O = 5, SC_XMAX_P = 6,
        SC_LS1 = 13, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
-enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_PAP, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
+enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
                    V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME, V_LEARNED };
 enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_ADOPT,
                    F_PJ_CHECK, F_LS_DIR, F_LS_NEG, F_LS_TEST };
@@ -52,9 +52,10 @@ struct LMArgs {
   size_t nprobe;           // complex entries of the probe
   ptlm_lm_state* st;
   ptlm_lm_params prm;
-  double* partials;        // >= vec_blocks * 4
+  double* partials;        // >= max(vec_blocks, pap_count) * 4
   double* scal;
   int vec_blocks;          // blocks of the vector kernels (lm_vec_blocks(n))
+  int pap_count;           // parts of p.Ap a PCG product leaves in column 0 of partials
   int tile_grid;           // workgroups of the tile kernels (partials of the trial loss)
   int t_max;               // outer iterations to run (ptlm_lm_init / batch binding)
   int* cg_flags;           // nullable, pinned host memory: slot j <- whether PCG iteration j runs

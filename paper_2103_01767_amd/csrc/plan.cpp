@@ -221,7 +221,10 @@ ptlm_status make_plan(const ptlm_desc* d, const int32_t* h_pos, Plan& p, double 
   p.off.trace = take((size_t)K * sizeof(double));
   p.off.strips = take((size_t)max_strip * sizeof(float2));
   p.off.probe_part = take(max_nseg * M * sizeof(float2));
-  p.off.partials = take((size_t)std::max(max_grid, 1024) * 4 * sizeof(double));
+  // FP64 partial sums: tile workgroups, vector-kernel blocks (at most 1024) and the p.Ap parts of
+  // a PCG product's sums (one per block of the object and probe sums)
+  const int pap_parts = (joint ? (M + 63) / 64 : 0) + p.oty * p.otx;
+  p.off.partials = take((size_t)std::max({max_grid, 1024, pap_parts}) * 4 * sizeof(double));
   p.off.scratch = d->my == 256 ? take((size_t)max_grid * M * sizeof(float2)) : 0;
   p.off.scal = take(64 * sizeof(double));  // [0..7], [12..17] LM scalars, [8..11] feature / learned-diagonal scratch
   // LM / PCG vectors (complex entries of R^(2n)) and real diagonals
