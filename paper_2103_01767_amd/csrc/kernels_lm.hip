@@ -83,6 +83,8 @@ __device__ __forceinline__ bool flag_clear(const LMArgs& a, int flag) {
 __device__ __forceinline__ double block_sum_partials(const double* partials, int count, int col) {
   __shared__ double sh[256];
   double acc = 0.0;
+  // (unrolled so that a thread's loads are in flight together; the sum keeps its order)
+#pragma unroll 4
   for (int i = threadIdx.x; i < count; i += 256) acc += partials[i * 4 + col];
   __syncthreads();
   sh[threadIdx.x] = acc;
