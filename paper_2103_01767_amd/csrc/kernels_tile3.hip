@@ -3,7 +3,8 @@
 //
 // Same pipeline as the power-of-two kernels (gather -> 2D transform -> per-pixel op ->
 // inverse transform -> atomic-free overlap-add into the segment's strip, probe part in
-// registers), with each length-L transform split as L = 16 x R (Cooley-Tukey,
+// registers, or in the segment's probe slot for the linearisation), with each length-L
+// transform split as L = 16 x R (Cooley-Tukey,
 // n = n1 + R n2, k = k1 + 16 k2):
 //   pass 1  R threads per line, 16 values each: DFT16 over n2, twiddle W_L^(n1 k1);
 //   pass 2  the 16 radix-R DFTs of a line (over n1, for each k1) dealt cyclically to the
