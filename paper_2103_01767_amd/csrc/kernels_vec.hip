@@ -12,9 +12,9 @@ namespace ptlm {
 // LDS, then every thread sums its pixel over the list with independent loads.
 constexpr int OBJ_LIST = 256;
 // p.Ap of a PCG iteration, folded into the sums that finish its product: each block of the
-// object and probe sums adds rdot(v, out) over its pixels (FP64; the pixels of the block the
-// alternating update leaves inactive count zero) and stores it at pap[4 * pidx] for the next
-// vector step to sum in a fixed order.
+// object and probe sums adds the real inner product of v and out over its pixels (FP64; the
+// pixels of the block the alternating update leaves inactive count zero) and stores it at
+// pap[4 * pidx] for the next vector step to sum in a fixed order.
 __device__ __forceinline__ double pdot(float2 a, float2 b) {
   return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
 }
