@@ -118,6 +118,44 @@ def test_first_attempt_matches_oracle_step():
             assert s.rho == pytest.approx(h0.rho, rel=1e-3, abs=1e-3)
 
 
+@pytest.mark.parametrize("mode,alternate", [("joint", 0), ("object", 0), ("joint", 1)])
+def test_first_pcg_curvature_matches_oracle(mode, alternate):
+    """p^T (G + lambda I) p of a PCG iteration, which the object and probe sums finishing the
+    product accumulate block by block (alg:lm_inexact), against the oracle: at t = 0, with D = I,
+    no preconditioner and one PCG iteration, PCG starts from zero and p = r = -g, so the state
+    holds g^T G g + lambda g^T g at the linearisation point.  Under the alternating update the
+    state is that of the probe sub-step: p is -g on the probe block and zero on the object, at
+    the object the first sub-step left."""
+    pr = synth.make_small(11, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode=mode)
+    rng = np.random.default_rng(11)
+    joint = mode == "joint"
+    y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
+    O0, P0 = pr.O_init.astype(np.complex64), pr.P_init.astype(np.complex64)
+    prob = pt.Problem(pr.O_true.shape, pr.P_true.shape, pr.pos, mode=mode, background=pr.background, device=DEV)
+    O, P, yd = to_dev(O0, np.complex64), to_dev(P0, np.complex64), to_dev(y, np.float32)
+    params = pt.default_params(scaling=0, precond=0, cg_max=1, alternate=alternate)
+    st = prob.new_state()
+    prob.lm_init(params, st)
+    prob.lm_step(O, P, yd, params, st)
+    s = pt.state_from_tensor(st)
+    # the probe sub-step linearises at the object the object sub-step left (read back)
+    Olin = O.cpu().numpy() if alternate else O0
+    lin = ptycho.linearize(Olin.astype(np.complex128), P0.astype(np.complex128), pr.pos, y.astype(np.float64),
+                           pr.background, "gauss", joint)
+    gO, gP = ptycho.gradient(lin)
+    if alternate:
+        GO, GP = ptycho.ggn_vp(lin, np.zeros_like(gO), gP)
+        ref = solver.rdot(gP, GP) + s.lambda_ * solver.rdot(gP, gP)
+    else:
+        GO, GP = ptycho.ggn_vp(lin, gO, gP)
+        ref = solver.rdot(gO, GO) + s.lambda_ * solver.rdot(gO, gO)
+        if joint:
+            ref += solver.rdot(gP, GP) + s.lambda_ * solver.rdot(gP, gP)
+    print(mode, alternate, "pap gpu", s.pap, "oracle", ref, "cg_iters", s.cg_iters)
+    assert s.cg_iters == 1
+    assert s.pap == pytest.approx(ref, rel=1e-5)
+
+
 def _small_joint(seed=9):
     pr = synth.make_small(seed, obj_side=40, probe=(16, 16), n=5, step=5, photons=1e3, mode="joint")
     rng = np.random.default_rng(seed)
