@@ -156,12 +156,13 @@ def test_first_pcg_curvature_matches_oracle(mode, alternate):
     assert s.pap == pytest.approx(ref, rel=1e-5)
 
 
-@pytest.mark.parametrize("side,metric", [(32, "gauss"), (48, "gauss"), (64, "gauss"), (96, "gauss"),
+@pytest.mark.parametrize("side,metric", [(32, "gauss"), (48, "gauss"), (64, "gauss"), (96, "gauss"), (256, "gauss"),
                                          (48, "poisson"), (96, "poisson")])
 def test_joint_lm_other_probe_sides_matches_oracle(side, metric):
     """The joint scaled-Jacobi LM (alg:lm_inexact) through the tile kernels of other probe sides:
     32 x 32 in its wide workgroup grouping, 48 x 48 and 96 x 96 with their 16 x 3 and 16 x 6
-    transforms (the linearisation keeping the probe partial in the segment slot), 64 x 64.
+    transforms (the linearisation keeping the probe partial in the segment slot), 64 x 64, and
+    256 x 256 with its three stages through the transform tile.
 
     Gaussian metric: ten outer iterations end within 1 % of the oracle's loss.  Poisson metric
     (about 0.4 photons per pixel, damping down to 1e-8): the first outer iteration (linearisation,
@@ -171,7 +172,7 @@ def test_joint_lm_other_probe_sides_matches_oracle(side, metric):
     (48 x 48: after ten iterations the GPU ends 16 % higher above the metric's minimum, and the
     oracle itself ends 13-21 % higher when its start is perturbed by 1e-7 or 1e-6 relative)."""
     print("case lm side", side, metric, flush=True)
-    n, step = 4, side // 4
+    n, step = (3, 64) if side == 256 else (4, side // 4)
     pr = synth.make_small(40 + side, obj_side=(n - 1) * step + side + 8, probe=(side, side), n=n, step=step,
                           photons=1e3, mode="joint")
     rng = np.random.default_rng(40 + side)
