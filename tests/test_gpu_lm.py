@@ -156,13 +156,15 @@ def test_first_pcg_curvature_matches_oracle(mode, alternate):
     assert s.pap == pytest.approx(ref, rel=1e-5)
 
 
-@pytest.mark.parametrize("side,metric", [(32, "gauss"), (48, "gauss"), (64, "gauss"), (96, "gauss"), (256, "gauss"),
-                                         (48, "poisson"), (96, "poisson")])
-def test_joint_lm_other_probe_sides_matches_oracle(side, metric):
-    """The joint scaled-Jacobi LM (alg:lm_inexact) through the tile kernels of other probe sides:
+@pytest.mark.parametrize("shape,metric", [((32, 32), "gauss"), ((48, 48), "gauss"), ((64, 64), "gauss"),
+                                          ((96, 96), "gauss"), ((256, 256), "gauss"), ((32, 64), "gauss"),
+                                          ((128, 32), "gauss"), ((48, 48), "poisson"), ((96, 96), "poisson")])
+def test_joint_lm_other_probe_sides_matches_oracle(shape, metric):
+    """The joint scaled-Jacobi LM (alg:lm_inexact) through the tile kernels of other probe shapes:
     32 x 32 in its wide workgroup grouping, 48 x 48 and 96 x 96 with their 16 x 3 and 16 x 6
-    transforms (the linearisation keeping the probe partial in the segment slot), 64 x 64, and
-    256 x 256 with its three stages through the transform tile.
+    transforms (the linearisation keeping the probe partial in the segment slot), 64 x 64,
+    256 x 256 with its three stages through the transform tile, and the rectangular 32 x 64 and
+    128 x 32.
 
     Gaussian metric: ten outer iterations end within 1 % of the oracle's loss.  Poisson metric
     (about 0.4 photons per pixel, damping down to 1e-8): the first outer iteration (linearisation,
@@ -171,11 +173,13 @@ def test_joint_lm_other_probe_sides_matches_oracle(side, metric):
     precision and the FP64 oracle take visibly different steps on this ill-conditioned system
     (48 x 48: after ten iterations the GPU ends 16 % higher above the metric's minimum, and the
     oracle itself ends 13-21 % higher when its start is perturbed by 1e-7 or 1e-6 relative)."""
-    print("case lm side", side, metric, flush=True)
+    print("case lm shape", shape, metric, flush=True)
+    side = max(shape)
+    seed = 40 + shape[0] + (shape[1] if shape[1] != shape[0] else 0)
     n, step = (3, 64) if side == 256 else (4, side // 4)
-    pr = synth.make_small(40 + side, obj_side=(n - 1) * step + side + 8, probe=(side, side), n=n, step=step,
-                          photons=1e3, mode="joint")
-    rng = np.random.default_rng(40 + side)
+    pr = synth.make_small(seed, obj_side=(n - 1) * step + side + 8, probe=shape, n=n, step=step, photons=1e3,
+                          mode="joint")
+    rng = np.random.default_rng(seed)
     O0 = pr.O_init.astype(np.complex64)
     P0 = pr.P_init.astype(np.complex64)
     y = synth.poisson_counts(rng, ptycho.intensity(pr.O_true, pr.P_true, pr.pos, pr.background)).astype(np.float32)
@@ -192,7 +196,7 @@ def test_joint_lm_other_probe_sides_matches_oracle(side, metric):
     prob.lm_solve(O, P, yd, params, T, st)
     f_gpu = float(prob.loss(O, P, yd).cpu()[0])
     f0 = ref.f_per_iter[0]
-    print("side %d %s: oracle f=%.6e gpu f=%.6e (start %.3e)" % (side, metric, ref.f, f_gpu, f0))
+    print("shape %s %s: oracle f=%.6e gpu f=%.6e (start %.3e)" % (shape, metric, ref.f, f_gpu, f0))
     assert f_gpu < f0
     if metric == "gauss":
         assert f_gpu <= 1.01 * ref.f
