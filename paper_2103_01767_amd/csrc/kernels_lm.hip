@@ -142,6 +142,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
     beta = (float)be;
   }
   double acc0 = 0.0, acc1 = 0.0;
+  double acc2 = 0.0, acc3 = 0.0;  // V_GNORM_DMAX: the diagonal's block maxima
   // steps of the PCG recurrence and of the projected plug-in touch the active block only;
   // V_CG_INIT and V_WARM_P clear the rest of their vectors, V_TRIAL keeps it at the iterate
   constexpr bool BLOCK = OP == V_CG_STEP || OP == V_P_STEP || OP == V_PROJ || OP == V_LS_DIR ||
@@ -201,6 +202,17 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       const float2 g = a.g[i];
       if (i < a.nobj) acc0 += rdot(g, g);
       else acc1 += rdot(g, g);
+    } else if constexpr (OP == V_GNORM_DMAX) {  // the sums of V_GNORM and the App. B diagonal's maxima
+      const float2 g = a.g[i];
+      const float2 d = a.diag[i];
+      const double m = fmax((double)d.x, (double)d.y);
+      if (i < a.nobj) {
+        acc0 += rdot(g, g);
+        acc2 = fmax(acc2, m);
+      } else {
+        acc1 += rdot(g, g);
+        acc3 = fmax(acc3, m);
+      }
     } else if constexpr (OP == V_SAME) {  // entries of the iterate that differ from the last trial point
       const float2 z = i < a.nobj ? a.O[i] : a.P[i - a.nobj];
       const float2 t = a.ztrial[i];
@@ -218,11 +230,6 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
     } else if constexpr (OP == V_WARM_P) {  // the warm-start vector restricted to the active block
       const bool in = i >= act.lo && i < act.hi;
       a.p[i] = in ? a.prev[i] : make_float2(0.f, 0.f);
-    } else if constexpr (OP == V_DIAGMAX) {
-      const float2 d = a.diag[i];
-      const double m = fmax((double)d.x, (double)d.y);
-      if (i < a.nobj) acc0 = fmax(acc0, m);
-      else acc1 = fmax(acc1, m);
     } else if constexpr (OP == V_DIAGFLOOR) {
       const float f = (float)(a.prm.diag_floor * (i < a.nobj ? a.scal[SC_DMAX_O] : a.scal[SC_DMAX_P]));
       const float2 d = a.diag[i];
@@ -306,7 +313,7 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       }
     }
   }
-  constexpr bool MAXR = OP == V_DIAGMAX || OP == V_XMAX;
+  constexpr bool MAXR = OP == V_XMAX;
   constexpr bool SUMS = OP == V_GNORM || MAXR || OP == V_CG_INIT || OP == V_CG_STEP ||
                         OP == V_TRIAL || OP == V_LS_DIR || OP == V_LS_NEG || OP == V_SAME;
   if constexpr (SUMS) {
@@ -333,6 +340,26 @@ __device__ __forceinline__ void vec_body(const LMArgs& a, int flag, int bid, int
       a.partials[bid * 4 + c] = sh[0][0];
       a.partials[bid * 4 + c + 1] = sh[0][1];
     }
+  }
+  if constexpr (OP == V_GNORM_DMAX) {
+    // columns 0, 1 summed as by V_GNORM, columns 2, 3 the maxima
+    __shared__ double sh4[256][4];
+    sh4[threadIdx.x][0] = acc0;
+    sh4[threadIdx.x][1] = acc1;
+    sh4[threadIdx.x][2] = acc2;
+    sh4[threadIdx.x][3] = acc3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        sh4[threadIdx.x][0] += sh4[threadIdx.x + w][0];
+        sh4[threadIdx.x][1] += sh4[threadIdx.x + w][1];
+        sh4[threadIdx.x][2] = fmax(sh4[threadIdx.x][2], sh4[threadIdx.x + w][2]);
+        sh4[threadIdx.x][3] = fmax(sh4[threadIdx.x][3], sh4[threadIdx.x + w][3]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      for (int c = 0; c < 4; ++c) a.partials[bid * 4 + c] = sh4[0][c];
   }
 }
 
@@ -372,9 +399,11 @@ __device__ __forceinline__ void ls_start(ptlm_lm_state& st, const ptlm_lm_params
 template <int OP>
 __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
   if (flag_clear(a, flag)) return;
-  __shared__ double sh[256][2];
-  double acc0 = 0.0, acc1 = 0.0;
-  constexpr bool MAXR = OP == F_DIAGMAX || OP == F_XMAX;
+  // F_LIN_DMAX also takes the maxima V_GNORM_DMAX leaves in columns 2, 3
+  constexpr bool BOTH = OP == F_LIN_DMAX;
+  __shared__ double sh[256][BOTH ? 4 : 2];
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  constexpr bool MAXR = OP == F_XMAX;
   for (int i = threadIdx.x; i < count; i += 256) {
     if constexpr (MAXR) {
       acc0 = fmax(acc0, a.partials[i * 4]);
@@ -383,9 +412,17 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
       acc0 += a.partials[i * 4];
       acc1 += a.partials[i * 4 + 1];
     }
+    if constexpr (BOTH) {
+      acc2 = fmax(acc2, a.partials[i * 4 + 2]);
+      acc3 = fmax(acc3, a.partials[i * 4 + 3]);
+    }
   }
   sh[threadIdx.x][0] = acc0;
   sh[threadIdx.x][1] = acc1;
+  if constexpr (BOTH) {
+    sh[threadIdx.x][2] = acc2;
+    sh[threadIdx.x][3] = acc3;
+  }
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
@@ -395,6 +432,10 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
       } else {
         sh[threadIdx.x][0] += sh[threadIdx.x + w][0];
         sh[threadIdx.x][1] += sh[threadIdx.x + w][1];
+      }
+      if constexpr (BOTH) {
+        sh[threadIdx.x][2] = fmax(sh[threadIdx.x][2], sh[threadIdx.x + w][2]);
+        sh[threadIdx.x][3] = fmax(sh[threadIdx.x][3], sh[threadIdx.x + w][3]);
       }
     }
     __syncthreads();
@@ -441,8 +482,13 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     st.ls_on = 0;
     st.ls_take = 0;
     st.ls_keep = 0;
-  } else if constexpr (OP == F_LIN) {
-    // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM
+  } else if constexpr (OP == F_LIN || OP == F_LIN_DMAX) {
+    // f and ||grad_zeta ell||^2 from the linearisation, ||g||^2 from V_GNORM (or V_GNORM_DMAX,
+    // with the App. B diagonal's block maxima)
+    if constexpr (BOTH) {
+      a.scal[SC_DMAX_O] = sh[0][2];
+      a.scal[SC_DMAX_P] = sh[0][3];
+    }
     st.f = a.scal[SC_F];
     st.resid_norm = sqrt(a.scal[SC_L1SQ]);
     a.scal[SC_G2_O] = s0;
@@ -455,9 +501,6 @@ __device__ __forceinline__ void fin_body(const LMArgs& a, int count, int flag) {
     }
     st.need_lin = 0;
     st.retries = 0;
-  } else if constexpr (OP == F_DIAGMAX) {
-    a.scal[SC_DMAX_O] = s0;
-    a.scal[SC_DMAX_P] = s1;
   } else if constexpr (OP == F_XMAX) {
     a.scal[SC_XMAX_O] = s0;
     a.scal[SC_XMAX_P] = s1;
@@ -625,11 +668,11 @@ static hipError_t fblaunch(const LMJob* jobs, int nj, int kind, int flag, hipStr
 }
 
 #define PTLM_VEC_CASES(X)                                                                                 \
-  X(V_GNORM) X(V_DIAGMAX) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
-  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME) X(V_LEARNED)
+  X(V_GNORM) X(V_DIAGFLOOR) X(V_CG_INIT) X(V_CG_STEP) X(V_P_STEP) X(V_TRIAL) X(V_XMAX) \
+  X(V_XFLOOR) X(V_PROJ) X(V_LS_DIR) X(V_LS_NEG) X(V_LS_CAND) X(V_WARM_P) X(V_SAME) X(V_LEARNED) X(V_GNORM_DMAX)
 #define PTLM_FIN_CASES(X)                                                                                 \
-  X(F_ATTEMPT) X(F_LIN) X(F_DIAGMAX) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \
-  X(F_INIT) X(F_ADOPT) X(F_PJ_CHECK) X(F_LS_DIR) X(F_LS_NEG) X(F_LS_TEST)
+  X(F_ATTEMPT) X(F_LIN) X(F_XMAX) X(F_BEGIN) X(F_CG_INIT) X(F_PRED) X(F_TRIAL_END) \
+  X(F_INIT) X(F_ADOPT) X(F_PJ_CHECK) X(F_LS_DIR) X(F_LS_NEG) X(F_LS_TEST) X(F_LIN_DMAX)
 
 hipError_t launch_vec(int op, const LMArgs& a, int flag, hipStream_t s, int iter) {
   switch (op) {

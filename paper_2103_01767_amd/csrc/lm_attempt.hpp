@@ -34,13 +34,16 @@ ptlm_status enqueue_attempt(Ops& o, const ptlm_lm_params& prm) {
   // ---- linearisation at z_t (only after an accepted step or at the start)
   PTLM_TRY(o.copy_lin());
   PTLM_TRY(o.linearize());  // f, ||grad_zeta ell||^2, g, phasor field, traces
-  PTLM_TRY(o.vec(V_GNORM, FL_LIN));
-  PTLM_TRY(o.fin(F_LIN, 1, FL_LIN));
   if (prm.scaling == 1 || prm.precond == 1 || prm.precond == 2) {
-    PTLM_TRY(o.diag_paper());  // App. B diagonal, then its floor (diag_floor x block maximum)
-    PTLM_TRY(o.vec(V_DIAGMAX, FL_LIN));
-    PTLM_TRY(o.fin(F_DIAGMAX, 1, FL_LIN));
+    // App. B diagonal; ||g||^2 and the diagonal's block maxima in one pass; then its floor
+    // (diag_floor x block maximum)
+    PTLM_TRY(o.diag_paper());
+    PTLM_TRY(o.vec(V_GNORM_DMAX, FL_LIN));
+    PTLM_TRY(o.fin(F_LIN_DMAX, 1, FL_LIN));
     PTLM_TRY(o.vec(V_DIAGFLOOR, FL_LIN));
+  } else {
+    PTLM_TRY(o.vec(V_GNORM, FL_LIN));
+    PTLM_TRY(o.fin(F_LIN, 1, FL_LIN));
   }
   if (prm.precond == 2) PTLM_TRY(o.learned());
   if (prm.precond == 3 || prm.precond == 4) {

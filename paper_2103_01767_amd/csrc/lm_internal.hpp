@@ -18,10 +18,10 @@ inline int lm_vec_blocks(size_t n) {
 enum { SC_F = 0, SC_L1SQ = 1, SC_DMAX_O = 2, SC_DMAX_P = 3, SC_XMAX_O = 5, SC_XMAX_P = 6,
        SC_LS1 = 13, SC_G2_O = 16, SC_G2_P = 17, SC_RZ = 18 /* and 19 */ };
 
-enum VecOp : int { V_GNORM, V_DIAGMAX, V_DIAGFLOOR, V_CG_INIT, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
-                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME, V_LEARNED };
-enum FinOp : int { F_ATTEMPT, F_LIN, F_DIAGMAX, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_ADOPT,
-                   F_PJ_CHECK, F_LS_DIR, F_LS_NEG, F_LS_TEST };
+enum VecOp : int { V_GNORM, V_DIAGFLOOR, V_CG_INIT, V_CG_STEP, V_P_STEP, V_TRIAL, V_XMAX, V_XFLOOR,
+                   V_PROJ, V_LS_DIR, V_LS_NEG, V_LS_CAND, V_WARM_P, V_SAME, V_LEARNED, V_GNORM_DMAX };
+enum FinOp : int { F_ATTEMPT, F_LIN, F_XMAX, F_BEGIN, F_CG_INIT, F_PRED, F_TRIAL_END, F_INIT, F_ADOPT,
+                   F_PJ_CHECK, F_LS_DIR, F_LS_NEG, F_LS_TEST, F_LIN_DMAX };
 
 // Device flags of the LM state that predicate a launch (int32 index into the state; -1: none).
 enum LMFlag : int {
