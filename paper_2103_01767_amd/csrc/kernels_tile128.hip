@@ -86,9 +86,11 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
 
   // probe partial of the overlap-add: accP[e * 8 + n2] <-> probe pixel (row, 2 lc + e + 16 n2).
   // The linearisation, which also keeps the loss sums and streams the counts and the phasor
-  // field, has no registers left for it: there the partial is read-modify-written in the
-  // segment's probe slot instead (the first position stores), in the same order of the sums.
-  constexpr bool PREG = OP != OP_LINEARIZE;
+  // field, has registers for only part of it or none: the groups n2 >= NREG are read-modify-
+  // written in the segment's probe slot instead (the first position stores), in the same order
+  // of the sums.  Half in registers measured fastest for the Gaussian metric (fewer spills
+  // than all, less slot traffic than none); the other metric codes spill more and keep none.
+  constexpr int NREG = OP != OP_LINEARIZE ? 8 : (MET == 0 ? 4 : 0);
   float2 accP[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) accP[j] = make_float2(0.f, 0.f);
@@ -283,36 +285,24 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
         }
         if (joint) {
           const c2* Oq = reinterpret_cast<const c2*>(a.O + (size_t)ry * g.nx + rx + lane_o);
-          if constexpr (PREG) {
+          c2* pq = reinterpret_cast<c2*>(g.probe_part + (size_t)seg * M + lane_p);
+          const bool first = k == kbeg;
 #pragma unroll
-            for (int nn = 0; nn < 8; nn += NO) {
+          for (int nn = 0; nn < 8; nn += NO) {
 #pragma unroll
-              for (int n2 = nn; n2 < nn + NO; ++n2) {
-                const c2 oo = Oq[8 * n2];
+            for (int n2 = nn; n2 < nn + NO; ++n2) {
+              const c2 oo = Oq[8 * n2];
+              if (n2 < NREG) {
                 accP[n2] = cadd(accP[n2], cmulc(v[n2], oo.a));
                 accP[8 + n2] = cadd(accP[8 + n2], cmulc(v[8 + n2], oo.b));
-              }
-              __builtin_amdgcn_sched_barrier(0);
-            }
-          } else {
-            c2* pq = reinterpret_cast<c2*>(g.probe_part + (size_t)seg * M + lane_p);
-            if (k == kbeg) {
-#pragma unroll
-              for (int n2 = 0; n2 < 8; ++n2) {
-                const c2 oo = Oq[8 * n2];
+              } else if (first) {
                 pq[8 * n2] = c2{cmulc(v[n2], oo.a), cmulc(v[8 + n2], oo.b)};
-              }
-            } else {
-#pragma unroll
-              for (int nn = 0; nn < 8; nn += NO) {
-#pragma unroll
-                for (int n2 = nn; n2 < nn + NO; ++n2) {
-                  const c2 oo = Oq[8 * n2], cur = pq[8 * n2];
-                  pq[8 * n2] = c2{cadd(cur.a, cmulc(v[n2], oo.a)), cadd(cur.b, cmulc(v[8 + n2], oo.b))};
-                }
-                __builtin_amdgcn_sched_barrier(0);
+              } else {
+                const c2 cur = pq[8 * n2];
+                pq[8 * n2] = c2{cadd(cur.a, cmulc(v[n2], oo.a)), cadd(cur.b, cmulc(v[8 + n2], oo.b))};
               }
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
@@ -321,10 +311,11 @@ __device__ __forceinline__ void body(const Geometry g, const TileArgs a, int bid
 
   if constexpr (INV) {
     // (an empty segment leaves a zero slot in either form)
-    if (joint && (PREG || kend == kbeg)) {
+    if (joint) {
       c2* pp = reinterpret_cast<c2*>(g.probe_part + (size_t)seg * M + row * L + 2 * lc);
 #pragma unroll
-      for (int n2 = 0; n2 < 8; ++n2) pp[8 * n2] = c2{accP[n2], accP[8 + n2]};
+      for (int n2 = 0; n2 < 8; ++n2)
+        if (n2 < NREG || kend == kbeg) pp[8 * n2] = c2{accP[n2], accP[8 + n2]};
     }
   }
   if constexpr (SUMS) {
